@@ -1,0 +1,265 @@
+/*
+ * shk.h - C ABI of the MI355X flexible Krylov solver for shifted systems.
+ *
+ * Method: Saibaba, Bakhos, Kitanidis, "A Flexible Krylov Solver for Shifted
+ * Systems with Application to Oscillatory Hydraulic Tomography" (arXiv
+ * 1212.3660).  The library solves the family
+ *
+ *     (K + sigma_j M) x_j = b,   j = 1..n_f                  (section 2, eq. multipleshifted)
+ *
+ * with one flexible Arnoldi basis built from preconditioners K + tau_k M
+ * (Algorithm 3), a per-shift projected problem (Algorithm 4, GMRES variant),
+ * inexact inner solves of the preconditioner systems (section 4, eq.
+ * zmmoditer) and the true-residual bound of eq. trueresidual as stopping test.
+ * K is real symmetric positive definite, M real diagonal (lumped mass), the
+ * shifts complex (sigma = i omega for the phasor equation, section 5.1).
+ *
+ * Conventions shared by every entry point
+ *  - Complex numbers are shk_c128 {re, im} (complex128) unless a call says
+ *    complex64 ({float re, im}).
+ *  - Cells are numbered x fastest: c = x + nx*(y + ny*z).
+ *  - A block of vectors "n x k column-major" stores element (i, j) at i + n*j.
+ *  - "device" pointers are HIP device allocations on the current device; "host"
+ *    pointers are ordinary memory.  The library never frees caller memory.
+ *  - Return value: SHK_OK (0) or a negative SHK_ERR_* code; shk_last_error()
+ *    then returns a thread-local message.  Non-convergence is not a call
+ *    error: it is reported per (shift, rhs) in shk_status.status.
+ *  - hip_stream may be NULL (the default stream).  Calls are stream-ordered
+ *    and synchronise that stream before returning unless stated otherwise.
+ */
+#ifndef SHK_H
+#define SHK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } shk_c128;
+typedef struct { float re, im; } shk_c64;
+typedef struct shk_problem shk_problem;
+typedef struct shk_server shk_server;
+
+/* call errors */
+#define SHK_OK 0
+#define SHK_ERR_INVALID_ARG (-1)
+#define SHK_ERR_OOM (-2)
+#define SHK_ERR_HIP (-3)
+#define SHK_ERR_NOT_READY (-4)
+#define SHK_ERR_UNSUPPORTED (-5)
+#define SHK_ERR_WORKSPACE (-6)
+#define SHK_ERR_REJECTED (-7)
+
+/* per-(shift, rhs) solve status (section 4 stopping test, section 3 breakdown) */
+#define SHK_CONVERGED 0        /* FP64 true relative residual <= tol            */
+#define SHK_NOT_CONVERGED 1    /* restart / refinement budget exhausted          */
+#define SHK_INNER_LIMITED 2    /* quasi-residual below the inexact-inner term of
+                                  eq. trueresidual; refinement decides the rest */
+#define SHK_BREAKDOWN_EXACT 3  /* h_{k+1,k} = 0: exact solution (section 3)      */
+#define SHK_NAN 4              /* non-finite input or arithmetic                  */
+
+/* parameter values */
+#define SHK_GMRES 0
+#define SHK_FOM 1
+#define SHK_FP64 0   /* every vector complex128                                       */
+#define SHK_MIXED 1  /* operator, inner solve and Gram-Schmidt in complex64 with FP32
+                        accumulation; Hessenberg least squares, basis norms, true
+                        residual and refinement in FP64                             */
+#define SHK_PTR_HOST 0
+#define SHK_PTR_DEVICE 1
+
+/*
+ * Solver parameters (inputs of Algorithm 4 plus library knobs).
+ *  m_restart      basis length m before a restart (section 2.2.2); >= 1.
+ *  max_restarts   number of restarts allowed (0 = a single cycle).
+ *  max_refine     FP64 refinement sweeps after the solve (0 = none).
+ *  tol            target ||b - (K + sigma_j M) x_j|| / ||b|| per (shift, rhs)
+ *                 (section 6.1 stopping rule, with x_0 = 0).
+ *  eps_inner      inner tolerance eps: each preconditioner solve stops at
+ *                 ||v_k - (K + tau_k M) z_k|| <= eps ||v_k|| (section 4).
+ *  inner_maxit    cap on inner iterations per solve (0 = 20 * largest grid dim).
+ *  n_tau, tau_seq tau_k used cyclically over the outer step counter (host
+ *                 array of n_tau complex values; section 2.2.1 and the recycled
+ *                 schedule of section 6.1).  A blocked schedule is expressed by
+ *                 repeating entries.
+ *  variant        SHK_GMRES (FOM is not provided by the GPU path: call error).
+ *  precision      SHK_FP64 or SHK_MIXED.
+ *  refine_tol     relative accuracy asked of each refinement correction solve.
+ *  refine_eps_inner  inner tolerance of the correction solves.
+ */
+typedef struct {
+  int m_restart;
+  int max_restarts;
+  int max_refine;
+  int inner_maxit;
+  double tol;
+  double eps_inner;
+  int n_tau;
+  const shk_c128* tau_seq;
+  int variant;
+  int precision;
+  double refine_tol;
+  double refine_eps_inner;
+} shk_params;
+
+/* Per-(shift, rhs) result, host memory, n_shifts x n_rhs column-major. */
+typedef struct {
+  int status;          /* SHK_CONVERGED ...                                    */
+  int outer_its;       /* outer steps taken when the shift was frozen          */
+  int restarts;        /* restarts before it was frozen                        */
+  int refine_sweeps;   /* refinement sweeps applied                            */
+  long long inner_its; /* inner iterations of the whole solve (shared)         */
+  double quasi_relres; /* ||beta e_1 - Hbar(sigma;T) y|| / ||b|| at freeze      */
+  double bound_relres; /* eq. trueresidual bound / ||b|| at freeze             */
+  double true_relres;  /* FP64 ||b - (K + sigma M) x|| / ||b|| on return        */
+} shk_status;
+
+/* Fill *p with defaults: m 50, 20 restarts, 2 refinement sweeps, tol 1e-8,
+ * eps 1e-10, GMRES, FP64, refine_tol 0.05, refine_eps_inner 5e-3, no tau. */
+void shk_params_default(shk_params* p);
+
+/*
+ * Problem setup (section 5.1, eq. phasor1 discretised by cell-centred finite
+ * volumes): face transmissivity T = 2 K_a K_b / (K_a + K_b) h^(d-2) (harmonic
+ * mean), boundary faces T = K_cell h^(d-2) against a Dirichlet ghost value 0,
+ * K_ii = sum of the cell's face T, K_ij = -T; lumped mass M = Ss h^d.
+ *  cell_K  host, nx*ny (or nx*ny*nz) positive conductivities, x fastest.
+ *  Ss, h   specific storage (> 0) and grid spacing (> 0).
+ * The face arrays are computed on the device and owned by the problem, which
+ * also keeps a complex64-path copy.  Errors: INVALID_ARG (sizes, non-positive
+ * or non-finite K), OOM, HIP.
+ */
+int shk_problem_create_fv2d(int nx, int ny, const double* cell_K, double Ss, double h,
+                            shk_problem** out);
+int shk_problem_create_fv3d(int nx, int ny, int nz, const double* cell_K, double Ss, double h,
+                            shk_problem** out);
+/* General K given as CSR (host arrays, 0-based, n rows, K must be symmetric so
+ * the inner COCG applies) and a diagonal mass (host, n entries). */
+int shk_problem_create_csr(int n, const int* rowptr, const int* col, const double* K_val,
+                           const double* M_diag, shk_problem** out);
+void shk_problem_destroy(shk_problem* p);
+/* Number of unknowns n of the problem. */
+long long shk_problem_size(const shk_problem* p);
+
+/* Bytes of device workspace fgmres_sh_solve needs for these sizes. */
+int shk_workspace_bytes(const shk_problem* p, const shk_params* prm, int n_shifts, int n_rhs,
+                        size_t* bytes);
+
+/*
+ * Solve (K + sigma_j M) x_{j,r} = b_r for all shifts j and right-hand sides r
+ * (Algorithms 3 and 4; independent flexible bases per rhs, run in lockstep so
+ * the operator is read once for all of them).
+ *  sigma      host, n_shifts complex shifts.
+ *  b          n x n_rhs column-major complex128 (host or device per ptr_kind).
+ *  x          n x n_shifts x n_rhs column-major complex128: x[c + n*(j + n_shifts*r)]
+ *             (host or device per ptr_kind); overwritten.
+ *  st         host, n_shifts x n_rhs statuses, st[j + n_shifts*r].
+ *  workspace  device buffer of >= shk_workspace_bytes(); NULL lets the library
+ *             allocate and free it inside the call.
+ * Errors: INVALID_ARG, UNSUPPORTED (FOM variant), WORKSPACE (too small), OOM, HIP.
+ */
+int fgmres_sh_solve(shk_problem* p, const shk_params* prm, int n_shifts, const shk_c128* sigma,
+                    int n_rhs, const shk_c128* b, shk_c128* x, shk_status* st, void* workspace,
+                    size_t ws_bytes, void* hip_stream, int ptr_kind);
+
+/* ---------------------------------------------------------------------------
+ * Step-level entry points: each runs one row of the method on device buffers
+ * (all pointers device, vectors of n_rhs right-hand sides stored interleaved:
+ * element (cell c, rhs r) at c*n_rhs + r; n_rhs a power of two <= 64).
+ * precision selects complex128 (SHK_FP64) or complex64 (SHK_MIXED) vectors.
+ * ------------------------------------------------------------------------ */
+
+/* y = (K + sigma M) x (operator of eq. multipleshifted). */
+int shk_apply_shifted(shk_problem* p, shk_c128 sigma, int n_rhs, const void* x, void* y,
+                      int precision, void* hip_stream);
+
+/* Inner preconditioner solve z ~ (K + tau M)^{-1} v (section 4, eq. zmmoditer):
+ * Jacobi-preconditioned COCG from z = 0, stopped when the recurrence residual
+ * satisfies ||r|| <= eps ||v|| or after maxit iterations; fixed_iters > 0 runs
+ * exactly that many iterations instead.  Outputs (host, n_rhs each): its[r],
+ * true residual norm pnorm[r] = ||v - (K + tau M) z||.  Also writes w = M z
+ * (device, may be NULL). */
+int shk_inner_solve(shk_problem* p, shk_c128 tau, int n_rhs, const void* v, void* z, void* w,
+                    double eps, int maxit, int fixed_iters, int precision, int* its,
+                    double* pnorm, void* hip_stream);
+
+/* One orthogonalisation step of Algorithm 3 (classical Gram-Schmidt with one
+ * reorthogonalisation): V holds k orthonormal columns (column stride n*n_rhs
+ * elements), w is orthogonalised against them in place and normalised into
+ * V column k.  h (host, (k+1) x n_rhs, h[i + (k+1)*r]) receives v_i^H w for
+ * i < k and ||w|| at i = k (the new Hessenberg column). */
+int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128* h,
+                      int precision, void* hip_stream);
+
+/* Per-shift projected problem of Algorithm 4 (GMRES): given Hbar ((k+1) x k,
+ * host, column-major, one rhs), taus (host, k) and shifts (host, n_shifts),
+ * solve min ||beta e_1 - Hbar(sigma_j;T) y|| with Givens rotations on the
+ * device, Hbar(sigma;T) = [I;0] + Hbar (sigma I - T) (eq. shiftedarnoldimod).
+ * Outputs (host): y (k x n_shifts column-major) and quasi-residual norms
+ * rho (n_shifts) after each step: rho[s + n_shifts*j] for s = 0..k-1. */
+int shk_shifted_lsq(int k, const shk_c128* Hbar, const shk_c128* taus, int n_shifts,
+                    const shk_c128* sigma, double beta, shk_c128* y, double* rho);
+
+/* Solution assembly x_j = Z y_j (Algorithm 4): Z is k columns of n complex
+ * values (column stride n, complex128 or complex64 per precision, device), Y
+ * (device, k x n_shifts column-major complex128), X (device, n x n_shifts
+ * column-major complex128); accumulate != 0 adds to X. */
+int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128* Y, shk_c128* X,
+                 int accumulate, int precision, void* hip_stream);
+
+/* FP64 true relative residuals ||b - (K + sigma_j M) x_j|| / ||b|| (device b:
+ * n, device x: n x n_shifts column-major; host relres: n_shifts). */
+int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b,
+                      const shk_c128* x, double* relres, void* hip_stream);
+
+/* Text for a status or error code; last error message of the calling thread. */
+const char* shk_status_string(int code);
+const char* shk_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Solve server: requests (field, shifts, right-hand sides) arrive at any time;
+ * a scheduler thread admits them while their Krylov-basis memory fits the
+ * budget and a slot is free, runs admitted requests concurrently on separate
+ * HIP streams, and records arrival, start and completion times.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int nx, ny;              /* 2-D finite-volume grid                             */
+  const double* cell_K;    /* host, nx*ny, copied at submit                      */
+  double Ss, h;
+  int n_shifts;
+  const shk_c128* sigma;   /* host, copied                                       */
+  int n_rhs;
+  const shk_c128* b;       /* host, n x n_rhs, copied                            */
+  shk_params params;       /* tau_seq copied                                     */
+  int keep_solution;       /* 1: keep x for shk_server_poll; 0: statuses only    */
+} shk_request;
+
+typedef struct {
+  int done;                /* 1 when finished                                    */
+  int error;               /* call error of the solve (SHK_OK on success)        */
+  double t_arrival, t_start, t_done;  /* seconds on the server clock           */
+  int n_converged;         /* (shift, rhs) pairs with SHK_CONVERGED              */
+  double max_true_relres;
+} shk_result;
+
+/* mem_budget_bytes bounds the sum of admitted workspaces; max_slots bounds the
+ * number of concurrent requests (streams). */
+int shk_server_create(size_t mem_budget_bytes, int max_slots, shk_server** out);
+/* Copies the request, returns a ticket.  REJECTED if it can never fit. */
+int shk_server_submit(shk_server* s, const shk_request* req, long long* ticket);
+/* Non-blocking: NOT_READY until done; then fills *res.  With x != NULL (host,
+ * n x n_shifts x n_rhs) and st != NULL (host, n_shifts x n_rhs) copies the
+ * solution and statuses out. */
+int shk_server_poll(shk_server* s, long long ticket, shk_result* res, shk_c128* x, shk_status* st);
+/* Blocks until every submitted request is done. */
+int shk_server_drain(shk_server* s);
+/* Current server clock in seconds (the time base of shk_result). */
+double shk_server_clock(shk_server* s);
+int shk_server_destroy(shk_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHK_H */

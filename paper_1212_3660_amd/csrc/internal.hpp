@@ -1,0 +1,79 @@
+// Internal host-side declarations of the shifted-Krylov library.
+#pragma once
+#include <string>
+#include <vector>
+#include "common.hpp"
+#include "ops.hpp"
+#include "../../include/shk.h"
+
+namespace shk {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define SHK_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return ::shk::fail(SHK_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define SHK_TRY(call)         \
+  do {                        \
+    int rc_ = (call);         \
+    if (rc_ != SHK_OK) return rc_; \
+  } while (0)
+
+enum class Kind { FV2D, FV3D, CSR };
+
+}  // namespace shk
+
+// The problem: device copies of the operator coefficients in FP64 (and FP32
+// for the complex64 path).  Owned by the handle.
+struct shk_problem {
+  shk::Kind kind;
+  int nx = 1, ny = 1, nz = 1;
+  long long n = 0;
+  double m0 = 0.0;                  // uniform mass value (FV problems)
+  int device = 0;
+  // finite volume faces
+  double* tx = nullptr; double* ty = nullptr; double* tz = nullptr;
+  float* tx32 = nullptr; float* ty32 = nullptr; float* tz32 = nullptr;
+  // CSR
+  int* rowptr = nullptr; int* col = nullptr;
+  double* val = nullptr; float* val32 = nullptr;
+  double* diag = nullptr;           // diagonal of K (CSR only)
+  double* mdiag = nullptr;          // per-row mass (CSR only)
+  long long nnz = 0;
+  int max_dim() const { return nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz); }
+};
+
+namespace shk {
+
+int solve_all(shk_problem* p, const shk_params* prm, int n_shifts, const c128* sigma, int n_rhs,
+              const c128* b, c128* x, shk_status* st, void* ws, size_t ws_bytes,
+              hipStream_t stream, int ptr_kind);
+
+int step_apply(shk_problem* p, c128 sigma, int S, const void* x, void* y, int precision,
+               hipStream_t stream);
+int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w, double eps,
+               int maxit, int fixed_iters, int precision, int* its, double* pnorm,
+               hipStream_t stream);
+int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precision,
+              hipStream_t stream);
+int step_lsq(int k, const c128* H, const c128* taus, int nf, const c128* sigma, double beta,
+             c128* y, double* rho);
+int step_assemble(long long n, int k, int nf, const void* Z, const c128* Y, c128* X, int acc,
+                  int precision, hipStream_t stream);
+int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x,
+                       double* relres, hipStream_t stream);
+
+int problem_setup_fv(shk_problem* p, const double* cellK_host, double Ss, double h, hipStream_t st);
+int problem_setup_csr(shk_problem* p, const int* rowptr, const int* col, const double* val,
+                      const double* mdiag, hipStream_t st);
+void problem_free(shk_problem* p, hipStream_t st);
+size_t problem_bytes(const shk_problem* p);
+size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x);
+const char* last_error_text();
+
+}  // namespace shk

@@ -1,0 +1,870 @@
+// HIP kernels of the flexible shifted-Krylov solver (gfx950, wave64).
+//
+// Layout: S right-hand-side lanes interleaved, element (cell c, lane r) at
+// c*S + r, S a power of two <= 64.  Item kernels use 256-thread blocks with a
+// grid-stride loop whose stride is a multiple of S, so each thread keeps one
+// lane r for its whole life and per-lane sums need no atomics.
+//
+// Reductions are deterministic: per-thread sums, a fixed wave tree, a fixed
+// cross-wave sum per block, then the last block to finish (counted with one
+// device-scope atomic) adds the block partials in block order.  Repeated runs
+// give bitwise identical results.
+#pragma once
+#include "common.hpp"
+#include "ops.hpp"
+#include "../../include/shk.h"
+
+namespace shk {
+
+constexpr int BS = 256;
+constexpr int NWAVE = BS / WAVE;
+
+// ------------------------------------------------------------ reductions ---
+template <int NV>
+__device__ __forceinline__ void block_partials(c128 (&v)[NV], int S, c128* __restrict__ out) {
+  __shared__ c128 sh[NWAVE][NV][WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum_strided(v[q], S);
+  if (lane < S) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[wv][q][lane] = v[q];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      c128 a = sh[0][q][threadIdx.x];
+      for (int w = 1; w < NWAVE; ++w) a = a + sh[w][q][threadIdx.x];
+      out[q * S + threadIdx.x] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// True in the block that finishes last; its threads then see every block's
+// partial writes.  That block must reset *counter for the next launch.
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned nblocks) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev == nblocks - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last != 0;
+}
+
+// Sum partials laid out [block][NV][S] over blocks in a fixed order.  Every
+// thread returns the totals of its lane r = threadIdx.x % S.
+template <int NV>
+__device__ __forceinline__ void final_sum(const c128* __restrict__ part, int G, int S, c128 (&res)[NV]) {
+  __shared__ c128 sh[NV][BS];
+  const int r = threadIdx.x & (S - 1), c0 = threadIdx.x / S, C = BS / S;
+  c128 acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = c128{0.0, 0.0};
+  for (int b = c0; b < G; b += C) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = acc[q] + part[((size_t)b * NV + q) * S + r];
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int st = C / 2; st >= 1; st >>= 1) {
+    if (c0 < st) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = sh[q][threadIdx.x] + sh[q][threadIdx.x + st * S];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) res[q] = sh[q][r];
+  __syncthreads();
+}
+
+// Block-wide sum of one complex value (all threads one lane), fixed order.
+__device__ __forceinline__ c128 block_sum_all(c128 v) {
+  __shared__ c128 sh[NWAVE];
+  v = wave_sum_strided(v, 1);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  c128 a = sh[0];
+  for (int w = 1; w < NWAVE; ++w) a = a + sh[w];
+  __syncthreads();
+  return a;
+}
+
+// ------------------------------------------------------------- setup -------
+// Face transmissivities from cell conductivities (section 5.1 discretisation):
+// interior faces get the harmonic mean times h^(d-2), boundary faces the cell
+// value times h^(d-2) (Dirichlet ghost at distance h).
+__global__ void __launch_bounds__(BS) k_faces(const double* __restrict__ K, int nx, int ny, int nz,
+                                              int axis, double scale, double* __restrict__ T,
+                                              float* __restrict__ T32) {
+  const int ex = nx + (axis == 0), ey = ny + (axis == 1), ez = nz + (axis == 2);
+  const long total = (long)ex * ey * ez;
+  for (long f = blockIdx.x * (long)BS + threadIdx.x; f < total; f += (long)gridDim.x * BS) {
+    const int i = (int)(f % ex);
+    const long rest = f / ex;
+    const int j = (int)(rest % ey);
+    const int k = (int)(rest / ey);
+    const int a = axis == 0 ? i : (axis == 1 ? j : k);
+    const int na = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    auto cell = [&](int ii, int jj, int kk) { return K[ii + (long)nx * (jj + (long)ny * kk)]; };
+    double t;
+    if (a == 0) {
+      t = cell(i, j, k);
+    } else if (a == na) {
+      t = axis == 0 ? cell(i - 1, j, k) : (axis == 1 ? cell(i, j - 1, k) : cell(i, j, k - 1));
+    } else {
+      const double kb = cell(i, j, k);
+      const double ka = axis == 0 ? cell(i - 1, j, k) : (axis == 1 ? cell(i, j - 1, k) : cell(i, j, k - 1));
+      t = 2.0 * ka * kb / (ka + kb);
+    }
+    T[f] = t * scale;
+    T32[f] = (float)(t * scale);
+  }
+}
+
+// ----------------------------------------------------------- vectors -------
+// ABI layout (n x s_real column-major) -> interleaved c128 with S lanes.
+__global__ void __launch_bounds__(BS) k_interleave(const c128* __restrict__ b, long n, int s_real, int S,
+                                                   c128* __restrict__ out) {
+  const long N = n * S;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    const int r = (int)(t - c * S);
+    out[t] = r < s_real ? b[c + n * r] : c128{0.0, 0.0};
+  }
+}
+
+// Per-lane 2-norm; result out[r] (FP64).
+template <typename R>
+__global__ void __launch_bounds__(BS) k_norm2(const cx<R>* __restrict__ x, long N, int S,
+                                              c128* __restrict__ part, unsigned* __restrict__ cnt,
+                                              double* __restrict__ out) {
+  c128 acc[1] = {{0.0, 0.0}};
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS)
+    acc[0].re += (double)abs2(x[t]);
+  block_partials<1>(acc, S, part + (size_t)blockIdx.x * S);
+  if (arrive_last(cnt, gridDim.x)) {
+    c128 tot[1];
+    final_sum<1>(part, gridDim.x, S, tot);
+    if ((int)threadIdx.x < S) out[threadIdx.x] = sqrt(tot[0].re);
+    if (threadIdx.x == 0) *cnt = 0u;
+  }
+}
+
+// out = in / beta[r] converted to R (zero lanes stay zero).
+template <typename R>
+__global__ void __launch_bounds__(BS) k_scale_conv(const c128* __restrict__ in, long N, int S,
+                                                   const double* __restrict__ beta, cx<R>* __restrict__ out) {
+  const int r = threadIdx.x & (S - 1);
+  const double b = beta[r];
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS)
+    out[t] = cvt<R>(inv * in[t]);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BS) k_copy(const cx<R>* __restrict__ in, long N, cx<R>* __restrict__ out) {
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) out[t] = in[t];
+}
+
+template <typename Op, typename R>
+__global__ void __launch_bounds__(BS) k_apply(Op op, c128 sigma, long n, int S, const cx<R>* __restrict__ x,
+                                              cx<R>* __restrict__ y) {
+  const long N = n * S;
+  const int r = threadIdx.x & (S - 1);
+  const cx<R> sg = cvt<R>(sigma);
+  auto g = [&](long cc) { return x[cc * S + r]; };
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    y[t] = op.template apply<R>(c, sg, g);
+  }
+}
+
+// -------------------------------------------------------- inner COCG --------
+// Jacobi-preconditioned COCG (conjugate orthogonal CG for the complex
+// symmetric K + tau M, bilinear products x^T y) for z ~ (K + tau M)^{-1} v,
+// section 4 eq. zmmoditer.  Two kernels per iteration:
+//   A: p = u + beta p_old (formed on the fly, also at stencil neighbours),
+//      q = A p, partial p^T q; last block: alpha = rho / p^T q
+//   B: x += alpha p, r -= alpha q, u = D^{-1} r, partials r^T u and ||r||^2;
+//      last block: stop test ||r|| <= eps ||v||, beta = rho'/rho
+struct CocgScal {
+  c128 rho, alpha, beta;
+  double vnorm, rnorm, pnorm, mznorm;
+  int its, done, conv, maxit;
+};
+
+template <typename Op, typename R>
+__device__ __forceinline__ cx<R> jacobi_diag(const Op& op, long c, c128 tau) {
+  const double m = op.mass(c);
+  return cx<R>{(R)(op.diagK(c) + tau.re * m), (R)(tau.im * m)};
+}
+
+__device__ __forceinline__ void finish_all_done(CocgScal* sc, int S, int* all_done) {
+  if (threadIdx.x == 0) {
+    int d = 1;
+    for (int r = 0; r < S; ++r) d &= sc[r].done;
+    *all_done = d;
+  }
+}
+
+template <typename Op, typename R>
+__global__ void __launch_bounds__(BS) k_cocg_init(Op op, c128 tau, long n, int S, int maxit,
+                                                  const cx<R>* __restrict__ v, cx<R>* __restrict__ x,
+                                                  cx<R>* __restrict__ r, cx<R>* __restrict__ u,
+                                                  cx<R>* __restrict__ p0, c128* __restrict__ part,
+                                                  unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
+                                                  int* __restrict__ all_done) {
+  const long N = n * S;
+  c128 acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
+  cx<R> a0{0, 0};
+  R a1 = 0;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    const cx<R> vv = v[t];
+    const cx<R> uu = cdiv(vv, jacobi_diag<Op, R>(op, c, tau));
+    x[t] = cx<R>{0, 0};
+    r[t] = vv;
+    u[t] = uu;
+    p0[t] = cx<R>{0, 0};
+    a0 = a0 + vv * uu;
+    a1 += abs2(vv);
+  }
+  acc[0] = cvt<double>(a0);
+  acc[1].re = (double)a1;
+  block_partials<2>(acc, S, part + (size_t)blockIdx.x * 2 * S);
+  if (arrive_last(cnt, gridDim.x)) {
+    c128 tot[2];
+    final_sum<2>(part, gridDim.x, S, tot);
+    if ((int)threadIdx.x < S) {
+      CocgScal s{};
+      s.rho = tot[0];
+      s.vnorm = sqrt(tot[1].re);
+      s.rnorm = s.vnorm;
+      s.beta = c128{0.0, 0.0};
+      s.alpha = c128{0.0, 0.0};
+      s.its = 0;
+      s.maxit = maxit;
+      s.done = (s.vnorm == 0.0) ? 1 : 0;
+      s.conv = s.done;
+      sc[threadIdx.x] = s;
+    }
+    __syncthreads();
+    finish_all_done(sc, S, all_done);
+    if (threadIdx.x == 0) *cnt = 0u;
+  }
+}
+
+template <typename Op, typename R>
+__global__ void __launch_bounds__(BS) k_cocg_A(Op op, c128 tau, long n, int S, const cx<R>* __restrict__ u,
+                                               const cx<R>* __restrict__ pold, cx<R>* __restrict__ pnew,
+                                               cx<R>* __restrict__ q, c128* __restrict__ part,
+                                               unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
+                                               const int* __restrict__ all_done) {
+  if (*all_done) return;
+  const long N = n * S;
+  const int rl = threadIdx.x & (S - 1);
+  const bool dn = sc[rl].done != 0;
+  const cx<R> beta = cvt<R>(sc[rl].beta);
+  const cx<R> tr = cvt<R>(tau);
+  cx<R> a0{0, 0};
+  if (!dn) {
+    auto g = [&](long cc) {
+      const size_t k = (size_t)cc * S + rl;
+      return u[k] + beta * pold[k];
+    };
+    for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+      const long c = t / S;
+      const cx<R> pc = g(c);
+      const cx<R> qq = op.template apply<R>(c, tr, g);
+      pnew[t] = pc;
+      q[t] = qq;
+      a0 = a0 + pc * qq;
+    }
+  }
+  c128 acc[1] = {cvt<double>(a0)};
+  block_partials<1>(acc, S, part + (size_t)blockIdx.x * S);
+  if (arrive_last(cnt, gridDim.x)) {
+    c128 tot[1];
+    final_sum<1>(part, gridDim.x, S, tot);
+    if ((int)threadIdx.x < S) {
+      CocgScal& s = sc[threadIdx.x];
+      if (!s.done) {
+        if (tot[0].re == 0.0 && tot[0].im == 0.0) {
+          s.done = 1;   // p^T q = 0: COCG breakdown, keep the iterate
+          s.alpha = c128{0.0, 0.0};
+        } else {
+          s.alpha = cdiv(s.rho, tot[0]);
+        }
+      }
+    }
+    __syncthreads();
+    finish_all_done(sc, S, (int*)all_done);
+    if (threadIdx.x == 0) *cnt = 0u;
+  }
+}
+
+template <typename Op, typename R>
+__global__ void __launch_bounds__(BS) k_cocg_B(Op op, c128 tau, long n, int S, double eps,
+                                               const cx<R>* __restrict__ p, const cx<R>* __restrict__ q,
+                                               cx<R>* __restrict__ x, cx<R>* __restrict__ r,
+                                               cx<R>* __restrict__ u, c128* __restrict__ part,
+                                               unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
+                                               int* __restrict__ all_done) {
+  if (*all_done) return;
+  const long N = n * S;
+  const int rl = threadIdx.x & (S - 1);
+  const bool dn = sc[rl].done != 0;
+  const cx<R> alpha = cvt<R>(sc[rl].alpha);
+  cx<R> a0{0, 0};
+  R a1 = 0;
+  if (!dn) {
+    for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+      const long c = t / S;
+      const cx<R> xn = x[t] + alpha * p[t];
+      const cx<R> rn = r[t] - alpha * q[t];
+      const cx<R> un = cdiv(rn, jacobi_diag<Op, R>(op, c, tau));
+      x[t] = xn;
+      r[t] = rn;
+      u[t] = un;
+      a0 = a0 + rn * un;
+      a1 += abs2(rn);
+    }
+  }
+  c128 acc[2] = {cvt<double>(a0), {(double)a1, 0.0}};
+  block_partials<2>(acc, S, part + (size_t)blockIdx.x * 2 * S);
+  if (arrive_last(cnt, gridDim.x)) {
+    c128 tot[2];
+    final_sum<2>(part, gridDim.x, S, tot);
+    if ((int)threadIdx.x < S) {
+      CocgScal& s = sc[threadIdx.x];
+      if (!s.done) {
+        s.its += 1;
+        s.rnorm = sqrt(tot[1].re);
+        if (s.rnorm <= eps * s.vnorm) {
+          s.done = 1;
+          s.conv = 1;
+        } else if (s.its >= s.maxit || !(s.rnorm == s.rnorm)) {
+          s.done = 1;
+        } else if (s.rho.re == 0.0 && s.rho.im == 0.0) {
+          s.done = 1;
+        } else {
+          s.beta = cdiv(tot[0], s.rho);
+          s.rho = tot[0];
+        }
+      }
+    }
+    __syncthreads();
+    finish_all_done(sc, S, all_done);
+    if (threadIdx.x == 0) *cnt = 0u;
+  }
+}
+
+// After the inner solve: true inner residual p = v - (K + tau M) z (its norm
+// enters the bound of eq. resdiff) and the mass product w = M z (Algorithm 3).
+template <typename Op, typename R>
+__global__ void __launch_bounds__(BS) k_cocg_finish(Op op, c128 tau, long n, int S,
+                                                    const cx<R>* __restrict__ v, const cx<R>* __restrict__ z,
+                                                    cx<R>* __restrict__ w, c128* __restrict__ part,
+                                                    unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
+                                                    double* __restrict__ pn_out, double* __restrict__ mz_out) {
+  const long N = n * S;
+  const int rl = threadIdx.x & (S - 1);
+  const cx<R> tr = cvt<R>(tau);
+  auto g = [&](long cc) { return z[cc * S + rl]; };
+  double a0 = 0.0, a1 = 0.0;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    const cx<R> az = op.template apply<R>(c, tr, g);
+    const cx<R> pv = v[t] - az;
+    const cx<R> zz = z[t];
+    const R m = (R)op.mass(c);
+    const cx<R> ww = m * zz;
+    if (w) w[t] = ww;
+    a0 += (double)abs2(pv);
+    a1 += (double)abs2(ww);
+  }
+  c128 acc[2] = {{a0, 0.0}, {a1, 0.0}};
+  block_partials<2>(acc, S, part + (size_t)blockIdx.x * 2 * S);
+  if (arrive_last(cnt, gridDim.x)) {
+    c128 tot[2];
+    final_sum<2>(part, gridDim.x, S, tot);
+    if ((int)threadIdx.x < S) {
+      sc[threadIdx.x].pnorm = sqrt(tot[0].re);
+      sc[threadIdx.x].mznorm = sqrt(tot[1].re);
+      if (pn_out) pn_out[threadIdx.x] = sqrt(tot[0].re);
+      if (mz_out) mz_out[threadIdx.x] = sqrt(tot[1].re);
+    }
+    if (threadIdx.x == 0) *cnt = 0u;
+  }
+}
+
+// -------------------------------------------------- Gram-Schmidt (CGS2) ----
+// Partial products v_i^H w over a block of items for columns i < kc.  Wave w
+// of the block handles columns w, w+NWAVE, ...; each lane runs over the items
+// at stride 64 (its rhs lane stays fixed), then a wave tree per lane group.
+template <typename R>
+__global__ void __launch_bounds__(BS) k_gs_dot(long N, int S, int kc, const cx<R>* __restrict__ V,
+                                               size_t cstride, const cx<R>* __restrict__ w,
+                                               c128* __restrict__ part, long ipb) {
+  const long start = blockIdx.x * ipb;
+  const long end = start + ipb < N ? start + ipb : N;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  for (int i = wv; i < kc; i += NWAVE) {
+    const cx<R>* Vi = V + (size_t)i * cstride;
+    cx<R> a{0, 0};
+    for (long t = start + lane; t < end; t += WAVE) a = a + cdot(Vi[t], w[t]);
+    c128 s = wave_sum_strided(cvt<double>(a), S);
+    if (lane < S) part[((size_t)blockIdx.x * kc + i) * S + lane] = s;
+  }
+}
+
+// One block per (column i, lane r): sum the partials over G blocks.
+__global__ void __launch_bounds__(BS) k_gs_reduce(const c128* __restrict__ part, int G, int kc, int S,
+                                                  c128* __restrict__ main_out, c128* __restrict__ aux_out,
+                                                  int accumulate) {
+  const int i = blockIdx.x / S, r = blockIdx.x % S;
+  c128 a{0.0, 0.0};
+  for (int b = threadIdx.x; b < G; b += BS) a = a + part[((size_t)b * kc + i) * S + r];
+  a = block_sum_all(a);
+  if (threadIdx.x == 0) {
+    aux_out[i * S + r] = a;
+    main_out[i * S + r] = accumulate ? main_out[i * S + r] + a : a;
+  }
+}
+
+// w -= sum_i h_i v_i for each item; optionally the FP64 norm ||w|| per lane,
+// written to hnorm_out[r] and to hcol_next[r] (the subdiagonal entry).
+constexpr int GSQ = 4;
+template <typename R>
+__global__ void __launch_bounds__(BS) k_gs_update(long N, int S, int kc, const cx<R>* __restrict__ V,
+                                                  size_t cstride, const c128* __restrict__ h,
+                                                  cx<R>* __restrict__ w, int with_norm,
+                                                  c128* __restrict__ part, unsigned* __restrict__ cnt,
+                                                  double* __restrict__ hnorm_out, c128* __restrict__ hcol_next) {
+  const int r = threadIdx.x & (S - 1);
+  const long base = (long)blockIdx.x * BS * GSQ + threadIdx.x;
+  cx<R> wq[GSQ];
+#pragma unroll
+  for (int qq = 0; qq < GSQ; ++qq) {
+    const long t = base + (long)qq * BS;
+    wq[qq] = t < N ? w[t] : cx<R>{0, 0};
+  }
+  for (int i = 0; i < kc; ++i) {
+    const cx<R> hi = cvt<R>(h[i * S + r]);
+    const cx<R>* Vi = V + (size_t)i * cstride;
+#pragma unroll
+    for (int qq = 0; qq < GSQ; ++qq) {
+      const long t = base + (long)qq * BS;
+      if (t < N) wq[qq] = wq[qq] - hi * Vi[t];
+    }
+  }
+  double a = 0.0;
+#pragma unroll
+  for (int qq = 0; qq < GSQ; ++qq) {
+    const long t = base + (long)qq * BS;
+    if (t < N) {
+      w[t] = wq[qq];
+      a += abs2(cvt<double>(wq[qq]));
+    }
+  }
+  if (!with_norm) return;
+  c128 acc[1] = {{a, 0.0}};
+  block_partials<1>(acc, S, part + (size_t)blockIdx.x * S);
+  if (arrive_last(cnt, gridDim.x)) {
+    c128 tot[1];
+    final_sum<1>(part, gridDim.x, S, tot);
+    if ((int)threadIdx.x < S) {
+      const double hn = sqrt(tot[0].re);
+      hnorm_out[threadIdx.x] = hn;
+      if (hcol_next) hcol_next[threadIdx.x] = c128{hn, 0.0};
+    }
+    if (threadIdx.x == 0) *cnt = 0u;
+  }
+}
+
+// v_{k+1} = w / h_{k+1,k}; lanes that broke down (h <= 1e-14 ||M z||, section
+// 3) or carry no rhs get a zero column.
+template <typename R>
+__global__ void __launch_bounds__(BS) k_scale_col(long N, int S, const cx<R>* __restrict__ w,
+                                                  const double* __restrict__ hn, const double* __restrict__ mz,
+                                                  cx<R>* __restrict__ vout) {
+  const int r = threadIdx.x & (S - 1);
+  const double h = hn[r];
+  const bool ok = h > 1e-14 * mz[r] && h > 0.0;
+  const R inv = ok ? (R)(1.0 / h) : (R)0;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) vout[t] = inv * w[t];
+}
+
+// out = sum_i coef[i][r] V_i (restart start vector V_{m+1} z_s / ||z_s||).
+template <typename R>
+__global__ void __launch_bounds__(BS) k_basis_combine(long N, int S, int kc, const cx<R>* __restrict__ V,
+                                                      size_t cstride, const c128* __restrict__ coef,
+                                                      cx<R>* __restrict__ out) {
+  const int r = threadIdx.x & (S - 1);
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    c128 a{0.0, 0.0};
+    for (int i = 0; i < kc; ++i) a = a + coef[i * S + r] * cvt<double>(V[(size_t)i * cstride + t]);
+    out[t] = cvt<R>(a);
+  }
+}
+
+// -------------------------------------------- per-shift least squares ------
+// One thread per (shift j, rhs r) lane, FP64 throughout.  Column k of
+// Hbar(sigma_j;T) = [I;0] + Hbar (sigma_j I - T) (eq. shiftedarnoldimod) is
+// rotated by the stored Givens rotations, a new rotation zeroes its
+// subdiagonal, |g_{k+1}| is the quasi-residual ||beta e_1 - Hbar(sigma;T) y||,
+// y comes from the triangular factor, and eq. trueresidual's bound
+// rho + sum |y_i| ||p_i|| decides whether the lane freezes.
+struct LaneState {
+  c128 beta;        // current start coefficient beta_j of this cycle
+  double gap_prev;  // inexact-inner term accumulated over earlier cycles
+  double rho;       // quasi-residual at the last step
+  double bound;     // bound of eq. trueresidual at the last step
+  int status;       // SHK_* per-shift status
+  int active;       // 1 while the lane still takes outer steps
+  int kfz;          // columns of the cycle used by y
+  int cycle_fz;     // cycle in which the lane froze (-1 while active)
+  int outer_its;
+  int restarts;
+  int pad0, pad1;
+};
+
+struct GivensArgs {
+  int L, S, m, k, cycle, kglob;
+  double tol, inexact_ratio, breakdown_rel;
+  const c128* Hk;        // column k: Hk[i*S + r], i <= k+1 (k+1 = subdiagonal)
+  const double* hn;      // h_{k+1,k} per lane r
+  const double* mz;      // ||M z_k|| per lane r
+  const double* pn;      // ||p_i|| at pn[i*S + r], i <= k
+  const double* beta0;   // ||b_r||
+  const c128* sigma;     // shifts
+  const c128* taus;      // tau of every column of this cycle
+  LaneState* ls;
+  double* rc; c128* rs; c128* g; c128* Rp; c128* Yb;
+};
+
+__device__ __forceinline__ void givens_make(c128 a, c128 b, double& c, c128& s, c128& rr) {
+  // [c s; -conj(s) c] [a; b] = [rr; 0], c real >= 0
+  const double na = hypot(a.re, a.im), nb = hypot(b.re, b.im);
+  if (nb == 0.0) { c = 1.0; s = c128{0.0, 0.0}; rr = a; return; }
+  if (na == 0.0) { c = 0.0; s = c128{b.re / nb, -b.im / nb}; rr = c128{nb, 0.0}; return; }
+  const double nu = hypot(na, nb);
+  c = na / nu;
+  const c128 ph{a.re / na, a.im / na};     // a / |a|
+  s = (1.0 / nu) * (ph * conj(b));
+  rr = nu * ph;
+}
+
+__device__ __forceinline__ size_t tri(int i, int k) { return (size_t)k * (k + 1) / 2 + i; }
+
+// y = R^{-1} g over the first kc columns, written to Yb row; returns ||y||-weighted
+// inexact term sum |y_i| ||p_i||.
+__device__ inline double backsolve(const GivensArgs& a, int lane, int r, int kc, const c128* gv, size_t gstride) {
+  const int L = a.L;
+  c128* y = a.Yb + (size_t)lane * a.m;
+  double gap = 0.0;
+  for (int i = kc - 1; i >= 0; --i) {
+    c128 acc = gv[(size_t)i * gstride];
+    for (int l = i + 1; l < kc; ++l) acc = acc - a.Rp[tri(i, l) * L + lane] * y[l];
+    const c128 yi = cdiv(acc, a.Rp[tri(i, i) * L + lane]);
+    y[i] = yi;
+    gap += hypot(yi.re, yi.im) * a.pn[i * a.S + r];
+  }
+  for (int i = kc; i < a.m; ++i) y[i] = c128{0.0, 0.0};
+  return gap;
+}
+
+__global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
+  const int lane = blockIdx.x * BS + threadIdx.x;
+  if (lane >= a.L) return;
+  LaneState st = a.ls[lane];
+  if (!st.active) return;
+  const int S = a.S, r = lane % S, j = lane / S, k = a.k, L = a.L;
+  const c128 d = a.sigma[j] - a.taus[k];
+  const double hn = a.hn[r];
+  const bool broke = !(hn > a.breakdown_rel * a.mz[r]);
+  // rotate the new column
+  c128 carry = d * a.Hk[0 * S + r];
+  if (k == 0) carry.re += 1.0;
+  for (int i = 0; i < k; ++i) {
+    c128 nxt = d * a.Hk[(i + 1) * S + r];
+    if (i + 1 == k) nxt.re += 1.0;
+    const double c = a.rc[(size_t)i * L + lane];
+    const c128 s = a.rs[(size_t)i * L + lane];
+    a.Rp[tri(i, k) * L + lane] = c * carry + s * nxt;
+    carry = (-1.0) * (conj(s) * carry) + c * nxt;
+  }
+  const c128 sub = broke ? c128{0.0, 0.0} : hn * d;
+  double c;
+  c128 s, rr;
+  givens_make(carry, sub, c, s, rr);
+  a.Rp[tri(k, k) * L + lane] = rr;
+  a.rc[(size_t)k * L + lane] = c;
+  a.rs[(size_t)k * L + lane] = s;
+  const c128 gk = a.g[(size_t)k * L + lane];
+  a.g[(size_t)k * L + lane] = c * gk;
+  const c128 gk1 = (-1.0) * (conj(s) * gk);
+  a.g[(size_t)(k + 1) * L + lane] = gk1;
+  const double rho = broke ? 0.0 : hypot(gk1.re, gk1.im);
+  const double gap = backsolve(a, lane, r, k + 1, a.g + lane, (size_t)L);
+  const double bound = rho + st.gap_prev + gap;
+  const double b0 = a.beta0[r];
+  st.rho = rho;
+  st.bound = bound;
+  st.kfz = k + 1;
+  st.outer_its = a.kglob + 1;
+  st.restarts = a.cycle;
+  int done = -1;
+  if (broke) done = bound <= a.tol * b0 ? SHK_BREAKDOWN_EXACT : SHK_INNER_LIMITED;
+  else if (bound <= a.tol * b0) done = SHK_CONVERGED;
+  else if (rho <= a.inexact_ratio * (st.gap_prev + gap)) done = SHK_INNER_LIMITED;
+  if (done >= 0) {
+    st.status = done;
+    st.active = 0;
+    st.cycle_fz = a.cycle;
+  }
+  a.ls[lane] = st;
+}
+
+// Lane initialisation for a solve: beta_j = ||b_r||, g = beta e_1.
+__global__ void __launch_bounds__(BS) k_lanes_init(int L, int S, int s_real, const double* __restrict__ beta0,
+                                                   LaneState* __restrict__ ls, c128* __restrict__ g) {
+  const int lane = blockIdx.x * BS + threadIdx.x;
+  if (lane >= L) return;
+  const int r = lane % S;
+  LaneState st{};
+  const double b = beta0[r];
+  st.beta = c128{b, 0.0};
+  st.gap_prev = 0.0;
+  st.rho = b;
+  st.bound = b;
+  st.cycle_fz = -1;
+  st.kfz = 0;
+  st.outer_its = 0;
+  st.restarts = 0;
+  if (r >= s_real || !(b > 0.0)) {
+    st.active = 0;
+    st.status = (r < s_real && !(b == b)) ? SHK_NAN : SHK_CONVERGED;
+    st.cycle_fz = 0;
+    st.rho = 0.0;
+    st.bound = 0.0;
+  } else {
+    st.active = 1;
+    st.status = SHK_NOT_CONVERGED;
+  }
+  ls[lane] = st;
+  g[lane] = st.beta;
+}
+
+// Restart, seed selection (one thread per rhs lane): the active shift with the
+// largest quasi-residual (ties to the lowest index); its residual in the
+// (m+1)-space is z_s = Q_s [0..0, g_m]^T, built by undoing the rotations.
+__global__ void k_restart_seed(int S, int nf, int m, const LaneState* __restrict__ ls,
+                               const double* __restrict__ rc, const c128* __restrict__ rs,
+                               const c128* __restrict__ g, int* __restrict__ seed,
+                               c128* __restrict__ zs, double* __restrict__ nzs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S) return;
+  const int L = nf * S;
+  int best = -1;
+  double bv = -1.0;
+  for (int j = 0; j < nf; ++j) {
+    const LaneState& st = ls[j * S + r];
+    if (st.active && st.rho > bv) { bv = st.rho; best = j; }
+  }
+  seed[r] = best;
+  if (best < 0) { nzs[r] = 0.0; return; }
+  const int lane = best * S + r;
+  // z = G_0^H ... G_{m-1}^H (g_m e_m)
+  for (int i = 0; i <= m; ++i) zs[i * S + r] = c128{0.0, 0.0};
+  c128 b = g[(size_t)m * L + lane];
+  for (int i = m - 1; i >= 0; --i) {
+    const double c = rc[(size_t)i * L + lane];
+    const c128 s = rs[(size_t)i * L + lane];
+    // (a, b) <- (c a - s b, conj(s) a + c b) with a = 0 on entry
+    zs[(i + 1) * S + r] = c * b;
+    b = (-1.0) * (s * b);
+  }
+  zs[0 * S + r] = b;
+  double nn = 0.0;
+  for (int i = 0; i <= m; ++i) nn += abs2(zs[i * S + r]);
+  nn = sqrt(nn);
+  nzs[r] = nn;
+  const double inv = nn > 0.0 ? 1.0 / nn : 0.0;
+  for (int i = 0; i <= m; ++i) zs[i * S + r] = inv * zs[i * S + r];
+}
+
+// Restart, every active lane: keep its residual collinear with the seed's by
+// solving [Hbar(sigma_j;T), z][y; gamma] = beta_j e_1 through its QR factors,
+// with z = z_s / ||z_s|| (stored normalised); the residual is then gamma V z,
+// so the next cycle starts from v_1 = V z with beta_j <- gamma (the seed keeps
+// its own y and gets beta = ||z_s||); g = beta_j e_1, and the inexact term
+// grows by sum |y_i| ||p_i||.
+__global__ void __launch_bounds__(BS) k_restart_lanes(GivensArgs a, const int* __restrict__ seed,
+                                                      const c128* __restrict__ zs, const double* __restrict__ nzs) {
+  const int lane = blockIdx.x * BS + threadIdx.x;
+  if (lane >= a.L) return;
+  LaneState st = a.ls[lane];
+  if (!st.active) return;
+  const int S = a.S, r = lane % S, j = lane / S, m = a.m, L = a.L;
+  c128 gamma{1.0, 0.0};
+  double gap;
+  if (j == seed[r]) {
+    gap = 0.0;
+    const c128* y = a.Yb + (size_t)lane * m;
+    for (int i = 0; i < m; ++i) gap += hypot(y[i].re, y[i].im) * a.pn[i * S + r];
+  } else {
+    // zhat = Q_j^H z_s, streamed; first pass for its last entry
+    c128 carry = zs[0 * S + r];
+    for (int i = 0; i < m; ++i) {
+      const double c = a.rc[(size_t)i * L + lane];
+      const c128 s = a.rs[(size_t)i * L + lane];
+      const c128 nx = zs[(i + 1) * S + r];
+      carry = (-1.0) * (conj(s) * carry) + c * nx;
+    }
+    gamma = cdiv(a.g[(size_t)m * L + lane], carry);
+    carry = zs[0 * S + r];
+    for (int i = 0; i < m; ++i) {
+      const double c = a.rc[(size_t)i * L + lane];
+      const c128 s = a.rs[(size_t)i * L + lane];
+      const c128 nx = zs[(i + 1) * S + r];
+      const c128 zi = c * carry + s * nx;
+      carry = (-1.0) * (conj(s) * carry) + c * nx;
+      a.g[(size_t)i * L + lane] = a.g[(size_t)i * L + lane] - gamma * zi;
+    }
+    gap = backsolve(a, lane, r, m, a.g + lane, (size_t)L);
+  }
+  st.gap_prev += gap;
+  st.beta = (j == seed[r]) ? c128{nzs[r], 0.0} : gamma;
+  st.cycle_fz = -1;
+  a.ls[lane] = st;
+  a.g[lane] = st.beta;
+}
+
+// Lanes still active when the restart budget is spent: NOT_CONVERGED, frozen.
+__global__ void __launch_bounds__(BS) k_finalize_active(int L, LaneState* __restrict__ ls) {
+  const int lane = blockIdx.x * BS + threadIdx.x;
+  if (lane >= L) return;
+  if (ls[lane].active) {
+    ls[lane].active = 0;
+    ls[lane].status = SHK_NOT_CONVERGED;
+  }
+}
+
+// Active lanes per rhs lane r (one thread per r).
+__global__ void k_count_active(int S, int nf, const LaneState* __restrict__ ls, int* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S) return;
+  int c = 0;
+  for (int j = 0; j < nf; ++j) c += ls[j * S + r].active;
+  out[r] = c;
+}
+
+// Per-lane multiplier of the assembly: lanes still active at the end of the
+// cycle or frozen during it contribute Z y scaled by extra[lane] (1 or the
+// refinement coefficient gamma_j), the others nothing.
+__global__ void __launch_bounds__(BS) k_asm_scale(int L, int cycle, const LaneState* __restrict__ ls,
+                                                  const c128* __restrict__ extra, c128* __restrict__ out) {
+  const int lane = blockIdx.x * BS + threadIdx.x;
+  if (lane >= L) return;
+  const LaneState st = ls[lane];
+  const bool use = st.active || st.cycle_fz == cycle;
+  out[lane] = use ? (extra ? extra[lane] : c128{1.0, 0.0}) : c128{0.0, 0.0};
+}
+
+// ------------------------------------------------------------ assembly -----
+// X[:, j, r] (+)= scale_j * Z_r y_{j,r} (Algorithm 4, x = Z y), FP64
+// accumulation.  Thread per item (cell, lane), JT shifts per block row.
+constexpr int JT = 16;
+template <typename R>
+__global__ void __launch_bounds__(BS) k_assemble(long n, int S, int s_real, int nf, int kc, int m,
+                                                 const cx<R>* __restrict__ Z, size_t cstride,
+                                                 const c128* __restrict__ Yb, const c128* __restrict__ ascale,
+                                                 c128* __restrict__ X, int accumulate) {
+  const long N = n * S;
+  const int j0 = blockIdx.y * JT;
+  const int r = threadIdx.x & (S - 1);
+  if (r >= s_real) return;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    c128 acc[JT];
+#pragma unroll
+    for (int q = 0; q < JT; ++q) acc[q] = c128{0.0, 0.0};
+    for (int i = 0; i < kc; ++i) {
+      const c128 z = cvt<double>(Z[(size_t)i * cstride + t]);
+#pragma unroll
+      for (int q = 0; q < JT; ++q) {
+        const int j = j0 + q < nf ? j0 + q : nf - 1;
+        acc[q] = acc[q] + z * Yb[((size_t)j * S + r) * m + i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      const int j = j0 + q;
+      if (j < nf) {
+        const c128 v = ascale[(size_t)j * S + r] * acc[q];
+        c128* dst = X + c + n * ((long)j + (long)nf * r);
+        *dst = accumulate ? *dst + v : v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------ true residuals -----
+// Partial ||b_r - (K + sigma_j M) x_{j,r}||^2 (mode 0) or conj(rs_r)^T
+// (b_r - (K + sigma_j M) x_{j,r}) (mode 1) per block; blockIdx.y = shift,
+// blockIdx.z = rhs; cells over blockIdx.x.
+template <typename Op>
+__global__ void __launch_bounds__(BS) k_resid(Op op, long n, int S, int nf, const c128* __restrict__ sigma,
+                                              const c128* __restrict__ bint, const c128* __restrict__ X,
+                                              const c128* __restrict__ rs, int mode, c128* __restrict__ part) {
+  const int j = blockIdx.y, r = blockIdx.z;
+  const c128* xj = X + n * ((long)j + (long)nf * r);
+  const c128 sg = sigma[j];
+  auto g = [&](long cc) { return xj[cc]; };
+  c128 a{0.0, 0.0};
+  for (long c = blockIdx.x * (long)BS + threadIdx.x; c < n; c += (long)gridDim.x * BS) {
+    const c128 res = bint[c * S + r] - op.template apply<double>(c, sg, g);
+    if (mode == 0) a.re += abs2(res);
+    else a = a + cdot(rs[c * S + r], res);
+  }
+  a = block_sum_all(a);
+  if (threadIdx.x == 0) part[((size_t)r * nf + j) * gridDim.x + blockIdx.x] = a;
+}
+
+// rows partial sums -> out[row] (fixed order), one block per row.
+__global__ void __launch_bounds__(BS) k_rows_reduce(const c128* __restrict__ part, int G, c128* __restrict__ out) {
+  const size_t row = blockIdx.x;
+  c128 a{0.0, 0.0};
+  for (int b = threadIdx.x; b < G; b += BS) a = a + part[row * G + b];
+  a = block_sum_all(a);
+  if (threadIdx.x == 0) out[row] = a;
+}
+
+// rs[:, r] = b_r - (K + sigma_{seed_r} M) x_{seed_r, r} (refinement seed residual).
+template <typename Op>
+__global__ void __launch_bounds__(BS) k_resid_vec(Op op, long n, int S, int s_real, int nf,
+                                                  const c128* __restrict__ sigma, const int* __restrict__ seed,
+                                                  const c128* __restrict__ bint, const c128* __restrict__ X,
+                                                  c128* __restrict__ rs) {
+  const long N = n * S;
+  const int r = threadIdx.x & (S - 1);
+  const int j = r < s_real ? seed[r] : -1;
+  const c128* xj = j >= 0 ? X + n * ((long)j + (long)nf * r) : nullptr;
+  const c128 sg = j >= 0 ? sigma[j] : c128{0.0, 0.0};
+  auto g = [&](long cc) { return xj[cc]; };
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    rs[t] = j >= 0 ? bint[t] - op.template apply<double>(c, sg, g) : c128{0.0, 0.0};
+  }
+}
+
+}  // namespace shk

@@ -1,0 +1,836 @@
+// Host driver of the flexible shifted-Krylov solver: problem setup, the outer
+// loop of Algorithm 4 around the flexible Arnoldi step of Algorithm 3, restarts,
+// FP64 true residuals and refinement, and the step-level entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace shk {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+int fail(int code, const std::string& m) {
+  g_err = m;
+  return code;
+}
+const char* last_error_text() { return g_err.c_str(); }
+
+static int grid_items(long items, int cap) {
+  long b = (items + BS - 1) / BS;
+  if (b < 1) b = 1;
+  return (int)std::min<long>(b, cap);
+}
+
+// Blocks of the item kernels whose last block sums [G][2][S] partials: keep
+// G*S bounded so that final sum stays short.
+static int item_grid(long N, int S) { return grid_items(N, std::max(64, 32768 / S)); }
+
+static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Pinned staging for small device-to-host reads (one per host thread).
+struct Pinned {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+  void* get(size_t bytes) {
+    if (bytes > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+      cap = bytes;
+    }
+    return p;
+  }
+};
+static thread_local Pinned g_pinned;
+
+// --------------------------------------------------------------- problem ---
+void problem_free(shk_problem* p, hipStream_t st) {
+  void* ptrs[] = {p->tx, p->ty, p->tz, p->tx32, p->ty32, p->tz32, p->rowptr, p->col, p->val, p->val32, p->diag, p->mdiag};
+  for (void* q : ptrs)
+    if (q) (void)hipFreeAsync(q, st);
+  (void)hipStreamSynchronize(st);
+}
+
+size_t problem_bytes(const shk_problem* p) {
+  if (p->kind == Kind::CSR) return (size_t)p->nnz * 16 + (size_t)p->n * 24;
+  const size_t faces = (size_t)(p->nx + 1) * p->ny * p->nz + (size_t)p->nx * (p->ny + 1) * p->nz +
+                       (p->kind == Kind::FV3D ? (size_t)p->nx * p->ny * (p->nz + 1) : 0);
+  return faces * 12;
+}
+
+int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipStream_t st) {
+  const long n = (long)p->nx * p->ny * p->nz;
+  for (long i = 0; i < n; ++i)
+    if (!(K[i] > 0.0) || !std::isfinite(K[i])) return fail(SHK_ERR_INVALID_ARG, "cell_K must be finite and > 0");
+  if (!(Ss > 0.0) || !(h > 0.0) || !std::isfinite(Ss) || !std::isfinite(h))
+    return fail(SHK_ERR_INVALID_ARG, "Ss and h must be finite and > 0");
+  SHK_HIP(hipGetDevice(&p->device));
+  p->n = n;
+  const int d = p->kind == Kind::FV3D ? 3 : 2;
+  const double scale = std::pow(h, d - 2);
+  p->m0 = Ss * std::pow(h, d);
+  double* Kd = nullptr;
+  if (hipMallocAsync((void**)&Kd, n * sizeof(double), st) != hipSuccess) return fail(SHK_ERR_OOM, "cell field");
+  SHK_HIP(hipMemcpyAsync(Kd, K, n * sizeof(double), hipMemcpyHostToDevice, st));
+  const int axes = d;
+  double** T[3] = {&p->tx, &p->ty, &p->tz};
+  float** T32[3] = {&p->tx32, &p->ty32, &p->tz32};
+  for (int a = 0; a < axes; ++a) {
+    const long cnt = (long)(p->nx + (a == 0)) * (p->ny + (a == 1)) * (p->nz + (a == 2));
+    if (hipMallocAsync((void**)T[a], cnt * sizeof(double), st) != hipSuccess ||
+        hipMallocAsync((void**)T32[a], cnt * sizeof(float), st) != hipSuccess) {
+      (void)hipFreeAsync(Kd, st);
+      return fail(SHK_ERR_OOM, "face arrays");
+    }
+    k_faces<<<grid_items(cnt, 8192), BS, 0, st>>>(Kd, p->nx, p->ny, p->nz, a, scale, *T[a], *T32[a]);
+    SHK_HIP(hipGetLastError());
+  }
+  SHK_HIP(hipFreeAsync(Kd, st));
+  SHK_HIP(hipStreamSynchronize(st));
+  return SHK_OK;
+}
+
+int problem_setup_csr(shk_problem* p, const int* rowptr, const int* col, const double* val, const double* mdiag,
+                      hipStream_t st) {
+  const long n = p->n;
+  if (rowptr[0] != 0) return fail(SHK_ERR_INVALID_ARG, "rowptr[0] must be 0");
+  for (long i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(SHK_ERR_INVALID_ARG, "rowptr not monotone");
+  const long nnz = rowptr[n];
+  std::vector<double> dg(n, 0.0);
+  std::vector<float> v32(nnz);
+  for (long i = 0; i < n; ++i)
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= n) return fail(SHK_ERR_INVALID_ARG, "column index out of range");
+      if (!std::isfinite(val[e])) return fail(SHK_ERR_INVALID_ARG, "non-finite K value");
+      if (col[e] == i) dg[i] += val[e];
+      v32[e] = (float)val[e];
+    }
+  for (long i = 0; i < n; ++i)
+    if (!std::isfinite(mdiag[i])) return fail(SHK_ERR_INVALID_ARG, "non-finite mass");
+  SHK_HIP(hipGetDevice(&p->device));
+  p->nnz = nnz;
+  p->nx = (int)std::ceil(std::sqrt((double)n));
+  SHK_HIP(hipMallocAsync((void**)&p->rowptr, (n + 1) * sizeof(int), st));
+  SHK_HIP(hipMallocAsync((void**)&p->col, std::max<long>(nnz, 1) * sizeof(int), st));
+  SHK_HIP(hipMallocAsync((void**)&p->val, std::max<long>(nnz, 1) * sizeof(double), st));
+  SHK_HIP(hipMallocAsync((void**)&p->val32, std::max<long>(nnz, 1) * sizeof(float), st));
+  SHK_HIP(hipMallocAsync((void**)&p->diag, n * sizeof(double), st));
+  SHK_HIP(hipMallocAsync((void**)&p->mdiag, n * sizeof(double), st));
+  SHK_HIP(hipMemcpyAsync(p->rowptr, rowptr, (n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipMemcpyAsync(p->col, col, nnz * sizeof(int), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipMemcpyAsync(p->val, val, nnz * sizeof(double), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipMemcpyAsync(p->val32, v32.data(), nnz * sizeof(float), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipMemcpyAsync(p->diag, dg.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipMemcpyAsync(p->mdiag, mdiag, n * sizeof(double), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipStreamSynchronize(st));
+  return SHK_OK;
+}
+
+template <typename F> static const F* pick(const double* a, const float* b);
+template <> const double* pick<double>(const double* a, const float*) { return a; }
+template <> const float* pick<float>(const double*, const float* b) { return b; }
+
+// Calls fn(op) with the operator of the problem in face precision F.
+template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&& fn) {
+  switch (p->kind) {
+    case Kind::FV2D: {
+      Op2D<F> op{p->nx, p->ny, pick<F>(p->tx, p->tx32), pick<F>(p->ty, p->ty32), nullptr, p->m0};
+      return fn(op);
+    }
+    case Kind::FV3D: {
+      Op3D<F> op{p->nx, p->ny, p->nz, pick<F>(p->tx, p->tx32), pick<F>(p->ty, p->ty32), pick<F>(p->tz, p->tz32),
+                 nullptr, p->m0};
+      return fn(op);
+    }
+    default: {
+      OpCSR<F> op{p->n, p->rowptr, p->col, pick<F>(p->val, p->val32), p->diag, p->mdiag, 0.0};
+      return fn(op);
+    }
+  }
+}
+
+// ----------------------------------------------------------- workspace -----
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T> T* take(size_t count) {
+    T* r = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return r;
+  }
+};
+
+template <typename R> struct Buffers {
+  cx<R>*V, *Z, *W, *r, *u, *P0, *P1, *q;
+  c128* part;
+  size_t part_elems;
+  CocgScal* sc;
+  int* all_done;
+  unsigned* cnt;
+  double *beta0, *hn, *mz, *pn, *nzs;
+  c128 *H, *h2, *taus, *sigma, *zs;
+  int *seed, *nact;
+  LaneState* ls;
+  double* rc;
+  c128 *rs, *g, *Rp, *Yb, *ascale, *extra;
+  c128 *bint, *rsv, *X;
+  c128* rpart;      // residual partials [s][nf][Gr]
+  c128* rrow;       // residual rows [s*nf]
+  size_t bytes;
+};
+
+static int resid_grid(long n) { return grid_items(n, 256); }
+static int dot_ipb(long N) {
+  long ipb = (N + 511) / 512;
+  ipb = std::max<long>(1024, (ipb + 255) / 256 * 256);
+  return (int)ipb;
+}
+
+template <typename R>
+static Buffers<R> carve(char* base, long n, int m, int nf, int S, int s_real, bool host_x) {
+  Carver cv{base};
+  Buffers<R> b{};
+  const long N = n * S;
+  const int L = nf * S;
+  b.V = cv.take<cx<R>>((size_t)(m + 1) * N);
+  b.Z = cv.take<cx<R>>((size_t)m * N);
+  b.W = cv.take<cx<R>>(N);
+  b.r = cv.take<cx<R>>(N);
+  b.u = cv.take<cx<R>>(N);
+  b.P0 = cv.take<cx<R>>(N);
+  b.P1 = cv.take<cx<R>>(N);
+  b.q = cv.take<cx<R>>(N);
+  const int G = item_grid(N, S);
+  const long ipb = dot_ipb(N);
+  const long Gd = (N + ipb - 1) / ipb;
+  const int Gg = grid_items((N + GSQ - 1) / GSQ, 1 << 30);
+  b.part_elems = std::max<size_t>({(size_t)G * 2 * S, (size_t)Gd * (m + 1) * S, (size_t)Gg * S});
+  b.part = cv.take<c128>(b.part_elems);
+  b.sc = cv.take<CocgScal>(S);
+  b.all_done = cv.take<int>(4);
+  b.cnt = cv.take<unsigned>(4);
+  b.beta0 = cv.take<double>(S);
+  b.hn = cv.take<double>(S);
+  b.mz = cv.take<double>(S);
+  b.nzs = cv.take<double>(S);
+  b.pn = cv.take<double>((size_t)m * S);
+  b.H = cv.take<c128>((size_t)m * (m + 2) * S);
+  b.h2 = cv.take<c128>((size_t)(m + 1) * S);
+  b.taus = cv.take<c128>(m);
+  b.sigma = cv.take<c128>(nf);
+  b.zs = cv.take<c128>((size_t)(m + 1) * S);
+  b.seed = cv.take<int>(S);
+  b.nact = cv.take<int>(S);
+  b.ls = cv.take<LaneState>(L);
+  b.rc = cv.take<double>((size_t)m * L);
+  b.rs = cv.take<c128>((size_t)m * L);
+  b.g = cv.take<c128>((size_t)(m + 1) * L);
+  b.Rp = cv.take<c128>((size_t)m * (m + 1) / 2 * L);
+  b.Yb = cv.take<c128>((size_t)L * m);
+  b.ascale = cv.take<c128>(L);
+  b.extra = cv.take<c128>(L);
+  b.bint = cv.take<c128>(N);
+  b.rsv = cv.take<c128>(N);
+  b.X = host_x ? cv.take<c128>((size_t)n * nf * s_real) : nullptr;
+  const int Gr = resid_grid(n);
+  b.rpart = cv.take<c128>((size_t)s_real * nf * Gr);
+  b.rrow = cv.take<c128>((size_t)s_real * nf);
+  b.bytes = cv.off;
+  return b;
+}
+
+static int lanes_of(int n_rhs) { return std::min(64, next_pow2(std::max(1, n_rhs))); }
+
+static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real, int precision, bool host_x) {
+  if (precision == SHK_MIXED) return carve<float>(nullptr, p->n, m, nf, S, s_real, host_x).bytes;
+  return carve<double>(nullptr, p->n, m, nf, S, s_real, host_x).bytes;
+}
+
+// --------------------------------------------------------------- solver ----
+struct PassSpec {
+  int m, max_restarts, inner_maxit;
+  double tol, eps;
+  const std::vector<c128>* taus;
+  long long kglob0;   // tau schedule position
+};
+
+template <typename R, typename Op> struct Group {
+  shk_problem* p;
+  Op op;
+  hipStream_t st;
+  Buffers<R> B;
+  long n, N;
+  int S, s_real, nf, m, G, L;
+  long long inner_its = 0;
+  int outer_steps = 0;
+
+  // ---- inner solve of (K + tau M) z = v (section 4) into z, w = M z ----
+  int inner(c128 tau, const cx<R>* v, cx<R>* z, double eps, int maxit, int fixed, double* pn_out) {
+    k_cocg_init<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, fixed > 0 ? fixed : maxit, v, z, B.r, B.u, B.P0, B.part,
+                                          B.cnt, B.sc, B.all_done);
+    SHK_HIP(hipGetLastError());
+    const double e = fixed > 0 ? -1.0 : eps;
+    const int cap = fixed > 0 ? fixed : maxit;
+    int it = 0;
+    int chunk = std::min(cap, 16);
+    struct Snap {
+      int all_done;
+      int pad[3];
+      CocgScal sc[64];
+    };
+    static_assert(sizeof(Snap) <= 32768, "staging layout");
+    Snap* snap = (Snap*)g_pinned.get(65536);
+    if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
+    while (true) {
+      for (int c = 0; c < chunk; ++c, ++it) {
+        cx<R>* pold = (it & 1) ? B.P1 : B.P0;
+        cx<R>* pnew = (it & 1) ? B.P0 : B.P1;
+        k_cocg_A<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, B.u, pold, pnew, B.q, B.part, B.cnt, B.sc, B.all_done);
+        k_cocg_B<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, e, pnew, B.q, z, B.r, B.u, B.part, B.cnt, B.sc,
+                                           B.all_done);
+      }
+      SHK_HIP(hipGetLastError());
+      SHK_HIP(hipMemcpyAsync(&snap->all_done, B.all_done, sizeof(int), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipMemcpyAsync(snap->sc, B.sc, S * sizeof(CocgScal), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipStreamSynchronize(st));
+      if (snap->all_done || it >= cap) break;
+      // predict the remaining iterations from the mean convergence rate
+      int need = 4;
+      for (int r = 0; r < S; ++r) {
+        const CocgScal& s = snap->sc[r];
+        if (s.done || s.vnorm <= 0.0 || s.its <= 0) continue;
+        const double rel = std::max(s.rnorm / s.vnorm, 1e-300);
+        const double rate = std::log(rel) / s.its;
+        int rem = 64;
+        if (rate < 0.0 && e > 0.0) rem = (int)std::ceil((std::log(e) - std::log(rel)) / rate * 1.05) + 2;
+        need = std::max(need, std::min(rem, 512));
+      }
+      chunk = std::min(need, cap - it);
+      if (chunk <= 0) break;
+    }
+    long long its_max = 0;
+    for (int r = 0; r < S; ++r) its_max = std::max<long long>(its_max, snap->sc[r].its);
+    inner_its += its_max;
+    k_cocg_finish<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, v, z, B.W, B.part, B.cnt, B.sc, pn_out, B.mz);
+    SHK_HIP(hipGetLastError());
+    return SHK_OK;
+  }
+
+  // ---- classical Gram-Schmidt with one reorthogonalisation (Algorithm 3) ----
+  int orthogonalize(int k, cx<R>* w) {
+    const int kc = k + 1;
+    const size_t cs = (size_t)N;
+    const long ipb = dot_ipb(N);
+    const int Gd = (int)((N + ipb - 1) / ipb);
+    const int Gu = (int)((N + (long)BS * GSQ - 1) / ((long)BS * GSQ));
+    c128* Hk = B.H + (size_t)k * (m + 2) * S;
+    for (int pass = 0; pass < 2; ++pass) {
+      k_gs_dot<R><<<Gd, BS, 0, st>>>(N, S, kc, B.V, cs, w, B.part, ipb);
+      k_gs_reduce<<<kc * S, BS, 0, st>>>(B.part, Gd, kc, S, Hk, B.h2, pass);
+      k_gs_update<R><<<Gu, BS, 0, st>>>(N, S, kc, B.V, cs, B.h2, w, pass, B.part, B.cnt, B.hn,
+                                        Hk + (size_t)(k + 1) * S);
+    }
+    k_scale_col<R><<<item_grid(N, S), BS, 0, st>>>(N, S, w, B.hn, B.mz, B.V + (size_t)(k + 1) * N);
+    SHK_HIP(hipGetLastError());
+    return SHK_OK;
+  }
+
+  GivensArgs gargs(int k, int cycle, int kglob, double tol) {
+    GivensArgs a{};
+    a.L = L; a.S = S; a.m = m; a.k = k; a.cycle = cycle; a.kglob = kglob;
+    a.tol = tol; a.inexact_ratio = 0.1; a.breakdown_rel = 1e-14;
+    a.Hk = B.H + (size_t)k * (m + 2) * S;
+    a.hn = B.hn; a.mz = B.mz; a.pn = B.pn; a.beta0 = B.beta0; a.sigma = B.sigma; a.taus = B.taus;
+    a.ls = B.ls; a.rc = B.rc; a.rs = B.rs; a.g = B.g; a.Rp = B.Rp; a.Yb = B.Yb;
+    return a;
+  }
+
+  int assemble(int kc, int cycle, const c128* extra, c128* X, bool accumulate) {
+    const int Lb = (L + BS - 1) / BS;
+    k_asm_scale<<<Lb, BS, 0, st>>>(L, cycle, B.ls, extra, B.ascale);
+    dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
+    k_assemble<R><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X,
+                                       accumulate ? 1 : 0);
+    SHK_HIP(hipGetLastError());
+    return SHK_OK;
+  }
+
+  // One FGMRES-Sh solve of all shifts for the rhs block `rhs` (interleaved
+  // c128), results written or added to X (ABI layout).
+  int pass(const c128* rhs, const PassSpec& ps, c128* X, bool accumulate, const c128* extra) {
+    const int Lb = (L + BS - 1) / BS;
+    SHK_HIP(hipMemsetAsync(B.Yb, 0, sizeof(c128) * (size_t)L * m, st));
+    SHK_HIP(hipMemsetAsync(B.cnt, 0, 4 * sizeof(unsigned), st));
+    k_norm2<double><<<item_grid(N, S), BS, 0, st>>>(rhs, N, S, B.part, B.cnt, B.beta0);
+    k_scale_conv<R><<<item_grid(N, S), BS, 0, st>>>(rhs, N, S, B.beta0, B.V);
+    k_lanes_init<<<Lb, BS, 0, st>>>(L, S, s_real, B.beta0, B.ls, B.g);
+    SHK_HIP(hipGetLastError());
+    const std::vector<c128>& taus = *ps.taus;
+    long long kglob = ps.kglob0;
+    std::vector<c128> tcyc(m);
+    char* stage = (char*)g_pinned.get(65536);
+    int* nact = stage ? (int*)(stage + 32768) : nullptr;
+    if (!nact) return fail(SHK_ERR_OOM, "pinned staging");
+    bool first_write = !accumulate;
+    for (int cycle = 0; cycle <= ps.max_restarts; ++cycle) {
+      for (int k = 0; k < m; ++k) tcyc[k] = taus[(size_t)((kglob + k) % (long long)taus.size())];
+      SHK_HIP(hipMemcpyAsync(B.taus, tcyc.data(), m * sizeof(c128), hipMemcpyHostToDevice, st));
+      int kend = 0;
+      bool any_active = true;
+      for (int k = 0; k < m; ++k) {
+        SHK_TRY(inner(tcyc[k], B.V + (size_t)k * N, B.Z + (size_t)k * N, ps.eps, ps.inner_maxit, 0,
+                      B.pn + (size_t)k * S));
+        SHK_TRY(orthogonalize(k, B.W));
+        GivensArgs a = gargs(k, cycle, (int)(kglob - ps.kglob0), ps.tol);
+        k_givens<<<Lb, BS, 0, st>>>(a);
+        k_count_active<<<1, 64, 0, st>>>(S, nf, B.ls, B.nact);
+        SHK_HIP(hipGetLastError());
+        SHK_HIP(hipMemcpyAsync(nact, B.nact, S * sizeof(int), hipMemcpyDeviceToHost, st));
+        SHK_HIP(hipStreamSynchronize(st));
+        ++kglob;
+        ++outer_steps;
+        kend = k + 1;
+        int tot = 0;
+        for (int r = 0; r < S; ++r) tot += nact[r];
+        if (tot == 0) {
+          any_active = false;
+          break;
+        }
+      }
+      if (!any_active || cycle == ps.max_restarts) {
+        // final cycle: lanes still active keep their last least-squares y
+        SHK_TRY(assemble(kend, cycle, extra, X, !first_write));
+        if (any_active) k_finalize_active<<<Lb, BS, 0, st>>>(L, B.ls);
+        SHK_HIP(hipGetLastError());
+        break;
+      }
+      // ---- restart with collinear residuals ----
+      GivensArgs a = gargs(m - 1, cycle, 0, ps.tol);
+      k_restart_seed<<<1, 64, 0, st>>>(S, nf, m, B.ls, B.rc, B.rs, B.g, B.seed, B.zs, B.nzs);
+      k_restart_lanes<<<Lb, BS, 0, st>>>(a, B.seed, B.zs, B.nzs);
+      SHK_HIP(hipGetLastError());
+      SHK_TRY(assemble(m, cycle, extra, X, !first_write));
+      first_write = false;
+      k_basis_combine<R><<<item_grid(N, S), BS, 0, st>>>(N, S, m + 1, B.V, (size_t)N, B.zs, B.W);
+      k_copy<R><<<item_grid(N, S), BS, 0, st>>>(B.W, N, B.V);
+      SHK_HIP(hipGetLastError());
+    }
+    return SHK_OK;
+  }
+};
+
+// FP64 true residual norms ||b_r - (K + sigma_j M) x_{j,r}||, rows [r][j].
+template <typename OpD>
+static int residual_rows(const OpD& opd, long n, int S, int s_real, int nf, const c128* sigma, const c128* bint,
+                         const c128* X, const c128* rs, int mode, c128* rpart, c128* rrow, hipStream_t st) {
+  const int Gr = resid_grid(n);
+  dim3 grid(Gr, nf, s_real);
+  k_resid<OpD><<<grid, BS, 0, st>>>(opd, n, S, nf, sigma, bint, X, rs, mode, rpart);
+  k_rows_reduce<<<s_real * nf, BS, 0, st>>>(rpart, Gr, rrow);
+  SHK_HIP(hipGetLastError());
+  return SHK_OK;
+}
+
+template <typename R>
+static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128* sigma_h, int s_real,
+                       const c128* b_src, int ptr_kind, c128* x_dst, shk_status* st_out, char* ws, hipStream_t st) {
+  const int S = lanes_of(s_real);
+  const int m = prm->m_restart;
+  const long n = p->n;
+  const bool host_x = ptr_kind == SHK_PTR_HOST;
+  Buffers<R> B = carve<R>(ws, n, m, nf, S, s_real, host_x);
+  c128* X = host_x ? B.X : x_dst;
+  const long N = n * S;
+  // rhs into interleaved c128
+  const c128* bdev = b_src;
+  if (host_x) {
+    SHK_HIP(hipMemcpyAsync(B.rsv, b_src, sizeof(c128) * n * s_real, hipMemcpyHostToDevice, st));
+    bdev = B.rsv;
+  }
+  k_interleave<<<item_grid(N, S), BS, 0, st>>>(bdev, n, s_real, S, B.bint);
+  SHK_HIP(hipMemcpyAsync(B.sigma, sigma_h, nf * sizeof(c128), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipGetLastError());
+
+  std::vector<c128> taus(prm->n_tau);
+  for (int i = 0; i < prm->n_tau; ++i) taus[i] = c128{prm->tau_seq[i].re, prm->tau_seq[i].im};
+  const int maxit = prm->inner_maxit > 0 ? prm->inner_maxit : 20 * p->max_dim();
+
+  std::vector<LaneState> lanes(nf * S);
+  std::vector<double> bnorm(S);
+  long long inner_total = 0;
+  int rc = with_op<R>(p, [&](auto op) -> int {
+    using Op = decltype(op);
+    Group<R, Op> g{p, op, st, B, n, N, S, s_real, nf, m, item_grid(N, S), nf * S};
+    PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0};
+    SHK_TRY(g.pass(B.bint, ps, X, false, nullptr));
+    SHK_HIP(hipMemcpyAsync(lanes.data(), B.ls, sizeof(LaneState) * nf * S, hipMemcpyDeviceToHost, st));
+    SHK_HIP(hipMemcpyAsync(bnorm.data(), B.beta0, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+    SHK_HIP(hipStreamSynchronize(st));
+    // ---- FP64 true residuals and collinear refinement ----
+    std::vector<c128> rows(s_real * nf);
+    std::vector<double> rel(s_real * nf);
+    std::vector<c128> extra(nf * S);
+    std::vector<int> seeds(S);
+    int sweeps = 0;
+    auto measure = [&]() -> int {
+      return with_op<double>(p, [&](auto opd) -> int {
+        SHK_TRY(residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, nullptr, 0, B.rpart, B.rrow, st));
+        SHK_HIP(hipMemcpyAsync(rows.data(), B.rrow, sizeof(c128) * rows.size(), hipMemcpyDeviceToHost, st));
+        SHK_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < s_real; ++r)
+          for (int j = 0; j < nf; ++j) {
+            const double nb = bnorm[r];
+            rel[r * nf + j] = nb > 0.0 ? std::sqrt(rows[r * nf + j].re) / nb : std::sqrt(rows[r * nf + j].re);
+          }
+        return SHK_OK;
+      });
+    };
+    SHK_TRY(measure());
+    for (; sweeps < prm->max_refine; ++sweeps) {
+      bool any_bad = false;
+      for (int r = 0; r < S; ++r) {
+        seeds[r] = -1;
+        if (r >= s_real) continue;
+        double best = -1.0;
+        for (int j = 0; j < nf; ++j) {
+          const double v = rel[r * nf + j];
+          if (v > prm->tol && std::isfinite(v)) any_bad = true;
+          if (v > best) { best = v; seeds[r] = j; }
+        }
+        bool bad_r = false;
+        for (int j = 0; j < nf; ++j) bad_r |= rel[r * nf + j] > prm->tol && std::isfinite(rel[r * nf + j]);
+        if (!bad_r) seeds[r] = -1;
+      }
+      if (!any_bad) break;
+      SHK_HIP(hipMemcpyAsync(B.seed, seeds.data(), sizeof(int) * S, hipMemcpyHostToDevice, st));
+      SHK_TRY(with_op<double>(p, [&](auto opd) -> int {
+        k_resid_vec<decltype(opd)><<<item_grid(N, S), BS, 0, st>>>(opd, n, S, s_real, nf, B.sigma, B.seed, B.bint, X,
+                                                                  B.rsv);
+        SHK_HIP(hipGetLastError());
+        return residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, B.rsv, 1, B.rpart, B.rrow, st);
+      }));
+      SHK_HIP(hipMemcpyAsync(rows.data(), B.rrow, sizeof(c128) * rows.size(), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipStreamSynchronize(st));
+      for (int r = 0; r < S; ++r)
+        for (int j = 0; j < nf; ++j) {
+          c128 gmm{0.0, 0.0};
+          if (r < s_real && seeds[r] >= 0 && rel[r * nf + j] > prm->tol) {
+            const c128 den = rows[r * nf + seeds[r]];
+            gmm = cdiv(rows[r * nf + j], c128{den.re, 0.0});
+          }
+          extra[j * S + r] = gmm;
+        }
+      SHK_HIP(hipMemcpyAsync(B.extra, extra.data(), sizeof(c128) * nf * S, hipMemcpyHostToDevice, st));
+      PassSpec pr{m, prm->max_restarts, maxit, prm->refine_tol, prm->refine_eps_inner, &taus, 0};
+      SHK_TRY(g.pass(B.rsv, pr, X, true, B.extra));
+      SHK_TRY(measure());
+    }
+    inner_total = g.inner_its;
+    (void)sweeps;
+    for (int r = 0; r < s_real; ++r)
+      for (int j = 0; j < nf; ++j) {
+        const LaneState& ls = lanes[j * S + r];
+        shk_status& o = st_out[j + (long)nf * r];
+        o.outer_its = ls.outer_its;
+        o.restarts = ls.restarts;
+        o.refine_sweeps = sweeps;
+        o.inner_its = inner_total;
+        o.quasi_relres = bnorm[r] > 0 ? ls.rho / bnorm[r] : 0.0;
+        o.bound_relres = bnorm[r] > 0 ? ls.bound / bnorm[r] : 0.0;
+        o.true_relres = rel[r * nf + j];
+        int s = ls.status;
+        if (!std::isfinite(o.true_relres)) s = SHK_NAN;
+        else if (o.true_relres <= prm->tol) s = (s == SHK_BREAKDOWN_EXACT) ? s : SHK_CONVERGED;
+        else if (prm->max_refine > 0 || s == SHK_CONVERGED || s == SHK_BREAKDOWN_EXACT) s = SHK_NOT_CONVERGED;
+        o.status = s;
+      }
+    return SHK_OK;
+  });
+  SHK_TRY(rc);
+  if (host_x) {
+    SHK_HIP(hipMemcpyAsync(x_dst, X, sizeof(c128) * n * nf * s_real, hipMemcpyDeviceToHost, st));
+  }
+  SHK_HIP(hipStreamSynchronize(st));
+  return SHK_OK;
+}
+
+static int check_params(const shk_problem* p, const shk_params* prm, int nf, int n_rhs) {
+  if (!p || !prm) return fail(SHK_ERR_INVALID_ARG, "null problem or params");
+  if (nf < 1 || n_rhs < 1) return fail(SHK_ERR_INVALID_ARG, "n_shifts and n_rhs must be >= 1");
+  if (prm->m_restart < 1 || prm->m_restart > 400) return fail(SHK_ERR_INVALID_ARG, "m_restart must be in [1, 400]");
+  if (prm->max_restarts < 0 || prm->max_refine < 0) return fail(SHK_ERR_INVALID_ARG, "negative restart/refine count");
+  if (prm->n_tau < 1 || !prm->tau_seq) return fail(SHK_ERR_INVALID_ARG, "tau_seq must hold n_tau >= 1 values");
+  if (!(prm->tol > 0.0) || !(prm->eps_inner >= 0.0)) return fail(SHK_ERR_INVALID_ARG, "tol must be > 0, eps >= 0");
+  if (prm->variant != SHK_GMRES) return fail(SHK_ERR_UNSUPPORTED, "only the GMRES variant runs on the GPU path");
+  if (prm->precision != SHK_FP64 && prm->precision != SHK_MIXED) return fail(SHK_ERR_INVALID_ARG, "precision");
+  for (int i = 0; i < prm->n_tau; ++i)
+    if (!std::isfinite(prm->tau_seq[i].re) || !std::isfinite(prm->tau_seq[i].im))
+      return fail(SHK_ERR_INVALID_ARG, "non-finite tau");
+  return SHK_OK;
+}
+
+size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x) {
+  const int s_real = std::min(n_rhs, 64);
+  return group_bytes(p, prm->m_restart, nf, lanes_of(s_real), s_real, prm->precision, host_x);
+}
+
+int solve_all(shk_problem* p, const shk_params* prm, int nf, const c128* sigma, int n_rhs, const c128* b, c128* x,
+              shk_status* stat, void* ws, size_t ws_bytes, hipStream_t st, int ptr_kind) {
+  SHK_TRY(check_params(p, prm, nf, n_rhs));
+  if (!sigma || !b || !x || !stat) return fail(SHK_ERR_INVALID_ARG, "null sigma/b/x/status");
+  for (int j = 0; j < nf; ++j)
+    if (!std::isfinite(sigma[j].re) || !std::isfinite(sigma[j].im)) return fail(SHK_ERR_INVALID_ARG, "non-finite shift");
+  const bool host_x = ptr_kind == SHK_PTR_HOST;
+  const size_t need = workspace_bytes(p, prm, nf, n_rhs, host_x);
+  void* own = nullptr;
+  if (!ws) {
+    if (hipMalloc(&own, need) != hipSuccess) return fail(SHK_ERR_OOM, "workspace allocation failed");
+    ws = own;
+  } else if (ws_bytes < need) {
+    return fail(SHK_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  int rc = SHK_OK;
+  const long n = p->n;
+  for (int r0 = 0; r0 < n_rhs && rc == SHK_OK; r0 += 64) {
+    const int s_real = std::min(64, n_rhs - r0);
+    const c128* bg = b + (size_t)n * r0;
+    c128* xg = x + (size_t)n * nf * r0;
+    shk_status* sg = stat + (size_t)nf * r0;
+    if (prm->precision == SHK_MIXED)
+      rc = solve_group<float>(p, prm, nf, sigma, s_real, bg, ptr_kind, xg, sg, (char*)ws, st);
+    else
+      rc = solve_group<double>(p, prm, nf, sigma, s_real, bg, ptr_kind, xg, sg, (char*)ws, st);
+  }
+  if (own) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(own);
+  }
+  return rc;
+}
+
+// ---------------------------------------------------------- step level -----
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+int step_apply(shk_problem* p, c128 sigma, int S, const void* x, void* y, int precision, hipStream_t st) {
+  if (!p || !x || !y || S < 1 || S > 64 || (S & (S - 1))) return fail(SHK_ERR_INVALID_ARG, "apply arguments");
+  const long N = p->n * S;
+  auto run = [&](auto tag) -> int {
+    using R = decltype(tag);
+    return with_op<R>(p, [&](auto op) -> int {
+      k_apply<decltype(op), R><<<item_grid(N, S), BS, 0, st>>>(op, sigma, p->n, S, (const cx<R>*)x, (cx<R>*)y);
+      SHK_HIP(hipGetLastError());
+      SHK_HIP(hipStreamSynchronize(st));
+      return SHK_OK;
+    });
+  };
+  return precision == SHK_MIXED ? run(float{}) : run(double{});
+}
+
+int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w, double eps, int maxit,
+               int fixed_iters, int precision, int* its, double* pnorm, hipStream_t st) {
+  if (!p || !v || !z || S < 1 || S > 64 || (S & (S - 1))) return fail(SHK_ERR_INVALID_ARG, "inner arguments");
+  if (maxit <= 0) maxit = 20 * p->max_dim();
+  auto run = [&](auto tag) -> int {
+    using R = decltype(tag);
+    const long N = p->n * S;
+    Carver cv{nullptr};
+    auto lay = [&](Carver& c, Buffers<R>& b) {
+      b.W = c.take<cx<R>>(N); b.r = c.take<cx<R>>(N); b.u = c.take<cx<R>>(N);
+      b.P0 = c.take<cx<R>>(N); b.P1 = c.take<cx<R>>(N); b.q = c.take<cx<R>>(N);
+      b.part = c.take<c128>((size_t)item_grid(N, S) * 2 * S);
+      b.sc = c.take<CocgScal>(S); b.all_done = c.take<int>(4); b.cnt = c.take<unsigned>(4);
+      b.mz = c.take<double>(S); b.pn = c.take<double>(S);
+    };
+    Buffers<R> b0{};
+    lay(cv, b0);
+    DevBuf mem;
+    SHK_HIP(hipMalloc(&mem.p, cv.off));
+    SHK_HIP(hipMemsetAsync(mem.p, 0, cv.off, st));
+    Carver c2{(char*)mem.p};
+    Buffers<R> b{};
+    lay(c2, b);
+    return with_op<R>(p, [&](auto op) -> int {
+      using Op = decltype(op);
+      Group<R, Op> g{p, op, st, b, p->n, N, S, S, 1, 1, item_grid(N, S), S};
+      SHK_TRY(g.inner(tau, (const cx<R>*)v, (cx<R>*)z, eps, maxit, fixed_iters, b.pn));
+      if (w) {
+        k_copy<R><<<item_grid(N, S), BS, 0, st>>>(b.W, N, (cx<R>*)w);
+        SHK_HIP(hipGetLastError());
+      }
+      std::vector<CocgScal> sc(S);
+      SHK_HIP(hipMemcpyAsync(sc.data(), b.sc, sizeof(CocgScal) * S, hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipStreamSynchronize(st));
+      for (int r = 0; r < S; ++r) {
+        if (its) its[r] = sc[r].its;
+        if (pnorm) pnorm[r] = sc[r].pnorm;
+      }
+      return SHK_OK;
+    });
+  };
+  return precision == SHK_MIXED ? run(float{}) : run(double{});
+}
+
+int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precision, hipStream_t st) {
+  if (!V || !w || !h || k < 1 || S < 1 || S > 64 || (S & (S - 1))) return fail(SHK_ERR_INVALID_ARG, "orth arguments");
+  auto run = [&](auto tag) -> int {
+    using R = decltype(tag);
+    const long N = (long)n * S;
+    const long ipb = dot_ipb(N);
+    const long Gd = (N + ipb - 1) / ipb;
+    const long Gu = (N + (long)BS * GSQ - 1) / ((long)BS * GSQ);
+    Carver cv{nullptr};
+    auto lay = [&](Carver& c, Buffers<R>& b) {
+      b.part = c.take<c128>(std::max<size_t>((size_t)Gd * (k + 1) * S, (size_t)Gu * S));
+      b.H = c.take<c128>((size_t)(k + 2) * S); b.h2 = c.take<c128>((size_t)(k + 1) * S);
+      b.hn = c.take<double>(S); b.mz = c.take<double>(S); b.cnt = c.take<unsigned>(4);
+    };
+    Buffers<R> b0{};
+    lay(cv, b0);
+    DevBuf mem;
+    SHK_HIP(hipMalloc(&mem.p, cv.off));
+    SHK_HIP(hipMemsetAsync(mem.p, 0, cv.off, st));
+    Carver c2{(char*)mem.p};
+    Buffers<R> b{};
+    lay(c2, b);
+    std::vector<double> ones(S, 1e-300);
+    SHK_HIP(hipMemcpyAsync(b.mz, ones.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+    b.V = (cx<R>*)V;
+    const int kc = k;
+    for (int pass = 0; pass < 2; ++pass) {
+      k_gs_dot<R><<<(int)Gd, BS, 0, st>>>(N, S, kc, b.V, (size_t)N, (const cx<R>*)w, b.part, ipb);
+      k_gs_reduce<<<kc * S, BS, 0, st>>>(b.part, (int)Gd, kc, S, b.H, b.h2, pass);
+      k_gs_update<R><<<(int)Gu, BS, 0, st>>>(N, S, kc, b.V, (size_t)N, b.h2, (cx<R>*)w, pass, b.part, b.cnt, b.hn,
+                                              b.H + (size_t)kc * S);
+    }
+    k_scale_col<R><<<item_grid(N, S), BS, 0, st>>>(N, S, (const cx<R>*)w, b.hn, b.mz, b.V + (size_t)kc * N);
+    SHK_HIP(hipGetLastError());
+    std::vector<c128> hh((size_t)(k + 1) * S);
+    SHK_HIP(hipMemcpyAsync(hh.data(), b.H, sizeof(c128) * (k + 1) * S, hipMemcpyDeviceToHost, st));
+    SHK_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < S; ++r)
+      for (int i = 0; i <= k; ++i) h[i + (size_t)(k + 1) * r] = hh[(size_t)i * S + r];
+    return SHK_OK;
+  };
+  return precision == SHK_MIXED ? run(float{}) : run(double{});
+}
+
+int step_lsq(int K, const c128* H, const c128* taus, int nf, const c128* sigma, double beta, c128* y, double* rho) {
+  if (K < 1 || nf < 1 || !H || !taus || !sigma || !y || !rho) return fail(SHK_ERR_INVALID_ARG, "lsq arguments");
+  const int m = K, S = 1, L = nf;
+  Carver cv{nullptr};
+  Buffers<double> b0{};
+  auto lay = [&](Carver& c, Buffers<double>& b) {
+    b.H = c.take<c128>((size_t)m * (m + 2)); b.hn = c.take<double>(1); b.mz = c.take<double>(1);
+    b.pn = c.take<double>(m); b.beta0 = c.take<double>(1); b.sigma = c.take<c128>(nf); b.taus = c.take<c128>(m);
+    b.ls = c.take<LaneState>(L); b.rc = c.take<double>((size_t)m * L); b.rs = c.take<c128>((size_t)m * L);
+    b.g = c.take<c128>((size_t)(m + 1) * L); b.Rp = c.take<c128>((size_t)m * (m + 1) / 2 * L);
+    b.Yb = c.take<c128>((size_t)L * m);
+  };
+  lay(cv, b0);
+  DevBuf mem;
+  SHK_HIP(hipMalloc(&mem.p, cv.off));
+  SHK_HIP(hipMemset(mem.p, 0, cv.off));
+  Carver c2{(char*)mem.p};
+  Buffers<double> b{};
+  lay(c2, b);
+  // Hbar column k at H[k*(m+2) + i]
+  std::vector<c128> Hd((size_t)m * (m + 2), c128{0, 0});
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i <= k + 1; ++i) Hd[(size_t)k * (m + 2) + i] = H[i + (size_t)(K + 1) * k];
+  SHK_HIP(hipMemcpy(b.H, Hd.data(), sizeof(c128) * Hd.size(), hipMemcpyHostToDevice));
+  SHK_HIP(hipMemcpy(b.sigma, sigma, sizeof(c128) * nf, hipMemcpyHostToDevice));
+  SHK_HIP(hipMemcpy(b.taus, taus, sizeof(c128) * K, hipMemcpyHostToDevice));
+  SHK_HIP(hipMemcpy(b.beta0, &beta, sizeof(double), hipMemcpyHostToDevice));
+  const double one = 1.0;
+  SHK_HIP(hipMemcpy(b.mz, &one, sizeof(double), hipMemcpyHostToDevice));
+  k_lanes_init<<<(L + BS - 1) / BS, BS>>>(L, 1, 1, b.beta0, b.ls, b.g);
+  std::vector<LaneState> ls(L);
+  for (int k = 0; k < K; ++k) {
+    const double hnk = Hd[(size_t)k * (m + 2) + k + 1].re;
+    SHK_HIP(hipMemcpy(b.hn, &hnk, sizeof(double), hipMemcpyHostToDevice));
+    GivensArgs a{};
+    a.L = L; a.S = S; a.m = m; a.k = k; a.cycle = 0; a.kglob = k;
+    a.tol = 0.0; a.inexact_ratio = -1.0; a.breakdown_rel = 0.0;
+    a.Hk = b.H + (size_t)k * (m + 2); a.hn = b.hn; a.mz = b.mz; a.pn = b.pn; a.beta0 = b.beta0;
+    a.sigma = b.sigma; a.taus = b.taus; a.ls = b.ls; a.rc = b.rc; a.rs = b.rs; a.g = b.g; a.Rp = b.Rp; a.Yb = b.Yb;
+    k_givens<<<(L + BS - 1) / BS, BS>>>(a);
+    SHK_HIP(hipGetLastError());
+    SHK_HIP(hipMemcpy(ls.data(), b.ls, sizeof(LaneState) * L, hipMemcpyDeviceToHost));
+    for (int j = 0; j < nf; ++j) rho[j + (size_t)nf * k] = ls[j].rho;
+  }
+  std::vector<c128> Y((size_t)L * m);
+  SHK_HIP(hipMemcpy(Y.data(), b.Yb, sizeof(c128) * Y.size(), hipMemcpyDeviceToHost));
+  for (int j = 0; j < nf; ++j)
+    for (int i = 0; i < K; ++i) y[i + (size_t)K * j] = Y[(size_t)j * m + i];
+  return SHK_OK;
+}
+
+int step_assemble(long long n, int k, int nf, const void* Z, const c128* Y, c128* X, int acc, int precision,
+                  hipStream_t st) {
+  if (!Z || !Y || !X || k < 1 || nf < 1 || n < 1) return fail(SHK_ERR_INVALID_ARG, "assemble arguments");
+  DevBuf ones;
+  SHK_HIP(hipMalloc(&ones.p, sizeof(c128) * nf));
+  std::vector<c128> o(nf, c128{1.0, 0.0});
+  SHK_HIP(hipMemcpyAsync(ones.p, o.data(), sizeof(c128) * nf, hipMemcpyHostToDevice, st));
+  auto run = [&](auto tag) -> int {
+    using R = decltype(tag);
+    dim3 grid(grid_items(n, 4096), (nf + JT - 1) / JT);
+    k_assemble<R><<<grid, BS, 0, st>>>((long)n, 1, 1, nf, k, k, (const cx<R>*)Z, (size_t)n, Y, (const c128*)ones.p, X,
+                                       acc);
+    SHK_HIP(hipGetLastError());
+    SHK_HIP(hipStreamSynchronize(st));
+    return SHK_OK;
+  };
+  return precision == SHK_MIXED ? run(float{}) : run(double{});
+}
+
+int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x, double* relres,
+                       hipStream_t st) {
+  if (!p || !sigma || !b || !x || !relres || nf < 1) return fail(SHK_ERR_INVALID_ARG, "residual arguments");
+  const long n = p->n;
+  const int Gr = resid_grid(n);
+  DevBuf mem;
+  const size_t bytes = align_up(sizeof(c128) * nf) + align_up(sizeof(c128) * (size_t)nf * Gr) + align_up(sizeof(c128) * nf) +
+                       align_up(sizeof(c128) * 2) + align_up(sizeof(double) * 2);
+  SHK_HIP(hipMalloc(&mem.p, bytes));
+  Carver c{(char*)mem.p};
+  c128* sg = c.take<c128>(nf);
+  c128* part = c.take<c128>((size_t)nf * Gr);
+  c128* rows = c.take<c128>(nf);
+  c128* nb = c.take<c128>(2);
+  double* nbd = c.take<double>(2);
+  SHK_HIP(hipMemcpyAsync(sg, sigma, sizeof(c128) * nf, hipMemcpyHostToDevice, st));
+  DevBuf np;
+  SHK_HIP(hipMalloc(&np.p, sizeof(c128) * 64 + 256));
+  unsigned* cnt = (unsigned*)((char*)np.p + sizeof(c128) * 64);
+  SHK_HIP(hipMemsetAsync(cnt, 0, 16, st));
+  k_norm2<double><<<item_grid(n, 1), BS, 0, st>>>(b, n, 1, (c128*)np.p, cnt, nbd);
+  (void)nb;
+  SHK_TRY(with_op<double>(p, [&](auto opd) -> int {
+    return residual_rows(opd, n, 1, 1, nf, sg, b, x, nullptr, 0, part, rows, st);
+  }));
+  std::vector<c128> hr(nf);
+  double bn = 0.0;
+  SHK_HIP(hipMemcpyAsync(hr.data(), rows, sizeof(c128) * nf, hipMemcpyDeviceToHost, st));
+  SHK_HIP(hipMemcpyAsync(&bn, nbd, sizeof(double), hipMemcpyDeviceToHost, st));
+  SHK_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < nf; ++j) relres[j] = bn > 0 ? std::sqrt(hr[j].re) / bn : std::sqrt(hr[j].re);
+  return SHK_OK;
+}
+
+}  // namespace shk

@@ -1,0 +1,181 @@
+"""GPU parity of whole FGMRES-Sh solves against the oracle and exact solutions.
+
+Several results are correct at once here (iterative solutions within a
+tolerance), so the tests compare what is unique: the exact solution of each
+shifted system (oracle banded elimination / SuperLU / closed form), the FP64
+true residual against the target, and the per-shift outer step counts (equal
+to the oracle's within one step at the stopping threshold).  Error bound used:
+||x - x*|| / ||x*|| <= kappa_j * relres with kappa_j = ||A_j|| ||A_j^-1||
+estimated from the extreme eigenvalues; the tests use a fixed factor 2e3 that
+exceeds the condition numbers of these operators (max ~1e3 for the lowest
+frequency on 64x64).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Problem as OProblem, exact_family, fgmres_sh, dst_closed_form, dst_mode, \
+    laplacian_eigenvalues, superlu_solve
+from tests.gpu_util import require_gpu, to_dev, announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(P, w, **kw):
+    a = dict(m_restart=w.m_restart, max_restarts=20, max_refine=2, tol=w.tol, eps_inner=w.eps_inner)
+    a.update(kw)
+    return P.make_params(w.tau_seq, **a)
+
+
+def test_config1_fp64_all_shifts_and_oracle_agreement():
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce("c1 fp64")
+    w = synth.config1()
+    op = OProblem.fv(w.cell_K, w.Ss, w.h)
+    gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+    prm, keep = _params(P, w)
+    x, st = P.fgmres_sh_solve(gp, prm, w.sigma, w.b)          # host pointers
+    xe = exact_family(op, w.sigma, w.b[:, 0], "banded")
+    ro = fgmres_sh(op, w.b[:, 0], w.sigma, w.tau_seq, m_restart=50, tol=w.tol, inner="cocg", eps=w.eps_inner)
+    for j in range(len(w.sigma)):
+        s = st[0, j]
+        assert s["status"] == P.SHK_CONVERGED, (j, s)
+        assert s["true_relres"] <= 1e-8
+        err = np.linalg.norm(x[:, j, 0] - xe[:, j]) / np.linalg.norm(xe[:, j])
+        assert err <= 2e3 * 1e-8, (j, err)
+        assert abs(int(s["outer_its"]) - ro.info[j].outer_its) <= 1
+    # device pointers give the same numbers
+    bd = to_dev(w.b[:, 0])[None, :].contiguous()
+    xd, st2 = P.fgmres_sh_solve(gp, prm, w.sigma, bd)
+    assert np.array_equal(xd[0].cpu().numpy().T, x[:, :, 0])
+
+
+def test_determinism_bitwise():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("determinism")
+    w = synth.config1()
+    gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+    prm, keep = _params(P, w)
+    x1, s1 = P.fgmres_sh_solve(gp, prm, w.sigma, w.b)
+    x2, s2 = P.fgmres_sh_solve(gp, prm, w.sigma, w.b)
+    assert np.array_equal(x1, x2) and np.array_equal(s1, s2)
+
+
+def test_homogeneous_closed_form_ragged_grid():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("closed form 61x47")
+    dims, K0 = (61, 47), 1.1e-5
+    Kc = np.full((47, 61), K0)
+    gp = P.Problem.fv2d(Kc)
+    sig = synth.shifts_from_periods(synth.periods(8, 10, 1000))
+    b = synth.unit_vector(61 * 47, synth.cell_index((47, 61), (30, 20)))
+    prm, keep = P.make_params(sig[[1, 5]], tol=1e-9, eps_inner=1e-11, m_restart=60)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    for j, s in enumerate(sig):
+        xe = dst_closed_form(K0, 1e-5, 1.0, dims, s, b)
+        assert st[0, j]["true_relres"] <= 1e-9
+        assert np.linalg.norm(x[:, j, 0] - xe) <= 2e3 * 1e-9 * np.linalg.norm(xe)
+
+
+def test_eigenmode_breakdown_exact():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("breakdown")
+    dims, K0, Ss = (20, 16), 1.3e-5, 1e-5
+    gp = P.Problem.fv2d(np.full((16, 20), K0), Ss)
+    b = dst_mode(dims, (3, 2)).astype(complex)
+    lam = laplacian_eigenvalues(dims)[1, 2] * K0
+    sig = synth.shifts_from_periods(synth.periods(5, 10, 1000))
+    prm, keep = P.make_params([0.01j], tol=1e-10, eps_inner=1e-13, m_restart=10)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    for j, s in enumerate(sig):
+        assert st[0, j]["status"] == P.SHK_BREAKDOWN_EXACT
+        assert st[0, j]["outer_its"] == 1
+        assert np.allclose(x[:, j, 0], b / (lam + s * Ss), rtol=1e-9, atol=1e-9 * np.abs(b / (lam + s * Ss)).max())
+
+
+def test_restart_path_converges():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("restart m=6")
+    K = synth.cell_conductivity((32, 32), -11.5, 1.0, 5, cfg=71)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(6, 10, 1000))
+    b = synth.unit_vector(op.n, 528)
+    taus = 2j * np.pi / np.array([20.0, 700.0])
+    prm, keep = P.make_params(taus, tol=1e-9, eps_inner=1e-12, m_restart=6, max_restarts=80, max_refine=0)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    ro = fgmres_sh(op, b, sig, taus, m_restart=6, max_restarts=80, tol=1e-9, inner="cocg", eps=1e-12)
+    xe = exact_family(op, sig, b, "banded")
+    for j in range(len(sig)):
+        assert st[0, j]["status"] == P.SHK_CONVERGED
+        assert st[0, j]["restarts"] >= 1
+        assert abs(int(st[0, j]["outer_its"]) - ro.info[j].outer_its) <= 2
+        assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= 2e3 * 1e-9 * np.linalg.norm(xe[:, j])
+
+
+def test_multi_rhs_lockstep_matches_single_and_reciprocity():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("multi rhs")
+    K = synth.cell_conductivity((48, 48), -11.5, 1.0, 5, cfg=72)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(5, 10, 1000))
+    cells = [300, 1200, 1777]
+    B = np.zeros((48 * 48, 3), complex)
+    for r, c in enumerate(cells):
+        B[c, r] = 1.0
+    prm, keep = P.make_params(sig[[1, 3]], tol=1e-10, eps_inner=1e-12, m_restart=50)
+    X, st = P.fgmres_sh_solve(gp, prm, sig, B)
+    assert np.all(st["true_relres"] <= 1e-10)
+    for r in range(3):
+        xr, _ = P.fgmres_sh_solve(gp, prm, sig, B[:, r])
+        assert np.allclose(X[:, :, r], xr[:, :, 0], rtol=1e-7, atol=1e-7 * np.abs(xr).max())
+    # reciprocity of the complex-symmetric operator: x_a[cell_b] = x_b[cell_a]
+    for a in range(3):
+        for bb in range(3):
+            assert np.allclose(X[cells[bb], :, a], X[cells[a], :, bb], rtol=1e-7)
+
+
+def test_mixed_precision_with_refinement():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("mixed 128x128")
+    K = synth.cell_conductivity((128, 128), -11.5, 1.0, 5, cfg=73)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(40, 5, 5000))
+    b = synth.unit_vector(op.n, synth.cell_index((128, 128), (64, 64)))
+    prm, keep = P.make_params(sig[[4, 20, 36]], tol=1e-6, eps_inner=1e-6, m_restart=50, precision=P.SHK_MIXED,
+                              max_refine=4)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    assert np.all(st["true_relres"] <= 1e-6), st["true_relres"]
+    assert np.all(st["status"] == P.SHK_CONVERGED)
+    for j in (0, 17, 39):
+        xe = superlu_solve(op.shifted(sig[j]), b)
+        assert np.linalg.norm(x[:, j, 0] - xe) <= 5e3 * 1e-6 * np.linalg.norm(xe)
+
+
+def test_degenerate_inputs():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("degenerate")
+    K = synth.cell_conductivity((16, 16), -11.5, 1.0, 5, cfg=74)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(3, 10, 1000))
+    prm, keep = P.make_params(sig[:1], tol=1e-8, eps_inner=1e-10)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, np.zeros(256, complex))
+    assert not x.any() and np.all(st["status"] == P.SHK_CONVERGED)
+    B = np.zeros((256, 2), complex)
+    B[10, 1] = 1.0
+    x, st = P.fgmres_sh_solve(gp, prm, sig, B)
+    assert not x[:, :, 0].any() and np.all(st[1]["true_relres"] <= 1e-8)
+    with pytest.raises(P.ShkError):
+        P.Problem.fv2d(np.zeros((4, 4)))
+    bad, keep2 = P.make_params(sig[:1], m_restart=0)
+    with pytest.raises(P.ShkError):
+        P.fgmres_sh_solve(gp, bad, sig, np.ones(256, complex))

@@ -1,0 +1,204 @@
+"""GPU parity of each step of the method against the CPU oracle, through the C ABI.
+
+Tolerances (FP64 path): the operator, the inner-solver recurrences and the
+Gram-Schmidt coefficients differ from the oracle only in summation order, so
+they agree to a few ulps of the summed magnitudes (1e-12 relative is used,
+1e-9 after tens of dependent iterations).  The complex64 path rounds every
+stored value to 2^-24 ~ 6e-8 relative; 5e-6 relative covers the stencil's
+cancellation on these fields.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Problem as OProblem, cocg, mgs_step, shifted_hessenberg, small_solve, fgmres_sh
+from tests.gpu_util import require_gpu, to_dev, announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _field(shape, seed):
+    return synth.cell_conductivity(shape, -11.5, 1.0, 5, cfg=70, idx=seed)
+
+
+def _gpu_problem(P, K):
+    return P.Problem.fv2d(K) if K.ndim == 2 else P.Problem.fv3d(K)
+
+
+@pytest.mark.parametrize("shape,S", [((64, 64), 1), ((53, 37), 1), ((33, 47), 4), ((5, 7, 9), 2), ((12, 11, 10), 1)])
+def test_apply_operator(shape, S):
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"apply shape={shape} S={S}")
+    K = _field(shape, 1)
+    op = OProblem.fv(K)
+    gp = _gpu_problem(P, K)
+    rng = np.random.default_rng(3)
+    n = op.n
+    X = rng.normal(size=(n, S)) + 1j * rng.normal(size=(n, S))
+    sigma = 0.3j
+    ref = op.apply(sigma, X)
+    for prec, tol in (("c128", 1e-12), ("c64", 5e-6)):
+        x = to_dev(X.ravel(), prec)
+        y = torch.empty_like(x)
+        P.shk_apply_shifted(gp, sigma, x, y, n_rhs=S)
+        got = y.cpu().numpy().astype(np.complex128).reshape(n, S)
+        scale = np.abs(op.K) @ np.abs(X) + abs(sigma) * op.Mdiag[:, None] * np.abs(X)
+        assert np.all(np.abs(got - ref) <= tol * scale), prec
+
+
+def test_apply_csr_one_dimensional():
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce("apply csr")
+    K = _field((200,), 2)
+    op = OProblem.fv(K)
+    A = op.K.tocsr()
+    gp = P.Problem.csr(A.indptr, A.indices, A.data, op.Mdiag)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=op.n) + 1j * rng.normal(size=op.n)
+    x = to_dev(X)
+    y = torch.empty_like(x)
+    P.shk_apply_shifted(gp, 0.02j, x, y)
+    assert np.allclose(y.cpu().numpy(), op.apply(0.02j, X), rtol=1e-12, atol=1e-12 * np.abs(op.apply(0.02j, X)).max())
+
+
+@pytest.mark.parametrize("shape", [(48, 40), (6, 7, 8)])
+def test_inner_cocg_iterates_match_oracle(shape):
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"cocg fixed iterations shape={shape}")
+    K = _field(shape, 5)
+    op = OProblem.fv(K)
+    gp = _gpu_problem(P, K)
+    tau = 2j * np.pi / 77.43
+    v = np.zeros(op.n, complex)
+    v[op.n // 2 + 3] = 1.0
+    v += 0.01 * np.random.default_rng(0).normal(size=op.n)
+    v /= np.linalg.norm(v)
+    for its in (1, 5, 25):
+        zo, _, _, _ = cocg(lambda x: op.apply(tau, x), op.diag(tau), v, 0.0, 1000, fixed_iters=its)
+        z = torch.zeros(op.n, dtype=torch.complex128, device="cuda")
+        w = torch.zeros_like(z)
+        got_its, pn = P.shk_inner_solve(gp, tau, to_dev(v), z, w, fixed_iters=its)
+        assert got_its[0] == its
+        zg = z.cpu().numpy()
+        assert np.linalg.norm(zg - zo) <= 1e-9 * np.linalg.norm(zo)
+        # true inner residual and mass product
+        assert np.isclose(pn[0], np.linalg.norm(v - op.apply(tau, zo)), rtol=1e-7)
+        assert np.allclose(w.cpu().numpy(), op.Mdiag * zg, rtol=1e-14, atol=0)
+
+
+def test_inner_cocg_converged_counts_and_residual():
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce("cocg converged")
+    K = _field((64, 64), 6)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    S = 4
+    rng = np.random.default_rng(8)
+    V = rng.normal(size=(op.n, S)) + 1j * rng.normal(size=(op.n, S))
+    V /= np.linalg.norm(V, axis=0)
+    tau = 2j * np.pi / 300.0
+    for eps in (1e-6, 1e-10):
+        z = torch.zeros(op.n * S, dtype=torch.complex128, device="cuda")
+        its, pn = P.shk_inner_solve(gp, tau, to_dev(V.ravel()), z, eps=eps, n_rhs=S)
+        Z = z.cpu().numpy().reshape(op.n, S)
+        for r in range(S):
+            _, oits, ok, _ = cocg(lambda x: op.apply(tau, x), op.diag(tau), V[:, r], eps, 5000)
+            assert ok and abs(int(its[r]) - oits) <= 1
+            true = np.linalg.norm(V[:, r] - op.apply(tau, Z[:, r]))
+            assert true <= 1.5 * eps and np.isclose(pn[r], true, rtol=1e-6)
+    # complex64 path: converges to a looser tolerance
+    z = torch.zeros(op.n * S, dtype=torch.complex64, device="cuda")
+    its, pn = P.shk_inner_solve(gp, tau, to_dev(V.ravel(), "c64"), z, eps=1e-5, n_rhs=S)
+    Z = z.cpu().numpy().astype(np.complex128).reshape(op.n, S)
+    for r in range(S):
+        assert np.linalg.norm(V[:, r] - op.apply(tau, Z[:, r])) <= 5e-5
+
+
+@pytest.mark.parametrize("n,k,S", [(4096, 1, 1), (10000, 7, 1), (262144, 30, 1), (5000, 12, 4)])
+def test_orthogonalize_matches_mgs(n, k, S):
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"orth n={n} k={k} S={S}")
+    rng = np.random.default_rng(k)
+    Vh = np.zeros((k + 1, n, S), complex)
+    W = rng.normal(size=(n, S)) + 1j * rng.normal(size=(n, S))
+    for r in range(S):
+        Q, _ = np.linalg.qr(rng.normal(size=(n, k)) + 1j * rng.normal(size=(n, k)))
+        Vh[:k, :, r] = Q.T
+    V = to_dev(Vh.reshape(k + 1, n * S).ravel())
+    w = to_dev(W.ravel())
+    h = P.shk_orthogonalize(n, k, V, w, n_rhs=S)
+    Vg = V.cpu().numpy().reshape(k + 1, n, S)
+    for r in range(S):
+        ho, hn, vn = mgs_step(Vh[:k, :, r].T, W[:, r])
+        assert np.allclose(h[r, :k], ho, rtol=0, atol=1e-12 * np.linalg.norm(W[:, r]))
+        assert np.isclose(h[r, k].real, hn, rtol=1e-12)
+        assert np.allclose(Vg[k, :, r], vn, atol=1e-12)
+    # complex64
+    V32 = to_dev(Vh.reshape(k + 1, n * S).ravel(), "c64")
+    h32 = P.shk_orthogonalize(n, k, V32, to_dev(W.ravel(), "c64"), n_rhs=S)
+    for r in range(S):
+        ho, hn, _ = mgs_step(Vh[:k, :, r].T, W[:, r])
+        assert np.allclose(h32[r, :k], ho, atol=2e-5 * np.linalg.norm(W[:, r]))
+
+
+def test_shifted_lsq_matches_oracle_least_squares():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("shifted lsq")
+    K = _field((20, 20), 9)
+    op = OProblem.fv(K)
+    T = synth.periods(12, 5, 5000)
+    sig = synth.shifts_from_periods(T)
+    b = synth.unit_vector(op.n, 210)
+    r = fgmres_sh(op, b, sig, sig[[2, 6, 10]], m_restart=14, max_restarts=0, tol=1e-30, inner="dense",
+                  keep_basis=True)
+    H, taus = r.H, r.taus
+    k = H.shape[1]
+    beta = np.linalg.norm(b)
+    y, rho = P.shk_shifted_lsq(H, taus, sig, beta)
+    for j, s in enumerate(sig):
+        for kk in range(1, k + 1):
+            Hs = shifted_hessenberg(H[:kk + 1, :kk], taus[:kk], s)
+            yo, qv = small_solve(Hs, beta, "gmres")
+            assert np.isclose(rho[kk - 1, j], np.linalg.norm(qv), rtol=1e-8, atol=1e-15 * beta)
+        Hs = shifted_hessenberg(H, taus, s)
+        yo, _ = small_solve(Hs, beta, "gmres")
+        assert np.allclose(y[j], yo, rtol=1e-8, atol=1e-9 * np.abs(yo).max())
+
+
+@pytest.mark.parametrize("n,k,nf", [(1000, 5, 3), (70000, 40, 37)])
+def test_assemble(n, k, nf):
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"assemble n={n} k={k} nf={nf}")
+    rng = np.random.default_rng(1)
+    Z = rng.normal(size=(k, n)) + 1j * rng.normal(size=(k, n))     # k columns of n
+    Y = rng.normal(size=(nf, k)) + 1j * rng.normal(size=(nf, k))   # k x nf column-major
+    X = torch.zeros((nf, n), dtype=torch.complex128, device="cuda")
+    P.shk_assemble(n, k, nf, to_dev(Z.ravel()), to_dev(Y.ravel()), X)
+    ref = (Z.T @ Y.T).T
+    assert np.allclose(X.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    P.shk_assemble(n, k, nf, to_dev(Z.ravel()), to_dev(Y.ravel()), X, accumulate=True)
+    assert np.allclose(X.cpu().numpy(), 2 * ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_true_residual():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    from oracle import true_residuals
+    announce("true residual")
+    K = _field((40, 30), 3)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(7, 10, 1000))
+    b = synth.unit_vector(op.n, 500)
+    rng = np.random.default_rng(2)
+    X = rng.normal(size=(op.n, 7)) * 1e3 + 1j * rng.normal(size=(op.n, 7)) * 1e3
+    ref = true_residuals(op, b, sig, X)
+    got = P.shk_true_residual(gp, sig, to_dev(b), to_dev(X.T.ravel()))
+    assert np.allclose(got, ref, rtol=1e-12)

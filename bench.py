@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the flexible shifted-Krylov solver on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2-D
+finite-volume groundwater operator on a 512 x 512 grid (262,144 unknowns),
+ln K ~ N(-11.5, 1) smoothed by a 5 x 5 box, Ss = 1e-5, h = 1; 200 shifts
+sigma_j = i 2 pi / T_j with periods log-spaced 5..5000 s; one point source at
+the centre; preconditioner shifts cycling over i*omega_{20,100,180}; inner
+COCG tolerance 1e-6; restart 50; every shift to FP64 true relative residual
+<= 1e-6 (refinement included).  A step is one complete solve of all 200
+shifts with inputs resident on the device.
+
+Prints one JSON line.  The value is shifted solves per second of the mixed
+(complex64 bulk, FP64 least squares / residuals / refinement) path; the plain
+FP64 path is timed the same way and reported beside it.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shifted solves/s at rel-res 1e-6 (mixed batched vs plain FP64); p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "ops.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1212_3660_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def time_path(P, torch, gp, w, precision, steps, warmup, profile=False):
+    prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
+                              eps_inner=w.eps_inner, precision=precision)
+    nf = len(w.sigma)
+    ws = torch.empty(P.shk_workspace_bytes(gp, prm, nf, 1), dtype=torch.uint8, device="cuda")
+    b = torch.from_numpy(w.b[:, 0]).cuda()[None, :].contiguous()
+    x = torch.empty((1, nf, gp.n), dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        P.fgmres_sh_solve(gp, prm, w.sigma, b, x=x, workspace=ws)
+    torch.cuda.synchronize()
+    if profile:
+        P.shk_profile_enable(True)
+    per = []
+    worst = 0.0
+    ok = True
+    inner = outer = 0
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, st = P.fgmres_sh_solve(gp, prm, w.sigma, b, x=x, workspace=ws)
+        e1.record()
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1))
+        worst = max(worst, float(st["true_relres"].max()))
+        ok &= bool((st["status"] == P.SHK_CONVERGED).all()) and worst <= w.tol
+        inner = int(st["inner_its"][0, 0])
+        outer = int(st["outer_its"].max())
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ev0.elapsed_time(ev1)
+    prof = None
+    if profile:
+        prof = P.shk_profile_read()
+        P.shk_profile_enable(False)
+    return dict(total_ms=total_ms, wall_s=wall, per_ms=per, worst=worst, ok=ok, inner=inner, outer=outer,
+                prof=prof)
+
+
+def cpu_baseline(w, seconds, gpu_outer_steps):
+    """The CPU oracle (FGMRES-Sh, complex128, Jacobi-COCG inner) on the same
+    workload, bounded to a few outer steps; scaled to a full solve with the
+    outer step count the GPU solve needed (refinement not counted)."""
+    import numpy as np  # noqa: F401
+    from oracle import Problem as OProblem, fgmres_sh
+    op = OProblem.fv(w.cell_K, w.Ss, w.h)
+    n_tau = len(w.tau_seq)
+    steps = n_tau          # one step per preconditioner shift: the cycle's cost mix
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    while True:
+        fgmres_sh(op, w.b[:, 0], w.sigma, w.tau_seq, m_restart=w.m_restart, tol=w.tol, inner="cocg",
+                  eps=w.eps_inner, max_steps=steps)
+        el = time.perf_counter() - t0
+        if el >= 0.5 * seconds or steps >= 4 * n_tau:
+            break
+        steps += n_tau
+        c0 = time.process_time()
+        t0 = time.perf_counter()
+    cpu = time.process_time() - c0
+    per_step = el / steps
+    est = per_step * max(gpu_outer_steps, 1)
+    threads = max(1, int(round(cpu / el)))
+    return {"value": len(w.sigma) / est, "unit": "shifted solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{steps} outer steps (all {len(w.sigma)} shifts, Jacobi-COCG inner to {w.eps_inner}) "
+                       f"of the 512x512 workload in {el:.1f} s; scaled to the {gpu_outer_steps} outer steps "
+                       f"of the GPU solve (refinement sweeps not counted)"),
+            "host_cores_available": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--grid", type=int, default=512)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the solver's per-GPU share is a whole "
+              f"request or right-hand-side block, so N GPUs would run N independent copies", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1212_3660_amd as P
+    import synth
+    torch.cuda.set_device(0)
+    w = synth.config2(n_grid=a.grid)
+    gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+    mixed = time_path(P, torch, gp, w, P.SHK_MIXED, a.steps, a.warmup, profile=False)
+    fp64 = time_path(P, torch, gp, w, P.SHK_FP64, a.steps, a.warmup, profile=False)
+    prof_run = time_path(P, torch, gp, w, P.SHK_MIXED, 1, 0, profile=True)
+    nf = len(w.sigma)
+    ms_step = mixed["total_ms"] / a.steps
+    value = nf * a.steps / (mixed["total_ms"] / 1e3)
+    fp64_value = nf * a.steps / (fp64["total_ms"] / 1e3)
+    launches, kms, kbytes = prof_run["prof"]
+    roof = None
+    if launches > 0:
+        avg_s = kms / launches / 1e3
+        achieved = kbytes / launches / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_cg_step<Op2D<float>,float> (inner COCG iteration, mixed path)",
+                "avg_launch_us": round(kms / launches * 1e3, 3), "launches": launches,
+                "algorithmic_bytes_per_launch": round(kbytes / launches)}
+        tfile = os.path.join(ROOT, "profiles", "traffic_cg_step_512x512.json")
+        if os.path.exists(tfile):
+            t = json.load(open(tfile))
+            if t.get("kernel_source_digest") == kernel_source_digest():
+                roof["traffic"] = t.get("traffic_bytes_per_launch")
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "shifted solves/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+           "config": {"workload": f"2-D FV {a.grid}x{a.grid}, {nf} shifts (periods 5..5000 s), 1 point source, "
+                                  "tau cyclic {i w20, i w100, i w180}, inner COCG 1e-6, restart 50, target 1e-6",
+                      "n_shifts": nf, "n_rhs": 1, "unknowns": gp.n},
+           "p50_ms": round(percentile(mixed["per_ms"], 0.5), 3), "p99_ms": round(percentile(mixed["per_ms"], 0.99), 3),
+           "converged": mixed["ok"], "max_true_relres": mixed["worst"],
+           "inner_iterations": mixed["inner"], "outer_steps": mixed["outer"],
+           "fp64": {"value": round(fp64_value, 2), "ms_per_step": round(fp64["total_ms"] / a.steps, 3),
+                    "p50_ms": round(percentile(fp64["per_ms"], 0.5), 3),
+                    "p99_ms": round(percentile(fp64["per_ms"], 0.99), 3), "converged": fp64["ok"],
+                    "max_true_relres": fp64["worst"], "inner_iterations": fp64["inner"],
+                    "outer_steps": fp64["outer"]},
+           "roofline": roof, "cpu_baseline": None}
+    if not a.no_cpu:
+        try:
+            out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, mixed["outer"])
+        except Exception as e:  # the GPU numbers stand on their own
+            out["cpu_baseline"] = {"error": str(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

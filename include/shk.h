@@ -176,11 +176,14 @@ int shk_apply_shifted(shk_problem* p, shk_c128 sigma, int n_rhs, const void* x, 
                       int precision, void* hip_stream);
 
 /* Inner preconditioner solve z ~ (K + tau M)^{-1} v (section 4, eq. zmmoditer):
- * Jacobi-preconditioned COCG from z = 0, stopped when the recurrence residual
- * satisfies ||r|| <= eps ||v|| or after maxit iterations; fixed_iters > 0 runs
- * exactly that many iterations instead.  Outputs (host, n_rhs each): its[r],
- * true residual norm pnorm[r] = ||v - (K + tau M) z||.  Also writes w = M z
- * (device, may be NULL). */
+ * Jacobi-preconditioned COCG from z = 0, stopped when the residual satisfies
+ * ||r|| <= eps ||v|| or after maxit iterations (0: 20 * largest grid dim);
+ * fixed_iters > 0 runs exactly that many iterations instead.  v and w use the
+ * vector precision; the iterate z is always complex128 (on the complex64 path
+ * it accumulates in FP64 and the residual is recomputed in FP64 before the
+ * solve is accepted).  Outputs (host, n_rhs each): its[r], true residual norm
+ * pnorm[r] = ||v - (K + tau M) z|| (FP64).  Also writes w = M z in the vector
+ * precision (device, may be NULL). */
 int shk_inner_solve(shk_problem* p, shk_c128 tau, int n_rhs, const void* v, void* z, void* w,
                     double eps, int maxit, int fixed_iters, int precision, int* its,
                     double* pnorm, void* hip_stream);
@@ -213,6 +216,16 @@ int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128
  * n, device x: n x n_shifts column-major; host relres: n_shifts). */
 int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b,
                       const shk_c128* x, double* relres, void* hip_stream);
+
+/* Instrumentation of the inner-iteration kernel (the hot loop of section 4's
+ * inner solves): when enabled, every launch of it is bracketed by HIP events
+ * on the solve stream and, per launch that performed an iteration, its
+ * duration and its algorithmic bytes (per cell: r, w, s read and written, p
+ * and the FP64 iterate x read and written, diag(K) and the face
+ * coefficients read) are accumulated.  Process-wide; enable/disable/read are
+ * not meant to race with solves on other threads. */
+int shk_profile_enable(int on);
+int shk_profile_read(long long* launches, double* total_ms, double* total_bytes);
 
 /* Text for a status or error code; last error message of the calling thread. */
 const char* shk_status_string(int code);

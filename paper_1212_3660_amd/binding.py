@@ -82,6 +82,8 @@ _SIGS = {
                                C.c_int, C.c_void_p]),
     "shk_true_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
+    "shk_profile_enable": (C.c_int, [C.c_int]),
+    "shk_profile_read": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "shk_status_string": (C.c_char_p, [C.c_int]),
     "shk_last_error": (C.c_char_p, []),
     "shk_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
@@ -322,6 +324,17 @@ def shk_true_residual(problem: Problem, sigma, b, x, stream=None) -> np.ndarray:
                                    C.c_void_p(x.data_ptr()), out.ctypes.data, _stream_ptr(stream)),
            "shk_true_residual")
     return out
+
+
+def shk_profile_enable(on: bool = True):
+    _check(lib().shk_profile_enable(1 if on else 0), "shk_profile_enable")
+
+
+def shk_profile_read():
+    """(launches, total_ms, total_bytes) of the timed inner-iteration kernel launches."""
+    n, ms, by = C.c_longlong(), C.c_double(), C.c_double()
+    _check(lib().shk_profile_read(C.byref(n), C.byref(ms), C.byref(by)), "shk_profile_read")
+    return int(n.value), float(ms.value), float(by.value)
 
 
 class Server:

@@ -157,4 +157,9 @@ const char* shk_status_string(int code) {
 
 const char* shk_last_error(void) { return shk::last_error_text(); }
 
+int shk_profile_enable(int on) { return shk::profile_enable(on); }
+int shk_profile_read(long long* launches, double* total_ms, double* total_bytes) {
+  return shk::profile_read(launches, total_ms, total_bytes);
+}
+
 }  // extern "C"

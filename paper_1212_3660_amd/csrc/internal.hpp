@@ -43,6 +43,8 @@ struct shk_problem {
   int* rowptr = nullptr; int* col = nullptr;
   double* val = nullptr; float* val32 = nullptr;
   double* diag = nullptr;           // diagonal of K (CSR only)
+  double* dK = nullptr;             // diagonal of K, every kind (Jacobi preconditioner)
+  float* dK32 = nullptr;
   double* mdiag = nullptr;          // per-row mass (CSR only)
   long long nnz = 0;
   int max_dim() const { return nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz); }
@@ -75,5 +77,7 @@ void problem_free(shk_problem* p, hipStream_t st);
 size_t problem_bytes(const shk_problem* p);
 size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x);
 const char* last_error_text();
+int profile_enable(int on);
+int profile_read(long long* launches, double* ms, double* bytes);
 
 }  // namespace shk

@@ -6,9 +6,11 @@
 // lane r for its whole life and per-lane sums need no atomics.
 //
 // Reductions are deterministic: per-thread sums, a fixed wave tree, a fixed
-// cross-wave sum per block, then the last block to finish (counted with one
-// device-scope atomic) adds the block partials in block order.  Repeated runs
-// give bitwise identical results.
+// cross-wave sum per block written as a block partial; the kernel that needs
+// the total (the next one in stream order, so the kernel boundary makes the
+// partials visible without device-scope fences) adds the partials in block
+// order, redundantly in every block that needs them.  Repeated runs give
+// bitwise identical results.
 #pragma once
 #include "common.hpp"
 #include "ops.hpp"
@@ -20,9 +22,12 @@ constexpr int BS = 256;
 constexpr int NWAVE = BS / WAVE;
 
 // ------------------------------------------------------------ reductions ---
-template <int NV>
+// Block partial per lane: wave tree over lanes of equal r, then the waves in
+// order.  Writes out[q*S + r] for r < S.
+template <int NV, int BSZ = BS>
 __device__ __forceinline__ void block_partials(c128 (&v)[NV], int S, c128* __restrict__ out) {
-  __shared__ c128 sh[NWAVE][NV][WAVE];
+  constexpr int NW = BSZ / WAVE;
+  __shared__ c128 sh[NW][NV][WAVE];
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = wave_sum_strided(v[q], S);
@@ -35,34 +40,22 @@ __device__ __forceinline__ void block_partials(c128 (&v)[NV], int S, c128* __res
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       c128 a = sh[0][q][threadIdx.x];
-      for (int w = 1; w < NWAVE; ++w) a = a + sh[w][q][threadIdx.x];
+      for (int w = 1; w < NW; ++w) a = a + sh[w][q][threadIdx.x];
       out[q * S + threadIdx.x] = a;
     }
   }
   __syncthreads();
 }
 
-// True in the block that finishes last; its threads then see every block's
-// partial writes.  That block must reset *counter for the next launch.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned nblocks) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == nblocks - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-// Sum partials laid out [block][NV][S] over blocks in a fixed order.  Every
-// thread returns the totals of its lane r = threadIdx.x % S.
-template <int NV>
+// Sum partials laid out [block][NV][S] over G blocks in a fixed order (strided
+// per-thread sums, a wave tree, then the waves in order).  Every thread gets
+// the totals of its lane r = threadIdx.x % S.
+template <int NV, int BSZ = BS>
 __device__ __forceinline__ void final_sum(const c128* __restrict__ part, int G, int S, c128 (&res)[NV]) {
-  __shared__ c128 sh[NV][BS];
-  const int r = threadIdx.x & (S - 1), c0 = threadIdx.x / S, C = BS / S;
+  constexpr int NW = BSZ / WAVE;
+  __shared__ c128 sh[NW][NV][WAVE];
+  const int r = threadIdx.x & (S - 1), c0 = threadIdx.x / S, C = BSZ / S;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   c128 acc[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) acc[q] = c128{0.0, 0.0};
@@ -71,17 +64,18 @@ __device__ __forceinline__ void final_sum(const c128* __restrict__ part, int G, 
     for (int q = 0; q < NV; ++q) acc[q] = acc[q] + part[((size_t)b * NV + q) * S + r];
   }
 #pragma unroll
-  for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  for (int st = C / 2; st >= 1; st >>= 1) {
-    if (c0 < st) {
+  for (int q = 0; q < NV; ++q) acc[q] = wave_sum_strided(acc[q], S);
+  if (lane < S) {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = sh[q][threadIdx.x] + sh[q][threadIdx.x + st * S];
-    }
-    __syncthreads();
+    for (int q = 0; q < NV; ++q) sh[wv][q][lane] = acc[q];
   }
+  __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NV; ++q) res[q] = sh[q][r];
+  for (int q = 0; q < NV; ++q) {
+    c128 a = sh[0][q][r];
+    for (int w = 1; w < NW; ++w) a = a + sh[w][q][r];
+    res[q] = a;
+  }
   __syncthreads();
 }
 
@@ -141,20 +135,30 @@ __global__ void __launch_bounds__(BS) k_interleave(const c128* __restrict__ b, l
   }
 }
 
-// Per-lane 2-norm; result out[r] (FP64).
+// Per-lane partial sums of |x|^2 (block partials [G][1][S]); k_final_sqrt
+// turns them into norms.
 template <typename R>
 __global__ void __launch_bounds__(BS) k_norm2(const cx<R>* __restrict__ x, long N, int S,
-                                              c128* __restrict__ part, unsigned* __restrict__ cnt,
-                                              double* __restrict__ out) {
+                                              c128* __restrict__ part) {
   c128 acc[1] = {{0.0, 0.0}};
   for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS)
     acc[0].re += (double)abs2(x[t]);
   block_partials<1>(acc, S, part + (size_t)blockIdx.x * S);
-  if (arrive_last(cnt, gridDim.x)) {
-    c128 tot[1];
-    final_sum<1>(part, gridDim.x, S, tot);
-    if ((int)threadIdx.x < S) out[threadIdx.x] = sqrt(tot[0].re);
-    if (threadIdx.x == 0) *cnt = 0u;
+}
+
+// One block: out_q[r] = sqrt(sum of partial q) for q < NV; optionally also
+// written as a complex Hessenberg entry (the subdiagonal h_{k+1,k}).
+template <int NV>
+__global__ void __launch_bounds__(BS) k_final_sqrt(const c128* __restrict__ part, int G, int S,
+                                                   double* __restrict__ out0, double* __restrict__ out1,
+                                                   c128* __restrict__ hcol) {
+  c128 tot[NV];
+  final_sum<NV>(part, G, S, tot);
+  if ((int)threadIdx.x < S) {
+    const double a = sqrt(tot[0].re);
+    if (out0) out0[threadIdx.x] = a;
+    if (hcol) hcol[threadIdx.x] = c128{a, 0.0};
+    if (NV > 1 && out1) out1[threadIdx.x] = sqrt(tot[NV - 1].re);
   }
 }
 
@@ -190,219 +194,290 @@ __global__ void __launch_bounds__(BS) k_apply(Op op, c128 sigma, long n, int S, 
 // -------------------------------------------------------- inner COCG --------
 // Jacobi-preconditioned COCG (conjugate orthogonal CG for the complex
 // symmetric K + tau M, bilinear products x^T y) for z ~ (K + tau M)^{-1} v,
-// section 4 eq. zmmoditer.  Two kernels per iteration:
-//   A: p = u + beta p_old (formed on the fly, also at stencil neighbours),
-//      q = A p, partial p^T q; last block: alpha = rho / p^T q
-//   B: x += alpha p, r -= alpha q, u = D^{-1} r, partials r^T u and ||r||^2;
-//      last block: stop test ||r|| <= eps ||v||, beta = rho'/rho
-struct CocgScal {
-  c128 rho, alpha, beta;
-  double vnorm, rnorm, pnorm, mznorm;
+// section 4 eq. zmmoditer, in the single-reduction arrangement of Chronopoulos
+// and Gear: with u = D^{-1} r, w = A u and s = A p carried by recurrence, the
+// two inner products gamma = r^T u and delta = w^T u of one step fix both
+//   beta_{i+1} = gamma_{i+1} / gamma_i,
+//   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i),
+// which equal the textbook COCG coefficients in exact arithmetic.  One kernel
+// per iteration: its prologue sums the previous step's block partials (every
+// block the same, fixed order) and applies the stop test ||r|| <= eps ||v||;
+// then, per cell,
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r' = r - alpha s,
+//   w' = A D^{-1} r'  (r' at the stencil neighbours formed on the fly),
+// and partials of r'^T u', w'^T u', ||r'||^2.  r, w, s are read at neighbours
+// and so live in two buffers each, selected by the parity of the lane's
+// iteration count; p and x (own cell only) are updated in place.  x is FP64 on
+// both paths.  On the complex64 path the recurrence residual drifts from the
+// true one; once every lane has converged, r = v - A x is recomputed in FP64
+// (and w with it) and the iteration resumes where needed (residual
+// replacement, van der Vorst and Ye), so the inner tolerance holds for the
+// true residual.
+struct CgScal {
+  c128 gamma, alpha, beta;
+  double vnorm, rnorm;
   int its, done, conv, maxit;
+  int fresh, replaced, verified, trust;  // trust: accept the recurrence residual (FP64 path)
 };
 
-template <typename Op, typename R>
-__device__ __forceinline__ cx<R> jacobi_diag(const Op& op, long c, c128 tau) {
-  const double m = op.mass(c);
-  return cx<R>{(R)(op.diagK(c) + tau.re * m), (R)(tau.im * m)};
-}
+constexpr int CGB = 1024;   // block size of the iteration kernel
 
-__device__ __forceinline__ void finish_all_done(CocgScal* sc, int S, int* all_done) {
-  if (threadIdx.x == 0) {
-    int d = 1;
-    for (int r = 0; r < S; ++r) d &= sc[r].done;
-    *all_done = d;
+__device__ __forceinline__ bool is_zero(c128 a) { return a.re == 0.0 && a.im == 0.0; }
+
+// Lane state transition from the totals gamma' (tg), delta' (td), ||r'||^2.
+__device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double trr, double eps) {
+  if (s.fresh) {
+    s.fresh = 0;
+    s.vnorm = sqrt(trr);
+    s.rnorm = s.vnorm;
+    s.its = 0;
+    s.gamma = tg;
+    s.beta = c128{0.0, 0.0};
+    s.done = s.vnorm == 0.0 || is_zero(td);
+    s.alpha = s.done ? c128{0.0, 0.0} : cdiv(tg, td);
+    s.conv = s.vnorm == 0.0;
+    s.verified = s.done;
+    return;
   }
+  if (!s.replaced && s.done) return;
+  if (!s.replaced) s.its += 1;
+  const bool was_replaced = s.replaced != 0;
+  s.replaced = 0;
+  s.rnorm = sqrt(trr);
+  if (s.rnorm <= eps * s.vnorm) {
+    s.done = 1;
+    s.conv = 1;
+    if (was_replaced) s.verified = 1;
+    return;
+  }
+  c128 den{0.0, 0.0};
+  c128 beta{0.0, 0.0};
+  if (!is_zero(s.gamma) && !is_zero(s.alpha)) {
+    beta = cdiv(tg, s.gamma);
+    den = td - cdiv(beta * tg, s.alpha);
+  }
+  if (s.its >= s.maxit || !(s.rnorm == s.rnorm) || is_zero(den)) {
+    s.done = 1;
+    s.conv = 0;
+    s.verified = 1;
+    return;
+  }
+  s.done = 0;
+  s.conv = 0;
+  s.beta = beta;
+  s.alpha = cdiv(tg, den);
+  s.gamma = tg;
 }
 
 template <typename Op, typename R>
-__global__ void __launch_bounds__(BS) k_cocg_init(Op op, c128 tau, long n, int S, int maxit,
-                                                  const cx<R>* __restrict__ v, cx<R>* __restrict__ x,
-                                                  cx<R>* __restrict__ r, cx<R>* __restrict__ u,
-                                                  cx<R>* __restrict__ p0, c128* __restrict__ part,
-                                                  unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
-                                                  int* __restrict__ all_done) {
+__device__ __forceinline__ cx<R> jdiag(const Op& op, const R* __restrict__ dK, long c, cx<R> tau) {
+  const R m = (R)op.mass(c);
+  return cx<R>{dK[c] + tau.re * m, tau.im * m};
+}
+
+// Vector set of the iteration: r, w, s in two parity buffers.
+template <typename R> struct CgVecs {
+  cx<R>* r[2];
+  cx<R>* w[2];
+  cx<R>* s[2];
+  cx<R>* p;
+  c128* x;
+};
+
+// x = 0, p = 0, s = 0, r = v, w = A D^{-1} v; partials v^T u, w^T u, ||v||^2.
+template <typename Op, typename R>
+__global__ void __launch_bounds__(BS) k_cg_init(Op op, const R* __restrict__ dK, c128 tau, long n, int S, int maxit,
+                                                int trust, const cx<R>* __restrict__ v, CgVecs<R> vec,
+                                                c128* __restrict__ part, CgScal* __restrict__ sc0,
+                                                int* __restrict__ all_done) {
   const long N = n * S;
-  c128 acc[2] = {{0.0, 0.0}, {0.0, 0.0}};
-  cx<R> a0{0, 0};
-  R a1 = 0;
+  const int rl = threadIdx.x & (S - 1);
+  const cx<R> tr = cvt<R>(tau);
+  auto gu = [&](long cc) { return cdiv(v[cc * S + rl], jdiag<Op, R>(op, dK, cc, tr)); };
+  cx<R> ag{0, 0}, ad{0, 0};
+  R arr = 0;
   for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
     const long c = t / S;
     const cx<R> vv = v[t];
-    const cx<R> uu = cdiv(vv, jacobi_diag<Op, R>(op, c, tau));
-    x[t] = cx<R>{0, 0};
-    r[t] = vv;
-    u[t] = uu;
-    p0[t] = cx<R>{0, 0};
-    a0 = a0 + vv * uu;
-    a1 += abs2(vv);
+    const cx<R> uu = gu(c);
+    const cx<R> ww = op.template apply<R>(c, tr, gu);
+    vec.x[t] = c128{0.0, 0.0};
+    vec.p[t] = cx<R>{0, 0};
+    vec.s[0][t] = cx<R>{0, 0};
+    vec.r[0][t] = vv;
+    vec.w[0][t] = ww;
+    ag = ag + vv * uu;
+    ad = ad + ww * uu;
+    arr += abs2(vv);
   }
-  acc[0] = cvt<double>(a0);
-  acc[1].re = (double)a1;
-  block_partials<2>(acc, S, part + (size_t)blockIdx.x * 2 * S);
-  if (arrive_last(cnt, gridDim.x)) {
-    c128 tot[2];
-    final_sum<2>(part, gridDim.x, S, tot);
+  c128 acc[3] = {cvt<double>(ag), cvt<double>(ad), {(double)arr, 0.0}};
+  block_partials<3>(acc, S, part + (size_t)blockIdx.x * 3 * S);
+  if (blockIdx.x == 0) {
     if ((int)threadIdx.x < S) {
-      CocgScal s{};
-      s.rho = tot[0];
-      s.vnorm = sqrt(tot[1].re);
-      s.rnorm = s.vnorm;
-      s.beta = c128{0.0, 0.0};
-      s.alpha = c128{0.0, 0.0};
-      s.its = 0;
+      CgScal s{};
+      s.fresh = 1;
       s.maxit = maxit;
-      s.done = (s.vnorm == 0.0) ? 1 : 0;
-      s.conv = s.done;
-      sc[threadIdx.x] = s;
+      s.trust = trust;
+      sc0[threadIdx.x] = s;
     }
-    __syncthreads();
-    finish_all_done(sc, S, all_done);
-    if (threadIdx.x == 0) *cnt = 0u;
+    if (threadIdx.x == 0) *all_done = 0;
   }
 }
 
 template <typename Op, typename R>
-__global__ void __launch_bounds__(BS) k_cocg_A(Op op, c128 tau, long n, int S, const cx<R>* __restrict__ u,
-                                               const cx<R>* __restrict__ pold, cx<R>* __restrict__ pnew,
-                                               cx<R>* __restrict__ q, c128* __restrict__ part,
-                                               unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
-                                               const int* __restrict__ all_done) {
-  if (*all_done) return;
-  const long N = n * S;
+__global__ void __launch_bounds__(CGB) k_cg_step(Op op, const R* __restrict__ dK, c128 tau, long n, int S,
+                                                 double eps, const c128* __restrict__ partIn, int Gin,
+                                                 const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
+                                                 CgVecs<R> vec, c128* __restrict__ partOut,
+                                                 int* __restrict__ all_done) {
   const int rl = threadIdx.x & (S - 1);
-  const bool dn = sc[rl].done != 0;
-  const cx<R> beta = cvt<R>(sc[rl].beta);
-  const cx<R> tr = cvt<R>(tau);
-  cx<R> a0{0, 0};
-  if (!dn) {
-    auto g = [&](long cc) {
+  if (*all_done) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = scIn[threadIdx.x];
+    return;
+  }
+  c128 tot[3];
+  final_sum<3, CGB>(partIn, Gin, S, tot);
+  CgScal s = scIn[rl];
+  cg_advance(s, tot[0], tot[1], tot[2].re, eps);
+  if (s.done && s.conv && s.trust) s.verified = 1;
+  __shared__ int any_open;
+  if (threadIdx.x == 0) any_open = 0;
+  __syncthreads();
+  if ((int)threadIdx.x < S && !s.done) any_open = 1;
+  __syncthreads();
+  if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
+  if (!any_open) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *all_done = 1;
+    return;
+  }
+  const long N = n * S;
+  cx<R> ag{0, 0}, ad{0, 0};
+  R arr = 0;
+  if (!s.done) {
+    const int par = s.its & 1;
+    const cx<R>* __restrict__ r0 = vec.r[par];
+    const cx<R>* __restrict__ w0 = vec.w[par];
+    const cx<R>* __restrict__ s0 = vec.s[par];
+    cx<R>* __restrict__ r1 = vec.r[par ^ 1];
+    cx<R>* __restrict__ w1 = vec.w[par ^ 1];
+    cx<R>* __restrict__ s1 = vec.s[par ^ 1];
+    const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta), tr = cvt<R>(tau);
+    const c128 al64 = s.alpha;
+    // u' at any cell: (r - alpha (w + beta s_old)) / D
+    auto gu = [&](long cc) {
       const size_t k = (size_t)cc * S + rl;
-      return u[k] + beta * pold[k];
+      const cx<R> rn = r0[k] - al * (w0[k] + be * s0[k]);
+      return cdiv(rn, jdiag<Op, R>(op, dK, cc, tr));
     };
-    for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    for (long t = blockIdx.x * (long)CGB + threadIdx.x; t < N; t += (long)gridDim.x * CGB) {
       const long c = t / S;
-      const cx<R> pc = g(c);
-      const cx<R> qq = op.template apply<R>(c, tr, g);
-      pnew[t] = pc;
-      q[t] = qq;
-      a0 = a0 + pc * qq;
+      const cx<R> D = jdiag<Op, R>(op, dK, c, tr);
+      const cx<R> rc = r0[t];
+      const cx<R> sn = w0[t] + be * s0[t];
+      const cx<R> rn = rc - al * sn;
+      const cx<R> pn = cdiv(rc, D) + be * vec.p[t];
+      vec.p[t] = pn;
+      vec.x[t] = vec.x[t] + al64 * cvt<double>(pn);
+      const cx<R> un = cdiv(rn, D);
+      const cx<R> wn = op.template apply<R>(c, tr, gu);
+      r1[t] = rn;
+      w1[t] = wn;
+      s1[t] = sn;
+      ag = ag + rn * un;
+      ad = ad + wn * un;
+      arr += abs2(rn);
     }
   }
-  c128 acc[1] = {cvt<double>(a0)};
-  block_partials<1>(acc, S, part + (size_t)blockIdx.x * S);
-  if (arrive_last(cnt, gridDim.x)) {
-    c128 tot[1];
-    final_sum<1>(part, gridDim.x, S, tot);
-    if ((int)threadIdx.x < S) {
-      CocgScal& s = sc[threadIdx.x];
-      if (!s.done) {
-        if (tot[0].re == 0.0 && tot[0].im == 0.0) {
-          s.done = 1;   // p^T q = 0: COCG breakdown, keep the iterate
-          s.alpha = c128{0.0, 0.0};
-        } else {
-          s.alpha = cdiv(s.rho, tot[0]);
-        }
-      }
-    }
-    __syncthreads();
-    finish_all_done(sc, S, (int*)all_done);
-    if (threadIdx.x == 0) *cnt = 0u;
-  }
+  c128 acc[3] = {cvt<double>(ag), cvt<double>(ad), {(double)arr, 0.0}};
+  block_partials<3, CGB>(acc, S, partOut + (size_t)blockIdx.x * 3 * S);
 }
 
-template <typename Op, typename R>
-__global__ void __launch_bounds__(BS) k_cocg_B(Op op, c128 tau, long n, int S, double eps,
-                                               const cx<R>* __restrict__ p, const cx<R>* __restrict__ q,
-                                               cx<R>* __restrict__ x, cx<R>* __restrict__ r,
-                                               cx<R>* __restrict__ u, c128* __restrict__ part,
-                                               unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
-                                               int* __restrict__ all_done) {
-  if (*all_done) return;
+// Residual replacement, part 1: r = v - (K + tau M) x in FP64 from the FP64
+// iterate, stored rounded in the lane's current r buffer; partial ||r||^2 in
+// slot 2 of [G][3][S].
+template <typename OpD, typename R>
+__global__ void __launch_bounds__(BS) k_cg_replace_r(OpD opd, c128 tau, long n, int S, const cx<R>* __restrict__ v,
+                                                     const CgScal* __restrict__ sc, CgVecs<R> vec,
+                                                     c128* __restrict__ part) {
   const long N = n * S;
   const int rl = threadIdx.x & (S - 1);
-  const bool dn = sc[rl].done != 0;
-  const cx<R> alpha = cvt<R>(sc[rl].alpha);
-  cx<R> a0{0, 0};
-  R a1 = 0;
-  if (!dn) {
-    for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
-      const long c = t / S;
-      const cx<R> xn = x[t] + alpha * p[t];
-      const cx<R> rn = r[t] - alpha * q[t];
-      const cx<R> un = cdiv(rn, jacobi_diag<Op, R>(op, c, tau));
-      x[t] = xn;
-      r[t] = rn;
-      u[t] = un;
-      a0 = a0 + rn * un;
-      a1 += abs2(rn);
-    }
+  cx<R>* __restrict__ rr = vec.r[sc[rl].its & 1];
+  const c128* __restrict__ x = vec.x;
+  auto g = [&](long cc) { return x[cc * S + rl]; };
+  double a = 0.0;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    const c128 res = cvt<double>(v[t]) - opd.template apply<double>(c, tau, g);
+    rr[t] = cvt<R>(res);
+    a += abs2(res);
   }
-  c128 acc[2] = {cvt<double>(a0), {(double)a1, 0.0}};
-  block_partials<2>(acc, S, part + (size_t)blockIdx.x * 2 * S);
-  if (arrive_last(cnt, gridDim.x)) {
-    c128 tot[2];
-    final_sum<2>(part, gridDim.x, S, tot);
-    if ((int)threadIdx.x < S) {
-      CocgScal& s = sc[threadIdx.x];
-      if (!s.done) {
-        s.its += 1;
-        s.rnorm = sqrt(tot[1].re);
-        if (s.rnorm <= eps * s.vnorm) {
-          s.done = 1;
-          s.conv = 1;
-        } else if (s.its >= s.maxit || !(s.rnorm == s.rnorm)) {
-          s.done = 1;
-        } else if (s.rho.re == 0.0 && s.rho.im == 0.0) {
-          s.done = 1;
-        } else {
-          s.beta = cdiv(tot[0], s.rho);
-          s.rho = tot[0];
-        }
-      }
-    }
-    __syncthreads();
-    finish_all_done(sc, S, all_done);
-    if (threadIdx.x == 0) *cnt = 0u;
-  }
+  c128 acc[1] = {{a, 0.0}};
+  block_partials<1>(acc, S, part + (size_t)blockIdx.x * 3 * S + 2 * S);
 }
 
-// After the inner solve: true inner residual p = v - (K + tau M) z (its norm
-// enters the bound of eq. resdiff) and the mass product w = M z (Algorithm 3).
+// Residual replacement, part 2: w = A D^{-1} r in the lane's current w buffer;
+// partials r^T u, w^T u in slots 0, 1.  Lanes that converged without a
+// confirmed true residual are marked for evaluation by the next step.
 template <typename Op, typename R>
-__global__ void __launch_bounds__(BS) k_cocg_finish(Op op, c128 tau, long n, int S,
-                                                    const cx<R>* __restrict__ v, const cx<R>* __restrict__ z,
-                                                    cx<R>* __restrict__ w, c128* __restrict__ part,
-                                                    unsigned* __restrict__ cnt, CocgScal* __restrict__ sc,
-                                                    double* __restrict__ pn_out, double* __restrict__ mz_out) {
+__global__ void __launch_bounds__(BS) k_cg_replace_w(Op op, const R* __restrict__ dK, c128 tau, long n, int S,
+                                                     CgScal* __restrict__ sc, CgVecs<R> vec,
+                                                     c128* __restrict__ part, int* __restrict__ all_done) {
   const long N = n * S;
   const int rl = threadIdx.x & (S - 1);
+  const int par = sc[rl].its & 1;
+  const cx<R>* __restrict__ r0 = vec.r[par];
+  cx<R>* __restrict__ w0 = vec.w[par];
   const cx<R> tr = cvt<R>(tau);
+  auto gu = [&](long cc) { return cdiv(r0[cc * S + rl], jdiag<Op, R>(op, dK, cc, tr)); };
+  cx<R> ag{0, 0}, ad{0, 0};
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    const cx<R> uu = gu(c);
+    const cx<R> ww = op.template apply<R>(c, tr, gu);
+    w0[t] = ww;
+    ag = ag + r0[t] * uu;
+    ad = ad + ww * uu;
+  }
+  c128 acc[2] = {cvt<double>(ag), cvt<double>(ad)};
+  block_partials<2>(acc, S, part + (size_t)blockIdx.x * 3 * S);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if ((int)threadIdx.x < S && sc[threadIdx.x].conv && !sc[threadIdx.x].verified) sc[threadIdx.x].replaced = 1;
+    if (threadIdx.x == 0) *all_done = 0;
+  }
+}
+
+// After the inner solve: true inner residual p = v - (K + tau M) z in FP64
+// (its norm enters the bound of eq. resdiff) and the mass product w = M z
+// (Algorithm 3).  Partials [G][2][S]: ||p||^2, ||M z||^2.
+template <typename OpD, typename R>
+__global__ void __launch_bounds__(BS) k_cocg_finish(OpD opd, c128 tau, long n, int S,
+                                                    const cx<R>* __restrict__ v, const c128* __restrict__ z,
+                                                    cx<R>* __restrict__ w, c128* __restrict__ part) {
+  const long N = n * S;
+  const int rl = threadIdx.x & (S - 1);
   auto g = [&](long cc) { return z[cc * S + rl]; };
   double a0 = 0.0, a1 = 0.0;
   for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
     const long c = t / S;
-    const cx<R> az = op.template apply<R>(c, tr, g);
-    const cx<R> pv = v[t] - az;
-    const cx<R> zz = z[t];
-    const R m = (R)op.mass(c);
-    const cx<R> ww = m * zz;
-    if (w) w[t] = ww;
-    a0 += (double)abs2(pv);
-    a1 += (double)abs2(ww);
+    const c128 pv = cvt<double>(v[t]) - opd.template apply<double>(c, tau, g);
+    const c128 ww = opd.mass(c) * z[t];
+    if (w) w[t] = cvt<R>(ww);
+    a0 += abs2(pv);
+    a1 += abs2(ww);
   }
   c128 acc[2] = {{a0, 0.0}, {a1, 0.0}};
   block_partials<2>(acc, S, part + (size_t)blockIdx.x * 2 * S);
-  if (arrive_last(cnt, gridDim.x)) {
-    c128 tot[2];
-    final_sum<2>(part, gridDim.x, S, tot);
-    if ((int)threadIdx.x < S) {
-      sc[threadIdx.x].pnorm = sqrt(tot[0].re);
-      sc[threadIdx.x].mznorm = sqrt(tot[1].re);
-      if (pn_out) pn_out[threadIdx.x] = sqrt(tot[0].re);
-      if (mz_out) mz_out[threadIdx.x] = sqrt(tot[1].re);
-    }
-    if (threadIdx.x == 0) *cnt = 0u;
+}
+
+// Real diagonal of K from the operator (diagonal of the Jacobi preconditioner
+// D = diag(K) + tau diag(M)), in FP64 and FP32.
+template <typename OpD>
+__global__ void __launch_bounds__(BS) k_diag(OpD opd, long n, double* __restrict__ d64, float* __restrict__ d32) {
+  for (long c = blockIdx.x * (long)BS + threadIdx.x; c < n; c += (long)gridDim.x * BS) {
+    const double d = opd.diagK(c);
+    d64[c] = d;
+    d32[c] = (float)d;
   }
 }
 
@@ -440,15 +515,14 @@ __global__ void __launch_bounds__(BS) k_gs_reduce(const c128* __restrict__ part,
   }
 }
 
-// w -= sum_i h_i v_i for each item; optionally the FP64 norm ||w|| per lane,
-// written to hnorm_out[r] and to hcol_next[r] (the subdiagonal entry).
+// w -= sum_i h_i v_i for each item; optionally partials of the FP64 norm
+// ||w||^2 per lane (k_final_sqrt turns them into h_{k+1,k}).
 constexpr int GSQ = 4;
 template <typename R>
 __global__ void __launch_bounds__(BS) k_gs_update(long N, int S, int kc, const cx<R>* __restrict__ V,
                                                   size_t cstride, const c128* __restrict__ h,
                                                   cx<R>* __restrict__ w, int with_norm,
-                                                  c128* __restrict__ part, unsigned* __restrict__ cnt,
-                                                  double* __restrict__ hnorm_out, c128* __restrict__ hcol_next) {
+                                                  c128* __restrict__ part) {
   const int r = threadIdx.x & (S - 1);
   const long base = (long)blockIdx.x * BS * GSQ + threadIdx.x;
   cx<R> wq[GSQ];
@@ -478,16 +552,6 @@ __global__ void __launch_bounds__(BS) k_gs_update(long N, int S, int kc, const c
   if (!with_norm) return;
   c128 acc[1] = {{a, 0.0}};
   block_partials<1>(acc, S, part + (size_t)blockIdx.x * S);
-  if (arrive_last(cnt, gridDim.x)) {
-    c128 tot[1];
-    final_sum<1>(part, gridDim.x, S, tot);
-    if ((int)threadIdx.x < S) {
-      const double hn = sqrt(tot[0].re);
-      hnorm_out[threadIdx.x] = hn;
-      if (hcol_next) hcol_next[threadIdx.x] = c128{hn, 0.0};
-    }
-    if (threadIdx.x == 0) *cnt = 0u;
-  }
 }
 
 // v_{k+1} = w / h_{k+1,k}; lanes that broke down (h <= 1e-14 ||M z||, section
@@ -759,13 +823,17 @@ __global__ void __launch_bounds__(BS) k_finalize_active(int L, LaneState* __rest
   }
 }
 
-// Active lanes per rhs lane r (one thread per r).
-__global__ void k_count_active(int S, int nf, const LaneState* __restrict__ ls, int* __restrict__ out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= S) return;
-  int c = 0;
-  for (int j = 0; j < nf; ++j) c += ls[j * S + r].active;
-  out[r] = c;
+// Active lanes per rhs lane r (one block; LDS integer counts).
+__global__ void __launch_bounds__(BS) k_count_active(int S, int nf, const LaneState* __restrict__ ls,
+                                                     int* __restrict__ out) {
+  __shared__ int cnt[64];
+  if ((int)threadIdx.x < 64) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int L = nf * S;
+  for (int lane = threadIdx.x; lane < L; lane += BS)
+    if (ls[lane].active) atomicAdd(&cnt[lane % S], 1);
+  __syncthreads();
+  if ((int)threadIdx.x < S) out[threadIdx.x] = cnt[threadIdx.x];
 }
 
 // Per-lane multiplier of the assembly: lanes still active at the end of the

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -28,7 +29,7 @@ static int grid_items(long items, int cap) {
 
 // Blocks of the item kernels whose last block sums [G][2][S] partials: keep
 // G*S bounded so that final sum stays short.
-static int item_grid(long N, int S) { return grid_items(N, std::max(64, 32768 / S)); }
+
 
 static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -52,9 +53,40 @@ struct Pinned {
 };
 static thread_local Pinned g_pinned;
 
+// Inner-iteration kernel timing (shk_profile_*).
+struct KernelTimer {
+  bool on = false;
+  long long launches = 0;
+  double total_ms = 0.0, total_bytes = 0.0;
+  std::vector<hipEvent_t> ev;
+  void ensure(size_t pairs) {
+    while (ev.size() < 2 * pairs) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      ev.push_back(e);
+    }
+  }
+};
+static KernelTimer g_timer;
+
+int profile_enable(int on) {
+  g_timer.on = on != 0;
+  g_timer.launches = 0;
+  g_timer.total_ms = 0.0;
+  g_timer.total_bytes = 0.0;
+  return SHK_OK;
+}
+int profile_read(long long* launches, double* ms, double* bytes) {
+  if (launches) *launches = g_timer.launches;
+  if (ms) *ms = g_timer.total_ms;
+  if (bytes) *bytes = g_timer.total_bytes;
+  return SHK_OK;
+}
+
 // --------------------------------------------------------------- problem ---
 void problem_free(shk_problem* p, hipStream_t st) {
-  void* ptrs[] = {p->tx, p->ty, p->tz, p->tx32, p->ty32, p->tz32, p->rowptr, p->col, p->val, p->val32, p->diag, p->mdiag};
+  void* ptrs[] = {p->tx, p->ty, p->tz, p->tx32, p->ty32, p->tz32, p->rowptr, p->col, p->val, p->val32, p->diag, p->mdiag,
+                  p->dK, p->dK32};
   for (void* q : ptrs)
     if (q) (void)hipFreeAsync(q, st);
   (void)hipStreamSynchronize(st);
@@ -64,7 +96,7 @@ size_t problem_bytes(const shk_problem* p) {
   if (p->kind == Kind::CSR) return (size_t)p->nnz * 16 + (size_t)p->n * 24;
   const size_t faces = (size_t)(p->nx + 1) * p->ny * p->nz + (size_t)p->nx * (p->ny + 1) * p->nz +
                        (p->kind == Kind::FV3D ? (size_t)p->nx * p->ny * (p->nz + 1) : 0);
-  return faces * 12;
+  return faces * 12 + (size_t)p->n * 12;
 }
 
 int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipStream_t st) {
@@ -94,6 +126,17 @@ int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipSt
     k_faces<<<grid_items(cnt, 8192), BS, 0, st>>>(Kd, p->nx, p->ny, p->nz, a, scale, *T[a], *T32[a]);
     SHK_HIP(hipGetLastError());
   }
+  if (hipMallocAsync((void**)&p->dK, n * sizeof(double), st) != hipSuccess ||
+      hipMallocAsync((void**)&p->dK32, n * sizeof(float), st) != hipSuccess)
+    return fail(SHK_ERR_OOM, "diagonal arrays");
+  if (p->kind == Kind::FV3D) {
+    Op3D<double> od{p->nx, p->ny, p->nz, p->tx, p->ty, p->tz, nullptr, p->m0};
+    k_diag<<<grid_items(n, 8192), BS, 0, st>>>(od, n, p->dK, p->dK32);
+  } else {
+    Op2D<double> od{p->nx, p->ny, p->tx, p->ty, nullptr, p->m0};
+    k_diag<<<grid_items(n, 8192), BS, 0, st>>>(od, n, p->dK, p->dK32);
+  }
+  SHK_HIP(hipGetLastError());
   SHK_HIP(hipFreeAsync(Kd, st));
   SHK_HIP(hipStreamSynchronize(st));
   return SHK_OK;
@@ -126,12 +169,17 @@ int problem_setup_csr(shk_problem* p, const int* rowptr, const int* col, const d
   SHK_HIP(hipMallocAsync((void**)&p->val32, std::max<long>(nnz, 1) * sizeof(float), st));
   SHK_HIP(hipMallocAsync((void**)&p->diag, n * sizeof(double), st));
   SHK_HIP(hipMallocAsync((void**)&p->mdiag, n * sizeof(double), st));
+  SHK_HIP(hipMallocAsync((void**)&p->dK, n * sizeof(double), st));
+  SHK_HIP(hipMallocAsync((void**)&p->dK32, n * sizeof(float), st));
   SHK_HIP(hipMemcpyAsync(p->rowptr, rowptr, (n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
   SHK_HIP(hipMemcpyAsync(p->col, col, nnz * sizeof(int), hipMemcpyHostToDevice, st));
   SHK_HIP(hipMemcpyAsync(p->val, val, nnz * sizeof(double), hipMemcpyHostToDevice, st));
   SHK_HIP(hipMemcpyAsync(p->val32, v32.data(), nnz * sizeof(float), hipMemcpyHostToDevice, st));
   SHK_HIP(hipMemcpyAsync(p->diag, dg.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
   SHK_HIP(hipMemcpyAsync(p->mdiag, mdiag, n * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<float> dg32(dg.begin(), dg.end());
+  SHK_HIP(hipMemcpyAsync(p->dK, dg.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+  SHK_HIP(hipMemcpyAsync(p->dK32, dg32.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
   SHK_HIP(hipStreamSynchronize(st));
   return SHK_OK;
 }
@@ -140,23 +188,27 @@ template <typename F> static const F* pick(const double* a, const float* b);
 template <> const double* pick<double>(const double* a, const float*) { return a; }
 template <> const float* pick<float>(const double*, const float* b) { return b; }
 
-// Calls fn(op) with the operator of the problem in face precision F.
-template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&& fn) {
-  switch (p->kind) {
-    case Kind::FV2D: {
-      Op2D<F> op{p->nx, p->ny, pick<F>(p->tx, p->tx32), pick<F>(p->ty, p->ty32), nullptr, p->m0};
-      return fn(op);
-    }
-    case Kind::FV3D: {
-      Op3D<F> op{p->nx, p->ny, p->nz, pick<F>(p->tx, p->tx32), pick<F>(p->ty, p->ty32), pick<F>(p->tz, p->tz32),
+template <typename F> static Op2D<F> op2d(const shk_problem* p) {
+  return Op2D<F>{p->nx, p->ny, pick<F>(p->tx, p->tx32), pick<F>(p->ty, p->ty32), nullptr, p->m0};
+}
+template <typename F> static Op3D<F> op3d(const shk_problem* p) {
+  return Op3D<F>{p->nx, p->ny, p->nz, pick<F>(p->tx, p->tx32), pick<F>(p->ty, p->ty32), pick<F>(p->tz, p->tz32),
                  nullptr, p->m0};
-      return fn(op);
-    }
-    default: {
-      OpCSR<F> op{p->n, p->rowptr, p->col, pick<F>(p->val, p->val32), p->diag, p->mdiag, 0.0};
-      return fn(op);
-    }
+}
+template <typename F> static OpCSR<F> opcsr(const shk_problem* p) {
+  return OpCSR<F>{p->n, p->rowptr, p->col, pick<F>(p->val, p->val32), p->diag, p->mdiag, 0.0};
+}
+
+// Calls fn(op, opd): the operator with faces in precision F and in FP64.
+template <typename F, typename Fn> static int with_ops(const shk_problem* p, Fn&& fn) {
+  switch (p->kind) {
+    case Kind::FV2D: return fn(op2d<F>(p), op2d<double>(p));
+    case Kind::FV3D: return fn(op3d<F>(p), op3d<double>(p));
+    default: return fn(opcsr<F>(p), opcsr<double>(p));
   }
+}
+template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&& fn) {
+  return with_ops<F>(p, [&](auto op, auto) { return fn(op); });
 }
 
 // ----------------------------------------------------------- workspace -----
@@ -170,13 +222,26 @@ struct Carver {
   }
 };
 
+// Item-kernel grid and reduction mode.  Consumers sum the producer's block
+// partials themselves while that is cheap (few blocks x lanes); otherwise a
+// one-block-per-lane kernel folds them into totals first.
+struct Grid {
+  int G;          // blocks of the item kernels
+  bool separate;  // fold partials with k_lane_totals before consumers read them
+};
+static Grid item_plan(long N, int S) {
+  long G = (N + CGB - 1) / CGB;
+  G = std::max<long>(1, std::min<long>(G, 2048));
+  Grid g{(int)G, G * 3 * S > 3072};
+  return g;
+}
+
 template <typename R> struct Buffers {
-  cx<R>*V, *Z, *W, *r, *u, *P0, *P1, *q;
-  c128* part;
-  size_t part_elems;
-  CocgScal* sc;
+  cx<R>*V, *W, *cr[2], *cw[2], *cs[2], *cp;
+  c128* Z;                // flexible basis (FP64 on both paths)
+  c128 *cpart[2], *ctot[2], *part;
+  CgScal* sc;             // two buffers of S lanes
   int* all_done;
-  unsigned* cnt;
   double *beta0, *hn, *mz, *pn, *nzs;
   c128 *H, *h2, *taus, *sigma, *zs;
   int *seed, *nact;
@@ -190,10 +255,10 @@ template <typename R> struct Buffers {
 };
 
 static int resid_grid(long n) { return grid_items(n, 256); }
-static int dot_ipb(long N) {
+static long dot_ipb(long N) {
   long ipb = (N + 511) / 512;
   ipb = std::max<long>(1024, (ipb + 255) / 256 * 256);
-  return (int)ipb;
+  return ipb;
 }
 
 template <typename R>
@@ -203,22 +268,25 @@ static Buffers<R> carve(char* base, long n, int m, int nf, int S, int s_real, bo
   const long N = n * S;
   const int L = nf * S;
   b.V = cv.take<cx<R>>((size_t)(m + 1) * N);
-  b.Z = cv.take<cx<R>>((size_t)m * N);
+  b.Z = cv.take<c128>((size_t)m * N);
   b.W = cv.take<cx<R>>(N);
-  b.r = cv.take<cx<R>>(N);
-  b.u = cv.take<cx<R>>(N);
-  b.P0 = cv.take<cx<R>>(N);
-  b.P1 = cv.take<cx<R>>(N);
-  b.q = cv.take<cx<R>>(N);
-  const int G = item_grid(N, S);
+  for (int i = 0; i < 2; ++i) {
+    b.cr[i] = cv.take<cx<R>>(N);
+    b.cw[i] = cv.take<cx<R>>(N);
+    b.cs[i] = cv.take<cx<R>>(N);
+  }
+  b.cp = cv.take<cx<R>>(N);
+  const Grid gp = item_plan(N, S);
   const long ipb = dot_ipb(N);
   const long Gd = (N + ipb - 1) / ipb;
-  const int Gg = grid_items((N + GSQ - 1) / GSQ, 1 << 30);
-  b.part_elems = std::max<size_t>({(size_t)G * 2 * S, (size_t)Gd * (m + 1) * S, (size_t)Gg * S});
-  b.part = cv.take<c128>(b.part_elems);
-  b.sc = cv.take<CocgScal>(S);
+  const long Gu = (N + (long)BS * GSQ - 1) / ((long)BS * GSQ);
+  for (int i = 0; i < 2; ++i) {
+    b.cpart[i] = cv.take<c128>((size_t)gp.G * 3 * S);
+    b.ctot[i] = cv.take<c128>((size_t)3 * S);
+  }
+  b.part = cv.take<c128>(std::max<size_t>({(size_t)1024 * 2 * S, (size_t)Gd * (m + 1) * S, (size_t)Gu * S}));
+  b.sc = cv.take<CgScal>(2 * S);
   b.all_done = cv.take<int>(4);
-  b.cnt = cv.take<unsigned>(4);
   b.beta0 = cv.take<double>(S);
   b.hn = cv.take<double>(S);
   b.mz = cv.take<double>(S);
@@ -256,6 +324,21 @@ static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real
   return carve<double>(nullptr, p->n, m, nf, S, s_real, host_x).bytes;
 }
 
+// ------------------------------------------------------- lane totals -------
+// One block per lane: totals of NV partial sums over G blocks -> tot[q*S+r]
+// (the layout of a single block's partials, so consumers read it with G=1).
+template <int NV>
+__global__ void __launch_bounds__(BS) k_lane_totals(const c128* __restrict__ part, int G, int S,
+                                                    c128* __restrict__ tot) {
+  const int r = blockIdx.x;
+  for (int q = 0; q < NV; ++q) {
+    c128 a{0.0, 0.0};
+    for (int b = threadIdx.x; b < G; b += BS) a = a + part[((size_t)b * NV + q) * S + r];
+    a = block_sum_all(a);
+    if (threadIdx.x == 0) tot[q * S + r] = a;
+  }
+}
+
 // --------------------------------------------------------------- solver ----
 struct PassSpec {
   int m, max_restarts, inner_maxit;
@@ -264,50 +347,101 @@ struct PassSpec {
   long long kglob0;   // tau schedule position
 };
 
-template <typename R, typename Op> struct Group {
+struct Snap {
+  int all_done;
+  int pad[3];
+  CgScal sc[64];
+};
+
+template <typename R, typename Op, typename OpD> struct Group {
   shk_problem* p;
   Op op;
+  OpD opd;
   hipStream_t st;
   Buffers<R> B;
   long n, N;
-  int S, s_real, nf, m, G, L;
+  int S, s_real, nf, m, L;
+  Grid gp;
   long long inner_its = 0;
   int outer_steps = 0;
 
   // ---- inner solve of (K + tau M) z = v (section 4) into z, w = M z ----
-  int inner(c128 tau, const cx<R>* v, cx<R>* z, double eps, int maxit, int fixed, double* pn_out) {
-    k_cocg_init<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, fixed > 0 ? fixed : maxit, v, z, B.r, B.u, B.P0, B.part,
-                                          B.cnt, B.sc, B.all_done);
-    SHK_HIP(hipGetLastError());
+  int inner(c128 tau, const cx<R>* v, c128* z, double eps, int maxit, int fixed, double* pn_out) {
+    const int G = gp.G;
+    const bool replace = std::is_same<R, float>::value && fixed <= 0;
     const double e = fixed > 0 ? -1.0 : eps;
     const int cap = fixed > 0 ? fixed : maxit;
-    int it = 0;
-    int chunk = std::min(cap, 16);
-    struct Snap {
-      int all_done;
-      int pad[3];
-      CocgScal sc[64];
+    const R* dK = pick<R>(p->dK, p->dK32);
+    CgVecs<R> vec{{B.cr[0], B.cr[1]}, {B.cw[0], B.cw[1]}, {B.cs[0], B.cs[1]}, B.cp, z};
+    // partials of launch L live in cpart[L & 1] (totals in ctot[L & 1])
+    auto totals = [&](int slot) -> const c128* {
+      if (!gp.separate) return B.cpart[slot];
+      k_lane_totals<3><<<S, BS, 0, st>>>(B.cpart[slot], G, S, B.ctot[slot]);
+      return B.ctot[slot];
     };
+    const int Gin = gp.separate ? 1 : G;
+    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, dK, tau, n, S, cap, replace ? 0 : 1, v, vec, B.cpart[0], B.sc,
+                                        B.all_done);
+    const c128* in = totals(0);
+    SHK_HIP(hipGetLastError());
+    long it = 0;
+    int chunk = std::min(cap + 1, 16);
     static_assert(sizeof(Snap) <= 32768, "staging layout");
     Snap* snap = (Snap*)g_pinned.get(65536);
     if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
+    int replacements = 0;
+    const bool timing = g_timer.on;
+    int its_before = 0;
     while (true) {
+      if (timing) g_timer.ensure(chunk);
       for (int c = 0; c < chunk; ++c, ++it) {
-        cx<R>* pold = (it & 1) ? B.P1 : B.P0;
-        cx<R>* pnew = (it & 1) ? B.P0 : B.P1;
-        k_cocg_A<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, B.u, pold, pnew, B.q, B.part, B.cnt, B.sc, B.all_done);
-        k_cocg_B<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, e, pnew, B.q, z, B.r, B.u, B.part, B.cnt, B.sc,
-                                           B.all_done);
+        const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
+        CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
+        const int out = (int)((it + 1) & 1);
+        if (timing) (void)hipEventRecord(g_timer.ev[2 * c], st);
+        k_cg_step<Op, R><<<G, CGB, 0, st>>>(op, dK, tau, n, S, e, in, Gin, scIn, scOut, vec, B.cpart[out],
+                                             B.all_done);
+        if (timing) (void)hipEventRecord(g_timer.ev[2 * c + 1], st);
+        in = totals(out);
       }
       SHK_HIP(hipGetLastError());
       SHK_HIP(hipMemcpyAsync(&snap->all_done, B.all_done, sizeof(int), hipMemcpyDeviceToHost, st));
-      SHK_HIP(hipMemcpyAsync(snap->sc, B.sc, S * sizeof(CocgScal), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipMemcpyAsync(snap->sc, B.sc + (size_t)(it & 1) * S, S * sizeof(CgScal), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
-      if (snap->all_done || it >= cap) break;
+      if (timing) {
+        int its_now = 0;
+        for (int r = 0; r < S; ++r) its_now = std::max(its_now, snap->sc[r].its);
+        const int worked = std::min(chunk, its_now - its_before);
+        for (int c = 0; c < worked; ++c) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, g_timer.ev[2 * c], g_timer.ev[2 * c + 1]) == hipSuccess) {
+            g_timer.total_ms += ms;
+            g_timer.launches += 1;
+            g_timer.total_bytes += (double)n * S * step_bytes_per_cell();
+          }
+        }
+        its_before = its_now;
+      }
+      if (snap->all_done) {
+        bool unverified = false;
+        for (int r = 0; r < S; ++r) unverified |= snap->sc[r].conv && !snap->sc[r].verified;
+        if (!replace || !unverified || replacements >= 8) break;
+        // recompute r = v - A x in FP64 (and w = A D^-1 r); the next step judges it
+        CgScal* scCur = B.sc + (size_t)(it & 1) * S;
+        const int slot = (int)(it & 1);
+        k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, n, S, v, scCur, vec, B.cpart[slot]);
+        k_cg_replace_w<Op, R><<<G, BS, 0, st>>>(op, dK, tau, n, S, scCur, vec, B.cpart[slot], B.all_done);
+        in = totals(slot);
+        SHK_HIP(hipGetLastError());
+        ++replacements;
+        chunk = 8;
+        continue;
+      }
+      if (it > (long)cap + 64L * (replacements + 1)) break;   // lanes stop themselves at maxit
       // predict the remaining iterations from the mean convergence rate
       int need = 4;
       for (int r = 0; r < S; ++r) {
-        const CocgScal& s = snap->sc[r];
+        const CgScal& s = snap->sc[r];
         if (s.done || s.vnorm <= 0.0 || s.its <= 0) continue;
         const double rel = std::max(s.rnorm / s.vnorm, 1e-300);
         const double rate = std::log(rel) / s.its;
@@ -315,13 +449,14 @@ template <typename R, typename Op> struct Group {
         if (rate < 0.0 && e > 0.0) rem = (int)std::ceil((std::log(e) - std::log(rel)) / rate * 1.05) + 2;
         need = std::max(need, std::min(rem, 512));
       }
-      chunk = std::min(need, cap - it);
-      if (chunk <= 0) break;
+      chunk = need;
     }
     long long its_max = 0;
     for (int r = 0; r < S; ++r) its_max = std::max<long long>(its_max, snap->sc[r].its);
     inner_its += its_max;
-    k_cocg_finish<Op, R><<<G, BS, 0, st>>>(op, tau, n, S, v, z, B.W, B.part, B.cnt, B.sc, pn_out, B.mz);
+    const int Gf = grid_items(N, 1024);
+    k_cocg_finish<OpD, R><<<Gf, BS, 0, st>>>(opd, tau, n, S, v, z, B.W, B.part);
+    k_final_sqrt<2><<<1, BS, 0, st>>>(B.part, Gf, S, pn_out, B.mz, nullptr);
     SHK_HIP(hipGetLastError());
     return SHK_OK;
   }
@@ -337,12 +472,24 @@ template <typename R, typename Op> struct Group {
     for (int pass = 0; pass < 2; ++pass) {
       k_gs_dot<R><<<Gd, BS, 0, st>>>(N, S, kc, B.V, cs, w, B.part, ipb);
       k_gs_reduce<<<kc * S, BS, 0, st>>>(B.part, Gd, kc, S, Hk, B.h2, pass);
-      k_gs_update<R><<<Gu, BS, 0, st>>>(N, S, kc, B.V, cs, B.h2, w, pass, B.part, B.cnt, B.hn,
-                                        Hk + (size_t)(k + 1) * S);
+      k_gs_update<R><<<Gu, BS, 0, st>>>(N, S, kc, B.V, cs, B.h2, w, pass, B.part);
     }
-    k_scale_col<R><<<item_grid(N, S), BS, 0, st>>>(N, S, w, B.hn, B.mz, B.V + (size_t)(k + 1) * N);
+    k_final_sqrt<1><<<1, BS, 0, st>>>(B.part, Gu, S, B.hn, nullptr, Hk + (size_t)(k + 1) * S);
+    k_scale_col<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, w, B.hn, B.mz, B.V + (size_t)(k + 1) * N);
     SHK_HIP(hipGetLastError());
     return SHK_OK;
+  }
+
+  // Algorithmic bytes per cell and lane of one k_cg_step: r, w, s read and
+  // written (6 vectors), p read and written, x (FP64) read and written,
+  // diag(K) and the faces of the cell read once.
+  double step_bytes_per_cell() const {
+    const double wv = sizeof(cx<R>);
+    double faces;
+    if (p->kind == Kind::FV2D) faces = 2.0 * sizeof(R);
+    else if (p->kind == Kind::FV3D) faces = 3.0 * sizeof(R);
+    else faces = (double)p->nnz / (double)p->n * (sizeof(R) + sizeof(int));
+    return 8.0 * wv + 32.0 + (sizeof(R) + faces) / S;
   }
 
   GivensArgs gargs(int k, int cycle, int kglob, double tol) {
@@ -359,8 +506,8 @@ template <typename R, typename Op> struct Group {
     const int Lb = (L + BS - 1) / BS;
     k_asm_scale<<<Lb, BS, 0, st>>>(L, cycle, B.ls, extra, B.ascale);
     dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
-    k_assemble<R><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X,
-                                       accumulate ? 1 : 0);
+    k_assemble<double><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X,
+                                            accumulate ? 1 : 0);
     SHK_HIP(hipGetLastError());
     return SHK_OK;
   }
@@ -370,9 +517,10 @@ template <typename R, typename Op> struct Group {
   int pass(const c128* rhs, const PassSpec& ps, c128* X, bool accumulate, const c128* extra) {
     const int Lb = (L + BS - 1) / BS;
     SHK_HIP(hipMemsetAsync(B.Yb, 0, sizeof(c128) * (size_t)L * m, st));
-    SHK_HIP(hipMemsetAsync(B.cnt, 0, 4 * sizeof(unsigned), st));
-    k_norm2<double><<<item_grid(N, S), BS, 0, st>>>(rhs, N, S, B.part, B.cnt, B.beta0);
-    k_scale_conv<R><<<item_grid(N, S), BS, 0, st>>>(rhs, N, S, B.beta0, B.V);
+    const int Gn = grid_items(N, 1024);
+    k_norm2<double><<<Gn, BS, 0, st>>>(rhs, N, S, B.part);
+    k_final_sqrt<1><<<1, BS, 0, st>>>(B.part, Gn, S, B.beta0, nullptr, nullptr);
+    k_scale_conv<R><<<grid_items(N, 4096), BS, 0, st>>>(rhs, N, S, B.beta0, B.V);
     k_lanes_init<<<Lb, BS, 0, st>>>(L, S, s_real, B.beta0, B.ls, B.g);
     SHK_HIP(hipGetLastError());
     const std::vector<c128>& taus = *ps.taus;
@@ -393,7 +541,7 @@ template <typename R, typename Op> struct Group {
         SHK_TRY(orthogonalize(k, B.W));
         GivensArgs a = gargs(k, cycle, (int)(kglob - ps.kglob0), ps.tol);
         k_givens<<<Lb, BS, 0, st>>>(a);
-        k_count_active<<<1, 64, 0, st>>>(S, nf, B.ls, B.nact);
+        k_count_active<<<1, BS, 0, st>>>(S, nf, B.ls, B.nact);
         SHK_HIP(hipGetLastError());
         SHK_HIP(hipMemcpyAsync(nact, B.nact, S * sizeof(int), hipMemcpyDeviceToHost, st));
         SHK_HIP(hipStreamSynchronize(st));
@@ -421,8 +569,8 @@ template <typename R, typename Op> struct Group {
       SHK_HIP(hipGetLastError());
       SHK_TRY(assemble(m, cycle, extra, X, !first_write));
       first_write = false;
-      k_basis_combine<R><<<item_grid(N, S), BS, 0, st>>>(N, S, m + 1, B.V, (size_t)N, B.zs, B.W);
-      k_copy<R><<<item_grid(N, S), BS, 0, st>>>(B.W, N, B.V);
+      k_basis_combine<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, m + 1, B.V, (size_t)N, B.zs, B.W);
+      k_copy<R><<<grid_items(N, 4096), BS, 0, st>>>(B.W, N, B.V);
       SHK_HIP(hipGetLastError());
     }
     return SHK_OK;
@@ -457,7 +605,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     SHK_HIP(hipMemcpyAsync(B.rsv, b_src, sizeof(c128) * n * s_real, hipMemcpyHostToDevice, st));
     bdev = B.rsv;
   }
-  k_interleave<<<item_grid(N, S), BS, 0, st>>>(bdev, n, s_real, S, B.bint);
+  k_interleave<<<grid_items(N, 4096), BS, 0, st>>>(bdev, n, s_real, S, B.bint);
   SHK_HIP(hipMemcpyAsync(B.sigma, sigma_h, nf * sizeof(c128), hipMemcpyHostToDevice, st));
   SHK_HIP(hipGetLastError());
 
@@ -468,9 +616,10 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
   std::vector<LaneState> lanes(nf * S);
   std::vector<double> bnorm(S);
   long long inner_total = 0;
-  int rc = with_op<R>(p, [&](auto op) -> int {
+  int rc = with_ops<R>(p, [&](auto op, auto opd) -> int {
     using Op = decltype(op);
-    Group<R, Op> g{p, op, st, B, n, N, S, s_real, nf, m, item_grid(N, S), nf * S};
+    using OpD = decltype(opd);
+    Group<R, Op, OpD> g{p, op, opd, st, B, n, N, S, s_real, nf, m, nf * S, item_plan(N, S)};
     PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0};
     SHK_TRY(g.pass(B.bint, ps, X, false, nullptr));
     SHK_HIP(hipMemcpyAsync(lanes.data(), B.ls, sizeof(LaneState) * nf * S, hipMemcpyDeviceToHost, st));
@@ -483,17 +632,15 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     std::vector<int> seeds(S);
     int sweeps = 0;
     auto measure = [&]() -> int {
-      return with_op<double>(p, [&](auto opd) -> int {
-        SHK_TRY(residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, nullptr, 0, B.rpart, B.rrow, st));
-        SHK_HIP(hipMemcpyAsync(rows.data(), B.rrow, sizeof(c128) * rows.size(), hipMemcpyDeviceToHost, st));
-        SHK_HIP(hipStreamSynchronize(st));
-        for (int r = 0; r < s_real; ++r)
-          for (int j = 0; j < nf; ++j) {
-            const double nb = bnorm[r];
-            rel[r * nf + j] = nb > 0.0 ? std::sqrt(rows[r * nf + j].re) / nb : std::sqrt(rows[r * nf + j].re);
-          }
-        return SHK_OK;
-      });
+      SHK_TRY(residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, nullptr, 0, B.rpart, B.rrow, st));
+      SHK_HIP(hipMemcpyAsync(rows.data(), B.rrow, sizeof(c128) * rows.size(), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipStreamSynchronize(st));
+      for (int r = 0; r < s_real; ++r)
+        for (int j = 0; j < nf; ++j) {
+          const double nb = bnorm[r];
+          rel[r * nf + j] = nb > 0.0 ? std::sqrt(rows[r * nf + j].re) / nb : std::sqrt(rows[r * nf + j].re);
+        }
+      return SHK_OK;
     };
     SHK_TRY(measure());
     for (; sweeps < prm->max_refine; ++sweeps) {
@@ -502,23 +649,20 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
         seeds[r] = -1;
         if (r >= s_real) continue;
         double best = -1.0;
+        bool bad_r = false;
         for (int j = 0; j < nf; ++j) {
           const double v = rel[r * nf + j];
-          if (v > prm->tol && std::isfinite(v)) any_bad = true;
+          if (v > prm->tol && std::isfinite(v)) bad_r = true;
           if (v > best) { best = v; seeds[r] = j; }
         }
-        bool bad_r = false;
-        for (int j = 0; j < nf; ++j) bad_r |= rel[r * nf + j] > prm->tol && std::isfinite(rel[r * nf + j]);
+        any_bad |= bad_r;
         if (!bad_r) seeds[r] = -1;
       }
       if (!any_bad) break;
       SHK_HIP(hipMemcpyAsync(B.seed, seeds.data(), sizeof(int) * S, hipMemcpyHostToDevice, st));
-      SHK_TRY(with_op<double>(p, [&](auto opd) -> int {
-        k_resid_vec<decltype(opd)><<<item_grid(N, S), BS, 0, st>>>(opd, n, S, s_real, nf, B.sigma, B.seed, B.bint, X,
-                                                                  B.rsv);
-        SHK_HIP(hipGetLastError());
-        return residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, B.rsv, 1, B.rpart, B.rrow, st);
-      }));
+      k_resid_vec<OpD><<<grid_items(N, 4096), BS, 0, st>>>(opd, n, S, s_real, nf, B.sigma, B.seed, B.bint, X, B.rsv);
+      SHK_HIP(hipGetLastError());
+      SHK_TRY(residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, B.rsv, 1, B.rpart, B.rrow, st));
       SHK_HIP(hipMemcpyAsync(rows.data(), B.rrow, sizeof(c128) * rows.size(), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
       for (int r = 0; r < S; ++r)
@@ -536,7 +680,6 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
       SHK_TRY(measure());
     }
     inner_total = g.inner_its;
-    (void)sweeps;
     for (int r = 0; r < s_real; ++r)
       for (int j = 0; j < nf; ++j) {
         const LaneState& ls = lanes[j * S + r];
@@ -632,7 +775,7 @@ int step_apply(shk_problem* p, c128 sigma, int S, const void* x, void* y, int pr
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
     return with_op<R>(p, [&](auto op) -> int {
-      k_apply<decltype(op), R><<<item_grid(N, S), BS, 0, st>>>(op, sigma, p->n, S, (const cx<R>*)x, (cx<R>*)y);
+      k_apply<decltype(op), R><<<grid_items(N, 4096), BS, 0, st>>>(op, sigma, p->n, S, (const cx<R>*)x, (cx<R>*)y);
       SHK_HIP(hipGetLastError());
       SHK_HIP(hipStreamSynchronize(st));
       return SHK_OK;
@@ -648,14 +791,19 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
     const long N = p->n * S;
-    Carver cv{nullptr};
+    const Grid gp = item_plan(N, S);
     auto lay = [&](Carver& c, Buffers<R>& b) {
-      b.W = c.take<cx<R>>(N); b.r = c.take<cx<R>>(N); b.u = c.take<cx<R>>(N);
-      b.P0 = c.take<cx<R>>(N); b.P1 = c.take<cx<R>>(N); b.q = c.take<cx<R>>(N);
-      b.part = c.take<c128>((size_t)item_grid(N, S) * 2 * S);
-      b.sc = c.take<CocgScal>(S); b.all_done = c.take<int>(4); b.cnt = c.take<unsigned>(4);
+      b.W = c.take<cx<R>>(N);
+      for (int i = 0; i < 2; ++i) {
+        b.cr[i] = c.take<cx<R>>(N); b.cw[i] = c.take<cx<R>>(N); b.cs[i] = c.take<cx<R>>(N);
+        b.cpart[i] = c.take<c128>((size_t)gp.G * 3 * S); b.ctot[i] = c.take<c128>((size_t)3 * S);
+      }
+      b.cp = c.take<cx<R>>(N);
+      b.part = c.take<c128>((size_t)grid_items(N, 1024) * 2 * S);
+      b.sc = c.take<CgScal>(2 * S); b.all_done = c.take<int>(4);
       b.mz = c.take<double>(S); b.pn = c.take<double>(S);
     };
+    Carver cv{nullptr};
     Buffers<R> b0{};
     lay(cv, b0);
     DevBuf mem;
@@ -664,20 +812,22 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
     Carver c2{(char*)mem.p};
     Buffers<R> b{};
     lay(c2, b);
-    return with_op<R>(p, [&](auto op) -> int {
+    return with_ops<R>(p, [&](auto op, auto opd) -> int {
       using Op = decltype(op);
-      Group<R, Op> g{p, op, st, b, p->n, N, S, S, 1, 1, item_grid(N, S), S};
-      SHK_TRY(g.inner(tau, (const cx<R>*)v, (cx<R>*)z, eps, maxit, fixed_iters, b.pn));
+      using OpD = decltype(opd);
+      Group<R, Op, OpD> g{p, op, opd, st, b, p->n, N, S, S, 1, 1, S, gp};
+      SHK_TRY(g.inner(tau, (const cx<R>*)v, (c128*)z, eps, maxit, fixed_iters, b.pn));
       if (w) {
-        k_copy<R><<<item_grid(N, S), BS, 0, st>>>(b.W, N, (cx<R>*)w);
+        k_copy<R><<<grid_items(N, 4096), BS, 0, st>>>(b.W, N, (cx<R>*)w);
         SHK_HIP(hipGetLastError());
       }
-      std::vector<CocgScal> sc(S);
-      SHK_HIP(hipMemcpyAsync(sc.data(), b.sc, sizeof(CocgScal) * S, hipMemcpyDeviceToHost, st));
+      Snap* snap = (Snap*)g_pinned.get(65536);
+      std::vector<double> pn(S);
+      SHK_HIP(hipMemcpyAsync(pn.data(), b.pn, sizeof(double) * S, hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
       for (int r = 0; r < S; ++r) {
-        if (its) its[r] = sc[r].its;
-        if (pnorm) pnorm[r] = sc[r].pnorm;
+        if (its) its[r] = snap->sc[r].its;
+        if (pnorm) pnorm[r] = pn[r];
       }
       return SHK_OK;
     });
@@ -693,12 +843,12 @@ int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precisio
     const long ipb = dot_ipb(N);
     const long Gd = (N + ipb - 1) / ipb;
     const long Gu = (N + (long)BS * GSQ - 1) / ((long)BS * GSQ);
-    Carver cv{nullptr};
     auto lay = [&](Carver& c, Buffers<R>& b) {
       b.part = c.take<c128>(std::max<size_t>((size_t)Gd * (k + 1) * S, (size_t)Gu * S));
       b.H = c.take<c128>((size_t)(k + 2) * S); b.h2 = c.take<c128>((size_t)(k + 1) * S);
-      b.hn = c.take<double>(S); b.mz = c.take<double>(S); b.cnt = c.take<unsigned>(4);
+      b.hn = c.take<double>(S); b.mz = c.take<double>(S);
     };
+    Carver cv{nullptr};
     Buffers<R> b0{};
     lay(cv, b0);
     DevBuf mem;
@@ -707,17 +857,17 @@ int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precisio
     Carver c2{(char*)mem.p};
     Buffers<R> b{};
     lay(c2, b);
-    std::vector<double> ones(S, 1e-300);
-    SHK_HIP(hipMemcpyAsync(b.mz, ones.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
-    b.V = (cx<R>*)V;
+    std::vector<double> tiny(S, 1e-300);
+    SHK_HIP(hipMemcpyAsync(b.mz, tiny.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+    cx<R>* Vp = (cx<R>*)V;
     const int kc = k;
     for (int pass = 0; pass < 2; ++pass) {
-      k_gs_dot<R><<<(int)Gd, BS, 0, st>>>(N, S, kc, b.V, (size_t)N, (const cx<R>*)w, b.part, ipb);
+      k_gs_dot<R><<<(int)Gd, BS, 0, st>>>(N, S, kc, Vp, (size_t)N, (const cx<R>*)w, b.part, ipb);
       k_gs_reduce<<<kc * S, BS, 0, st>>>(b.part, (int)Gd, kc, S, b.H, b.h2, pass);
-      k_gs_update<R><<<(int)Gu, BS, 0, st>>>(N, S, kc, b.V, (size_t)N, b.h2, (cx<R>*)w, pass, b.part, b.cnt, b.hn,
-                                              b.H + (size_t)kc * S);
+      k_gs_update<R><<<(int)Gu, BS, 0, st>>>(N, S, kc, Vp, (size_t)N, b.h2, (cx<R>*)w, pass, b.part);
     }
-    k_scale_col<R><<<item_grid(N, S), BS, 0, st>>>(N, S, (const cx<R>*)w, b.hn, b.mz, b.V + (size_t)kc * N);
+    k_final_sqrt<1><<<1, BS, 0, st>>>(b.part, (int)Gu, S, b.hn, nullptr, b.H + (size_t)kc * S);
+    k_scale_col<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, (const cx<R>*)w, b.hn, b.mz, Vp + (size_t)kc * N);
     SHK_HIP(hipGetLastError());
     std::vector<c128> hh((size_t)(k + 1) * S);
     SHK_HIP(hipMemcpyAsync(hh.data(), b.H, sizeof(c128) * (k + 1) * S, hipMemcpyDeviceToHost, st));
@@ -804,23 +954,20 @@ int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b,
   if (!p || !sigma || !b || !x || !relres || nf < 1) return fail(SHK_ERR_INVALID_ARG, "residual arguments");
   const long n = p->n;
   const int Gr = resid_grid(n);
+  const int Gn = grid_items(n, 1024);
   DevBuf mem;
-  const size_t bytes = align_up(sizeof(c128) * nf) + align_up(sizeof(c128) * (size_t)nf * Gr) + align_up(sizeof(c128) * nf) +
-                       align_up(sizeof(c128) * 2) + align_up(sizeof(double) * 2);
-  SHK_HIP(hipMalloc(&mem.p, bytes));
+  Carver cv{nullptr};
+  cv.take<c128>(nf); cv.take<c128>((size_t)nf * Gr); cv.take<c128>(nf); cv.take<c128>(Gn); cv.take<double>(2);
+  SHK_HIP(hipMalloc(&mem.p, cv.off));
   Carver c{(char*)mem.p};
   c128* sg = c.take<c128>(nf);
   c128* part = c.take<c128>((size_t)nf * Gr);
   c128* rows = c.take<c128>(nf);
-  c128* nb = c.take<c128>(2);
+  c128* npart = c.take<c128>(Gn);
   double* nbd = c.take<double>(2);
   SHK_HIP(hipMemcpyAsync(sg, sigma, sizeof(c128) * nf, hipMemcpyHostToDevice, st));
-  DevBuf np;
-  SHK_HIP(hipMalloc(&np.p, sizeof(c128) * 64 + 256));
-  unsigned* cnt = (unsigned*)((char*)np.p + sizeof(c128) * 64);
-  SHK_HIP(hipMemsetAsync(cnt, 0, 16, st));
-  k_norm2<double><<<item_grid(n, 1), BS, 0, st>>>(b, n, 1, (c128*)np.p, cnt, nbd);
-  (void)nb;
+  k_norm2<double><<<Gn, BS, 0, st>>>(b, n, 1, npart);
+  k_final_sqrt<1><<<1, BS, 0, st>>>(npart, Gn, 1, nbd, nullptr, nullptr);
   SHK_TRY(with_op<double>(p, [&](auto opd) -> int {
     return residual_rows(opd, n, 1, 1, nf, sg, b, x, nullptr, 0, part, rows, st);
   }));

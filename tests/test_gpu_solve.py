@@ -135,10 +135,14 @@ def test_multi_rhs_lockstep_matches_single_and_reciprocity():
     for r in range(3):
         xr, _ = P.fgmres_sh_solve(gp, prm, sig, B[:, r])
         assert np.allclose(X[:, :, r], xr[:, :, 0], rtol=1e-7, atol=1e-7 * np.abs(xr).max())
-    # reciprocity of the complex-symmetric operator: x_a[cell_b] = x_b[cell_a]
+    # reciprocity of the complex-symmetric operator: x_a[cell_b] = x_b[cell_a].
+    # Each entry carries an error <= ||A_j^-1|| ||r|| <= tol ||b|| / (omega_j Ss)
+    # (K is positive semidefinite and sigma M = i omega Ss I, so
+    # |z^H A_j z| >= omega_j Ss ||z||^2); two solves enter each comparison.
+    bound = 2 * 1e-10 / (np.abs(sig.imag) * 1e-5)
     for a in range(3):
         for bb in range(3):
-            assert np.allclose(X[cells[bb], :, a], X[cells[a], :, bb], rtol=1e-7)
+            assert np.all(np.abs(X[cells[bb], :, a] - X[cells[a], :, bb]) <= bound)
 
 
 def test_mixed_precision_with_refinement():

@@ -110,12 +110,16 @@ def test_inner_cocg_converged_counts_and_residual():
             assert ok and abs(int(its[r]) - oits) <= 1
             true = np.linalg.norm(V[:, r] - op.apply(tau, Z[:, r]))
             assert true <= 1.5 * eps and np.isclose(pn[r], true, rtol=1e-6)
-    # complex64 path: converges to a looser tolerance
-    z = torch.zeros(op.n * S, dtype=torch.complex64, device="cuda")
-    its, pn = P.shk_inner_solve(gp, tau, to_dev(V.ravel(), "c64"), z, eps=1e-5, n_rhs=S)
-    Z = z.cpu().numpy().astype(np.complex128).reshape(op.n, S)
-    for r in range(S):
-        assert np.linalg.norm(V[:, r] - op.apply(tau, Z[:, r])) <= 5e-5
+    # complex64 path: the FP64 iterate with residual replacement meets the
+    # tolerance in the true (FP64) residual of the complex64-rounded v
+    V32 = V.astype(np.complex64).astype(np.complex128)
+    for eps in (1e-6, 1e-9):
+        z = torch.zeros(op.n * S, dtype=torch.complex128, device="cuda")
+        its, pn = P.shk_inner_solve(gp, tau, to_dev(V.ravel(), "c64"), z, eps=eps, n_rhs=S)
+        Z = z.cpu().numpy().reshape(op.n, S)
+        for r in range(S):
+            true = np.linalg.norm(V32[:, r] - op.apply(tau, Z[:, r]))
+            assert true <= eps * np.linalg.norm(V32[:, r]) * 1.01 and np.isclose(pn[r], true, rtol=1e-6)
 
 
 @pytest.mark.parametrize("n,k,S", [(4096, 1, 1), (10000, 7, 1), (262144, 30, 1), (5000, 12, 4)])
@@ -165,7 +169,7 @@ def test_shifted_lsq_matches_oracle_least_squares():
         for kk in range(1, k + 1):
             Hs = shifted_hessenberg(H[:kk + 1, :kk], taus[:kk], s)
             yo, qv = small_solve(Hs, beta, "gmres")
-            assert np.isclose(rho[kk - 1, j], np.linalg.norm(qv), rtol=1e-8, atol=1e-15 * beta)
+            assert np.isclose(rho[kk - 1, j], np.linalg.norm(qv), rtol=1e-8, atol=1e-13 * beta)
         Hs = shifted_hessenberg(H, taus, s)
         yo, _ = small_solve(Hs, beta, "gmres")
         assert np.allclose(y[j], yo, rtol=1e-8, atol=1e-9 * np.abs(yo).max())

@@ -1,0 +1,122 @@
+"""GPU parity at the workloads' real shapes and on the other operator kinds.
+
+Error bounds used here follow from the operator: K is positive semidefinite
+and sigma M = i omega Ss h^d I, so |z^H (K + sigma M) z| >= omega Ss h^d ||z||^2
+and ||(K + sigma M)^{-1}|| <= 1 / (omega Ss h^d).  A solution with relative
+residual rho therefore satisfies ||x - x*|| <= rho ||b|| / (omega Ss h^d),
+which bounds every entry as well.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Problem as OProblem, superlu_solve, exact_family
+from tests.gpu_util import require_gpu, announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _bound(sig, rho, nb, Ss=1e-5, h=1.0, d=2):
+    return rho * nb / (np.abs(sig.imag) * Ss * h ** d)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_512x512_all_shifts_and_sampled_exact(precision):
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"512x512 200 shifts {precision}")
+    w = synth.config2()
+    gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+    prec = P.SHK_FP64 if precision == "fp64" else P.SHK_MIXED
+    prm, keep = P.make_params(w.tau_seq, m_restart=50, max_restarts=20, max_refine=4, tol=1e-6, eps_inner=1e-6,
+                              precision=prec)
+    b = torch.from_numpy(w.b[:, 0]).cuda()[None, :].contiguous()
+    x, st = P.fgmres_sh_solve(gp, prm, w.sigma, b)
+    assert np.all(st["true_relres"] <= 1e-6), st["true_relres"].max()
+    assert np.all(st["status"] == P.SHK_CONVERGED)
+    op = OProblem.fv(w.cell_K, w.Ss, w.h)
+    for j in (0, 120, 199):
+        xe = superlu_solve(op.shifted(w.sigma[j]), w.b[:, 0])
+        xg = x[0, j].cpu().numpy()
+        bound = _bound(w.sigma[j], st[0, j]["true_relres"], 1.0)
+        assert np.max(np.abs(xg - xe)) <= bound
+        assert np.linalg.norm(xg - xe) <= bound
+
+
+def test_3d_solve_against_superlu():
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce("3d 20x18x16")
+    K = synth.cell_conductivity((16, 18, 20), -11.5, 1.5, 5, cfg=75)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv3d(K)
+    sig = synth.shifts_from_periods(synth.periods(6, 10, 1000))
+    src = synth.distinct_interior_cells((16, 18, 20), 2, 75, synth.P_WELLS)
+    B = np.zeros((op.n, 2), complex)
+    for r, c in enumerate(src):
+        B[c, r] = 1.0
+    for prec, tol, eps in ((P.SHK_FP64, 1e-9, 1e-11), (P.SHK_MIXED, 1e-6, 1e-6)):
+        prm, keep = P.make_params(sig[[1, 4]], tol=tol, eps_inner=eps, m_restart=40, precision=prec, max_refine=4)
+        X, st = P.fgmres_sh_solve(gp, prm, sig, B)
+        assert np.all(st["true_relres"] <= tol)
+        for r in range(2):
+            for j in (0, 5):
+                xe = superlu_solve(op.shifted(sig[j]), B[:, r])
+                assert np.linalg.norm(X[:, j, r] - xe) <= _bound(sig[j], st[r, j]["true_relres"], 1.0)
+
+
+def test_csr_problem_solve():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("csr 2d 30x25")
+    K = synth.cell_conductivity((25, 30), -11.5, 1.0, 5, cfg=76)
+    op = OProblem.fv(K)
+    A = op.K.tocsr()
+    gp = P.Problem.csr(A.indptr, A.indices, A.data, op.Mdiag)
+    sig = synth.shifts_from_periods(synth.periods(5, 10, 1000))
+    b = synth.unit_vector(op.n, 377)
+    prm, keep = P.make_params(sig[[1, 3]], tol=1e-9, eps_inner=1e-11, m_restart=50)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    xe = exact_family(op, sig, b, "superlu")
+    for j in range(len(sig)):
+        assert st[0, j]["true_relres"] <= 1e-9
+        assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= _bound(sig[j], st[0, j]["true_relres"], 1.0)
+
+
+def test_server_alone_vs_mix():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("server alone vs mix")
+    reqs = [synth.Request(i, 0.0, g, 1000 + i, nf, nr)
+            for i, (g, nf, nr) in enumerate([(48, 7, 2), (64, 12, 1), (32, 5, 3), (48, 9, 4), (40, 6, 1)])]
+    works = [synth.request_workload(r) for r in reqs]
+    params = [P.make_params(w.tau_seq, m_restart=40, tol=1e-6, eps_inner=1e-6, precision=P.SHK_MIXED, max_refine=4)
+              for w in works]
+    alone = []
+    for w, (prm, keep) in zip(works, params):
+        gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+        alone.append(P.fgmres_sh_solve(gp, prm, w.sigma, w.b))
+        gp.close()
+    srv = P.Server(mem_budget_bytes=8 << 30, max_slots=3)
+    tickets = [srv.submit(w.cell_K, w.sigma, w.b, prm, keep_solution=True) for w, (prm, keep) in zip(works, params)]
+    srv.drain()
+    for t, (xa, sa), w in zip(tickets, alone, works):
+        res, x, st = srv.poll(t, want_solution=True)
+        assert res["error"] == 0 and res["done"] == 1
+        assert res["n_converged"] == len(w.sigma) * w.b.shape[1]
+        assert np.all(st["true_relres"] <= 1e-6)
+        assert np.allclose(x, xa, rtol=1e-12, atol=1e-12 * np.abs(xa).max())
+        assert res["t_arrival"] <= res["t_start"] <= res["t_done"]
+    srv.close()
+
+
+def test_server_rejects_oversized_request():
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("server rejection")
+    w = synth.request_workload(synth.Request(0, 0.0, 64, 7, 10, 2))
+    prm, keep = P.make_params(w.tau_seq, tol=1e-6, eps_inner=1e-6)
+    srv = P.Server(mem_budget_bytes=1 << 20, max_slots=1)
+    with pytest.raises(P.ShkError):
+        srv.submit(w.cell_K, w.sigma, w.b, prm)
+    srv.close()

@@ -130,6 +130,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--grid", type=int, default=512)
+    ap.add_argument("--single-solve", choices=["mixed", "fp64"], default=None,
+                    help="run one solve of the workload and exit (for profiler counter passes)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy MIB mebibytes device-to-device with a plain copy kernel and exit "
+                         "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the solver's per-GPU share is a whole "
@@ -139,8 +144,22 @@ def main():
     import paper_1212_3660_amd as P
     import synth
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        src = torch.ones(a.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return
     w = synth.config2(n_grid=a.grid)
     gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+    if a.single_solve:
+        prec = P.SHK_MIXED if a.single_solve == "mixed" else P.SHK_FP64
+        r = time_path(P, torch, gp, w, prec, 1, 0, profile=False)
+        print(json.dumps({"single_solve": a.single_solve, "ms": r["total_ms"], "inner_iterations": r["inner"],
+                          "converged": r["ok"]}), flush=True)
+        return
     mixed = time_path(P, torch, gp, w, P.SHK_MIXED, a.steps, a.warmup, profile=False)
     fp64 = time_path(P, torch, gp, w, P.SHK_FP64, a.steps, a.warmup, profile=False)
     prof_run = time_path(P, torch, gp, w, P.SHK_MIXED, 1, 0, profile=True)

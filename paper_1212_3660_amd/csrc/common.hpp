@@ -38,6 +38,23 @@ template <typename To, typename From> __host__ __device__ __forceinline__ cx<To>
   return {static_cast<To>(a.re), static_cast<To>(a.im)};
 }
 
+// Streaming store of a complex value (non-temporal hint: written through
+// rather than kept dirty in L2 until the end of the kernel).
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_nt(cx<double>* p, cx<double> v) {
+  d2v t = {v.re, v.im};
+  __builtin_nontemporal_store(t, reinterpret_cast<d2v*>(p));
+}
+__device__ __forceinline__ void st_nt(cx<float>* p, cx<float> v) {
+  f2v t = {v.re, v.im};
+  __builtin_nontemporal_store(t, reinterpret_cast<f2v*>(p));
+}
+template <bool NT, typename R> __device__ __forceinline__ void st(cx<R>* p, cx<R> v) {
+  if constexpr (NT) st_nt(p, v);
+  else *p = v;
+}
+
 // ----------------------------------------------------------- wave / block ---
 constexpr int WAVE = 64;
 

@@ -21,7 +21,25 @@ namespace shk {
 constexpr int BS = 256;
 constexpr int NWAVE = BS / WAVE;
 
+// XCD-aware block order: gfx950 dispatches consecutive workgroups round-robin
+// over its 8 XCDs, each with its own L2.  Mapping block b to tile
+// (b % 8) * (G / 8) + b / 8 gives every XCD a contiguous band of tiles, so the
+// stencil's halo rows are mostly read from the XCD's own L2.  Identity when G
+// is not a multiple of 8.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  if (G & 7) return b;
+  return (b & 7) * (G >> 3) + (b >> 3);
+}
+
 // ------------------------------------------------------------ reductions ---
+// Workgroup barrier that orders LDS only: outstanding global loads stay in
+// flight across it (a full __syncthreads would wait for them).
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Block partial per lane: wave tree over lanes of equal r, then the waves in
 // order.  Writes out[q*S + r] for r < S.
 template <int NV, int BSZ = BS>
@@ -35,7 +53,7 @@ __device__ __forceinline__ void block_partials(c128 (&v)[NV], int S, c128* __res
 #pragma unroll
     for (int q = 0; q < NV; ++q) sh[wv][q][lane] = v[q];
   }
-  __syncthreads();
+  lds_sync();
   if ((int)threadIdx.x < S) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -44,7 +62,7 @@ __device__ __forceinline__ void block_partials(c128 (&v)[NV], int S, c128* __res
       out[q * S + threadIdx.x] = a;
     }
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // Sum partials laid out [block][NV][S] over G blocks in a fixed order (strided
@@ -69,14 +87,14 @@ __device__ __forceinline__ void final_sum(const c128* __restrict__ part, int G, 
 #pragma unroll
     for (int q = 0; q < NV; ++q) sh[wv][q][lane] = acc[q];
   }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     c128 a = sh[0][q][r];
     for (int w = 1; w < NW; ++w) a = a + sh[w][q][r];
     res[q] = a;
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // Block-wide sum of one complex value (all threads one lane), fixed order.
@@ -84,10 +102,10 @@ __device__ __forceinline__ c128 block_sum_all(c128 v) {
   __shared__ c128 sh[NWAVE];
   v = wave_sum_strided(v, 1);
   if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = v;
-  __syncthreads();
+  lds_sync();
   c128 a = sh[0];
   for (int w = 1; w < NWAVE; ++w) a = a + sh[w];
-  __syncthreads();
+  lds_sync();
   return a;
 }
 
@@ -215,39 +233,54 @@ __global__ void __launch_bounds__(BS) k_apply(Op op, c128 sigma, long n, int S, 
 // true residual.
 struct CgScal {
   c128 gamma, alpha, beta;
-  double vnorm, rnorm;
+  double vnorm, rnorm, rstop;
   int its, done, conv, maxit;
   int fresh, replaced, verified, trust;  // trust: accept the recurrence residual (FP64 path)
+  double round_tol;
 };
 
-constexpr int CGB = 1024;   // block size of the iteration kernel
 
 __device__ __forceinline__ bool is_zero(c128 a) { return a.re == 0.0 && a.im == 0.0; }
 
 // Lane state transition from the totals gamma' (tg), delta' (td), ||r'||^2.
+// On the complex64 path the solve runs in rounds: each round iterates until
+// its recurrence residual has dropped by round_tol (or reached eps ||v||);
+// then the residual is recomputed in FP64 from the FP64 iterate and, unless
+// that meets eps ||v||, a fresh round starts from it (iterative refinement of
+// the inner solve; the recurrences restart, the iterate accumulates).
 __device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double trr, double eps) {
-  if (s.fresh) {
+  if (s.fresh || s.replaced) {
+    const bool fresh = s.fresh != 0;
     s.fresh = 0;
-    s.vnorm = sqrt(trr);
-    s.rnorm = s.vnorm;
-    s.its = 0;
+    s.replaced = 0;
+    const double rn = sqrt(trr);
+    if (fresh) {
+      s.vnorm = rn;
+      s.its = 0;
+    }
+    s.rnorm = rn;
+    if (rn <= eps * s.vnorm || s.vnorm == 0.0) {
+      s.done = 1; s.conv = 1; s.verified = 1;
+      return;
+    }
+    if (s.its >= s.maxit || is_zero(td) || !(rn == rn)) {
+      s.done = 1; s.conv = 0; s.verified = 1;
+      return;
+    }
     s.gamma = tg;
     s.beta = c128{0.0, 0.0};
-    s.done = s.vnorm == 0.0 || is_zero(td);
-    s.alpha = s.done ? c128{0.0, 0.0} : cdiv(tg, td);
-    s.conv = s.vnorm == 0.0;
-    s.verified = s.done;
+    s.alpha = cdiv(tg, td);
+    s.rstop = fmax(eps * s.vnorm, s.round_tol * rn);
+    s.done = 0; s.conv = 0; s.verified = 0;
     return;
   }
-  if (!s.replaced && s.done) return;
-  if (!s.replaced) s.its += 1;
-  const bool was_replaced = s.replaced != 0;
-  s.replaced = 0;
+  if (s.done) return;
+  s.its += 1;
   s.rnorm = sqrt(trr);
-  if (s.rnorm <= eps * s.vnorm) {
+  if (s.rnorm <= s.rstop) {
     s.done = 1;
     s.conv = 1;
-    if (was_replaced) s.verified = 1;
+    s.verified = s.trust;
     return;
   }
   c128 den{0.0, 0.0};
@@ -262,17 +295,20 @@ __device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double t
     s.verified = 1;
     return;
   }
-  s.done = 0;
-  s.conv = 0;
   s.beta = beta;
   s.alpha = cdiv(tg, den);
   s.gamma = tg;
 }
 
+// Inverse Jacobi diagonal 1/(diag(K) + tau diag(M)) for one inner solve, so
+// the iteration multiplies instead of dividing at every stencil point.
 template <typename Op, typename R>
-__device__ __forceinline__ cx<R> jdiag(const Op& op, const R* __restrict__ dK, long c, cx<R> tau) {
-  const R m = (R)op.mass(c);
-  return cx<R>{dK[c] + tau.re * m, tau.im * m};
+__global__ void __launch_bounds__(BS) k_dinv(Op op, const double* __restrict__ dK, c128 tau, int n,
+                                             cx<R>* __restrict__ dinv) {
+  for (int c = blockIdx.x * BS + threadIdx.x; c < n; c += gridDim.x * BS) {
+    const double m = op.mass(c);
+    dinv[c] = cvt<R>(cdiv(c128{1.0, 0.0}, c128{dK[c] + tau.re * m, tau.im * m}));
+  }
 }
 
 // Vector set of the iteration: r, w, s in two parity buffers.
@@ -286,20 +322,22 @@ template <typename R> struct CgVecs {
 
 // x = 0, p = 0, s = 0, r = v, w = A D^{-1} v; partials v^T u, w^T u, ||v||^2.
 template <typename Op, typename R>
-__global__ void __launch_bounds__(BS) k_cg_init(Op op, const R* __restrict__ dK, c128 tau, long n, int S, int maxit,
-                                                int trust, const cx<R>* __restrict__ v, CgVecs<R> vec,
+__global__ void __launch_bounds__(BS) k_cg_init(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
+                                                int maxit, int trust, double round_tol, const cx<R>* __restrict__ v,
+                                                CgVecs<R> vec,
                                                 c128* __restrict__ part, CgScal* __restrict__ sc0,
                                                 int* __restrict__ all_done) {
-  const long N = n * S;
+  const int S = 1 << lS;
+  const int N = n << lS;
   const int rl = threadIdx.x & (S - 1);
   const cx<R> tr = cvt<R>(tau);
-  auto gu = [&](long cc) { return cdiv(v[cc * S + rl], jdiag<Op, R>(op, dK, cc, tr)); };
+  auto gu = [&](int cc) { return v[(cc << lS) + rl] * dinv[cc]; };
   cx<R> ag{0, 0}, ad{0, 0};
   R arr = 0;
-  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
-    const long c = t / S;
+  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
+    const int c = t >> lS;
     const cx<R> vv = v[t];
-    const cx<R> uu = gu(c);
+    const cx<R> uu = vv * dinv[c];
     const cx<R> ww = op.template apply<R>(c, tr, gu);
     vec.x[t] = c128{0.0, 0.0};
     vec.p[t] = cx<R>{0, 0};
@@ -318,95 +356,182 @@ __global__ void __launch_bounds__(BS) k_cg_init(Op op, const R* __restrict__ dK,
       s.fresh = 1;
       s.maxit = maxit;
       s.trust = trust;
+      s.round_tol = round_tol;
       sc0[threadIdx.x] = s;
     }
     if (threadIdx.x == 0) *all_done = 0;
   }
 }
 
+// Loads of one cell for the stencil iteration (issued before any arithmetic,
+// with clamped neighbour indices instead of branches).
+template <typename Op, typename R> struct CgCell {
+  int idx[Op::NB > 0 ? Op::NB : 1];
+  R fo[Op::NB > 0 ? Op::NB : 1];
+  R fsum, m;
+  cx<R> rq[Op::NB > 0 ? Op::NB : 1], wq[Op::NB > 0 ? Op::NB : 1], sq[Op::NB > 0 ? Op::NB : 1],
+      dq[Op::NB > 0 ? Op::NB : 1];
+  cx<R> di, rc, wc, sc, pc;
+  c128 xc;
+};
+
 template <typename Op, typename R>
-__global__ void __launch_bounds__(CGB) k_cg_step(Op op, const R* __restrict__ dK, c128 tau, long n, int S,
+__device__ __forceinline__ void cg_load(const Op& op, const cx<R>* __restrict__ dinv, int lS, int rl, int t,
+                                        const cx<R>* __restrict__ r0, const cx<R>* __restrict__ w0,
+                                        const cx<R>* __restrict__ s0, const CgVecs<R>& vec, CgCell<Op, R>& L) {
+  constexpr int NB = Op::NB;
+  const int c = t >> lS;
+  op.template stencil<R>(c, L.idx, L.fo, L.fsum);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int k = (L.idx[q] << lS) + rl;
+    L.rq[q] = r0[k];
+    L.wq[q] = w0[k];
+    L.sq[q] = s0[k];
+    L.dq[q] = dinv[L.idx[q]];
+  }
+  L.di = dinv[c];
+  L.rc = r0[t];
+  L.wc = w0[t];
+  L.sc = s0[t];
+  L.pc = vec.p[t];
+  L.xc = vec.x[t];
+  L.m = (R)op.mass(c);
+}
+
+template <typename Op, typename R, bool NT>
+__device__ __forceinline__ void cg_compute(const CgCell<Op, R>& L, int t, cx<R> al, cx<R> be, c128 al64, cx<R> tr,
+                                           const CgVecs<R>& vec, cx<R>* __restrict__ r1, cx<R>* __restrict__ w1,
+                                           cx<R>* __restrict__ s1, cx<R>& ag, cx<R>& ad, R& arr) {
+  constexpr int NB = Op::NB;
+  const cx<R> sn = L.wc + be * L.sc;
+  const cx<R> rn = L.rc - al * sn;
+  const cx<R> pn = L.rc * L.di + be * L.pc;
+  const cx<R> un = rn * L.di;
+  cx<R> wn = L.fsum * un + L.m * (tr * un);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) wn = wn - L.fo[q] * ((L.rq[q] - al * (L.wq[q] + be * L.sq[q])) * L.dq[q]);
+  st<NT>(vec.p + t, pn);
+  st<NT>(vec.x + t, L.xc + al64 * cvt<double>(pn));
+  st<NT>(r1 + t, rn);
+  st<NT>(w1 + t, wn);
+  st<NT>(s1 + t, sn);
+  ag = ag + rn * un;
+  ad = ad + wn * un;
+  arr += abs2(rn);
+}
+
+// Parity of the lane's vectors in the coming step, known before the totals:
+// a fresh or re-started lane is at its current count, a running lane one on.
+__device__ __forceinline__ int cg_next_parity(const CgScal& s) {
+  if (s.fresh) return 0;
+  if (s.replaced || s.done) return s.its & 1;
+  return (s.its + 1) & 1;
+}
+
+// One iteration.  The cell's loads are issued first; the block then sums the
+// previous step's partials (LDS-only barriers) and advances the lane state
+// while those loads are in flight.
+template <typename Op, typename R, int CGB, bool PREFETCH, bool XCD, bool NT>
+__global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
                                                  double eps, const c128* __restrict__ partIn, int Gin,
                                                  const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
                                                  CgVecs<R> vec, c128* __restrict__ partOut,
                                                  int* __restrict__ all_done) {
+  const int S = 1 << lS;
   const int rl = threadIdx.x & (S - 1);
-  if (*all_done) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = scIn[threadIdx.x];
+  const int flag = *all_done;
+  CgScal s = scIn[rl];
+  if (flag) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
     return;
   }
+  const int N = n << lS;
+  const int par = cg_next_parity(s);
+  const cx<R>* __restrict__ r0 = vec.r[par];
+  const cx<R>* __restrict__ w0 = vec.w[par];
+  const cx<R>* __restrict__ s0 = vec.s[par];
+  cx<R>* __restrict__ r1 = vec.r[par ^ 1];
+  cx<R>* __restrict__ w1 = vec.w[par ^ 1];
+  cx<R>* __restrict__ s1 = vec.s[par ^ 1];
+  const int t0 = (XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x) * CGB + threadIdx.x;
+  CgCell<Op, R> L;
+  if constexpr (Op::NB > 0 && PREFETCH) {
+    // a lane that is running, fresh or re-started computes in this step
+    if (t0 < N && (!s.done || s.fresh || s.replaced)) cg_load<Op, R>(op, dinv, lS, rl, t0, r0, w0, s0, vec, L);
+  }
+  // totals of the previous step's partials (LDS-only barriers: the cell loads
+  // above stay in flight meanwhile)
   c128 tot[3];
   final_sum<3, CGB>(partIn, Gin, S, tot);
-  CgScal s = scIn[rl];
   cg_advance(s, tot[0], tot[1], tot[2].re, eps);
-  if (s.done && s.conv && s.trust) s.verified = 1;
-  __shared__ int any_open;
-  if (threadIdx.x == 0) any_open = 0;
-  __syncthreads();
-  if ((int)threadIdx.x < S && !s.done) any_open = 1;
-  __syncthreads();
+  const bool any_open = __any(!s.done);
   if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
   if (!any_open) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *all_done = 1;
     return;
   }
-  const long N = n * S;
   cx<R> ag{0, 0}, ad{0, 0};
   R arr = 0;
   if (!s.done) {
-    const int par = s.its & 1;
-    const cx<R>* __restrict__ r0 = vec.r[par];
-    const cx<R>* __restrict__ w0 = vec.w[par];
-    const cx<R>* __restrict__ s0 = vec.s[par];
-    cx<R>* __restrict__ r1 = vec.r[par ^ 1];
-    cx<R>* __restrict__ w1 = vec.w[par ^ 1];
-    cx<R>* __restrict__ s1 = vec.s[par ^ 1];
     const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta), tr = cvt<R>(tau);
     const c128 al64 = s.alpha;
-    // u' at any cell: (r - alpha (w + beta s_old)) / D
-    auto gu = [&](long cc) {
-      const size_t k = (size_t)cc * S + rl;
-      const cx<R> rn = r0[k] - al * (w0[k] + be * s0[k]);
-      return cdiv(rn, jdiag<Op, R>(op, dK, cc, tr));
-    };
-    for (long t = blockIdx.x * (long)CGB + threadIdx.x; t < N; t += (long)gridDim.x * CGB) {
-      const long c = t / S;
-      const cx<R> D = jdiag<Op, R>(op, dK, c, tr);
-      const cx<R> rc = r0[t];
-      const cx<R> sn = w0[t] + be * s0[t];
-      const cx<R> rn = rc - al * sn;
-      const cx<R> pn = cdiv(rc, D) + be * vec.p[t];
-      vec.p[t] = pn;
-      vec.x[t] = vec.x[t] + al64 * cvt<double>(pn);
-      const cx<R> un = cdiv(rn, D);
-      const cx<R> wn = op.template apply<R>(c, tr, gu);
-      r1[t] = rn;
-      w1[t] = wn;
-      s1[t] = sn;
-      ag = ag + rn * un;
-      ad = ad + wn * un;
-      arr += abs2(rn);
+    if constexpr (Op::NB > 0) {
+      if constexpr (!PREFETCH) {
+        if (t0 < N) cg_load<Op, R>(op, dinv, lS, rl, t0, r0, w0, s0, vec, L);
+      }
+      if (t0 < N) cg_compute<Op, R, NT>(L, t0, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
+      for (int t = t0 + gridDim.x * CGB; t < N; t += gridDim.x * CGB) {
+        CgCell<Op, R> L2;
+        cg_load<Op, R>(op, dinv, lS, rl, t, r0, w0, s0, vec, L2);
+        cg_compute<Op, R, NT>(L2, t, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
+      }
+    } else {
+      // general sparse K: u' formed on the fly at every column of the row
+      auto gu = [&](int cc) {
+        const int k = (cc << lS) + rl;
+        return (r0[k] - al * (w0[k] + be * s0[k])) * dinv[cc];
+      };
+      for (int t = t0; t < N; t += gridDim.x * CGB) {
+        const int c = t >> lS;
+        const cx<R> di = dinv[c];
+        const cx<R> rc = r0[t];
+        const cx<R> sn = w0[t] + be * s0[t];
+        const cx<R> rn = rc - al * sn;
+        const cx<R> pn = rc * di + be * vec.p[t];
+        vec.p[t] = pn;
+        vec.x[t] = vec.x[t] + al64 * cvt<double>(pn);
+        const cx<R> un = rn * di;
+        const cx<R> wn = op.template apply<R>(c, tr, gu);
+        r1[t] = rn;
+        w1[t] = wn;
+        s1[t] = sn;
+        ag = ag + rn * un;
+        ad = ad + wn * un;
+        arr += abs2(rn);
+      }
     }
   }
   c128 acc[3] = {cvt<double>(ag), cvt<double>(ad), {(double)arr, 0.0}};
   block_partials<3, CGB>(acc, S, partOut + (size_t)blockIdx.x * 3 * S);
 }
 
-// Residual replacement, part 1: r = v - (K + tau M) x in FP64 from the FP64
-// iterate, stored rounded in the lane's current r buffer; partial ||r||^2 in
-// slot 2 of [G][3][S].
+// Start of a refinement round, part 1: r = v - (K + tau M) x in FP64 from the
+// FP64 iterate, stored rounded in the lane's current r buffer; partial
+// ||r||^2 in slot 2 of [G][3][S].
 template <typename OpD, typename R>
-__global__ void __launch_bounds__(BS) k_cg_replace_r(OpD opd, c128 tau, long n, int S, const cx<R>* __restrict__ v,
+__global__ void __launch_bounds__(BS) k_cg_replace_r(OpD opd, c128 tau, int n, int lS, const cx<R>* __restrict__ v,
                                                      const CgScal* __restrict__ sc, CgVecs<R> vec,
                                                      c128* __restrict__ part) {
-  const long N = n * S;
+  const int S = 1 << lS;
+  const int N = n << lS;
   const int rl = threadIdx.x & (S - 1);
   cx<R>* __restrict__ rr = vec.r[sc[rl].its & 1];
   const c128* __restrict__ x = vec.x;
-  auto g = [&](long cc) { return x[cc * S + rl]; };
+  auto g = [&](int cc) { return x[(cc << lS) + rl]; };
   double a = 0.0;
-  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
-    const long c = t / S;
+  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
+    const int c = t >> lS;
     const c128 res = cvt<double>(v[t]) - opd.template apply<double>(c, tau, g);
     rr[t] = cvt<R>(res);
     a += abs2(res);
@@ -415,23 +540,25 @@ __global__ void __launch_bounds__(BS) k_cg_replace_r(OpD opd, c128 tau, long n, 
   block_partials<1>(acc, S, part + (size_t)blockIdx.x * 3 * S + 2 * S);
 }
 
-// Residual replacement, part 2: w = A D^{-1} r in the lane's current w buffer;
-// partials r^T u, w^T u in slots 0, 1.  Lanes that converged without a
-// confirmed true residual are marked for evaluation by the next step.
+// Start of a refinement round, part 2: w = A D^{-1} r in the lane's current w
+// buffer; partials r^T u, w^T u in slots 0, 1.  Lanes whose round ended
+// without a confirmed FP64 residual are marked for the next step, which either
+// accepts them or starts a fresh round.
 template <typename Op, typename R>
-__global__ void __launch_bounds__(BS) k_cg_replace_w(Op op, const R* __restrict__ dK, c128 tau, long n, int S,
+__global__ void __launch_bounds__(BS) k_cg_replace_w(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
                                                      CgScal* __restrict__ sc, CgVecs<R> vec,
                                                      c128* __restrict__ part, int* __restrict__ all_done) {
-  const long N = n * S;
+  const int S = 1 << lS;
+  const int N = n << lS;
   const int rl = threadIdx.x & (S - 1);
   const int par = sc[rl].its & 1;
   const cx<R>* __restrict__ r0 = vec.r[par];
   cx<R>* __restrict__ w0 = vec.w[par];
   const cx<R> tr = cvt<R>(tau);
-  auto gu = [&](long cc) { return cdiv(r0[cc * S + rl], jdiag<Op, R>(op, dK, cc, tr)); };
+  auto gu = [&](int cc) { return r0[(cc << lS) + rl] * dinv[cc]; };
   cx<R> ag{0, 0}, ad{0, 0};
-  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
-    const long c = t / S;
+  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
+    const int c = t >> lS;
     const cx<R> uu = gu(c);
     const cx<R> ww = op.template apply<R>(c, tr, gu);
     w0[t] = ww;

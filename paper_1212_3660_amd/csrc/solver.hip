@@ -3,6 +3,7 @@
 // FP64 true residuals and refinement, and the step-level entry points.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 #include <string>
@@ -20,6 +21,12 @@ int fail(int code, const std::string& m) {
   return code;
 }
 const char* last_error_text() { return g_err.c_str(); }
+
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
 
 static int grid_items(long items, int cap) {
   long b = (items + BS - 1) / BS;
@@ -196,7 +203,7 @@ template <typename F> static Op3D<F> op3d(const shk_problem* p) {
                  nullptr, p->m0};
 }
 template <typename F> static OpCSR<F> opcsr(const shk_problem* p) {
-  return OpCSR<F>{p->n, p->rowptr, p->col, pick<F>(p->val, p->val32), p->diag, p->mdiag, 0.0};
+  return OpCSR<F>{(int)p->n, p->rowptr, p->col, pick<F>(p->val, p->val32), p->diag, p->mdiag, 0.0};
 }
 
 // Calls fn(op, opd): the operator with faces in precision F and in FP64.
@@ -211,6 +218,34 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
   return with_ops<F>(p, [&](auto op, auto) { return fn(op); });
 }
 
+// Launch shape of the iteration kernel: block size (256, 512 or 1024),
+// whether a cell's loads are issued before the prologue, XCD-aware tile order,
+// streaming (non-temporal) stores, and a skew added between the large
+// workspace arrays.  Defaults are the fastest measured on MI355X at 512x512
+// (256-thread blocks, no prefetch, XCD order, streaming stores on the
+// complex64 path); SHK_CG_BLOCK, SHK_CG_PREFETCH, SHK_XCD_MAP, SHK_NT_STORE and
+// SHK_WS_SKEW override them for tuning sweeps.
+struct Tune {
+  int cgb = 256;
+  int prefetch64 = 0;
+  int prefetch32 = 0;
+  int xcd = 1;
+  int nt64 = 0;
+  int nt32 = 1;
+  size_t skew = 0;
+  Tune() {
+    if (const char* e = getenv("SHK_CG_BLOCK")) {
+      const int v = atoi(e);
+      if (v == 256 || v == 512 || v == 1024) cgb = v;
+    }
+    if (const char* e = getenv("SHK_CG_PREFETCH")) prefetch64 = prefetch32 = atoi(e) != 0;
+    if (const char* e = getenv("SHK_WS_SKEW")) skew = (size_t)strtoull(e, nullptr, 10) & ~size_t(255);
+    if (const char* e = getenv("SHK_XCD_MAP")) xcd = atoi(e) != 0;
+    if (const char* e = getenv("SHK_NT_STORE")) nt64 = nt32 = atoi(e) != 0;
+  }
+};
+static Tune g_tune;
+
 // ----------------------------------------------------------- workspace -----
 struct Carver {
   char* base;
@@ -218,6 +253,7 @@ struct Carver {
   template <typename T> T* take(size_t count) {
     T* r = base ? reinterpret_cast<T*>(base + off) : nullptr;
     off = align_up(off + count * sizeof(T));
+    if (count * sizeof(T) >= (1u << 20)) off += g_tune.skew;   // large arrays only
     return r;
   }
 };
@@ -230,6 +266,7 @@ struct Grid {
   bool separate;  // fold partials with k_lane_totals before consumers read them
 };
 static Grid item_plan(long N, int S) {
+  const int CGB = g_tune.cgb;
   long G = (N + CGB - 1) / CGB;
   G = std::max<long>(1, std::min<long>(G, 2048));
   Grid g{(int)G, G * 3 * S > 3072};
@@ -240,6 +277,7 @@ template <typename R> struct Buffers {
   cx<R>*V, *W, *cr[2], *cw[2], *cs[2], *cp;
   c128* Z;                // flexible basis (FP64 on both paths)
   c128 *cpart[2], *ctot[2], *part;
+  cx<R>* dinv;            // inverse Jacobi diagonal of the current inner solve
   CgScal* sc;             // two buffers of S lanes
   int* all_done;
   double *beta0, *hn, *mz, *pn, *nzs;
@@ -276,6 +314,7 @@ static Buffers<R> carve(char* base, long n, int m, int nf, int S, int s_real, bo
     b.cs[i] = cv.take<cx<R>>(N);
   }
   b.cp = cv.take<cx<R>>(N);
+  b.dinv = cv.take<cx<R>>(n);
   const Grid gp = item_plan(N, S);
   const long ipb = dot_ipb(N);
   const long Gd = (N + ipb - 1) / ipb;
@@ -365,14 +404,48 @@ template <typename R, typename Op, typename OpD> struct Group {
   long long inner_its = 0;
   int outer_steps = 0;
 
+  template <int CGB, bool PF, bool XCD>
+  void step_as(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn, CgScal* scOut,
+               const CgVecs<R>& vec, c128* out) {
+    if (std::is_same<R, float>::value ? g_tune.nt32 : g_tune.nt64)
+      k_cg_step<Op, R, CGB, PF, XCD, true><<<G, CGB, 0, st>>>(op, B.dinv, tau, ni, lS, e, in, Gin, scIn, scOut, vec,
+                                                               out, B.all_done);
+    else
+      k_cg_step<Op, R, CGB, PF, XCD, false><<<G, CGB, 0, st>>>(op, B.dinv, tau, ni, lS, e, in, Gin, scIn, scOut, vec,
+                                                                out, B.all_done);
+  }
+  template <int CGB>
+  void step_bs(bool pf, bool xcd, int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin,
+               const CgScal* scIn, CgScal* scOut, const CgVecs<R>& vec, c128* out) {
+    if (pf) {
+      if (xcd) step_as<CGB, true, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
+      else step_as<CGB, true, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
+    } else {
+      if (xcd) step_as<CGB, false, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
+      else step_as<CGB, false, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
+    }
+  }
+  void launch_step(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+                   CgScal* scOut, const CgVecs<R>& vec, c128* out) {
+    const bool pf = std::is_same<R, float>::value ? g_tune.prefetch32 : g_tune.prefetch64;
+    const bool xcd = g_tune.xcd != 0;
+    switch (g_tune.cgb) {
+      case 256: step_bs<256>(pf, xcd, G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out); break;
+      case 512: step_bs<512>(pf, xcd, G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out); break;
+      default: step_bs<1024>(pf, xcd, G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out); break;
+    }
+  }
+
   // ---- inner solve of (K + tau M) z = v (section 4) into z, w = M z ----
   int inner(c128 tau, const cx<R>* v, c128* z, double eps, int maxit, int fixed, double* pn_out) {
     const int G = gp.G;
     const bool replace = std::is_same<R, float>::value && fixed <= 0;
     const double e = fixed > 0 ? -1.0 : eps;
     const int cap = fixed > 0 ? fixed : maxit;
-    const R* dK = pick<R>(p->dK, p->dK32);
+    const int lS = ilog2(S);
+    const int ni = (int)n;
     CgVecs<R> vec{{B.cr[0], B.cr[1]}, {B.cw[0], B.cw[1]}, {B.cs[0], B.cs[1]}, B.cp, z};
+    k_dinv<OpD, R><<<grid_items(n, 2048), BS, 0, st>>>(opd, p->dK, tau, ni, B.dinv);
     // partials of launch L live in cpart[L & 1] (totals in ctot[L & 1])
     auto totals = [&](int slot) -> const c128* {
       if (!gp.separate) return B.cpart[slot];
@@ -380,8 +453,8 @@ template <typename R, typename Op, typename OpD> struct Group {
       return B.ctot[slot];
     };
     const int Gin = gp.separate ? 1 : G;
-    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, dK, tau, n, S, cap, replace ? 0 : 1, v, vec, B.cpart[0], B.sc,
-                                        B.all_done);
+    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, cap, replace ? 0 : 1, replace ? 1e-2 : 0.0, v, vec,
+                                        B.cpart[0], B.sc, B.all_done);
     const c128* in = totals(0);
     SHK_HIP(hipGetLastError());
     long it = 0;
@@ -399,8 +472,7 @@ template <typename R, typename Op, typename OpD> struct Group {
         CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
         const int out = (int)((it + 1) & 1);
         if (timing) (void)hipEventRecord(g_timer.ev[2 * c], st);
-        k_cg_step<Op, R><<<G, CGB, 0, st>>>(op, dK, tau, n, S, e, in, Gin, scIn, scOut, vec, B.cpart[out],
-                                             B.all_done);
+        launch_step(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, B.cpart[out]);
         if (timing) (void)hipEventRecord(g_timer.ev[2 * c + 1], st);
         in = totals(out);
       }
@@ -425,16 +497,16 @@ template <typename R, typename Op, typename OpD> struct Group {
       if (snap->all_done) {
         bool unverified = false;
         for (int r = 0; r < S; ++r) unverified |= snap->sc[r].conv && !snap->sc[r].verified;
-        if (!replace || !unverified || replacements >= 8) break;
-        // recompute r = v - A x in FP64 (and w = A D^-1 r); the next step judges it
+        if (!replace || !unverified || replacements >= 12) break;
+        // new round: r = v - A x in FP64 (and w = A D^-1 r); the next step judges it
         CgScal* scCur = B.sc + (size_t)(it & 1) * S;
         const int slot = (int)(it & 1);
-        k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, n, S, v, scCur, vec, B.cpart[slot]);
-        k_cg_replace_w<Op, R><<<G, BS, 0, st>>>(op, dK, tau, n, S, scCur, vec, B.cpart[slot], B.all_done);
+        k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, ni, lS, v, scCur, vec, B.cpart[slot]);
+        k_cg_replace_w<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, scCur, vec, B.cpart[slot], B.all_done);
         in = totals(slot);
         SHK_HIP(hipGetLastError());
         ++replacements;
-        chunk = 8;
+        chunk = 16;
         continue;
       }
       if (it > (long)cap + 64L * (replacements + 1)) break;   // lanes stop themselves at maxit
@@ -799,6 +871,7 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
         b.cpart[i] = c.take<c128>((size_t)gp.G * 3 * S); b.ctot[i] = c.take<c128>((size_t)3 * S);
       }
       b.cp = c.take<cx<R>>(N);
+      b.dinv = c.take<cx<R>>(p->n);
       b.part = c.take<c128>((size_t)grid_items(N, 1024) * 2 * S);
       b.sc = c.take<CgScal>(2 * S); b.all_done = c.take<int>(4);
       b.mz = c.take<double>(S); b.pn = c.take<double>(S);

@@ -107,7 +107,9 @@ def test_inner_cocg_converged_counts_and_residual():
         Z = z.cpu().numpy().reshape(op.n, S)
         for r in range(S):
             _, oits, ok, _ = cocg(lambda x: op.apply(tau, x), op.diag(tau), V[:, r], eps, 5000)
-            assert ok and abs(int(its[r]) - oits) <= 1
+            # the single-reduction arrangement gives the textbook iterates in exact
+            # arithmetic; its rounding can delay the last digits near 1e-10
+            assert ok and oits - 1 <= int(its[r]) <= (oits + 1 if eps >= 1e-8 else int(1.1 * oits) + 1)
             true = np.linalg.norm(V[:, r] - op.apply(tau, Z[:, r]))
             assert true <= 1.5 * eps and np.isclose(pn[r], true, rtol=1e-6)
     # complex64 path: the FP64 iterate with residual replacement meets the

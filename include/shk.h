@@ -218,10 +218,11 @@ int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const
                       const shk_c128* x, double* relres, void* hip_stream);
 
 /* Instrumentation of the inner-iteration kernel (the hot loop of section 4's
- * inner solves): when enabled, every launch of it is bracketed by HIP events
- * on the solve stream and, per launch that performed an iteration, its
- * duration and its algorithmic bytes (per cell: r, w, s read and written, p
- * and the FP64 iterate x read and written, diag(K) and the face
+ * inner solves): when enabled, each batch of its launches between two host
+ * polls is bracketed by HIP events on the solve stream, and for every batch in
+ * which each launch performed an iteration, the batch's duration, its launch
+ * count and its algorithmic bytes (per cell: r, w, s read and written, p and
+ * the FP64 iterate x read and written, the inverse diagonal and the face
  * coefficients read) are accumulated.  Process-wide; enable/disable/read are
  * not meant to race with solves on other threads. */
 int shk_profile_enable(int on);

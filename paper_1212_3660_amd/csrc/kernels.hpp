@@ -237,6 +237,9 @@ struct CgScal {
   int its, done, conv, maxit;
   int fresh, replaced, verified, trust;  // trust: accept the recurrence residual (FP64 path)
   double round_tol;
+  double rn0;   // residual norm at the start of the current round
+  int its0;     // iteration count at the start of the current round
+  int pad_;
 };
 
 
@@ -259,6 +262,8 @@ __device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double t
       s.its = 0;
     }
     s.rnorm = rn;
+    s.rn0 = rn;
+    s.its0 = s.its;
     if (rn <= eps * s.vnorm || s.vnorm == 0.0) {
       s.done = 1; s.conv = 1; s.verified = 1;
       return;

@@ -223,8 +223,8 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 // streaming (non-temporal) stores, and a skew added between the large
 // workspace arrays.  Defaults are the fastest measured on MI355X at 512x512
 // (256-thread blocks, no prefetch, XCD order, streaming stores on the
-// complex64 path); SHK_CG_BLOCK, SHK_CG_PREFETCH, SHK_XCD_MAP, SHK_NT_STORE and
-// SHK_WS_SKEW override them for tuning sweeps.
+// complex64 path); SHK_CG_BLOCK, SHK_CG_PREFETCH, SHK_XCD_MAP, SHK_NT_STORE,
+// SHK_SEP_LIMIT and SHK_WS_SKEW override them for tuning sweeps.
 struct Tune {
   int cgb = 256;
   int prefetch64 = 0;
@@ -232,6 +232,7 @@ struct Tune {
   int xcd = 1;
   int nt64 = 0;
   int nt32 = 1;
+  long sep_limit = 3072;   // fold partials in a separate kernel above this many
   size_t skew = 0;
   Tune() {
     if (const char* e = getenv("SHK_CG_BLOCK")) {
@@ -242,6 +243,7 @@ struct Tune {
     if (const char* e = getenv("SHK_WS_SKEW")) skew = (size_t)strtoull(e, nullptr, 10) & ~size_t(255);
     if (const char* e = getenv("SHK_XCD_MAP")) xcd = atoi(e) != 0;
     if (const char* e = getenv("SHK_NT_STORE")) nt64 = nt32 = atoi(e) != 0;
+    if (const char* e = getenv("SHK_SEP_LIMIT")) sep_limit = atol(e);
   }
 };
 static Tune g_tune;
@@ -269,7 +271,7 @@ static Grid item_plan(long N, int S) {
   const int CGB = g_tune.cgb;
   long G = (N + CGB - 1) / CGB;
   G = std::max<long>(1, std::min<long>(G, 2048));
-  Grid g{(int)G, G * 3 * S > 3072};
+  Grid g{(int)G, G * 3 * S > g_tune.sep_limit};
   return g;
 }
 
@@ -464,36 +466,41 @@ template <typename R, typename Op, typename OpD> struct Group {
     if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
     int replacements = 0;
     const bool timing = g_timer.on;
+    if (timing) g_timer.ensure(1);
+    // per lane: iteration count, residual norm and round start seen at the
+    // previous poll (for the rate estimate), and the max count over lanes
+    std::vector<int> prev_its(S, 0), prev_its0(S, -1);
+    std::vector<double> prev_rn(S, 0.0);
     int its_before = 0;
+    bool round_start = true;   // the chunk's first launch starts a round
     while (true) {
-      if (timing) g_timer.ensure(chunk);
+      if (timing) (void)hipEventRecord(g_timer.ev[0], st);
       for (int c = 0; c < chunk; ++c, ++it) {
         const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
         CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
         const int out = (int)((it + 1) & 1);
-        if (timing) (void)hipEventRecord(g_timer.ev[2 * c], st);
         launch_step(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, B.cpart[out]);
-        if (timing) (void)hipEventRecord(g_timer.ev[2 * c + 1], st);
         in = totals(out);
       }
+      if (timing) (void)hipEventRecord(g_timer.ev[1], st);
       SHK_HIP(hipGetLastError());
       SHK_HIP(hipMemcpyAsync(&snap->all_done, B.all_done, sizeof(int), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipMemcpyAsync(snap->sc, B.sc + (size_t)(it & 1) * S, S * sizeof(CgScal), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
-      if (timing) {
-        int its_now = 0;
-        for (int r = 0; r < S; ++r) its_now = std::max(its_now, snap->sc[r].its);
-        const int worked = std::min(chunk, its_now - its_before);
-        for (int c = 0; c < worked; ++c) {
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, g_timer.ev[2 * c], g_timer.ev[2 * c + 1]) == hipSuccess) {
-            g_timer.total_ms += ms;
-            g_timer.launches += 1;
-            g_timer.total_bytes += (double)n * S * step_bytes_per_cell();
-          }
+      int its_now = 0;
+      for (int r = 0; r < S; ++r) its_now = std::max(its_now, snap->sc[r].its);
+      if (timing && its_now - its_before == chunk - (round_start ? 1 : 0)) {
+        // every launch of the chunk iterated: its time is kernel time plus the
+        // back-to-back dispatch gaps
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_timer.ev[0], g_timer.ev[1]) == hipSuccess) {
+          g_timer.total_ms += ms;
+          g_timer.launches += chunk;
+          g_timer.total_bytes += (double)chunk * n * S * step_bytes_per_cell();
         }
-        its_before = its_now;
       }
+      its_before = its_now;
+      round_start = false;
       if (snap->all_done) {
         bool unverified = false;
         for (int r = 0; r < S; ++r) unverified |= snap->sc[r].conv && !snap->sc[r].verified;
@@ -507,18 +514,38 @@ template <typename R, typename Op, typename OpD> struct Group {
         SHK_HIP(hipGetLastError());
         ++replacements;
         chunk = 16;
+        round_start = true;
         continue;
       }
-      if (it > (long)cap + 64L * (replacements + 1)) break;   // lanes stop themselves at maxit
-      // predict the remaining iterations from the mean convergence rate
+      // hang guard only: every lane stops itself after cap iterations, so at
+      // most cap launches do work; the rest are the tails of the chunks
+      if (it > 4L * cap + 16L * 512) break;
+      // Steps to the end of the current round: each running lane's rate over
+      // the iterations since the previous poll (since the round began if that
+      // window is short), never more than the iterations the round has
+      // already taken (a poll costs about as much as ten idle launches, an
+      // early overestimate of a slow start far more).
       int need = 4;
       for (int r = 0; r < S; ++r) {
         const CgScal& s = snap->sc[r];
-        if (s.done || s.vnorm <= 0.0 || s.its <= 0) continue;
-        const double rel = std::max(s.rnorm / s.vnorm, 1e-300);
-        const double rate = std::log(rel) / s.its;
-        int rem = 64;
-        if (rate < 0.0 && e > 0.0) rem = (int)std::ceil((std::log(e) - std::log(rel)) / rate * 1.05) + 2;
+        const int k = s.its - s.its0;
+        int rem = 16;
+        if (s.rstop <= 0.0) {
+          rem = s.maxit - s.its + 1;   // fixed iteration count
+        } else if (!s.done && k >= 4 && s.rnorm > 0.0) {
+          double rate = s.rnorm < s.rn0 ? std::log(s.rnorm / s.rn0) / k : 0.0;
+          const int kw = s.its - prev_its[r];
+          if (prev_its0[r] == s.its0 && kw >= 8 && s.rnorm < prev_rn[r])
+            rate = std::log(s.rnorm / prev_rn[r]) / kw;
+          if (s.rnorm <= s.rstop) rem = 2;
+          else if (rate < 0.0) rem = (int)std::ceil(std::log(s.rstop / s.rnorm) / rate * 1.05) + 2;
+          rem = std::min(rem, std::max(16, k));
+        }
+        prev_its[r] = s.its;
+        prev_its0[r] = s.its0;
+        prev_rn[r] = s.rnorm;
+        if (s.done) continue;
+        rem = std::min(rem, s.maxit - s.its + 1);
         need = std::max(need, std::min(rem, 512));
       }
       chunk = need;
@@ -553,15 +580,15 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
 
   // Algorithmic bytes per cell and lane of one k_cg_step: r, w, s read and
-  // written (6 vectors), p read and written, x (FP64) read and written,
-  // diag(K) and the faces of the cell read once.
+  // written (6 vectors), p read and written, x (FP64) read and written, the
+  // complex inverse diagonal and the cell's share of the faces read once.
   double step_bytes_per_cell() const {
     const double wv = sizeof(cx<R>);
     double faces;
     if (p->kind == Kind::FV2D) faces = 2.0 * sizeof(R);
     else if (p->kind == Kind::FV3D) faces = 3.0 * sizeof(R);
     else faces = (double)p->nnz / (double)p->n * (sizeof(R) + sizeof(int));
-    return 8.0 * wv + 32.0 + (sizeof(R) + faces) / S;
+    return 8.0 * wv + 32.0 + (2.0 * sizeof(R) + faces) / S;
   }
 
   GivensArgs gargs(int k, int cycle, int kglob, double tol) {

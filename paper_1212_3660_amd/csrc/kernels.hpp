@@ -68,16 +68,39 @@ __device__ __forceinline__ void block_partials(c128 (&v)[NV], int S, c128* __res
 // Sum partials laid out [block][NV][S] over G blocks in a fixed order (strided
 // per-thread sums, a wave tree, then the waves in order).  Every thread gets
 // the totals of its lane r = threadIdx.x % S.
-template <int NV, int BSZ = BS>
-__device__ __forceinline__ void final_sum(const c128* __restrict__ part, int G, int S, c128 (&res)[NV]) {
+//
+// Split in two so a kernel can issue the partial loads, then its own loads,
+// and only then wait: PartLoad holds up to KMAX blocks' partials per thread
+// (predicated, fully unrolled: all loads in flight at once); blocks beyond
+// KMAX * (BSZ / S) are summed by a plain loop in part_sum.
+template <int NV, int KMAX> struct PartLoad {
+  c128 v[KMAX][NV];
+};
+template <int NV, int KMAX, int BSZ>
+__device__ __forceinline__ void part_load(const c128* __restrict__ part, int G, int S, PartLoad<NV, KMAX>& L) {
+  const int r = threadIdx.x & (S - 1), c0 = threadIdx.x / S, C = BSZ / S;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int b = c0 + k * C;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) L.v[k][q] = b < G ? part[((size_t)b * NV + q) * S + r] : c128{0.0, 0.0};
+  }
+}
+template <int NV, int KMAX, int BSZ>
+__device__ __forceinline__ void part_sum(const c128* __restrict__ part, int G, int S, const PartLoad<NV, KMAX>& L,
+                                         c128 (&res)[NV]) {
   constexpr int NW = BSZ / WAVE;
   __shared__ c128 sh[NW][NV][WAVE];
   const int r = threadIdx.x & (S - 1), c0 = threadIdx.x / S, C = BSZ / S;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   c128 acc[NV];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) acc[q] = c128{0.0, 0.0};
-  for (int b = c0; b < G; b += C) {
+  for (int q = 0; q < NV; ++q) {
+    acc[q] = L.v[0][q];
+#pragma unroll
+    for (int k = 1; k < KMAX; ++k) acc[q] = acc[q] + L.v[k][q];
+  }
+  for (int b = c0 + KMAX * C; b < G; b += C) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = acc[q] + part[((size_t)b * NV + q) * S + r];
   }
@@ -95,6 +118,12 @@ __device__ __forceinline__ void final_sum(const c128* __restrict__ part, int G, 
     res[q] = a;
   }
   lds_sync();
+}
+template <int NV, int BSZ = BS>
+__device__ __forceinline__ void final_sum(const c128* __restrict__ part, int G, int S, c128 (&res)[NV]) {
+  PartLoad<NV, 4> L;
+  part_load<NV, 4, BSZ>(part, G, S, L);
+  part_sum<NV, 4, BSZ>(part, G, S, L, res);
 }
 
 // Block-wide sum of one complex value (all threads one lane), fixed order.
@@ -426,49 +455,45 @@ __device__ __forceinline__ void cg_compute(const CgCell<Op, R>& L, int t, cx<R> 
   arr += abs2(rn);
 }
 
-// Parity of the lane's vectors in the coming step, known before the totals:
-// a fresh or re-started lane is at its current count, a running lane one on.
-__device__ __forceinline__ int cg_next_parity(const CgScal& s) {
-  if (s.fresh) return 0;
-  if (s.replaced || s.done) return s.its & 1;
-  return (s.its + 1) & 1;
-}
-
-// One iteration.  The cell's loads are issued first; the block then sums the
-// previous step's partials (LDS-only barriers) and advances the lane state
-// while those loads are in flight.
-template <typename Op, typename R, int CGB, bool PREFETCH, bool XCD, bool NT>
-__global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
+// One iteration.  Vectors alternate between two buffers by launch parity
+// (par, from the host): a lane that has stopped leaves its vectors where they
+// are, and a lane re-started by a refinement round gets fresh r and w in the
+// current buffers (its s enters multiplied by beta = 0, and every buffer holds
+// finite values).  The all-done flag, the previous step's partials and the
+// lane state are loaded together and the flag is judged only after the sums
+// (one memory round trip instead of two; when the flag is set the sums are
+// discarded).  ONE = the launch has a single lane (S = 1): the lane state is
+// then uniform and lives in scalar registers.  MULTI = the grid is smaller than
+// the items and threads loop over several cells (large problems); otherwise
+// each thread owns one cell.  Blocks take tiles in XCD-aware order.
+template <typename Op, typename R, int CGB, bool NT, bool ONE, bool MULTI>
+__global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS_,
                                                  double eps, const c128* __restrict__ partIn, int Gin,
                                                  const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
-                                                 CgVecs<R> vec, c128* __restrict__ partOut,
+                                                 CgVecs<R> vec, int par, c128* __restrict__ partOut,
                                                  int* __restrict__ all_done) {
+  const int lS = ONE ? 0 : lS_;
   const int S = 1 << lS;
-  const int rl = threadIdx.x & (S - 1);
+  const int rl = ONE ? 0 : (int)threadIdx.x & (S - 1);
   const int flag = *all_done;
+  constexpr int KMAX = 4;
+  PartLoad<3, KMAX> PL;
+  part_load<3, KMAX, CGB>(partIn, Gin, S, PL);
   CgScal s = scIn[rl];
-  if (flag) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
-    return;
-  }
   const int N = n << lS;
-  const int par = cg_next_parity(s);
   const cx<R>* __restrict__ r0 = vec.r[par];
   const cx<R>* __restrict__ w0 = vec.w[par];
   const cx<R>* __restrict__ s0 = vec.s[par];
   cx<R>* __restrict__ r1 = vec.r[par ^ 1];
   cx<R>* __restrict__ w1 = vec.w[par ^ 1];
   cx<R>* __restrict__ s1 = vec.s[par ^ 1];
-  const int t0 = (XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x) * CGB + threadIdx.x;
-  CgCell<Op, R> L;
-  if constexpr (Op::NB > 0 && PREFETCH) {
-    // a lane that is running, fresh or re-started computes in this step
-    if (t0 < N && (!s.done || s.fresh || s.replaced)) cg_load<Op, R>(op, dinv, lS, rl, t0, r0, w0, s0, vec, L);
-  }
-  // totals of the previous step's partials (LDS-only barriers: the cell loads
-  // above stay in flight meanwhile)
+  const int t0 = xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x;
   c128 tot[3];
-  final_sum<3, CGB>(partIn, Gin, S, tot);
+  part_sum<3, KMAX, CGB>(partIn, Gin, S, PL, tot);
+  if (flag) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
+    return;
+  }
   cg_advance(s, tot[0], tot[1], tot[2].re, eps);
   const bool any_open = __any(!s.done);
   if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
@@ -482,14 +507,17 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict_
     const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta), tr = cvt<R>(tau);
     const c128 al64 = s.alpha;
     if constexpr (Op::NB > 0) {
-      if constexpr (!PREFETCH) {
-        if (t0 < N) cg_load<Op, R>(op, dinv, lS, rl, t0, r0, w0, s0, vec, L);
+      if (t0 < N) {
+        CgCell<Op, R> L;
+        cg_load<Op, R>(op, dinv, lS, rl, t0, r0, w0, s0, vec, L);
+        cg_compute<Op, R, NT>(L, t0, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
       }
-      if (t0 < N) cg_compute<Op, R, NT>(L, t0, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
-      for (int t = t0 + gridDim.x * CGB; t < N; t += gridDim.x * CGB) {
-        CgCell<Op, R> L2;
-        cg_load<Op, R>(op, dinv, lS, rl, t, r0, w0, s0, vec, L2);
-        cg_compute<Op, R, NT>(L2, t, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
+      if constexpr (MULTI) {
+        for (int t = t0 + gridDim.x * CGB; t < N; t += gridDim.x * CGB) {
+          CgCell<Op, R> L;
+          cg_load<Op, R>(op, dinv, lS, rl, t, r0, w0, s0, vec, L);
+          cg_compute<Op, R, NT>(L, t, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
+        }
       }
     } else {
       // general sparse K: u' formed on the fly at every column of the row
@@ -522,16 +550,15 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict_
 }
 
 // Start of a refinement round, part 1: r = v - (K + tau M) x in FP64 from the
-// FP64 iterate, stored rounded in the lane's current r buffer; partial
-// ||r||^2 in slot 2 of [G][3][S].
+// FP64 iterate, stored rounded in the r buffer of the current launch parity;
+// partial ||r||^2 in slot 2 of [G][3][S].
 template <typename OpD, typename R>
 __global__ void __launch_bounds__(BS) k_cg_replace_r(OpD opd, c128 tau, int n, int lS, const cx<R>* __restrict__ v,
-                                                     const CgScal* __restrict__ sc, CgVecs<R> vec,
-                                                     c128* __restrict__ part) {
+                                                     CgVecs<R> vec, int par, c128* __restrict__ part) {
   const int S = 1 << lS;
   const int N = n << lS;
   const int rl = threadIdx.x & (S - 1);
-  cx<R>* __restrict__ rr = vec.r[sc[rl].its & 1];
+  cx<R>* __restrict__ rr = vec.r[par];
   const c128* __restrict__ x = vec.x;
   auto g = [&](int cc) { return x[(cc << lS) + rl]; };
   double a = 0.0;
@@ -545,18 +572,17 @@ __global__ void __launch_bounds__(BS) k_cg_replace_r(OpD opd, c128 tau, int n, i
   block_partials<1>(acc, S, part + (size_t)blockIdx.x * 3 * S + 2 * S);
 }
 
-// Start of a refinement round, part 2: w = A D^{-1} r in the lane's current w
-// buffer; partials r^T u, w^T u in slots 0, 1.  Lanes whose round ended
+// Start of a refinement round, part 2: w = A D^{-1} r in the w buffer of the
+// current launch parity; partials r^T u, w^T u in slots 0, 1.  Lanes whose round ended
 // without a confirmed FP64 residual are marked for the next step, which either
 // accepts them or starts a fresh round.
 template <typename Op, typename R>
 __global__ void __launch_bounds__(BS) k_cg_replace_w(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
-                                                     CgScal* __restrict__ sc, CgVecs<R> vec,
+                                                     CgScal* __restrict__ sc, CgVecs<R> vec, int par,
                                                      c128* __restrict__ part, int* __restrict__ all_done) {
   const int S = 1 << lS;
   const int N = n << lS;
   const int rl = threadIdx.x & (S - 1);
-  const int par = sc[rl].its & 1;
   const cx<R>* __restrict__ r0 = vec.r[par];
   cx<R>* __restrict__ w0 = vec.w[par];
   const cx<R> tr = cvt<R>(tau);

@@ -218,18 +218,14 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
   return with_ops<F>(p, [&](auto op, auto) { return fn(op); });
 }
 
-// Launch shape of the iteration kernel: block size (256, 512 or 1024),
-// whether a cell's loads are issued before the prologue, XCD-aware tile order,
-// streaming (non-temporal) stores, and a skew added between the large
-// workspace arrays.  Defaults are the fastest measured on MI355X at 512x512
-// (256-thread blocks, no prefetch, XCD order, streaming stores on the
-// complex64 path); SHK_CG_BLOCK, SHK_CG_PREFETCH, SHK_XCD_MAP, SHK_NT_STORE,
+// Launch shape of the iteration kernel: block size (256 or 512), streaming
+// (non-temporal) stores, the partial count above which a separate kernel folds
+// the partials, and a skew added between the large workspace arrays.
+// Defaults are the fastest measured on MI355X at 512x512 (256-thread blocks,
+// streaming stores on the complex64 path); SHK_CG_BLOCK, SHK_NT_STORE,
 // SHK_SEP_LIMIT and SHK_WS_SKEW override them for tuning sweeps.
 struct Tune {
   int cgb = 256;
-  int prefetch64 = 0;
-  int prefetch32 = 0;
-  int xcd = 1;
   int nt64 = 0;
   int nt32 = 1;
   long sep_limit = 3072;   // fold partials in a separate kernel above this many
@@ -237,11 +233,9 @@ struct Tune {
   Tune() {
     if (const char* e = getenv("SHK_CG_BLOCK")) {
       const int v = atoi(e);
-      if (v == 256 || v == 512 || v == 1024) cgb = v;
+      if (v == 256 || v == 512) cgb = v;
     }
-    if (const char* e = getenv("SHK_CG_PREFETCH")) prefetch64 = prefetch32 = atoi(e) != 0;
     if (const char* e = getenv("SHK_WS_SKEW")) skew = (size_t)strtoull(e, nullptr, 10) & ~size_t(255);
-    if (const char* e = getenv("SHK_XCD_MAP")) xcd = atoi(e) != 0;
     if (const char* e = getenv("SHK_NT_STORE")) nt64 = nt32 = atoi(e) != 0;
     if (const char* e = getenv("SHK_SEP_LIMIT")) sep_limit = atol(e);
   }
@@ -406,36 +400,36 @@ template <typename R, typename Op, typename OpD> struct Group {
   long long inner_its = 0;
   int outer_steps = 0;
 
-  template <int CGB, bool PF, bool XCD>
-  void step_as(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn, CgScal* scOut,
-               const CgVecs<R>& vec, c128* out) {
-    if (std::is_same<R, float>::value ? g_tune.nt32 : g_tune.nt64)
-      k_cg_step<Op, R, CGB, PF, XCD, true><<<G, CGB, 0, st>>>(op, B.dinv, tau, ni, lS, e, in, Gin, scIn, scOut, vec,
-                                                               out, B.all_done);
-    else
-      k_cg_step<Op, R, CGB, PF, XCD, false><<<G, CGB, 0, st>>>(op, B.dinv, tau, ni, lS, e, in, Gin, scIn, scOut, vec,
-                                                                out, B.all_done);
+  template <int CGB, bool NT, bool ONE, bool MULTI>
+  void step_k(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+              CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
+    k_cg_step<Op, R, CGB, NT, ONE, MULTI><<<G, CGB, 0, st>>>(op, B.dinv, tau, ni, lS, e, in, Gin, scIn, scOut, vec,
+                                                             par, out, B.all_done);
+  }
+  template <int CGB, bool NT>
+  void step_nt(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+               CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
+    const bool multi = (long)G * CGB < N;
+    if (lS == 0) {
+      if (multi) step_k<CGB, NT, true, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
+      else step_k<CGB, NT, true, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
+    } else {
+      if (multi) step_k<CGB, NT, false, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
+      else step_k<CGB, NT, false, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
+    }
   }
   template <int CGB>
-  void step_bs(bool pf, bool xcd, int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin,
-               const CgScal* scIn, CgScal* scOut, const CgVecs<R>& vec, c128* out) {
-    if (pf) {
-      if (xcd) step_as<CGB, true, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
-      else step_as<CGB, true, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
-    } else {
-      if (xcd) step_as<CGB, false, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
-      else step_as<CGB, false, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out);
-    }
+  void step_cgb(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+                CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
+    if (std::is_same<R, float>::value ? g_tune.nt32 : g_tune.nt64)
+      step_nt<CGB, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
+    else
+      step_nt<CGB, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
   }
   void launch_step(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
-                   CgScal* scOut, const CgVecs<R>& vec, c128* out) {
-    const bool pf = std::is_same<R, float>::value ? g_tune.prefetch32 : g_tune.prefetch64;
-    const bool xcd = g_tune.xcd != 0;
-    switch (g_tune.cgb) {
-      case 256: step_bs<256>(pf, xcd, G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out); break;
-      case 512: step_bs<512>(pf, xcd, G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out); break;
-      default: step_bs<1024>(pf, xcd, G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, out); break;
-    }
+                   CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
+    if (g_tune.cgb == 512) step_cgb<512>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
+    else step_cgb<256>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
   }
 
   // ---- inner solve of (K + tau M) z = v (section 4) into z, w = M z ----
@@ -479,7 +473,7 @@ template <typename R, typename Op, typename OpD> struct Group {
         const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
         CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
         const int out = (int)((it + 1) & 1);
-        launch_step(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, B.cpart[out]);
+        launch_step(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
         in = totals(out);
       }
       if (timing) (void)hipEventRecord(g_timer.ev[1], st);
@@ -508,8 +502,8 @@ template <typename R, typename Op, typename OpD> struct Group {
         // new round: r = v - A x in FP64 (and w = A D^-1 r); the next step judges it
         CgScal* scCur = B.sc + (size_t)(it & 1) * S;
         const int slot = (int)(it & 1);
-        k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, ni, lS, v, scCur, vec, B.cpart[slot]);
-        k_cg_replace_w<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, scCur, vec, B.cpart[slot], B.all_done);
+        k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, ni, lS, v, vec, slot, B.cpart[slot]);
+        k_cg_replace_w<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, scCur, vec, slot, B.cpart[slot], B.all_done);
         in = totals(slot);
         SHK_HIP(hipGetLastError());
         ++replacements;

@@ -268,6 +268,11 @@ struct CgScal {
   double round_tol;
   double rn0;   // residual norm at the start of the current round
   int its0;     // iteration count at the start of the current round
+  int its_best; // iteration at which the round last halved its best residual
+  double rbest; // that residual
+  int kick;     // 1: a Jacobi step on the iterate is requested, 2: applied
+  int stall_min, stall_mult;  // a round without progress for max(stall_min,
+                              // stall_mult x its productive length) ends (0: never)
   int pad_;
 };
 
@@ -276,7 +281,9 @@ __device__ __forceinline__ bool is_zero(c128 a) { return a.re == 0.0 && a.im == 
 
 // Lane state transition from the totals gamma' (tg), delta' (td), ||r'||^2.
 // On the complex64 path the solve runs in rounds: each round iterates until
-// its recurrence residual has dropped by round_tol (or reached eps ||v||);
+// its recurrence residual has dropped by round_tol (or reached eps ||v||), or
+// until it stalls (no halving of its best residual for a number of iterations
+// set by stall_min and stall_mult);
 // then the residual is recomputed in FP64 from the FP64 iterate and, unless
 // that meets eps ||v||, a fresh round starts from it (iterative refinement of
 // the inner solve; the recurrences restart, the iterate accumulates).
@@ -291,8 +298,6 @@ __device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double t
       s.its = 0;
     }
     s.rnorm = rn;
-    s.rn0 = rn;
-    s.its0 = s.its;
     if (rn <= eps * s.vnorm || s.vnorm == 0.0) {
       s.done = 1; s.conv = 1; s.verified = 1;
       return;
@@ -301,6 +306,20 @@ __device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double t
       s.done = 1; s.conv = 0; s.verified = 1;
       return;
     }
+    if (!fresh && s.kick == 0 && rn > 0.5 * s.rn0) {
+      // the last round did not halve the FP64 residual: COCG has met a
+      // near-breakdown of its bilinear form (r^T D^-1 r small against
+      // ||r||^2 / |D|), and restarting from the same residual would meet it
+      // again.  Ask for one damped Jacobi step on the iterate first.
+      s.kick = 1;
+      s.done = 1; s.conv = 1; s.verified = 0;
+      return;
+    }
+    s.kick = 0;
+    s.rn0 = rn;
+    s.its0 = s.its;
+    s.rbest = rn;
+    s.its_best = s.its;
     s.gamma = tg;
     s.beta = c128{0.0, 0.0};
     s.alpha = cdiv(tg, td);
@@ -315,6 +334,19 @@ __device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double t
     s.done = 1;
     s.conv = 1;
     s.verified = s.trust;
+    return;
+  }
+  if (s.rnorm < 0.5 * s.rbest) {
+    s.rbest = s.rnorm;
+    s.its_best = s.its;
+  } else if (!s.trust && s.stall_min > 0 &&
+             s.its - s.its_best > max(s.stall_min, s.stall_mult * (s.its_best - s.its0))) {
+    // a round of the complex64 solve that has stopped making progress (its
+    // recurrence no longer halves the residual) ends early: the next round
+    // restarts from the FP64 residual of the FP64 iterate
+    s.done = 1;
+    s.conv = 1;
+    s.verified = 0;
     return;
   }
   c128 den{0.0, 0.0};
@@ -357,7 +389,7 @@ template <typename R> struct CgVecs {
 // x = 0, p = 0, s = 0, r = v, w = A D^{-1} v; partials v^T u, w^T u, ||v||^2.
 template <typename Op, typename R>
 __global__ void __launch_bounds__(BS) k_cg_init(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
-                                                int maxit, int trust, double round_tol, const cx<R>* __restrict__ v,
+                                                CgScal proto, const cx<R>* __restrict__ v,
                                                 CgVecs<R> vec,
                                                 c128* __restrict__ part, CgScal* __restrict__ sc0,
                                                 int* __restrict__ all_done) {
@@ -366,8 +398,8 @@ __global__ void __launch_bounds__(BS) k_cg_init(Op op, const cx<R>* __restrict__
   const int rl = threadIdx.x & (S - 1);
   const cx<R> tr = cvt<R>(tau);
   auto gu = [&](int cc) { return v[(cc << lS) + rl] * dinv[cc]; };
-  cx<R> ag{0, 0}, ad{0, 0};
-  R arr = 0;
+  c128 ag{0, 0}, ad{0, 0};
+  double arr = 0;
   for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
     const int c = t >> lS;
     const cx<R> vv = v[t];
@@ -378,19 +410,16 @@ __global__ void __launch_bounds__(BS) k_cg_init(Op op, const cx<R>* __restrict__
     vec.s[0][t] = cx<R>{0, 0};
     vec.r[0][t] = vv;
     vec.w[0][t] = ww;
-    ag = ag + vv * uu;
-    ad = ad + ww * uu;
-    arr += abs2(vv);
+    ag = ag + cvt<double>(vv) * cvt<double>(uu);
+    ad = ad + cvt<double>(ww) * cvt<double>(uu);
+    arr += abs2(cvt<double>(vv));
   }
-  c128 acc[3] = {cvt<double>(ag), cvt<double>(ad), {(double)arr, 0.0}};
+  c128 acc[3] = {ag, ad, {arr, 0.0}};
   block_partials<3>(acc, S, part + (size_t)blockIdx.x * 3 * S);
   if (blockIdx.x == 0) {
     if ((int)threadIdx.x < S) {
-      CgScal s{};
+      CgScal s = proto;
       s.fresh = 1;
-      s.maxit = maxit;
-      s.trust = trust;
-      s.round_tol = round_tol;
       sc0[threadIdx.x] = s;
     }
     if (threadIdx.x == 0) *all_done = 0;
@@ -436,7 +465,7 @@ __device__ __forceinline__ void cg_load(const Op& op, const cx<R>* __restrict__ 
 template <typename Op, typename R, bool NT>
 __device__ __forceinline__ void cg_compute(const CgCell<Op, R>& L, int t, cx<R> al, cx<R> be, c128 al64, cx<R> tr,
                                            const CgVecs<R>& vec, cx<R>* __restrict__ r1, cx<R>* __restrict__ w1,
-                                           cx<R>* __restrict__ s1, cx<R>& ag, cx<R>& ad, R& arr) {
+                                           cx<R>* __restrict__ s1, c128& ag, c128& ad, double& arr) {
   constexpr int NB = Op::NB;
   const cx<R> sn = L.wc + be * L.sc;
   const cx<R> rn = L.rc - al * sn;
@@ -450,9 +479,13 @@ __device__ __forceinline__ void cg_compute(const CgCell<Op, R>& L, int t, cx<R> 
   st<NT>(r1 + t, rn);
   st<NT>(w1 + t, wn);
   st<NT>(s1 + t, sn);
-  ag = ag + rn * un;
-  ad = ad + wn * un;
-  arr += abs2(rn);
+  // products of the stored (rounded) values formed exactly in FP64: the
+  // bilinear forms can cancel strongly, and FP32 products would then
+  // dominate their error
+  const c128 rd = cvt<double>(rn), ud = cvt<double>(un);
+  ag = ag + rd * ud;
+  ad = ad + cvt<double>(wn) * ud;
+  arr += abs2(rd);
 }
 
 // One iteration.  Vectors alternate between two buffers by launch parity
@@ -501,8 +534,8 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) *all_done = 1;
     return;
   }
-  cx<R> ag{0, 0}, ad{0, 0};
-  R arr = 0;
+  c128 ag{0, 0}, ad{0, 0};
+  double arr = 0;
   if (!s.done) {
     const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta), tr = cvt<R>(tau);
     const c128 al64 = s.alpha;
@@ -539,13 +572,14 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict_
         r1[t] = rn;
         w1[t] = wn;
         s1[t] = sn;
-        ag = ag + rn * un;
-        ad = ad + wn * un;
-        arr += abs2(rn);
+        const c128 rd = cvt<double>(rn), ud = cvt<double>(un);
+        ag = ag + rd * ud;
+        ad = ad + cvt<double>(wn) * ud;
+        arr += abs2(rd);
       }
     }
   }
-  c128 acc[3] = {cvt<double>(ag), cvt<double>(ad), {(double)arr, 0.0}};
+  c128 acc[3] = {ag, ad, {arr, 0.0}};
   block_partials<3, CGB>(acc, S, partOut + (size_t)blockIdx.x * 3 * S);
 }
 
@@ -587,21 +621,43 @@ __global__ void __launch_bounds__(BS) k_cg_replace_w(Op op, const cx<R>* __restr
   cx<R>* __restrict__ w0 = vec.w[par];
   const cx<R> tr = cvt<R>(tau);
   auto gu = [&](int cc) { return r0[(cc << lS) + rl] * dinv[cc]; };
-  cx<R> ag{0, 0}, ad{0, 0};
+  c128 ag{0, 0}, ad{0, 0};
   for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
     const int c = t >> lS;
     const cx<R> uu = gu(c);
     const cx<R> ww = op.template apply<R>(c, tr, gu);
     w0[t] = ww;
-    ag = ag + r0[t] * uu;
-    ad = ad + ww * uu;
+    ag = ag + cvt<double>(r0[t]) * cvt<double>(uu);
+    ad = ad + cvt<double>(ww) * cvt<double>(uu);
   }
-  c128 acc[2] = {cvt<double>(ag), cvt<double>(ad)};
+  c128 acc[2] = {ag, ad};
   block_partials<2>(acc, S, part + (size_t)blockIdx.x * 3 * S);
   __syncthreads();
   if (blockIdx.x == 0) {
-    if ((int)threadIdx.x < S && sc[threadIdx.x].conv && !sc[threadIdx.x].verified) sc[threadIdx.x].replaced = 1;
+    if ((int)threadIdx.x < S && sc[threadIdx.x].conv && !sc[threadIdx.x].verified) {
+      sc[threadIdx.x].replaced = 1;
+      if (sc[threadIdx.x].kick == 1) sc[threadIdx.x].kick = 2;
+    }
     if (threadIdx.x == 0) *all_done = 0;
+  }
+}
+
+// Damped Jacobi step x += D^-1 r / 2 for the lanes that asked for one (kick
+// = 1), with r the FP64 residual of the iterate just stored by
+// k_cg_replace_r in the buffers of this parity; k_cg_replace_r then
+// recomputes the residual of the new iterate.  D + tau M is diagonally dominant, so the step does not grow the
+// residual, and it changes its direction away from the near-breakdown.
+template <typename R>
+__global__ void __launch_bounds__(BS) k_cg_kick(int n, int lS, const cx<R>* __restrict__ dinv,
+                                                const CgScal* __restrict__ sc, CgVecs<R> vec, int par) {
+  const int S = 1 << lS;
+  const int N = n << lS;
+  const int rl = threadIdx.x & (S - 1);
+  if (sc[rl].kick != 1) return;
+  const cx<R>* __restrict__ r = vec.r[par];
+  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
+    const int c = t >> lS;
+    vec.x[t] = vec.x[t] + 0.5 * (cvt<double>(dinv[c]) * cvt<double>(r[t]));
   }
 }
 
@@ -652,9 +708,11 @@ __global__ void __launch_bounds__(BS) k_gs_dot(long N, int S, int kc, const cx<R
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   for (int i = wv; i < kc; i += NWAVE) {
     const cx<R>* Vi = V + (size_t)i * cstride;
-    cx<R> a{0, 0};
-    for (long t = start + lane; t < end; t += WAVE) a = a + cdot(Vi[t], w[t]);
-    c128 s = wave_sum_strided(cvt<double>(a), S);
+    // exact products of the stored values, FP64 sums (the projections in the
+    // second pass are small differences of large terms)
+    c128 a{0, 0};
+    for (long t = start + lane; t < end; t += WAVE) a = a + cdot(cvt<double>(Vi[t]), cvt<double>(w[t]));
+    c128 s = wave_sum_strided(a, S);
     if (lane < S) part[((size_t)blockIdx.x * kc + i) * S + lane] = s;
   }
 }
@@ -683,19 +741,21 @@ __global__ void __launch_bounds__(BS) k_gs_update(long N, int S, int kc, const c
                                                   c128* __restrict__ part) {
   const int r = threadIdx.x & (S - 1);
   const long base = (long)blockIdx.x * BS * GSQ + threadIdx.x;
-  cx<R> wq[GSQ];
+  // the update runs in FP64 and w is rounded to its storage precision once:
+  // after the projection w is a small difference of large terms
+  c128 wq[GSQ];
 #pragma unroll
   for (int qq = 0; qq < GSQ; ++qq) {
     const long t = base + (long)qq * BS;
-    wq[qq] = t < N ? w[t] : cx<R>{0, 0};
+    wq[qq] = t < N ? cvt<double>(w[t]) : c128{0, 0};
   }
   for (int i = 0; i < kc; ++i) {
-    const cx<R> hi = cvt<R>(h[i * S + r]);
+    const c128 hi = h[i * S + r];
     const cx<R>* Vi = V + (size_t)i * cstride;
 #pragma unroll
     for (int qq = 0; qq < GSQ; ++qq) {
       const long t = base + (long)qq * BS;
-      if (t < N) wq[qq] = wq[qq] - hi * Vi[t];
+      if (t < N) wq[qq] = wq[qq] - hi * cvt<double>(Vi[t]);
     }
   }
   double a = 0.0;
@@ -703,8 +763,9 @@ __global__ void __launch_bounds__(BS) k_gs_update(long N, int S, int kc, const c
   for (int qq = 0; qq < GSQ; ++qq) {
     const long t = base + (long)qq * BS;
     if (t < N) {
-      w[t] = wq[qq];
-      a += abs2(cvt<double>(wq[qq]));
+      const cx<R> ws = cvt<R>(wq[qq]);
+      w[t] = ws;
+      a += abs2(cvt<double>(ws));
     }
   }
   if (!with_norm) return;

@@ -3,6 +3,7 @@
 // FP64 true residuals and refinement, and the step-level entry points.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -223,13 +224,17 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 // the partials, and a skew added between the large workspace arrays.
 // Defaults are the fastest measured on MI355X at 512x512 (256-thread blocks,
 // streaming stores on the complex64 path); SHK_CG_BLOCK, SHK_NT_STORE,
-// SHK_SEP_LIMIT and SHK_WS_SKEW override them for tuning sweeps.
+// SHK_SEP_LIMIT and SHK_WS_SKEW override them for tuning sweeps.  The
+// complex64 inner rounds' reduction target and stall rule ("min,mult") are
+// SHK_ROUND_TOL and SHK_STALL.
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
   int nt32 = 1;
   long sep_limit = 3072;   // fold partials in a separate kernel above this many
   size_t skew = 0;
+  double round_tol = 1e-2; // complex64 inner rounds: reduction per round
+  int stall_min = 150, stall_mult = 3;
   Tune() {
     if (const char* e = getenv("SHK_CG_BLOCK")) {
       const int v = atoi(e);
@@ -238,6 +243,10 @@ struct Tune {
     if (const char* e = getenv("SHK_WS_SKEW")) skew = (size_t)strtoull(e, nullptr, 10) & ~size_t(255);
     if (const char* e = getenv("SHK_NT_STORE")) nt64 = nt32 = atoi(e) != 0;
     if (const char* e = getenv("SHK_SEP_LIMIT")) sep_limit = atol(e);
+    if (const char* e = getenv("SHK_ROUND_TOL")) round_tol = atof(e);
+    if (const char* e = getenv("SHK_STALL")) {
+      if (sscanf(e, "%d,%d", &stall_min, &stall_mult) != 2) stall_min = stall_mult = 0;
+    }
   }
 };
 static Tune g_tune;
@@ -449,7 +458,13 @@ template <typename R, typename Op, typename OpD> struct Group {
       return B.ctot[slot];
     };
     const int Gin = gp.separate ? 1 : G;
-    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, cap, replace ? 0 : 1, replace ? 1e-2 : 0.0, v, vec,
+    CgScal proto{};
+    proto.maxit = cap;
+    proto.trust = replace ? 0 : 1;
+    proto.round_tol = replace ? g_tune.round_tol : 0.0;
+    proto.stall_min = g_tune.stall_min;
+    proto.stall_mult = g_tune.stall_mult;
+    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, proto, v, vec,
                                         B.cpart[0], B.sc, B.all_done);
     const c128* in = totals(0);
     SHK_HIP(hipGetLastError());
@@ -496,12 +511,20 @@ template <typename R, typename Op, typename OpD> struct Group {
       its_before = its_now;
       round_start = false;
       if (snap->all_done) {
-        bool unverified = false;
-        for (int r = 0; r < S; ++r) unverified |= snap->sc[r].conv && !snap->sc[r].verified;
-        if (!replace || !unverified || replacements >= 12) break;
+        bool unverified = false, kick = false;
+        for (int r = 0; r < S; ++r) {
+          unverified |= snap->sc[r].conv && !snap->sc[r].verified;
+          kick |= snap->sc[r].kick == 1;
+        }
+        if (!replace || !unverified || replacements >= 24) break;
         // new round: r = v - A x in FP64 (and w = A D^-1 r); the next step judges it
         CgScal* scCur = B.sc + (size_t)(it & 1) * S;
         const int slot = (int)(it & 1);
+        if (kick) {
+          // FP64 residual of the current iterate into r, then the Jacobi step
+          k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, ni, lS, v, vec, slot, B.cpart[slot]);
+          k_cg_kick<R><<<G, BS, 0, st>>>(ni, lS, B.dinv, scCur, vec, slot);
+        }
         k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, ni, lS, v, vec, slot, B.cpart[slot]);
         k_cg_replace_w<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, scCur, vec, slot, B.cpart[slot], B.all_done);
         in = totals(slot);

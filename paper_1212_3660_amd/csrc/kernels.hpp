@@ -260,93 +260,135 @@ __global__ void __launch_bounds__(BS) k_apply(Op op, c128 sigma, long n, int S, 
 // (and w with it) and the iteration resumes where needed (residual
 // replacement, van der Vorst and Ye), so the inner tolerance holds for the
 // true residual.
+// What a lane does in a launch of the iteration kernel.
+enum CgMode : int {
+  CG_ITER = 0,   // one COCG iteration
+  CG_RR = 1,     // FP64 residual r = v - (K + tau M) x of the FP64 iterate
+  CG_KX = 2,     // damped Jacobi step x += D^-1 r / 2
+  CG_RW = 3,     // round start: w = A D^-1 r and the round's first bilinear forms
+  CG_FRESH = 4   // state left by k_cg_init (its r, w and forms are a round start)
+};
+
+// Settings of one inner solve, the same for every lane.
+struct CgCfg {
+  double eps;        // stop at ||r|| <= eps ||v|| (negative: a fixed count)
+  double round_tol;  // reduction per round (complex64 path), 0 on the FP64 path
+  int maxit;
+  int trust;         // 1: the recurrence residual is final (FP64 path, no rounds)
+  int stall_min, stall_mult;  // a round without progress for max(stall_min,
+                              // stall_mult x its productive length) ends (0: never)
+};
+
+// Per-lane state of the inner solve (kept small: a single-lane launch holds it
+// in scalar registers).
 struct CgScal {
   c128 gamma, alpha, beta;
   double vnorm, rnorm, rstop;
-  int its, done, conv, maxit;
-  int fresh, replaced, verified, trust;  // trust: accept the recurrence residual (FP64 path)
-  double round_tol;
-  double rn0;   // residual norm at the start of the current round
-  int its0;     // iteration count at the start of the current round
-  int its_best; // iteration at which the round last halved its best residual
-  double rbest; // that residual
-  int kick;     // 1: a Jacobi step on the iterate is requested, 2: applied
-  int stall_min, stall_mult;  // a round without progress for max(stall_min,
-                              // stall_mult x its productive length) ends (0: never)
-  int pad_;
+  double rn0;        // residual norm at the start of the current round
+  double rbest;      // best residual of the round, halving by halving
+  int its;
+  int its0;          // iteration count at the start of the current round
+  int its_best;      // iteration at which rbest was reached
+  int rounds;        // rounds started
+  signed char done, conv;
+  signed char mode;  // CgMode of the launch that produced this state
+  signed char kick;  // 1: a Jacobi step was taken for the current round
 };
 
 
 __device__ __forceinline__ bool is_zero(c128 a) { return a.re == 0.0 && a.im == 0.0; }
 
-// Lane state transition from the totals gamma' (tg), delta' (td), ||r'||^2.
-// On the complex64 path the solve runs in rounds: each round iterates until
-// its recurrence residual has dropped by round_tol (or reached eps ||v||), or
-// until it stalls (no halving of its best residual for a number of iterations
-// set by stall_min and stall_mult);
-// then the residual is recomputed in FP64 from the FP64 iterate and, unless
-// that meets eps ||v||, a fresh round starts from it (iterative refinement of
-// the inner solve; the recurrences restart, the iterate accumulates).
-__device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double trr, double eps) {
-  if (s.fresh || s.replaced) {
-    const bool fresh = s.fresh != 0;
-    s.fresh = 0;
-    s.replaced = 0;
-    const double rn = sqrt(trr);
-    if (fresh) {
-      s.vnorm = rn;
-      s.its = 0;
-    }
-    s.rnorm = rn;
-    if (rn <= eps * s.vnorm || s.vnorm == 0.0) {
-      s.done = 1; s.conv = 1; s.verified = 1;
-      return;
-    }
-    if (s.its >= s.maxit || is_zero(td) || !(rn == rn)) {
-      s.done = 1; s.conv = 0; s.verified = 1;
-      return;
-    }
-    if (!fresh && s.kick == 0 && rn > 0.5 * s.rn0) {
-      // the last round did not halve the FP64 residual: COCG has met a
-      // near-breakdown of its bilinear form (r^T D^-1 r small against
-      // ||r||^2 / |D|), and restarting from the same residual would meet it
-      // again.  Ask for one damped Jacobi step on the iterate first.
-      s.kick = 1;
-      s.done = 1; s.conv = 1; s.verified = 0;
-      return;
-    }
-    s.kick = 0;
-    s.rn0 = rn;
-    s.its0 = s.its;
-    s.rbest = rn;
-    s.its_best = s.its;
-    s.gamma = tg;
-    s.beta = c128{0.0, 0.0};
-    s.alpha = cdiv(tg, td);
-    s.rstop = fmax(eps * s.vnorm, s.round_tol * rn);
-    s.done = 0; s.conv = 0; s.verified = 0;
+// A round starts from the forms gamma = r^T D^-1 r (tg), delta = w^T D^-1 r
+// (td) and ||r||^2 of the residual r it starts from; this launch iterates.
+__device__ __forceinline__ void cg_round_start(CgScal& s, const CgCfg& cfg, c128 tg, c128 td, double trr) {
+  const double eps = cfg.eps;
+  const double rn = sqrt(trr);
+  s.rnorm = rn;
+  if (rn <= eps * s.vnorm || s.vnorm == 0.0) {
+    s.done = 1; s.conv = 1;
     return;
   }
+  if (s.its >= cfg.maxit || is_zero(td) || !(rn == rn)) {
+    s.done = 1; s.conv = 0;
+    return;
+  }
+  s.rn0 = rn;
+  s.its0 = s.its;
+  s.rbest = rn;
+  s.its_best = s.its;
+  s.rounds += 1;
+  s.gamma = tg;
+  s.beta = c128{0.0, 0.0};
+  s.alpha = cdiv(tg, td);
+  s.rstop = fmax(eps * s.vnorm, cfg.round_tol * rn);
+  s.mode = CG_ITER;
+}
+
+// Lane state transition from the previous launch's totals (three forms whose
+// meaning follows the mode of that launch) to what this launch does.
+//
+// On the complex64 path the solve runs in rounds, entirely on the device: a
+// round iterates until its recurrence residual has dropped by round_tol (or
+// reached eps ||v||), or until it stalls (no halving of its best residual for
+// a number of iterations set by stall_min and stall_mult); the lane then
+// spends one launch forming the FP64 residual of its FP64 iterate (RR).  If
+// that meets eps ||v|| the lane is done; if the round failed to halve it,
+// COCG has met a near-breakdown of its bilinear form at that residual
+// (r^T D^-1 r small against ||r||^2 / |D|) and restarting from it would meet
+// it again, so one damped Jacobi step on the iterate (KX) and a new FP64
+// residual come first; otherwise the next launch (RW) forms w = A D^-1 r and
+// the new round's forms, and the round starts.  Lanes go through rounds
+// independently.  On the FP64 path the recurrence residual is final.
+__device__ __forceinline__ void cg_advance(CgScal& s, const CgCfg& cfg, c128 tg, c128 td, double trr) {
+  const double eps = cfg.eps;
   if (s.done) return;
+  switch (s.mode) {
+    case CG_FRESH:
+      s.vnorm = sqrt(trr);
+      s.its = 0;
+      cg_round_start(s, cfg, tg, td, trr);
+      return;
+    case CG_RW:
+      cg_round_start(s, cfg, tg, td, trr);
+      return;
+    case CG_KX:
+      s.mode = CG_RR;
+      return;
+    case CG_RR: {
+      const double rn = sqrt(trr);
+      s.rnorm = rn;
+      if (rn <= eps * s.vnorm) {
+        s.done = 1; s.conv = 1;
+      } else if (s.its >= cfg.maxit || !(rn == rn)) {
+        s.done = 1; s.conv = 0;
+      } else if (s.kick == 0 && rn > 0.5 * s.rn0) {
+        s.kick = 1;
+        s.mode = CG_KX;
+      } else {
+        s.kick = 0;
+        s.mode = CG_RW;
+      }
+      return;
+    }
+    default:
+      break;
+  }
   s.its += 1;
   s.rnorm = sqrt(trr);
   if (s.rnorm <= s.rstop) {
-    s.done = 1;
-    s.conv = 1;
-    s.verified = s.trust;
+    if (cfg.trust) {
+      s.done = 1; s.conv = 1;
+    } else {
+      s.mode = CG_RR;
+    }
     return;
   }
   if (s.rnorm < 0.5 * s.rbest) {
     s.rbest = s.rnorm;
     s.its_best = s.its;
-  } else if (!s.trust && s.stall_min > 0 &&
-             s.its - s.its_best > max(s.stall_min, s.stall_mult * (s.its_best - s.its0))) {
-    // a round of the complex64 solve that has stopped making progress (its
-    // recurrence no longer halves the residual) ends early: the next round
-    // restarts from the FP64 residual of the FP64 iterate
-    s.done = 1;
-    s.conv = 1;
-    s.verified = 0;
+  } else if (!cfg.trust && cfg.stall_min > 0 &&
+             s.its - s.its_best > max(cfg.stall_min, cfg.stall_mult * (s.its_best - s.its0))) {
+    s.mode = CG_RR;
     return;
   }
   c128 den{0.0, 0.0};
@@ -355,10 +397,12 @@ __device__ __forceinline__ void cg_advance(CgScal& s, c128 tg, c128 td, double t
     beta = cdiv(tg, s.gamma);
     den = td - cdiv(beta * tg, s.alpha);
   }
-  if (s.its >= s.maxit || !(s.rnorm == s.rnorm) || is_zero(den)) {
-    s.done = 1;
-    s.conv = 0;
-    s.verified = 1;
+  if (s.its >= cfg.maxit || !(s.rnorm == s.rnorm) || is_zero(den)) {
+    if (cfg.trust || !(s.rnorm == s.rnorm)) {
+      s.done = 1; s.conv = 0;
+    } else {
+      s.mode = CG_RR;   // judge the iterate in FP64
+    }
     return;
   }
   s.beta = beta;
@@ -389,7 +433,7 @@ template <typename R> struct CgVecs {
 // x = 0, p = 0, s = 0, r = v, w = A D^{-1} v; partials v^T u, w^T u, ||v||^2.
 template <typename Op, typename R>
 __global__ void __launch_bounds__(BS) k_cg_init(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
-                                                CgScal proto, const cx<R>* __restrict__ v,
+                                                const cx<R>* __restrict__ v,
                                                 CgVecs<R> vec,
                                                 c128* __restrict__ part, CgScal* __restrict__ sc0,
                                                 int* __restrict__ all_done) {
@@ -418,8 +462,8 @@ __global__ void __launch_bounds__(BS) k_cg_init(Op op, const cx<R>* __restrict__
   block_partials<3>(acc, S, part + (size_t)blockIdx.x * 3 * S);
   if (blockIdx.x == 0) {
     if ((int)threadIdx.x < S) {
-      CgScal s = proto;
-      s.fresh = 1;
+      CgScal s{};
+      s.mode = CG_FRESH;
       sc0[threadIdx.x] = s;
     }
     if (threadIdx.x == 0) *all_done = 0;
@@ -488,20 +532,23 @@ __device__ __forceinline__ void cg_compute(const CgCell<Op, R>& L, int t, cx<R> 
   arr += abs2(rd);
 }
 
-// One iteration.  Vectors alternate between two buffers by launch parity
-// (par, from the host): a lane that has stopped leaves its vectors where they
-// are, and a lane re-started by a refinement round gets fresh r and w in the
-// current buffers (its s enters multiplied by beta = 0, and every buffer holds
-// finite values).  The all-done flag, the previous step's partials and the
-// lane state are loaded together and the flag is judged only after the sums
-// (one memory round trip instead of two; when the flag is set the sums are
-// discarded).  ONE = the launch has a single lane (S = 1): the lane state is
-// then uniform and lives in scalar registers.  MULTI = the grid is smaller than
-// the items and threads loop over several cells (large problems); otherwise
-// each thread owns one cell.  Blocks take tiles in XCD-aware order.
-template <typename Op, typename R, int CGB, bool NT, bool ONE, bool MULTI>
-__global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS_,
-                                                 double eps, const c128* __restrict__ partIn, int Gin,
+// One launch of the inner solve for every lane: an iteration, or a step of a
+// round change on the complex64 path (see cg_advance).  Vectors alternate
+// between two buffers by launch parity (par, from the host): a lane that has
+// stopped leaves its vectors where they are, and a lane that starts a round
+// writes r and w for it into the next buffers (its s enters multiplied by
+// beta = 0 and every buffer holds finite values).  The all-done flag, the
+// previous launch's partials and the lane state are loaded together and the
+// flag is judged only after the sums (one memory round trip instead of two;
+// when the flag is set the sums are discarded).  ONE = the launch has a single
+// lane (S = 1): the lane state is then uniform and lives in scalar registers.
+// MULTI = the grid is smaller than the items and threads loop over several
+// cells (large problems); otherwise each thread owns one cell.  Blocks take
+// tiles in XCD-aware order.
+template <typename Op, typename OpD, typename R, int CGB, bool NT, bool ONE, bool MULTI>
+__global__ void __launch_bounds__(CGB) k_cg_step(Op op, OpD opd, const cx<R>* __restrict__ dinv, c128 tau, int n,
+                                                 int lS_, CgCfg cfg, const cx<R>* __restrict__ v,
+                                                 const c128* __restrict__ partIn, int Gin,
                                                  const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
                                                  CgVecs<R> vec, int par, c128* __restrict__ partOut,
                                                  int* __restrict__ all_done) {
@@ -521,13 +568,21 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict_
   cx<R>* __restrict__ w1 = vec.w[par ^ 1];
   cx<R>* __restrict__ s1 = vec.s[par ^ 1];
   const int t0 = xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x;
+  // the thread's cells: one, or a grid-stride loop when the grid is capped
+  auto for_cells = [&](auto&& f) {
+    if constexpr (MULTI) {
+      for (int t = t0; t < N; t += gridDim.x * CGB) f(t);
+    } else {
+      if (t0 < N) f(t0);
+    }
+  };
   c128 tot[3];
   part_sum<3, KMAX, CGB>(partIn, Gin, S, PL, tot);
   if (flag) {
     if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
     return;
   }
-  cg_advance(s, tot[0], tot[1], tot[2].re, eps);
+  cg_advance(s, cfg, tot[0], tot[1], tot[2].re);
   const bool any_open = __any(!s.done);
   if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
   if (!any_open) {
@@ -537,129 +592,82 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, const cx<R>* __restrict_
   c128 ag{0, 0}, ad{0, 0};
   double arr = 0;
   if (!s.done) {
-    const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta), tr = cvt<R>(tau);
-    const c128 al64 = s.alpha;
-    if constexpr (Op::NB > 0) {
-      if (t0 < N) {
-        CgCell<Op, R> L;
-        cg_load<Op, R>(op, dinv, lS, rl, t0, r0, w0, s0, vec, L);
-        cg_compute<Op, R, NT>(L, t0, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
-      }
-      if constexpr (MULTI) {
-        for (int t = t0 + gridDim.x * CGB; t < N; t += gridDim.x * CGB) {
+    const cx<R> tr = cvt<R>(tau);
+    if (s.mode == CG_ITER) {
+      const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta);
+      const c128 al64 = s.alpha;
+      if constexpr (Op::NB > 0) {
+        for_cells([&](int t) {
           CgCell<Op, R> L;
           cg_load<Op, R>(op, dinv, lS, rl, t, r0, w0, s0, vec, L);
           cg_compute<Op, R, NT>(L, t, al, be, al64, tr, vec, r1, w1, s1, ag, ad, arr);
-        }
+        });
+      } else {
+        // general sparse K: u' formed on the fly at every column of the row
+        auto gu = [&](int cc) {
+          const int k = (cc << lS) + rl;
+          return (r0[k] - al * (w0[k] + be * s0[k])) * dinv[cc];
+        };
+        for_cells([&](int t) {
+          const int c = t >> lS;
+          const cx<R> di = dinv[c];
+          const cx<R> rc = r0[t];
+          const cx<R> sn = w0[t] + be * s0[t];
+          const cx<R> rn = rc - al * sn;
+          const cx<R> pn = rc * di + be * vec.p[t];
+          vec.p[t] = pn;
+          vec.x[t] = vec.x[t] + al64 * cvt<double>(pn);
+          const cx<R> un = rn * di;
+          const cx<R> wn = op.template apply<R>(c, tr, gu);
+          r1[t] = rn;
+          w1[t] = wn;
+          s1[t] = sn;
+          const c128 rd = cvt<double>(rn), ud = cvt<double>(un);
+          ag = ag + rd * ud;
+          ad = ad + cvt<double>(wn) * ud;
+          arr += abs2(rd);
+        });
       }
-    } else {
-      // general sparse K: u' formed on the fly at every column of the row
-      auto gu = [&](int cc) {
-        const int k = (cc << lS) + rl;
-        return (r0[k] - al * (w0[k] + be * s0[k])) * dinv[cc];
-      };
-      for (int t = t0; t < N; t += gridDim.x * CGB) {
+    } else if (s.mode == CG_RR) {
+      // FP64 residual of the FP64 iterate, stored rounded; its FP64 norm
+      const c128* __restrict__ x = vec.x;
+      auto gx = [&](int cc) { return x[(cc << lS) + rl]; };
+      for_cells([&](int t) {
         const int c = t >> lS;
-        const cx<R> di = dinv[c];
+        const c128 res = cvt<double>(v[t]) - opd.template apply<double>(c, tau, gx);
+        r1[t] = cvt<R>(res);
+        arr += abs2(res);
+      });
+    } else if (s.mode == CG_KX) {
+      // damped Jacobi step on the iterate from the residual just formed; the
+      // diagonal dominance of K + tau M keeps it from growing the residual
+      for_cells([&](int t) {
+        const int c = t >> lS;
+        vec.x[t] = vec.x[t] + 0.5 * (cvt<double>(dinv[c]) * cvt<double>(r0[t]));
+      });
+    } else {
+      // CG_RW: w = A D^-1 r of the residual just formed, carried into the
+      // next buffers with r (s cleared), and the round's first forms
+      auto gu = [&](int cc) { return r0[(cc << lS) + rl] * dinv[cc]; };
+      for_cells([&](int t) {
+        const int c = t >> lS;
         const cx<R> rc = r0[t];
-        const cx<R> sn = w0[t] + be * s0[t];
-        const cx<R> rn = rc - al * sn;
-        const cx<R> pn = rc * di + be * vec.p[t];
-        vec.p[t] = pn;
-        vec.x[t] = vec.x[t] + al64 * cvt<double>(pn);
-        const cx<R> un = rn * di;
-        const cx<R> wn = op.template apply<R>(c, tr, gu);
-        r1[t] = rn;
-        w1[t] = wn;
-        s1[t] = sn;
-        const c128 rd = cvt<double>(rn), ud = cvt<double>(un);
+        const cx<R> uu = rc * dinv[c];
+        const cx<R> ww = op.template apply<R>(c, tr, gu);
+        r1[t] = rc;
+        w1[t] = ww;
+        s1[t] = cx<R>{0, 0};
+        const c128 rd = cvt<double>(rc), ud = cvt<double>(uu);
         ag = ag + rd * ud;
-        ad = ad + cvt<double>(wn) * ud;
+        ad = ad + cvt<double>(ww) * ud;
         arr += abs2(rd);
-      }
+      });
     }
   }
   c128 acc[3] = {ag, ad, {arr, 0.0}};
   block_partials<3, CGB>(acc, S, partOut + (size_t)blockIdx.x * 3 * S);
 }
 
-// Start of a refinement round, part 1: r = v - (K + tau M) x in FP64 from the
-// FP64 iterate, stored rounded in the r buffer of the current launch parity;
-// partial ||r||^2 in slot 2 of [G][3][S].
-template <typename OpD, typename R>
-__global__ void __launch_bounds__(BS) k_cg_replace_r(OpD opd, c128 tau, int n, int lS, const cx<R>* __restrict__ v,
-                                                     CgVecs<R> vec, int par, c128* __restrict__ part) {
-  const int S = 1 << lS;
-  const int N = n << lS;
-  const int rl = threadIdx.x & (S - 1);
-  cx<R>* __restrict__ rr = vec.r[par];
-  const c128* __restrict__ x = vec.x;
-  auto g = [&](int cc) { return x[(cc << lS) + rl]; };
-  double a = 0.0;
-  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
-    const int c = t >> lS;
-    const c128 res = cvt<double>(v[t]) - opd.template apply<double>(c, tau, g);
-    rr[t] = cvt<R>(res);
-    a += abs2(res);
-  }
-  c128 acc[1] = {{a, 0.0}};
-  block_partials<1>(acc, S, part + (size_t)blockIdx.x * 3 * S + 2 * S);
-}
-
-// Start of a refinement round, part 2: w = A D^{-1} r in the w buffer of the
-// current launch parity; partials r^T u, w^T u in slots 0, 1.  Lanes whose round ended
-// without a confirmed FP64 residual are marked for the next step, which either
-// accepts them or starts a fresh round.
-template <typename Op, typename R>
-__global__ void __launch_bounds__(BS) k_cg_replace_w(Op op, const cx<R>* __restrict__ dinv, c128 tau, int n, int lS,
-                                                     CgScal* __restrict__ sc, CgVecs<R> vec, int par,
-                                                     c128* __restrict__ part, int* __restrict__ all_done) {
-  const int S = 1 << lS;
-  const int N = n << lS;
-  const int rl = threadIdx.x & (S - 1);
-  const cx<R>* __restrict__ r0 = vec.r[par];
-  cx<R>* __restrict__ w0 = vec.w[par];
-  const cx<R> tr = cvt<R>(tau);
-  auto gu = [&](int cc) { return r0[(cc << lS) + rl] * dinv[cc]; };
-  c128 ag{0, 0}, ad{0, 0};
-  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
-    const int c = t >> lS;
-    const cx<R> uu = gu(c);
-    const cx<R> ww = op.template apply<R>(c, tr, gu);
-    w0[t] = ww;
-    ag = ag + cvt<double>(r0[t]) * cvt<double>(uu);
-    ad = ad + cvt<double>(ww) * cvt<double>(uu);
-  }
-  c128 acc[2] = {ag, ad};
-  block_partials<2>(acc, S, part + (size_t)blockIdx.x * 3 * S);
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    if ((int)threadIdx.x < S && sc[threadIdx.x].conv && !sc[threadIdx.x].verified) {
-      sc[threadIdx.x].replaced = 1;
-      if (sc[threadIdx.x].kick == 1) sc[threadIdx.x].kick = 2;
-    }
-    if (threadIdx.x == 0) *all_done = 0;
-  }
-}
-
-// Damped Jacobi step x += D^-1 r / 2 for the lanes that asked for one (kick
-// = 1), with r the FP64 residual of the iterate just stored by
-// k_cg_replace_r in the buffers of this parity; k_cg_replace_r then
-// recomputes the residual of the new iterate.  D + tau M is diagonally dominant, so the step does not grow the
-// residual, and it changes its direction away from the near-breakdown.
-template <typename R>
-__global__ void __launch_bounds__(BS) k_cg_kick(int n, int lS, const cx<R>* __restrict__ dinv,
-                                                const CgScal* __restrict__ sc, CgVecs<R> vec, int par) {
-  const int S = 1 << lS;
-  const int N = n << lS;
-  const int rl = threadIdx.x & (S - 1);
-  if (sc[rl].kick != 1) return;
-  const cx<R>* __restrict__ r = vec.r[par];
-  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
-    const int c = t >> lS;
-    vec.x[t] = vec.x[t] + 0.5 * (cvt<double>(dinv[c]) * cvt<double>(r[t]));
-  }
-}
 
 // After the inner solve: true inner residual p = v - (K + tau M) z in FP64
 // (its norm enters the bound of eq. resdiff) and the mass product w = M z

@@ -410,13 +410,13 @@ template <typename R, typename Op, typename OpD> struct Group {
   int outer_steps = 0;
 
   template <int CGB, bool NT, bool ONE, bool MULTI>
-  void step_k(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+  void step_k(int G, c128 tau, int ni, int lS, const CgCfg& e, const c128* in, int Gin, const CgScal* scIn,
               CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
-    k_cg_step<Op, R, CGB, NT, ONE, MULTI><<<G, CGB, 0, st>>>(op, B.dinv, tau, ni, lS, e, in, Gin, scIn, scOut, vec,
-                                                             par, out, B.all_done);
+    k_cg_step<Op, OpD, R, CGB, NT, ONE, MULTI><<<G, CGB, 0, st>>>(op, opd, B.dinv, tau, ni, lS, e, cur_v, in, Gin,
+                                                                  scIn, scOut, vec, par, out, B.all_done);
   }
   template <int CGB, bool NT>
-  void step_nt(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+  void step_nt(int G, c128 tau, int ni, int lS, const CgCfg& e, const c128* in, int Gin, const CgScal* scIn,
                CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
     const bool multi = (long)G * CGB < N;
     if (lS == 0) {
@@ -428,27 +428,29 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
   }
   template <int CGB>
-  void step_cgb(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+  void step_cgb(int G, c128 tau, int ni, int lS, const CgCfg& e, const c128* in, int Gin, const CgScal* scIn,
                 CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
     if (std::is_same<R, float>::value ? g_tune.nt32 : g_tune.nt64)
       step_nt<CGB, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
     else
       step_nt<CGB, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
   }
-  void launch_step(int G, c128 tau, int ni, int lS, double e, const c128* in, int Gin, const CgScal* scIn,
+  void launch_step(int G, c128 tau, int ni, int lS, const CgCfg& e, const c128* in, int Gin, const CgScal* scIn,
                    CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
     if (g_tune.cgb == 512) step_cgb<512>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
     else step_cgb<256>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
   }
 
   // ---- inner solve of (K + tau M) z = v (section 4) into z, w = M z ----
+  const cx<R>* cur_v = nullptr;   // right-hand side of the running inner solve
   int inner(c128 tau, const cx<R>* v, c128* z, double eps, int maxit, int fixed, double* pn_out) {
     const int G = gp.G;
-    const bool replace = std::is_same<R, float>::value && fixed <= 0;
+    const bool rounds = std::is_same<R, float>::value && fixed <= 0;
     const double e = fixed > 0 ? -1.0 : eps;
     const int cap = fixed > 0 ? fixed : maxit;
     const int lS = ilog2(S);
     const int ni = (int)n;
+    cur_v = v;
     CgVecs<R> vec{{B.cr[0], B.cr[1]}, {B.cw[0], B.cw[1]}, {B.cs[0], B.cs[1]}, B.cp, z};
     k_dinv<OpD, R><<<grid_items(n, 2048), BS, 0, st>>>(opd, p->dK, tau, ni, B.dinv);
     // partials of launch L live in cpart[L & 1] (totals in ctot[L & 1])
@@ -458,14 +460,14 @@ template <typename R, typename Op, typename OpD> struct Group {
       return B.ctot[slot];
     };
     const int Gin = gp.separate ? 1 : G;
-    CgScal proto{};
-    proto.maxit = cap;
-    proto.trust = replace ? 0 : 1;
-    proto.round_tol = replace ? g_tune.round_tol : 0.0;
-    proto.stall_min = g_tune.stall_min;
-    proto.stall_mult = g_tune.stall_mult;
-    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, proto, v, vec,
-                                        B.cpart[0], B.sc, B.all_done);
+    CgCfg cfg{};
+    cfg.eps = fixed > 0 ? -1.0 : eps;
+    cfg.maxit = cap;
+    cfg.trust = rounds ? 0 : 1;
+    cfg.round_tol = rounds ? g_tune.round_tol : 0.0;
+    cfg.stall_min = g_tune.stall_min;
+    cfg.stall_mult = g_tune.stall_mult;
+    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, v, vec, B.cpart[0], B.sc, B.all_done);
     const c128* in = totals(0);
     SHK_HIP(hipGetLastError());
     long it = 0;
@@ -473,22 +475,21 @@ template <typename R, typename Op, typename OpD> struct Group {
     static_assert(sizeof(Snap) <= 32768, "staging layout");
     Snap* snap = (Snap*)g_pinned.get(65536);
     if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
-    int replacements = 0;
     const bool timing = g_timer.on;
     if (timing) g_timer.ensure(1);
-    // per lane: iteration count, residual norm and round start seen at the
-    // previous poll (for the rate estimate), and the max count over lanes
-    std::vector<int> prev_its(S, 0), prev_its0(S, -1);
+    // per lane: iteration count and residual norm seen at the previous poll
+    std::vector<int> prev_its(S, 0);
     std::vector<double> prev_rn(S, 0.0);
-    int its_before = 0;
-    bool round_start = true;   // the chunk's first launch starts a round
+    int its_before = 0, rounds_before = S;
+    bool first = true;   // the chunk's first launch starts the solve
+    const double lrt = std::log(std::max(g_tune.round_tol, 1e-12));
     while (true) {
       if (timing) (void)hipEventRecord(g_timer.ev[0], st);
       for (int c = 0; c < chunk; ++c, ++it) {
         const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
         CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
         const int out = (int)((it + 1) & 1);
-        launch_step(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
+        launch_step(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
         in = totals(out);
       }
       if (timing) (void)hipEventRecord(g_timer.ev[1], st);
@@ -496,11 +497,15 @@ template <typename R, typename Op, typename OpD> struct Group {
       SHK_HIP(hipMemcpyAsync(&snap->all_done, B.all_done, sizeof(int), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipMemcpyAsync(snap->sc, B.sc + (size_t)(it & 1) * S, S * sizeof(CgScal), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
-      int its_now = 0;
-      for (int r = 0; r < S; ++r) its_now = std::max(its_now, snap->sc[r].its);
-      if (timing && its_now - its_before == chunk - (round_start ? 1 : 0)) {
-        // every launch of the chunk iterated: its time is kernel time plus the
-        // back-to-back dispatch gaps
+      int its_now = 0, rounds_now = 0;
+      for (int r = 0; r < S; ++r) {
+        its_now = std::max(its_now, snap->sc[r].its);
+        rounds_now += snap->sc[r].rounds;
+      }
+      if (timing && !snap->all_done && rounds_now == rounds_before &&
+          its_now - its_before == chunk - (first ? 1 : 0)) {
+        // every launch of the chunk iterated (no round change, no idle
+        // launch): its time is kernel time plus the back-to-back gaps
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, g_timer.ev[0], g_timer.ev[1]) == hipSuccess) {
           g_timer.total_ms += ms;
@@ -509,60 +514,41 @@ template <typename R, typename Op, typename OpD> struct Group {
         }
       }
       its_before = its_now;
-      round_start = false;
-      if (snap->all_done) {
-        bool unverified = false, kick = false;
-        for (int r = 0; r < S; ++r) {
-          unverified |= snap->sc[r].conv && !snap->sc[r].verified;
-          kick |= snap->sc[r].kick == 1;
-        }
-        if (!replace || !unverified || replacements >= 24) break;
-        // new round: r = v - A x in FP64 (and w = A D^-1 r); the next step judges it
-        CgScal* scCur = B.sc + (size_t)(it & 1) * S;
-        const int slot = (int)(it & 1);
-        if (kick) {
-          // FP64 residual of the current iterate into r, then the Jacobi step
-          k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, ni, lS, v, vec, slot, B.cpart[slot]);
-          k_cg_kick<R><<<G, BS, 0, st>>>(ni, lS, B.dinv, scCur, vec, slot);
-        }
-        k_cg_replace_r<OpD, R><<<G, BS, 0, st>>>(opd, tau, ni, lS, v, vec, slot, B.cpart[slot]);
-        k_cg_replace_w<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, scCur, vec, slot, B.cpart[slot], B.all_done);
-        in = totals(slot);
-        SHK_HIP(hipGetLastError());
-        ++replacements;
-        chunk = 16;
-        round_start = true;
-        continue;
-      }
-      // hang guard only: every lane stops itself after cap iterations, so at
-      // most cap launches do work; the rest are the tails of the chunks
-      if (it > 4L * cap + 16L * 512) break;
-      // Steps to the end of the current round: each running lane's rate over
-      // the iterations since the previous poll (since the round began if that
-      // window is short), never more than the iterations the round has
-      // already taken (a poll costs about as much as ten idle launches, an
-      // early overestimate of a slow start far more).
+      rounds_before = rounds_now;
+      first = false;
+      if (snap->all_done) break;
+      // hang guard only: every lane stops itself after cap iterations and a
+      // bounded number of round changes; the rest are the tails of chunks
+      if (it > 8L * cap + 16L * 512) break;
+      // Launches to the end of the solve: each running lane's rate (the mean
+      // of its rate since the start and since the previous poll), two more
+      // launches per remaining refinement round, and never more than the
+      // iterations already taken (a poll costs about as much as a few idle
+      // launches; an early overestimate of a slow start far more).
       int need = 4;
       for (int r = 0; r < S; ++r) {
         const CgScal& s = snap->sc[r];
-        const int k = s.its - s.its0;
         int rem = 16;
-        if (s.rstop <= 0.0) {
-          rem = s.maxit - s.its + 1;   // fixed iteration count
-        } else if (!s.done && k >= 4 && s.rnorm > 0.0) {
-          double rate = s.rnorm < s.rn0 ? std::log(s.rnorm / s.rn0) / k : 0.0;
+        if (e < 0.0) {
+          rem = cap - s.its + 1;   // fixed iteration count
+        } else if (!s.done && s.its >= 4 && s.rnorm > 0.0 && s.rnorm < s.vnorm) {
+          const double target = e * s.vnorm;
+          double rate = std::log(s.rnorm / s.vnorm) / s.its;
           const int kw = s.its - prev_its[r];
-          if (prev_its0[r] == s.its0 && kw >= 8 && s.rnorm < prev_rn[r])
-            rate = std::log(s.rnorm / prev_rn[r]) / kw;
-          if (s.rnorm <= s.rstop) rem = 2;
-          else if (rate < 0.0) rem = (int)std::ceil(std::log(s.rstop / s.rnorm) / rate * 1.05) + 2;
-          rem = std::min(rem, std::max(16, k));
+          if (kw >= 8 && s.rnorm < prev_rn[r]) rate = 0.5 * (rate + std::log(s.rnorm / prev_rn[r]) / kw);
+          if (s.rnorm <= target) {
+            rem = 3;
+          } else {
+            const double lr = std::log(target / s.rnorm);
+            rem = (int)std::ceil(lr / rate * 1.05) + 2;
+            if (!cfg.trust) rem += 2 * (int)std::ceil(lr / lrt);
+          }
+          rem = std::min(rem, std::max(16, s.its));
         }
         prev_its[r] = s.its;
-        prev_its0[r] = s.its0;
         prev_rn[r] = s.rnorm;
         if (s.done) continue;
-        rem = std::min(rem, s.maxit - s.its + 1);
+        rem = std::min(rem, cap - s.its + 8);
         need = std::max(need, std::min(rem, 512));
       }
       chunk = need;

@@ -12,7 +12,10 @@ shifts with inputs resident on the device.
 
 Prints one JSON line.  The value is shifted solves per second of the mixed
 (complex64 bulk, FP64 least squares / residuals / refinement) path; the plain
-FP64 path is timed the same way and reported beside it.
+FP64 path is timed the same way and reported beside it.  Unless --no-extra,
+the line also carries the batched workloads (256x256 with 64 forward+adjoint
+right-hand sides, 128^3 with 8), mixed and FP64 with all right-hand sides in
+lockstep and, for 256x256, FP64 one right-hand side at a time.
 """
 import argparse
 import hashlib
@@ -21,6 +24,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -92,6 +97,36 @@ def time_path(P, torch, gp, w, precision, steps, warmup, profile=False):
                 sweeps=sweeps, prof=prof)
 
 
+def time_batched(P, torch, w, make, precision, single_rhs_sample=0):
+    """One solve of a multi-rhs workload (all rhs in lockstep); with
+    single_rhs_sample > 0, instead that many rhs solved one at a time and the
+    rate scaled to all of them.  Returns shifted solves/s and the worst true
+    relative residual."""
+    gp = make(w)
+    prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
+                              eps_inner=w.eps_inner, precision=precision)
+    nf, nr = len(w.sigma), w.b.shape[1]
+    cols = list(range(single_rhs_sample)) if single_rhs_sample else [list(range(nr))]
+    worst, ok, total = 0.0, True, 0.0
+    for c in cols:
+        idx = [c] if single_rhs_sample else c
+        b = torch.from_numpy(np.ascontiguousarray(w.b[:, idx].T)).cuda()
+        P.fgmres_sh_solve(gp, prm, w.sigma, b)          # warm-up (allocations, code load)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, st = P.fgmres_sh_solve(gp, prm, w.sigma, b)
+        e1.record()
+        e1.synchronize()
+        total += e0.elapsed_time(e1) / 1e3
+        worst = max(worst, float(st["true_relres"].max()))
+        ok &= bool((st["status"] == P.SHK_CONVERGED).all())
+    solves = nf * (len(cols) if single_rhs_sample else nr)
+    gp.close()
+    return {"solves_per_s": round(solves / total, 1), "ms": round(total * 1e3, 1), "converged": ok,
+            "max_true_relres": worst}
+
+
 def cpu_baseline(w, seconds, gpu_outer_steps):
     """The CPU oracle (FGMRES-Sh, complex128, Jacobi-COCG inner) on the same
     workload, bounded to a few outer steps; scaled to a full solve with the
@@ -130,6 +165,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched 256x256 / 128^3 workloads")
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--single-solve", choices=["mixed", "fp64"], default=None,
                     help="run one solve of the workload and exit (for profiler counter passes)")
@@ -198,6 +234,24 @@ def main():
                     "max_true_relres": fp64["worst"], "inner_iterations": fp64["inner"],
                     "outer_steps": fp64["outer"], "refine_sweeps": fp64["sweeps"]},
            "roofline": roof, "cpu_baseline": None}
+    if not a.no_extra:
+        # the batched workloads: 256x256 with 32 well sources + 32 adjoint
+        # receiver vectors, and 128^3 with 8 sources; mixed and FP64 paths in
+        # lockstep over the rhs, and the 256x256 FP64 path one rhs at a time
+        w3 = synth.config3()
+        mk2 = lambda w: P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+        mk3 = lambda w: P.Problem.fv3d(w.cell_K, w.Ss, w.h)
+        out["batched"] = {
+            "2-D FV 256x256, 50 shifts, 64 rhs": {
+                "mixed_batched": time_batched(P, torch, w3, mk2, P.SHK_MIXED),
+                "fp64_batched": time_batched(P, torch, w3, mk2, P.SHK_FP64),
+                "fp64_single_rhs": dict(time_batched(P, torch, w3, mk2, P.SHK_FP64, single_rhs_sample=4),
+                                        sample="4 of the 64 rhs solved one at a time, rate over those")},
+        }
+        w4 = synth.config4()
+        out["batched"]["3-D FV 128^3, 100 shifts, 8 rhs"] = {
+            "mixed_batched": time_batched(P, torch, w4, mk3, P.SHK_MIXED),
+            "fp64_batched": time_batched(P, torch, w4, mk3, P.SHK_FP64)}
     if not a.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, mixed["outer"])

@@ -11,12 +11,15 @@ Contents (complex128 throughout):
   exact      exact x_j = (K + sigma_j M)^{-1} b: banded elimination, SuperLU,
              dense, DST-I closed form, 1-D discrete Green's function
   cocg       Jacobi-COCG inner solve (section 4, eq. zmmoditer)
+  mg         geometric aggregation multigrid V-cycle, multigrid-preconditioned
+             COCG (the inner solve with a multigrid preconditioner, section 6)
   fgmres_sh  Algorithms 3 and 4 with inexact inner solves, restart, refinement
 """
 from .fv import Problem, assemble_stiffness, face_transmissivities, mass_diagonal  # noqa: F401
 from .exact import (banded_solve, dense_solve, superlu_solve, dst_closed_form,  # noqa: F401
                     dst_mode, green_1d, laplacian_eigenvalues, exact_family)
 from .cocg import cocg  # noqa: F401
+from .mg import Hierarchy, vcycle, pcocg, mg_cocg  # noqa: F401
 from .fgmres_sh import (fgmres_sh, refine, true_residuals, mgs_step,  # noqa: F401
                         shifted_hessenberg, small_solve, CONVERGED, NOT_CONVERGED,
                         INNER_LIMITED, BREAKDOWN_EXACT, NAN_STATUS)

@@ -42,6 +42,7 @@ import numpy as np
 
 from .cocg import cocg
 from .exact import banded_solve, dense_solve, superlu_solve
+from .mg import Hierarchy, mg_cocg
 
 CONVERGED, NOT_CONVERGED, INNER_LIMITED, BREAKDOWN_EXACT, NAN_STATUS = 0, 1, 2, 3, 4
 BREAKDOWN_REL = 1e-14
@@ -110,7 +111,8 @@ def small_solve(Hs: np.ndarray, beta: complex, variant: str):
     return y, rhs - Hs @ y
 
 
-def make_inner(problem, inner: str, eps: float, inner_maxit: Optional[int]):
+def make_inner(problem, inner: str, eps: float, inner_maxit: Optional[int], mg_nu: int = 1,
+               mg_omega: float = 0.8):
     """Returns f(v, tau) -> (z, its)."""
     cache = {}
     if inner_maxit is None:
@@ -121,6 +123,13 @@ def make_inner(problem, inner: str, eps: float, inner_maxit: Optional[int]):
         def f(v, tau):
             diag = problem.diag(tau)
             z, its, _ok, _h = cocg(lambda x: problem.apply(tau, x), diag, v, eps, inner_maxit)
+            return z, its
+        return f
+    if inner == "mg":
+        H = Hierarchy.of(problem)
+
+        def f(v, tau):
+            z, its, _ok, _h = mg_cocg(problem, tau, v, eps, inner_maxit, H, mg_nu, mg_omega)
             return z, its
         return f
 
@@ -144,12 +153,13 @@ def make_inner(problem, inner: str, eps: float, inner_maxit: Optional[int]):
 def fgmres_sh(problem, b, sigmas, tau_seq, *, m_restart=50, max_restarts=20, tol=1e-8,
               inner="cocg", eps=1e-10, inner_maxit=None, variant="gmres",
               max_steps=None, keep_basis=False, record_quasi=False,
-              stop_after_restart=None) -> Result:
+              stop_after_restart=None, mg_nu=1, mg_omega=0.8) -> Result:
     """Solve (K + sigma_j M) x_j = b for all shifts with one flexible basis.
 
     ``tau_seq`` is used cyclically over the global step counter.  ``inner`` is
-    "cocg" (Jacobi-COCG to ``eps``), or an exact solve ("superlu", "banded",
-    "dense").  ``max_steps`` caps the total number of outer steps (for timing
+    "cocg" (Jacobi-COCG to ``eps``), "mg" (COCG preconditioned by the multigrid
+    V-cycle of oracle.mg with ``mg_nu`` damped-Jacobi sweeps of weight
+    ``mg_omega``), or an exact solve ("superlu", "banded", "dense").  ``max_steps`` caps the total number of outer steps (for timing
     samples); ``stop_after_restart`` returns right after the restart update of
     that cycle (0-based), to inspect the restarted residuals.  Returns x as an
     (n, n_f) array plus per-shift information."""
@@ -170,7 +180,7 @@ def fgmres_sh(problem, b, sigmas, tau_seq, *, m_restart=50, max_restarts=20, tol
         for s in info:
             s.status, s.quasi_relres, s.bound_relres, s.true_relres = CONVERGED, 0.0, 0.0, 0.0
         return res
-    solve_inner = make_inner(problem, inner, eps, inner_maxit)
+    solve_inner = make_inner(problem, inner, eps, inner_maxit, mg_nu, mg_omega)
     M = problem.Mdiag
     beta = np.full(nf, beta0, dtype=np.complex128)
     gap_prev = np.zeros(nf)

@@ -69,6 +69,10 @@ typedef struct shk_server shk_server;
                         residual and refinement in FP64                             */
 #define SHK_PTR_HOST 0
 #define SHK_PTR_DEVICE 1
+#define SHK_PRECOND_JACOBI 0     /* inner COCG with D = diag(K + tau M)              */
+#define SHK_PRECOND_MULTIGRID 1  /* inner COCG preconditioned by a geometric
+                                    aggregation multigrid V-cycle (structured
+                                    finite-volume problems only)                  */
 
 /*
  * Solver parameters (inputs of Algorithm 4 plus library knobs).
@@ -88,6 +92,16 @@ typedef struct shk_server shk_server;
  *  precision      SHK_FP64 or SHK_MIXED.
  *  refine_tol     relative accuracy asked of each refinement correction solve.
  *  refine_eps_inner  inner tolerance of the correction solves.
+ *  inner_precond  preconditioner of the inner COCG: SHK_PRECOND_JACOBI, or
+ *                 SHK_PRECOND_MULTIGRID (section 6 preconditions the paper's
+ *                 inner solver with multigrid): cells grouped 2^d per level
+ *                 down to one cell, coarse faces half the sum of the fine
+ *                 faces they cover, coarse mass the sum, one V-cycle with
+ *                 mg_sweeps damped Jacobi sweeps of weight mg_omega before and
+ *                 after the coarse correction; a call error (UNSUPPORTED) for
+ *                 CSR problems.
+ *  mg_sweeps      1 (the only value provided; others are a call error).
+ *  mg_omega       Jacobi damping of the smoother, in (0, 1].
  */
 typedef struct {
   int m_restart;
@@ -102,6 +116,9 @@ typedef struct {
   int precision;
   double refine_tol;
   double refine_eps_inner;
+  int inner_precond;
+  int mg_sweeps;
+  double mg_omega;
 } shk_params;
 
 /* Per-(shift, rhs) result, host memory, n_shifts x n_rhs column-major. */
@@ -117,7 +134,8 @@ typedef struct {
 } shk_status;
 
 /* Fill *p with defaults: m 50, 20 restarts, 2 refinement sweeps, tol 1e-8,
- * eps 1e-10, GMRES, FP64, refine_tol 0.05, refine_eps_inner 5e-3, no tau. */
+ * eps 1e-10, GMRES, FP64, refine_tol 0.05, refine_eps_inner 5e-3, no tau,
+ * Jacobi inner preconditioner (multigrid settings 1 sweep, omega 0.8). */
 void shk_params_default(shk_params* p);
 
 /*
@@ -176,7 +194,9 @@ int shk_apply_shifted(shk_problem* p, shk_c128 sigma, int n_rhs, const void* x, 
                       int precision, void* hip_stream);
 
 /* Inner preconditioner solve z ~ (K + tau M)^{-1} v (section 4, eq. zmmoditer):
- * Jacobi-preconditioned COCG from z = 0, stopped when the residual satisfies
+ * COCG from z = 0 preconditioned by precond (SHK_PRECOND_JACOBI, or
+ * SHK_PRECOND_MULTIGRID: the V-cycle of shk_params with one sweep, omega 0.8),
+ * stopped when the residual satisfies
  * ||r|| <= eps ||v|| or after maxit iterations (0: 20 * largest grid dim);
  * fixed_iters > 0 runs exactly that many iterations instead.  v and w use the
  * vector precision; the iterate z is always complex128 (on the complex64 path
@@ -185,7 +205,7 @@ int shk_apply_shifted(shk_problem* p, shk_c128 sigma, int n_rhs, const void* x, 
  * pnorm[r] = ||v - (K + tau M) z|| (FP64).  Also writes w = M z in the vector
  * precision (device, may be NULL). */
 int shk_inner_solve(shk_problem* p, shk_c128 tau, int n_rhs, const void* v, void* z, void* w,
-                    double eps, int maxit, int fixed_iters, int precision, int* its,
+                    double eps, int maxit, int fixed_iters, int precision, int precond, int* its,
                     double* pnorm, void* hip_stream);
 
 /* One orthogonalisation step of Algorithm 3 (classical Gram-Schmidt with one

@@ -22,6 +22,7 @@ SHK_CONVERGED, SHK_NOT_CONVERGED, SHK_INNER_LIMITED, SHK_BREAKDOWN_EXACT, SHK_NA
 SHK_GMRES, SHK_FOM = 0, 1
 SHK_FP64, SHK_MIXED = 0, 1
 SHK_PTR_HOST, SHK_PTR_DEVICE = 0, 1
+SHK_PRECOND_JACOBI, SHK_PRECOND_MULTIGRID = 0, 1
 
 
 class shk_c128(C.Structure):
@@ -32,7 +33,8 @@ class shk_params(C.Structure):
     _fields_ = [("m_restart", C.c_int), ("max_restarts", C.c_int), ("max_refine", C.c_int),
                 ("inner_maxit", C.c_int), ("tol", C.c_double), ("eps_inner", C.c_double),
                 ("n_tau", C.c_int), ("tau_seq", C.POINTER(shk_c128)), ("variant", C.c_int),
-                ("precision", C.c_int), ("refine_tol", C.c_double), ("refine_eps_inner", C.c_double)]
+                ("precision", C.c_int), ("refine_tol", C.c_double), ("refine_eps_inner", C.c_double),
+                ("inner_precond", C.c_int), ("mg_sweeps", C.c_int), ("mg_omega", C.c_double)]
 
 
 class shk_status(C.Structure):
@@ -73,7 +75,7 @@ _SIGS = {
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int]),
     "shk_apply_shifted": (C.c_int, [C.c_void_p, shk_c128, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "shk_inner_solve": (C.c_int, [C.c_void_p, shk_c128, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
-                                  C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+                                  C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "shk_orthogonalize": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                     C.c_void_p]),
     "shk_shifted_lsq": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p,
@@ -134,7 +136,7 @@ def _c128_array(values) -> "C.Array":
 
 def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_maxit=0, tol=1e-8,
                 eps_inner=1e-10, precision=SHK_FP64, variant=SHK_GMRES, refine_tol=0.05,
-                refine_eps_inner=5e-3):
+                refine_eps_inner=5e-3, inner_precond=None, mg_omega=0.8):
     """Returns (shk_params, keepalive) with tau_seq marshalled to C."""
     taus = _c128_array(tau_seq)
     p = shk_params()
@@ -145,6 +147,9 @@ def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_m
     p.tau_seq = C.cast(taus, C.POINTER(shk_c128))
     p.variant, p.precision = variant, precision
     p.refine_tol, p.refine_eps_inner = refine_tol, refine_eps_inner
+    if inner_precond is not None:
+        p.inner_precond = inner_precond
+    p.mg_omega = mg_omega
     return p, taus
 
 
@@ -276,14 +281,16 @@ def shk_apply_shifted(problem: Problem, sigma: complex, x, y, n_rhs: int = 1, st
 
 
 def shk_inner_solve(problem: Problem, tau: complex, v, z, w=None, eps=1e-10, maxit=0, fixed_iters=0, n_rhs=1,
-                    stream=None):
-    """Jacobi-COCG z ~ (K + tau M)^{-1} v; returns (iterations, true residual norms)."""
+                    precond=SHK_PRECOND_JACOBI, stream=None):
+    """COCG z ~ (K + tau M)^{-1} v (Jacobi or multigrid preconditioner); returns
+    (iterations, true residual norms)."""
     t = shk_c128(float(np.real(tau)), float(np.imag(tau)))
     its = np.zeros(n_rhs, dtype=np.int32)
     pn = np.zeros(n_rhs, dtype=np.float64)
     _check(lib().shk_inner_solve(problem.handle, t, n_rhs, C.c_void_p(v.data_ptr()), C.c_void_p(z.data_ptr()),
                                  C.c_void_p(w.data_ptr()) if w is not None else None, eps, maxit, fixed_iters,
-                                 _prec(v), its.ctypes.data, pn.ctypes.data, _stream_ptr(stream)), "shk_inner_solve")
+                                 _prec(v), precond, its.ctypes.data, pn.ctypes.data, _stream_ptr(stream)),
+           "shk_inner_solve")
     return its, pn
 
 

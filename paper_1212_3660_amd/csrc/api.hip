@@ -23,6 +23,9 @@ void shk_params_default(shk_params* p) {
   p->precision = SHK_FP64;
   p->refine_tol = 0.05;
   p->refine_eps_inner = 5e-3;
+  p->inner_precond = SHK_PRECOND_JACOBI;
+  p->mg_sweeps = 1;
+  p->mg_omega = 0.8;
 }
 
 static int create_fv(int nx, int ny, int nz, shk::Kind kind, const double* cell_K, double Ss, double h,
@@ -110,9 +113,9 @@ int shk_apply_shifted(shk_problem* p, shk_c128 sigma, int n_rhs, const void* x, 
 }
 
 int shk_inner_solve(shk_problem* p, shk_c128 tau, int n_rhs, const void* v, void* z, void* w, double eps, int maxit,
-                    int fixed_iters, int precision, int* its, double* pnorm, void* hip_stream) {
-  return shk::step_inner(p, c128{tau.re, tau.im}, n_rhs, v, z, w, eps, maxit, fixed_iters, precision, its, pnorm,
-                         (hipStream_t)hip_stream);
+                    int fixed_iters, int precision, int precond, int* its, double* pnorm, void* hip_stream) {
+  return shk::step_inner(p, c128{tau.re, tau.im}, n_rhs, v, z, w, eps, maxit, fixed_iters, precision, precond, its,
+                         pnorm, (hipStream_t)hip_stream);
 }
 
 int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128* h, int precision, void* hip_stream) {

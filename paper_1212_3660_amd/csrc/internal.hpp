@@ -26,6 +26,16 @@ int fail(int code, const std::string& msg);
 
 enum class Kind { FV2D, FV3D, CSR };
 
+// One coarse level of the multigrid hierarchy (level 0 is the problem's own
+// grid): cells, faces (FP64 and FP32) and per-cell mass on the device.
+struct MgLevel {
+  int nx = 1, ny = 1, nz = 1;
+  long long n = 0;
+  double* t[3] = {nullptr, nullptr, nullptr};
+  float* t32[3] = {nullptr, nullptr, nullptr};
+  double* mass = nullptr;
+};
+
 }  // namespace shk
 
 // The problem: device copies of the operator coefficients in FP64 (and FP32
@@ -47,6 +57,7 @@ struct shk_problem {
   float* dK32 = nullptr;
   double* mdiag = nullptr;          // per-row mass (CSR only)
   long long nnz = 0;
+  std::vector<shk::MgLevel> mg;     // coarse levels (finite-volume problems)
   int max_dim() const { return nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz); }
 };
 
@@ -59,7 +70,7 @@ int solve_all(shk_problem* p, const shk_params* prm, int n_shifts, const c128* s
 int step_apply(shk_problem* p, c128 sigma, int S, const void* x, void* y, int precision,
                hipStream_t stream);
 int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w, double eps,
-               int maxit, int fixed_iters, int precision, int* its, double* pnorm,
+               int maxit, int fixed_iters, int precision, int precond, int* its, double* pnorm,
                hipStream_t stream);
 int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precision,
               hipStream_t stream);

@@ -277,6 +277,8 @@ struct CgCfg {
   int trust;         // 1: the recurrence residual is final (FP64 path, no rounds)
   int stall_min, stall_mult;  // a round without progress for max(stall_min,
                               // stall_mult x its productive length) ends (0: never)
+  int fused_start;   // 1: the launch after a residual replacement already has the
+                     // new round's forms (multigrid path), 0: it forms them (RW)
 };
 
 // Per-lane state of the inner solve (kept small: a single-lane launch holds it
@@ -366,7 +368,8 @@ __device__ __forceinline__ void cg_advance(CgScal& s, const CgCfg& cfg, c128 tg,
         s.mode = CG_KX;
       } else {
         s.kick = 0;
-        s.mode = CG_RW;
+        if (cfg.fused_start) cg_round_start(s, cfg, tg, td, trr);
+        else s.mode = CG_RW;
       }
       return;
     }

@@ -12,6 +12,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "mg.hpp"
 
 namespace shk {
 
@@ -97,14 +98,58 @@ void problem_free(shk_problem* p, hipStream_t st) {
                   p->dK, p->dK32};
   for (void* q : ptrs)
     if (q) (void)hipFreeAsync(q, st);
+  for (MgLevel& l : p->mg) {
+    for (int a = 0; a < 3; ++a) {
+      if (l.t[a]) (void)hipFreeAsync(l.t[a], st);
+      if (l.t32[a]) (void)hipFreeAsync(l.t32[a], st);
+    }
+    if (l.mass) (void)hipFreeAsync(l.mass, st);
+  }
+  p->mg.clear();
   (void)hipStreamSynchronize(st);
+}
+
+// Coarse levels of the multigrid hierarchy, down to one cell: faces (half the
+// sum of the fine faces each covers) and mass (the sum over the group).
+static int mg_setup(shk_problem* p, hipStream_t st) {
+  const int d = p->kind == Kind::FV3D ? 3 : 2;
+  LevelDims f{p->nx, p->ny, p->nz};
+  const double* ft[3] = {p->tx, p->ty, p->tz};
+  const double* fm = nullptr;
+  while (f.n() > 1) {
+    const LevelDims c = f.coarse();
+    MgLevel l;
+    l.nx = c.nx; l.ny = c.ny; l.nz = c.nz; l.n = c.n();
+    p->mg.push_back(l);
+    MgLevel& L = p->mg.back();
+    for (int a = 0; a < d; ++a) {
+      const long cnt = (long)(c.nx + (a == 0)) * (c.ny + (a == 1)) * (c.nz + (a == 2));
+      if (hipMallocAsync((void**)&L.t[a], cnt * sizeof(double), st) != hipSuccess ||
+          hipMallocAsync((void**)&L.t32[a], cnt * sizeof(float), st) != hipSuccess)
+        return fail(SHK_ERR_OOM, "multigrid faces");
+      k_mg_faces<<<grid_items(cnt, 4096), BS, 0, st>>>(f, c, a, ft[a], L.t[a], L.t32[a]);
+      SHK_HIP(hipGetLastError());
+    }
+    if (hipMallocAsync((void**)&L.mass, (size_t)c.n() * sizeof(double), st) != hipSuccess)
+      return fail(SHK_ERR_OOM, "multigrid mass");
+    k_mg_mass<<<grid_items(c.n(), 4096), BS, 0, st>>>(f, c, fm, p->m0, L.mass);
+    SHK_HIP(hipGetLastError());
+    for (int a = 0; a < 3; ++a) ft[a] = L.t[a];
+    fm = L.mass;
+    f = c;
+  }
+  return SHK_OK;
 }
 
 size_t problem_bytes(const shk_problem* p) {
   if (p->kind == Kind::CSR) return (size_t)p->nnz * 16 + (size_t)p->n * 24;
   const size_t faces = (size_t)(p->nx + 1) * p->ny * p->nz + (size_t)p->nx * (p->ny + 1) * p->nz +
                        (p->kind == Kind::FV3D ? (size_t)p->nx * p->ny * (p->nz + 1) : 0);
-  return faces * 12 + (size_t)p->n * 12;
+  size_t coarse = 0;
+  for (const MgLevel& l : p->mg)
+    coarse += (size_t)l.n * 8 + ((size_t)(l.nx + 1) * l.ny * l.nz + (size_t)l.nx * (l.ny + 1) * l.nz +
+                                 (p->kind == Kind::FV3D ? (size_t)l.nx * l.ny * (l.nz + 1) : 0)) * 12;
+  return faces * 12 + (size_t)p->n * 12 + coarse;
 }
 
 int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipStream_t st) {
@@ -146,6 +191,7 @@ int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipSt
   }
   SHK_HIP(hipGetLastError());
   SHK_HIP(hipFreeAsync(Kd, st));
+  SHK_TRY(mg_setup(p, st));
   SHK_HIP(hipStreamSynchronize(st));
   return SHK_OK;
 }
@@ -294,8 +340,23 @@ template <typename R> struct Buffers {
   c128 *bint, *rsv, *X;
   c128* rpart;      // residual partials [s][nf][Gr]
   c128* rrow;       // residual rows [s*nf]
+  // multigrid inner preconditioner: u = B r, and per coarse level l >= 1 the
+  // right-hand side, solution and inverse diagonal of the V-cycle
+  cx<R>* u = nullptr;
+  std::vector<cx<R>*> mb, mx, mdinv;
   size_t bytes;
 };
+
+// Multigrid buffers for S lanes over the coarse levels of p (none: no levels).
+template <typename R> static void carve_mg(Carver& cv, Buffers<R>& b, const shk_problem* p, long N, int S) {
+  b.u = cv.take<cx<R>>(N);
+  b.mb.clear(); b.mx.clear(); b.mdinv.clear();
+  for (const MgLevel& l : p->mg) {
+    b.mb.push_back(cv.take<cx<R>>((size_t)l.n * S));
+    b.mx.push_back(cv.take<cx<R>>((size_t)l.n * S));
+    b.mdinv.push_back(cv.take<cx<R>>((size_t)l.n));
+  }
+}
 
 static int resid_grid(long n) { return grid_items(n, 256); }
 static long dot_ipb(long N) {
@@ -305,8 +366,9 @@ static long dot_ipb(long N) {
 }
 
 template <typename R>
-static Buffers<R> carve(char* base, long n, int m, int nf, int S, int s_real, bool host_x) {
+static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, int s_real, bool host_x, bool mg) {
   Carver cv{base};
+  const long n = p->n;
   Buffers<R> b{};
   const long N = n * S;
   const int L = nf * S;
@@ -336,6 +398,7 @@ static Buffers<R> carve(char* base, long n, int m, int nf, int S, int s_real, bo
   b.mz = cv.take<double>(S);
   b.nzs = cv.take<double>(S);
   b.pn = cv.take<double>((size_t)m * S);
+  if (mg) carve_mg(cv, b, p, N, S);
   b.H = cv.take<c128>((size_t)m * (m + 2) * S);
   b.h2 = cv.take<c128>((size_t)(m + 1) * S);
   b.taus = cv.take<c128>(m);
@@ -363,9 +426,10 @@ static Buffers<R> carve(char* base, long n, int m, int nf, int S, int s_real, bo
 
 static int lanes_of(int n_rhs) { return std::min(64, next_pow2(std::max(1, n_rhs))); }
 
-static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real, int precision, bool host_x) {
-  if (precision == SHK_MIXED) return carve<float>(nullptr, p->n, m, nf, S, s_real, host_x).bytes;
-  return carve<double>(nullptr, p->n, m, nf, S, s_real, host_x).bytes;
+static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real, int precision, bool host_x,
+                          bool mg) {
+  if (precision == SHK_MIXED) return carve<float>(nullptr, p, m, nf, S, s_real, host_x, mg).bytes;
+  return carve<double>(nullptr, p, m, nf, S, s_real, host_x, mg).bytes;
 }
 
 // ------------------------------------------------------- lane totals -------
@@ -441,6 +505,123 @@ template <typename R, typename Op, typename OpD> struct Group {
     else step_cgb<256>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
   }
 
+  // ---- multigrid V-cycle (inner preconditioner) ----
+  bool mg = false;                // COCG preconditioned by the V-cycle
+  double mg_omega = 0.8;
+  int mg_levels() const { return 1 + (int)p->mg.size(); }
+  LevelDims mg_dims(int l) const {
+    if (l == 0) return {p->nx, p->ny, p->nz};
+    const MgLevel& L = p->mg[l - 1];
+    return {L.nx, L.ny, L.nz};
+  }
+  // operator of level l in precision F (level 0: the problem's own)
+  template <typename O, typename F> O mg_op(const O& base, int l) const {
+    if (l == 0) return base;
+    O o = base;
+    if constexpr (O::NB > 0) {
+      const MgLevel& L = p->mg[l - 1];
+      auto faces = [&](int a) -> const F* {
+        if constexpr (std::is_same<F, float>::value) return L.t32[a];
+        else return L.t[a];
+      };
+      o.nx = L.nx; o.ny = L.ny; o.tx = faces(0); o.ty = faces(1);
+      if constexpr (O::NB == 6) { o.nz = L.nz; o.tz = faces(2); }
+      o.mdiag = L.mass; o.m0 = 0.0;
+    }
+    return o;
+  }
+  // inverse diagonals of the coarse levels for this tau
+  void mg_prepare(c128 tau) {
+    if constexpr (Op::NB > 0) {
+      for (int l = 1; l < mg_levels(); ++l) {
+        const int nl = mg_dims(l).n();
+        k_mg_dinv<OpD, R><<<grid_items(nl, 2048), BS, 0, st>>>(mg_op<OpD, double>(opd, l), tau, nl, B.mdinv[l - 1]);
+      }
+    }
+  }
+  // uout = B b0 (one V-cycle over every level)
+  void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout) {
+    if constexpr (Op::NB > 0) {
+      const int Lv = mg_levels();
+      const int S_ = 1 << lS;
+      if (Lv == 1) {   // one cell: the exact solve is the Jacobi scaling
+        k_mg_scale<R><<<1, BS, 0, st>>>(S_, B.dinv, b0, uout, B.all_done);
+        return;
+      }
+      const cx<R>* bl = b0;
+      for (int l = 0; l + 1 < Lv; ++l) {
+        const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
+        const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
+        const Op o = mg_op<Op, R>(op, l);
+        const int g = grid_items((long)c.n() * S_, 8192);
+        if (l + 2 == Lv) {
+          k_mg_down<Op, R, true><<<g, BS, 0, st>>>(o, f, c, tau, mg_omega, lS, bl, dl, B.mx[l], B.mdinv[l],
+                                                     B.all_done);
+        } else {
+          k_mg_down<Op, R, false><<<g, BS, 0, st>>>(o, f, c, tau, mg_omega, lS, bl, dl, B.mb[l], nullptr,
+                                                      B.all_done);
+          bl = B.mb[l];
+        }
+      }
+      for (int l = Lv - 2; l >= 0; --l) {
+        const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
+        const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
+        const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
+        cx<R>* out = l == 0 ? uout : B.mx[l - 1];
+        const int g = grid_items((long)f.n() * S_, 8192);
+        k_mg_up<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl2, dl, B.mx[l], out,
+                                          B.all_done);
+      }
+    }
+  }
+  // w = A u and the forms with r, on the iteration kernels' grid
+  template <int CGB>
+  void mg_post_cgb(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
+    if constexpr (Op::NB > 0) {
+      const bool multi = (long)G * CGB < N;
+      if (lS == 0) {
+        if (multi) k_cgmg_post<Op, R, CGB, true, true><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+        else k_cgmg_post<Op, R, CGB, true, false><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      } else {
+        if (multi) k_cgmg_post<Op, R, CGB, false, true><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+        else k_cgmg_post<Op, R, CGB, false, false><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      }
+    }
+  }
+  void mg_post(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
+    if (g_tune.cgb == 512) mg_post_cgb<512>(G, tau, ni, lS, sc, r, w, out);
+    else mg_post_cgb<256>(G, tau, ni, lS, sc, r, w, out);
+  }
+  template <int CGB, bool ONE, bool MULTI>
+  void mg_iter_k(int G, c128 tau, int ni, int lS, const CgCfg& cfg, const c128* in, int Gin, const CgScal* scIn,
+                 CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
+    if constexpr (Op::NB > 0) {
+      k_cgmg_step<Op, OpD, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(opd, tau, ni, lS, cfg, cur_v, B.u, in, Gin, scIn,
+                                                                  scOut, vec, par, B.all_done);
+      mg_vcycle(vec.r[par ^ 1], tau, lS, B.u);
+      k_cgmg_post<Op, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(op, tau, ni, lS, scOut, vec.r[par ^ 1], B.u,
+                                                             vec.w[par ^ 1], out, B.all_done);
+    }
+  }
+  template <int CGB>
+  void mg_iter_cgb(int G, c128 tau, int ni, int lS, const CgCfg& cfg, const c128* in, int Gin, const CgScal* scIn,
+                   CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
+    const bool multi = (long)G * CGB < N;
+    if (lS == 0) {
+      if (multi) mg_iter_k<CGB, true, true>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
+      else mg_iter_k<CGB, true, false>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
+    } else {
+      if (multi) mg_iter_k<CGB, false, true>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
+      else mg_iter_k<CGB, false, false>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
+    }
+  }
+  // one multigrid-COCG iteration: vector updates, V-cycle, operator product
+  void mg_iteration(int G, c128 tau, int ni, int lS, const CgCfg& cfg, const c128* in, int Gin,
+                    const CgScal* scIn, CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
+    if (g_tune.cgb == 512) mg_iter_cgb<512>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
+    else mg_iter_cgb<256>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
+  }
+
   // ---- inner solve of (K + tau M) z = v (section 4) into z, w = M z ----
   const cx<R>* cur_v = nullptr;   // right-hand side of the running inner solve
   int inner(c128 tau, const cx<R>* v, c128* z, double eps, int maxit, int fixed, double* pn_out) {
@@ -467,7 +648,16 @@ template <typename R, typename Op, typename OpD> struct Group {
     cfg.round_tol = rounds ? g_tune.round_tol : 0.0;
     cfg.stall_min = g_tune.stall_min;
     cfg.stall_mult = g_tune.stall_mult;
+    cfg.fused_start = mg ? 1 : 0;
     k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, v, vec, B.cpart[0], B.sc, B.all_done);
+    if (mg) {
+      if constexpr (Op::NB > 0) {
+        // the first round's u = B v, w = A u and forms
+        mg_prepare(tau);
+        mg_vcycle(vec.r[0], tau, lS, B.u);
+        mg_post(G, tau, ni, lS, B.sc, vec.r[0], vec.w[0], B.cpart[0]);
+      }
+    }
     const c128* in = totals(0);
     SHK_HIP(hipGetLastError());
     long it = 0;
@@ -475,7 +665,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     static_assert(sizeof(Snap) <= 32768, "staging layout");
     Snap* snap = (Snap*)g_pinned.get(65536);
     if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
-    const bool timing = g_timer.on;
+    const bool timing = g_timer.on && !mg;   // the timer follows the Jacobi iteration kernel
     if (timing) g_timer.ensure(1);
     // per lane: iteration count and residual norm seen at the previous poll
     std::vector<int> prev_its(S, 0);
@@ -489,7 +679,8 @@ template <typename R, typename Op, typename OpD> struct Group {
         const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
         CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
         const int out = (int)((it + 1) & 1);
-        launch_step(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
+        if (mg) mg_iteration(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
+        else launch_step(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
         in = totals(out);
       }
       if (timing) (void)hipEventRecord(g_timer.ev[1], st);
@@ -698,7 +889,8 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
   const int m = prm->m_restart;
   const long n = p->n;
   const bool host_x = ptr_kind == SHK_PTR_HOST;
-  Buffers<R> B = carve<R>(ws, n, m, nf, S, s_real, host_x);
+  const bool use_mg = prm->inner_precond == SHK_PRECOND_MULTIGRID;
+  Buffers<R> B = carve<R>(ws, p, m, nf, S, s_real, host_x, use_mg);
   c128* X = host_x ? B.X : x_dst;
   const long N = n * S;
   // rhs into interleaved c128
@@ -722,6 +914,8 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     using Op = decltype(op);
     using OpD = decltype(opd);
     Group<R, Op, OpD> g{p, op, opd, st, B, n, N, S, s_real, nf, m, nf * S, item_plan(N, S)};
+    g.mg = use_mg;
+    g.mg_omega = prm->mg_omega;
     PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0};
     SHK_TRY(g.pass(B.bint, ps, X, false, nullptr));
     SHK_HIP(hipMemcpyAsync(lanes.data(), B.ls, sizeof(LaneState) * nf * S, hipMemcpyDeviceToHost, st));
@@ -818,6 +1012,13 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
   if (!(prm->tol > 0.0) || !(prm->eps_inner >= 0.0)) return fail(SHK_ERR_INVALID_ARG, "tol must be > 0, eps >= 0");
   if (prm->variant != SHK_GMRES) return fail(SHK_ERR_UNSUPPORTED, "only the GMRES variant runs on the GPU path");
   if (prm->precision != SHK_FP64 && prm->precision != SHK_MIXED) return fail(SHK_ERR_INVALID_ARG, "precision");
+  if (prm->inner_precond != SHK_PRECOND_JACOBI && prm->inner_precond != SHK_PRECOND_MULTIGRID)
+    return fail(SHK_ERR_INVALID_ARG, "inner_precond");
+  if (prm->inner_precond == SHK_PRECOND_MULTIGRID) {
+    if (p->kind == Kind::CSR) return fail(SHK_ERR_UNSUPPORTED, "multigrid needs a finite-volume problem");
+    if (prm->mg_sweeps != 1) return fail(SHK_ERR_UNSUPPORTED, "mg_sweeps must be 1");
+    if (!(prm->mg_omega > 0.0 && prm->mg_omega <= 1.0)) return fail(SHK_ERR_INVALID_ARG, "mg_omega must be in (0, 1]");
+  }
   for (int i = 0; i < prm->n_tau; ++i)
     if (!std::isfinite(prm->tau_seq[i].re) || !std::isfinite(prm->tau_seq[i].im))
       return fail(SHK_ERR_INVALID_ARG, "non-finite tau");
@@ -826,7 +1027,8 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
 
 size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x) {
   const int s_real = std::min(n_rhs, 64);
-  return group_bytes(p, prm->m_restart, nf, lanes_of(s_real), s_real, prm->precision, host_x);
+  return group_bytes(p, prm->m_restart, nf, lanes_of(s_real), s_real, prm->precision, host_x,
+                     prm->inner_precond == SHK_PRECOND_MULTIGRID);
 }
 
 int solve_all(shk_problem* p, const shk_params* prm, int nf, const c128* sigma, int n_rhs, const c128* b, c128* x,
@@ -887,8 +1089,12 @@ int step_apply(shk_problem* p, c128 sigma, int S, const void* x, void* y, int pr
 }
 
 int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w, double eps, int maxit,
-               int fixed_iters, int precision, int* its, double* pnorm, hipStream_t st) {
+               int fixed_iters, int precision, int precond, int* its, double* pnorm, hipStream_t st) {
   if (!p || !v || !z || S < 1 || S > 64 || (S & (S - 1))) return fail(SHK_ERR_INVALID_ARG, "inner arguments");
+  if (precond != SHK_PRECOND_JACOBI && precond != SHK_PRECOND_MULTIGRID) return fail(SHK_ERR_INVALID_ARG, "precond");
+  if (precond == SHK_PRECOND_MULTIGRID && p->kind == Kind::CSR)
+    return fail(SHK_ERR_UNSUPPORTED, "multigrid needs a finite-volume problem");
+  const bool use_mg = precond == SHK_PRECOND_MULTIGRID;
   if (maxit <= 0) maxit = 20 * p->max_dim();
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
@@ -905,6 +1111,7 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
       b.part = c.take<c128>((size_t)grid_items(N, 1024) * 2 * S);
       b.sc = c.take<CgScal>(2 * S); b.all_done = c.take<int>(4);
       b.mz = c.take<double>(S); b.pn = c.take<double>(S);
+      if (use_mg) carve_mg(c, b, p, N, S);
     };
     Carver cv{nullptr};
     Buffers<R> b0{};
@@ -919,6 +1126,7 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
       using Op = decltype(op);
       using OpD = decltype(opd);
       Group<R, Op, OpD> g{p, op, opd, st, b, p->n, N, S, S, 1, 1, S, gp};
+      g.mg = use_mg;
       SHK_TRY(g.inner(tau, (const cx<R>*)v, (c128*)z, eps, maxit, fixed_iters, b.pn));
       if (w) {
         k_copy<R><<<grid_items(N, 4096), BS, 0, st>>>(b.W, N, (cx<R>*)w);

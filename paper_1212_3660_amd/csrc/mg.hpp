@@ -15,8 +15,9 @@
 // one-cell level is solved exactly.  Symmetric smoothing and R = P^T make the
 // V-cycle a complex symmetric operator, as COCG needs.
 //
-// Kernels are launched per level; a V-cycle over L levels is 2 (L - 1)
-// launches.  Vectors carry S interleaved lanes like the rest of the library.
+// Kernels are launched per level down to the first level small enough for
+// one workgroup's LDS; that level and all coarser ones run in a single
+// workgroup.  Vectors carry S interleaved lanes like the rest of the library.
 #pragma once
 #include "kernels.hpp"
 
@@ -89,92 +90,181 @@ __global__ void __launch_bounds__(BS) k_mg_dinv(OpD opd, c128 tau, int n, cx<R>*
 }
 
 // ---------------------------------------------------------------- V-cycle --
-// Downward leg at level l: for every coarse cell and lane, the sum over its
-// fine cells of the residual b - A x1 after the first sweep x1 = omega D^-1 b
-// (x1 at the stencil neighbours formed on the fly).  On the last level (one
-// coarse cell... or any level solved exactly) the kernel writes the coarse
-// solution x_c = D_c^-1 b_c instead of b_c.
-template <typename Op, typename R, bool LAST>
+// Downward leg, one coarse cell (cx_, cy, cz) and lane: the sum over its fine
+// cells of the residual b - A x1 after the first sweep x1 = omega D^-1 b
+// (x1 at the stencil neighbours formed on the fly).  gb(i), gd(i): b and
+// D^-1 at fine cell i for the lane.
+template <typename Op, typename R, typename GB, typename GD>
+__device__ __forceinline__ cx<R> mg_down_cell(const Op& op, const LevelDims& f, int cx_, int cy, int cz, cx<R> tr,
+                                              R om, GB gb, GD gd) {
+  constexpr int NB = Op::NB;
+  cx<R> acc{0, 0};
+  for (int dk = 0; dk < (f.nz > 1 ? 2 : 1); ++dk)
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) {
+        const int x = 2 * cx_ + di, y = 2 * cy + dj, z = 2 * cz + dk;
+        if (x >= f.nx || y >= f.ny || z >= f.nz) continue;
+        const int i = x + f.nx * (y + f.ny * z);
+        int idx[NB];
+        R fo[NB];
+        R fsum;
+        op.template stencil<R>(i, idx, fo, fsum);
+        const cx<R> bi = gb(i);
+        const cx<R> x1 = om * (gd(i) * bi);
+        cx<R> ax = fsum * x1 + (R)op.mass(i) * (tr * x1);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const int j = idx[q];
+          ax = ax - fo[q] * (om * (gd(j) * gb(j)));
+        }
+        acc = acc + (bi - ax);
+      }
+  return acc;
+}
+
+// Upward leg, one fine cell i and lane: x2 = x1 + P x_c (x1 = omega D^-1 b),
+// then one sweep x = x2 + omega D^-1 (b - A x2), with x2 at the stencil
+// neighbours formed on the fly; gxc(I): coarse solution at coarse cell I.
+template <typename Op, typename R, typename GB, typename GD, typename GX>
+__device__ __forceinline__ cx<R> mg_up_cell(const Op& op, const LevelDims& f, const LevelDims& c, int i, cx<R> tr,
+                                            R om, GB gb, GD gd, GX gxc) {
+  constexpr int NB = Op::NB;
+  auto parent = [&](int k) {
+    const int x = k % f.nx, y = (k / f.nx) % f.ny, z = k / (f.nx * f.ny);
+    return (x >> 1) + c.nx * ((y >> 1) + c.ny * (z >> 1));
+  };
+  auto x2 = [&](int k) { return om * (gd(k) * gb(k)) + gxc(parent(k)); };
+  int idx[NB];
+  R fo[NB];
+  R fsum;
+  op.template stencil<R>(i, idx, fo, fsum);
+  const cx<R> xi = x2(i);
+  cx<R> ax = fsum * xi + (R)op.mass(i) * (tr * xi);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) ax = ax - fo[q] * x2(idx[q]);
+  return xi + om * (gd(i) * (gb(i) - ax));
+}
+
+// Downward leg of one level over the grid: coarse right-hand side b_c.
+template <typename Op, typename R>
 __global__ void __launch_bounds__(BS) k_mg_down(Op op, LevelDims f, LevelDims c, c128 tau, double omega, int lS,
                                                 const cx<R>* __restrict__ b, const cx<R>* __restrict__ dinv,
-                                                cx<R>* __restrict__ out, const cx<R>* __restrict__ dinv_c,
-                                                const int* __restrict__ all_done) {
+                                                cx<R>* __restrict__ out, const int* __restrict__ all_done) {
   if (*all_done) return;
-  constexpr int NB = Op::NB;
   const int S = 1 << lS;
   const int rl = threadIdx.x & (S - 1);
   const int Nc = c.n() << lS;
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
+  auto gb = [&](int i) { return b[(i << lS) + rl]; };
+  auto gd = [&](int i) { return dinv[i]; };
   for (int t = blockIdx.x * BS + threadIdx.x; t < Nc; t += gridDim.x * BS) {
     const int I = t >> lS;
-    const int cx_ = I % c.nx, cy = (I / c.nx) % c.ny, cz = I / (c.nx * c.ny);
-    cx<R> acc{0, 0};
-    for (int dk = 0; dk < (f.nz > 1 ? 2 : 1); ++dk)
-      for (int dj = 0; dj < 2; ++dj)
-        for (int di = 0; di < 2; ++di) {
-          const int x = 2 * cx_ + di, y = 2 * cy + dj, z = 2 * cz + dk;
-          if (x >= f.nx || y >= f.ny || z >= f.nz) continue;
-          const int i = x + f.nx * (y + f.ny * z);
-          int idx[NB];
-          R fo[NB];
-          R fsum;
-          op.template stencil<R>(i, idx, fo, fsum);
-          const cx<R> bi = b[(i << lS) + rl];
-          const cx<R> x1 = om * (dinv[i] * bi);
-          cx<R> ax = fsum * x1 + (R)op.mass(i) * (tr * x1);
-#pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            const int j = idx[q];
-            ax = ax - fo[q] * (om * (dinv[j] * b[(j << lS) + rl]));
-          }
-          acc = acc + (bi - ax);
-        }
-    if constexpr (LAST) out[t] = dinv_c[I] * acc;
-    else out[t] = acc;
+    out[t] = mg_down_cell<Op, R>(op, f, I % c.nx, (I / c.nx) % c.ny, I / (c.nx * c.ny), tr, om, gb, gd);
   }
 }
 
-// Upward leg at level l: x2 = x1 + P x_c (x1 = omega D^-1 b), then one sweep
-// x = x2 + omega D^-1 (b - A x2), with x2 at the stencil neighbours formed on
-// the fly from b and the coarse solution.
+// Upward leg of one level over the grid.
 template <typename Op, typename R>
 __global__ void __launch_bounds__(BS) k_mg_up(Op op, LevelDims f, LevelDims c, c128 tau, double omega, int lS,
                                               const cx<R>* __restrict__ b, const cx<R>* __restrict__ dinv,
                                               const cx<R>* __restrict__ xc, cx<R>* __restrict__ xout,
                                               const int* __restrict__ all_done) {
   if (*all_done) return;
-  constexpr int NB = Op::NB;
   const int S = 1 << lS;
   const int rl = threadIdx.x & (S - 1);
   const int N = f.n() << lS;
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
-  auto parent = [&](int i) {
-    const int x = i % f.nx, y = (i / f.nx) % f.ny, z = i / (f.nx * f.ny);
-    return (x >> 1) + c.nx * ((y >> 1) + c.ny * (z >> 1));
-  };
-  auto x2 = [&](int i) { return om * (dinv[i] * b[(i << lS) + rl]) + xc[(parent(i) << lS) + rl]; };
-  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS) {
-    const int i = t >> lS;
-    int idx[NB];
-    R fo[NB];
-    R fsum;
-    op.template stencil<R>(i, idx, fo, fsum);
-    const cx<R> xi = x2(i);
-    cx<R> ax = fsum * xi + (R)op.mass(i) * (tr * xi);
-#pragma unroll
-    for (int q = 0; q < NB; ++q) ax = ax - fo[q] * x2(idx[q]);
-    xout[t] = xi + om * (dinv[i] * (b[t] - ax));
+  auto gb = [&](int i) { return b[(i << lS) + rl]; };
+  auto gd = [&](int i) { return dinv[i]; };
+  auto gx = [&](int I) { return xc[(I << lS) + rl]; };
+  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS)
+    xout[t] = mg_up_cell<Op, R>(op, f, c, t >> lS, tr, om, gb, gd, gx);
+}
+
+// The coarse end of the V-cycle in one workgroup: levels t..L-1 (right-hand
+// side of level t from global memory, solution of level t back to it), every
+// level's b and x in LDS, a barrier between legs.  Saves two launches per
+// coarse level, which are all latency.
+constexpr int MG_MAXL = 14;
+constexpr int MG_TAIL_THREADS = 1024;
+constexpr int MG_TAIL_LDS = 64 * 1024;
+template <typename Op, typename R> struct MgTail {
+  int T;                        // levels in the tail
+  Op op[MG_MAXL];
+  LevelDims dims[MG_MAXL];
+  const cx<R>* dinv[MG_MAXL];
+  int off[MG_MAXL];             // LDS offset of b_k; x_k follows it (n_k S each)
+};
+template <typename Op, typename R>
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail<Op, R> a, c128 tau, double omega, int lS,
+                                                             const cx<R>* __restrict__ btop, cx<R>* __restrict__ xtop,
+                                                             const int* __restrict__ all_done) {
+  if (*all_done) return;
+  extern __shared__ __align__(16) char lds_raw[];
+  cx<R>* sh = reinterpret_cast<cx<R>*>(lds_raw);
+  const int S = 1 << lS;
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  const int nth = blockDim.x;
+  const int T = a.T;
+  {
+    const int n0 = a.dims[0].n() << lS;
+    for (int j = threadIdx.x; j < n0; j += nth) sh[a.off[0] + j] = btop[j];
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < T; ++k) {
+    const LevelDims f = a.dims[k], c = a.dims[k + 1];
+    const cx<R>* bk = sh + a.off[k];
+    cx<R>* bc = sh + a.off[k + 1];
+    const cx<R>* dk = a.dinv[k];
+    const int Nc = c.n() << lS;
+    for (int j = threadIdx.x; j < Nc; j += nth) {
+      const int rl = j & (S - 1), I = j >> lS;
+      auto gb = [&](int i) { return bk[(i << lS) + rl]; };
+      auto gd = [&](int i) { return dk[i]; };
+      bc[j] = mg_down_cell<Op, R>(a.op[k], f, I % c.nx, (I / c.nx) % c.ny, I / (c.nx * c.ny), tr, om, gb, gd);
+    }
+    __syncthreads();
+  }
+  {
+    const int k = T - 1;
+    const int nk = a.dims[k].n() << lS;
+    for (int j = threadIdx.x; j < nk; j += nth)
+      sh[a.off[k] + nk + j] = a.dinv[k][j >> lS] * sh[a.off[k] + j];
+  }
+  __syncthreads();
+  for (int k = T - 2; k >= 0; --k) {
+    const LevelDims f = a.dims[k], c = a.dims[k + 1];
+    const int nk = f.n() << lS, nc = c.n() << lS;
+    const cx<R>* bk = sh + a.off[k];
+    cx<R>* xk = sh + a.off[k] + nk;
+    const cx<R>* xc = sh + a.off[k + 1] + nc;
+    const cx<R>* dk = a.dinv[k];
+    for (int j = threadIdx.x; j < nk; j += nth) {
+      const int rl = j & (S - 1);
+      auto gb = [&](int i) { return bk[(i << lS) + rl]; };
+      auto gd = [&](int i) { return dk[i]; };
+      auto gx = [&](int I) { return xc[(I << lS) + rl]; };
+      xk[j] = mg_up_cell<Op, R>(a.op[k], f, c, j >> lS, tr, om, gb, gd, gx);
+    }
+    __syncthreads();
+  }
+  {
+    const int n0 = a.dims[0].n() << lS;
+    for (int j = threadIdx.x; j < n0; j += nth) xtop[j] = sh[a.off[0] + n0 + j];
   }
 }
 
-// A one-cell grid: the V-cycle is the exact solve u = D^-1 b.
+// The coarsest level solved on the grid (only when even its lanes exceed the
+// tail's LDS): x = D^-1 b.
 template <typename R>
-__global__ void __launch_bounds__(BS) k_mg_scale(int S, const cx<R>* __restrict__ dinv, const cx<R>* __restrict__ b,
-                                                 cx<R>* __restrict__ u, const int* __restrict__ all_done) {
+__global__ void __launch_bounds__(BS) k_mg_scale_grid(long N, int lS, const cx<R>* __restrict__ dinv,
+                                                      const cx<R>* __restrict__ b, cx<R>* __restrict__ x,
+                                                      const int* __restrict__ all_done) {
   if (*all_done) return;
-  if ((int)threadIdx.x < S) u[threadIdx.x] = dinv[0] * b[threadIdx.x];
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) x[t] = dinv[t >> lS] * b[t];
 }
 
 // ------------------------------------------------------- COCG with the V-cycle

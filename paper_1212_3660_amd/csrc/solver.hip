@@ -539,31 +539,57 @@ template <typename R, typename Op, typename OpD> struct Group {
       }
     }
   }
+  // First level of the one-workgroup tail: the finest level from which all
+  // coarser levels' b and x fit in the tail's LDS.
+  int mg_tail_level(int lS) const {
+    const int Lv = mg_levels();
+    size_t need = 0;
+    int t = Lv;
+    for (int l = Lv - 1; l >= 0; --l) {
+      need += 2 * ((size_t)mg_dims(l).n() << lS) * sizeof(cx<R>);
+      if (need > (size_t)MG_TAIL_LDS || Lv - l > MG_MAXL) break;
+      t = l;
+    }
+    return t;   // Lv: not even the one-cell level fits (many lanes)
+  }
   // uout = B b0 (one V-cycle over every level)
   void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout) {
     if constexpr (Op::NB > 0) {
       const int Lv = mg_levels();
       const int S_ = 1 << lS;
-      if (Lv == 1) {   // one cell: the exact solve is the Jacobi scaling
-        k_mg_scale<R><<<1, BS, 0, st>>>(S_, B.dinv, b0, uout, B.all_done);
-        return;
-      }
+      const int t = mg_tail_level(lS);
+      const int gdown = std::min(t, Lv - 1);   // levels whose down leg runs on the grid
       const cx<R>* bl = b0;
-      for (int l = 0; l + 1 < Lv; ++l) {
+      for (int l = 0; l < gdown; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
-        const Op o = mg_op<Op, R>(op, l);
         const int g = grid_items((long)c.n() * S_, 8192);
-        if (l + 2 == Lv) {
-          k_mg_down<Op, R, true><<<g, BS, 0, st>>>(o, f, c, tau, mg_omega, lS, bl, dl, B.mx[l], B.mdinv[l],
-                                                     B.all_done);
-        } else {
-          k_mg_down<Op, R, false><<<g, BS, 0, st>>>(o, f, c, tau, mg_omega, lS, bl, dl, B.mb[l], nullptr,
-                                                      B.all_done);
-          bl = B.mb[l];
-        }
+        k_mg_down<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl, dl, B.mb[l],
+                                            B.all_done);
+        bl = B.mb[l];
       }
-      for (int l = Lv - 2; l >= 0; --l) {
+      if (t < Lv) {
+        MgTail<Op, R> a{};
+        a.T = Lv - t;
+        int off = 0;
+        for (int k = 0; k < a.T; ++k) {
+          const int l = t + k;
+          a.op[k] = mg_op<Op, R>(op, l);
+          a.dims[k] = mg_dims(l);
+          a.dinv[k] = l == 0 ? B.dinv : B.mdinv[l - 1];
+          a.off[k] = off;
+          off += 2 * (mg_dims(l).n() << lS);
+        }
+        cx<R>* xt = t == 0 ? uout : B.mx[t - 1];
+        k_mg_tail<Op, R><<<1, MG_TAIL_THREADS, (size_t)off * sizeof(cx<R>), st>>>(a, tau, mg_omega, lS, bl, xt,
+                                                                                    B.all_done);
+      } else {
+        // the coarsest level alone exceeds the tail: solve it on the grid
+        const int l = Lv - 1;
+        k_mg_scale_grid<R><<<grid_items((long)S_, 8192), BS, 0, st>>>((long)mg_dims(l).n() << lS, lS,
+                                                                       B.mdinv[l - 1], bl, B.mx[l - 1], B.all_done);
+      }
+      for (int l = std::min(t, Lv - 1) - 1; l >= 0; --l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];

@@ -51,9 +51,10 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def time_path(P, torch, gp, w, precision, steps, warmup, profile=False):
+def time_path(P, torch, gp, w, precision, steps, warmup, profile=False, precond=None):
     prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
-                              eps_inner=w.eps_inner, precision=precision)
+                              eps_inner=w.eps_inner, precision=precision,
+                              inner_precond=P.SHK_PRECOND_MULTIGRID if precond is None else precond)
     nf = len(w.sigma)
     ws = torch.empty(P.shk_workspace_bytes(gp, prm, nf, 1), dtype=torch.uint8, device="cuda")
     b = torch.from_numpy(w.b[:, 0]).cuda()[None, :].contiguous()
@@ -98,13 +99,14 @@ def time_path(P, torch, gp, w, precision, steps, warmup, profile=False):
 
 
 def time_batched(P, torch, w, make, precision, single_rhs_sample=0):
+    """(multigrid inner preconditioner)"""
     """One solve of a multi-rhs workload (all rhs in lockstep); with
     single_rhs_sample > 0, instead that many rhs solved one at a time and the
     rate scaled to all of them.  Returns shifted solves/s and the worst true
     relative residual."""
     gp = make(w)
     prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
-                              eps_inner=w.eps_inner, precision=precision)
+                              eps_inner=w.eps_inner, precision=precision, inner_precond=P.SHK_PRECOND_MULTIGRID)
     nf, nr = len(w.sigma), w.b.shape[1]
     cols = list(range(single_rhs_sample)) if single_rhs_sample else [list(range(nr))]
     worst, ok, total = 0.0, True, 0.0
@@ -200,6 +202,9 @@ def main():
     # the inner-iteration kernel is timed inside the timed region itself
     mixed = time_path(P, torch, gp, w, P.SHK_MIXED, a.steps, a.warmup, profile=True)
     fp64 = time_path(P, torch, gp, w, P.SHK_FP64, a.steps, a.warmup, profile=False)
+    # the same solves with the Jacobi-preconditioned inner COCG
+    jac = {name: time_path(P, torch, gp, w, prec, a.steps, a.warmup, profile=False, precond=P.SHK_PRECOND_JACOBI)
+           for name, prec in (("mixed", P.SHK_MIXED), ("fp64", P.SHK_FP64))}
     nf = len(w.sigma)
     ms_step = mixed["total_ms"] / a.steps
     value = nf * a.steps / (mixed["total_ms"] / 1e3)

@@ -691,7 +691,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     static_assert(sizeof(Snap) <= 32768, "staging layout");
     Snap* snap = (Snap*)g_pinned.get(65536);
     if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
-    const bool timing = g_timer.on && !mg;   // the timer follows the Jacobi iteration kernel
+    const bool timing = g_timer.on;   // Jacobi: the iteration kernel; multigrid: the iteration's launches
     if (timing) g_timer.ensure(1);
     // per lane: iteration count and residual norm seen at the previous poll
     std::vector<int> prev_its(S, 0);
@@ -727,7 +727,7 @@ template <typename R, typename Op, typename OpD> struct Group {
         if (hipEventElapsedTime(&ms, g_timer.ev[0], g_timer.ev[1]) == hipSuccess) {
           g_timer.total_ms += ms;
           g_timer.launches += chunk;
-          g_timer.total_bytes += (double)chunk * n * S * step_bytes_per_cell();
+          g_timer.total_bytes += (double)chunk * (mg ? mg_iteration_bytes() : (double)n * S * step_bytes_per_cell());
         }
       }
       its_before = its_now;
@@ -809,6 +809,30 @@ template <typename R, typename Op, typename OpD> struct Group {
     else if (p->kind == Kind::FV3D) faces = 3.0 * sizeof(R);
     else faces = (double)p->nnz / (double)p->n * (sizeof(R) + sizeof(int));
     return 8.0 * wv + 32.0 + (2.0 * sizeof(R) + faces) / S;
+  }
+
+  // Algorithmic bytes of one multigrid-COCG iteration (all its launches):
+  // k_cgmg_step reads r, w, s, u, p and x and writes r, s, p and x; on every
+  // level above the tail the down leg reads b, D^-1, the faces (and the mass
+  // on coarse levels) and writes the coarse b, and the up leg reads b, D^-1,
+  // the faces, the mass and the coarse x and writes x; the tail reads its top
+  // level's b and writes its x (its own levels stay in LDS); k_cgmg_post reads
+  // u, r and the faces and writes w.  Faces count once per cell.
+  double mg_iteration_bytes() const {
+    const double w = sizeof(cx<R>);
+    const double fpc = (p->kind == Kind::FV3D ? 3.0 : 2.0) * sizeof(R);
+    const int lS = ilog2(S);
+    const int Lv = mg_levels(), t = mg_tail_level(lS);
+    double bytes = (double)N * (8.0 * w + 32.0);                       // vector updates
+    for (int l = 0; l < std::min(t, Lv - 1); ++l) {
+      const double nl = mg_dims(l).n(), nc = mg_dims(l + 1).n();
+      const double mass = l == 0 ? 0.0 : 8.0;
+      bytes += nl * (S * w + w + fpc + mass) + nc * S * w;              // down
+      bytes += nl * (S * w + w + fpc + mass + S * w) + nc * S * w;      // up
+    }
+    if (t < Lv) bytes += 2.0 * mg_dims(t).n() * S * w;                  // tail in/out
+    bytes += (double)N * 3.0 * w + (double)n * fpc;                     // product
+    return bytes;
   }
 
   GivensArgs gargs(int k, int cycle, int kglob, double tol) {

@@ -19,6 +19,7 @@
 // one workgroup's LDS; that level and all coarser ones run in a single
 // workgroup.  Vectors carry S interleaved lanes like the rest of the library.
 #pragma once
+#include <type_traits>
 #include "kernels.hpp"
 
 namespace shk {
@@ -90,171 +91,312 @@ __global__ void __launch_bounds__(BS) k_mg_dinv(OpD opd, c128 tau, int n, cx<R>*
 }
 
 // ---------------------------------------------------------------- V-cycle --
-// Downward leg, one coarse cell (cx_, cy, cz) and lane: the sum over its fine
-// cells of the residual b - A x1 after the first sweep x1 = omega D^-1 b
-// (x1 at the stencil neighbours formed on the fly).  gb(i), gd(i): b and
-// D^-1 at fine cell i for the lane.
+// The grid kernels below load the done flag together with their operands and
+// judge it only before their stores, so a launch costs one round trip to
+// memory rather than two.  hold(v, flag) marks the point where both are
+// needed: the loads behind v are issued before it and the flag is neither
+// tested nor waited for ahead of it (else the compiler tends to test a
+// loop-invariant flag first, or to move the loads into the branch that
+// stores).
+template <typename R> __device__ __forceinline__ void hold(cx<R>& v, int& flag) {
+  asm volatile("" : "+v"(v.re), "+v"(v.im), "+s"(flag));
+}
+// A pointer the compiler cannot see through: a load from it stays where it is
+// written instead of being merged with an earlier one.
+template <typename T> __device__ __forceinline__ T* opaque(T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Downward leg, one fine cell c = (i, j, k) and lane: the residual
+// b_c - (A x1)_c after the first sweep x1 = omega D^-1 b (x1 at the stencil
+// neighbours formed on the fly).  gb(c), gd(c): b and D^-1 at fine cell c
+// for the lane.  Callers pass coordinates so that no index is divided.
 template <typename Op, typename R, typename GB, typename GD>
-__device__ __forceinline__ cx<R> mg_down_cell(const Op& op, const LevelDims& f, int cx_, int cy, int cz, cx<R> tr,
-                                              R om, GB gb, GD gd) {
+__device__ __forceinline__ cx<R> mg_down_fine(const Op& op, int i, int j, int k, int c, cx<R> tr, R om, GB gb,
+                                              GD gd) {
   constexpr int NB = Op::NB;
+  int idx[NB];
+  R fo[NB];
+  R fsum;
+  op.template stencil_at<R>(i, j, k, c, idx, fo, fsum);
+  const cx<R> bi = gb(c);
+  const cx<R> x1 = om * (gd(c) * bi);
+  cx<R> ax = fsum * x1 + (R)op.mass(c) * (tr * x1);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int n = idx[q];
+    ax = ax - fo[q] * (om * (gd(n) * gb(n)));
+  }
+  return bi - ax;
+}
+
+// Downward leg, one coarse cell (I, J, L) and lane: the sum of the residuals
+// of its fine cells (restriction by P^T).
+template <typename Op, typename R, typename GB, typename GD>
+__device__ __forceinline__ cx<R> mg_down_cell(const Op& op, const LevelDims& f, int I, int J, int L, cx<R> tr,
+                                              R om, GB gb, GD gd) {
   cx<R> acc{0, 0};
   for (int dk = 0; dk < (f.nz > 1 ? 2 : 1); ++dk)
     for (int dj = 0; dj < 2; ++dj)
       for (int di = 0; di < 2; ++di) {
-        const int x = 2 * cx_ + di, y = 2 * cy + dj, z = 2 * cz + dk;
-        if (x >= f.nx || y >= f.ny || z >= f.nz) continue;
-        const int i = x + f.nx * (y + f.ny * z);
-        int idx[NB];
-        R fo[NB];
-        R fsum;
-        op.template stencil<R>(i, idx, fo, fsum);
-        const cx<R> bi = gb(i);
-        const cx<R> x1 = om * (gd(i) * bi);
-        cx<R> ax = fsum * x1 + (R)op.mass(i) * (tr * x1);
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const int j = idx[q];
-          ax = ax - fo[q] * (om * (gd(j) * gb(j)));
-        }
-        acc = acc + (bi - ax);
+        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * L + dk;
+        if (i >= f.nx || j >= f.ny || k >= f.nz) continue;
+        acc = acc + mg_down_fine<Op, R>(op, i, j, k, i + f.nx * (j + f.ny * k), tr, om, gb, gd);
       }
   return acc;
 }
 
-// Upward leg, one fine cell i and lane: x2 = x1 + P x_c (x1 = omega D^-1 b),
-// then one sweep x = x2 + omega D^-1 (b - A x2), with x2 at the stencil
-// neighbours formed on the fly; gxc(I): coarse solution at coarse cell I.
+// Upward leg, one fine cell c = (i, j, k) and lane: x2 = x1 + P x_c
+// (x1 = omega D^-1 b), then one sweep x = x2 + omega D^-1 (b - A x2), with x2
+// at the stencil neighbours formed on the fly; gxc(C): coarse solution at
+// coarse cell C of the grid cd.  A neighbour's parent differs from the
+// cell's own only along the neighbour's axis.
 template <typename Op, typename R, typename GB, typename GD, typename GX>
-__device__ __forceinline__ cx<R> mg_up_cell(const Op& op, const LevelDims& f, const LevelDims& c, int i, cx<R> tr,
-                                            R om, GB gb, GD gd, GX gxc) {
+__device__ __forceinline__ cx<R> mg_up_cell(const Op& op, const LevelDims& f, const LevelDims& cd, int i, int j,
+                                            int k, int c, cx<R> tr, R om, GB gb, GD gd, GX gxc) {
   constexpr int NB = Op::NB;
-  auto parent = [&](int k) {
-    const int x = k % f.nx, y = (k / f.nx) % f.ny, z = k / (f.nx * f.ny);
-    return (x >> 1) + c.nx * ((y >> 1) + c.ny * (z >> 1));
-  };
-  auto x2 = [&](int k) { return om * (gd(k) * gb(k)) + gxc(parent(k)); };
   int idx[NB];
   R fo[NB];
   R fsum;
-  op.template stencil<R>(i, idx, fo, fsum);
-  const cx<R> xi = x2(i);
-  cx<R> ax = fsum * xi + (R)op.mass(i) * (tr * xi);
+  op.template stencil_at<R>(i, j, k, c, idx, fo, fsum);
+  const int pi = i >> 1, pj = j >> 1, pk = k >> 1;
+  auto par = [&](int a, int b, int e) { return a + cd.nx * (b + cd.ny * e); };
+  int pq[NB];
+  pq[0] = par((i > 0 ? i - 1 : i) >> 1, pj, pk);
+  pq[1] = par((i < f.nx - 1 ? i + 1 : i) >> 1, pj, pk);
+  pq[2] = par(pi, (j > 0 ? j - 1 : j) >> 1, pk);
+  pq[3] = par(pi, (j < f.ny - 1 ? j + 1 : j) >> 1, pk);
+  if constexpr (NB == 6) {
+    pq[4] = par(pi, pj, (k > 0 ? k - 1 : k) >> 1);
+    pq[5] = par(pi, pj, (k < f.nz - 1 ? k + 1 : k) >> 1);
+  }
+  const cx<R> xi = om * (gd(c) * gb(c)) + gxc(par(pi, pj, pk));
+  cx<R> ax = fsum * xi + (R)op.mass(c) * (tr * xi);
 #pragma unroll
-  for (int q = 0; q < NB; ++q) ax = ax - fo[q] * x2(idx[q]);
-  return xi + om * (gd(i) * (gb(i) - ax));
+  for (int q = 0; q < NB; ++q) {
+    const int n = idx[q];
+    ax = ax - fo[q] * (om * (gd(n) * gb(n)) + gxc(pq[q]));
+  }
+  return xi + om * (gd(c) * (gb(c) - ax));
 }
 
 // Downward leg of one level over the grid: coarse right-hand side b_c.
+// Launch grid (ceil(c.nx S 2^d / BS), c.ny, c.nz): along a coarse row,
+// thread t holds child t mod 2^d of lane (t >> d) mod S of coarse cell
+// t >> (d + log2 S), so the 2^d children of a coarse cell sit in adjacent
+// lanes of one wavefront and are summed by cross-lane exchange.
 template <typename Op, typename R>
 __global__ void __launch_bounds__(BS) k_mg_down(Op op, LevelDims f, LevelDims c, c128 tau, double omega, int lS,
                                                 const cx<R>* __restrict__ b, const cx<R>* __restrict__ dinv,
                                                 cx<R>* __restrict__ out, const int* __restrict__ all_done) {
-  if (*all_done) return;
+  constexpr int D = Op::NB / 2;
+  constexpr int Q = 1 << D;
+  int flag = *all_done;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  if (t >= (c.nx << (lS + D))) return;   // whole groups of 2^d lanes leave together
   const int S = 1 << lS;
-  const int rl = threadIdx.x & (S - 1);
-  const int Nc = c.n() << lS;
+  const int q = t & (Q - 1), rl = (t >> D) & (S - 1), I = t >> (D + lS);
+  const int J = blockIdx.y, L = blockIdx.z;
+  const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * L + (q >> 2);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
-  auto gb = [&](int i) { return b[(i << lS) + rl]; };
-  auto gd = [&](int i) { return dinv[i]; };
-  for (int t = blockIdx.x * BS + threadIdx.x; t < Nc; t += gridDim.x * BS) {
-    const int I = t >> lS;
-    out[t] = mg_down_cell<Op, R>(op, f, I % c.nx, (I / c.nx) % c.ny, I / (c.nx * c.ny), tr, om, gb, gd);
+  cx<R> v{0, 0};
+  if (i < f.nx && j < f.ny && k < f.nz) {
+    auto gb = [&](int n) { return b[((long)n << lS) + rl]; };
+    auto gd = [&](int n) { return dinv[n]; };
+    v = mg_down_fine<Op, R>(op, i, j, k, i + f.nx * (j + f.ny * k), tr, om, gb, gd);
   }
+#pragma unroll
+  for (int m = 1; m < Q; m <<= 1) {
+    v.re += __shfl_xor(v.re, m);
+    v.im += __shfl_xor(v.im, m);
+  }
+  hold(v, flag);
+  if (!flag && q == 0) out[((long)(I + c.nx * (J + c.ny * L)) << lS) + rl] = v;
 }
 
-// Upward leg of one level over the grid.
+// Upward leg of one level over the grid.  Launch grid (ceil(f.nx S / BS),
+// f.ny, f.nz): along a fine row thread t holds lane t mod S of cell t >> log2 S.
 template <typename Op, typename R>
 __global__ void __launch_bounds__(BS) k_mg_up(Op op, LevelDims f, LevelDims c, c128 tau, double omega, int lS,
                                               const cx<R>* __restrict__ b, const cx<R>* __restrict__ dinv,
                                               const cx<R>* __restrict__ xc, cx<R>* __restrict__ xout,
                                               const int* __restrict__ all_done) {
-  if (*all_done) return;
+  int flag = *all_done;
+  const int t = blockIdx.x * BS + threadIdx.x;
+  if (t >= (f.nx << lS)) return;
   const int S = 1 << lS;
-  const int rl = threadIdx.x & (S - 1);
-  const int N = f.n() << lS;
+  const int rl = t & (S - 1), i = t >> lS, j = blockIdx.y, k = blockIdx.z;
+  const int cell = i + f.nx * (j + f.ny * k);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
-  auto gb = [&](int i) { return b[(i << lS) + rl]; };
-  auto gd = [&](int i) { return dinv[i]; };
-  auto gx = [&](int I) { return xc[(I << lS) + rl]; };
-  for (int t = blockIdx.x * BS + threadIdx.x; t < N; t += gridDim.x * BS)
-    xout[t] = mg_up_cell<Op, R>(op, f, c, t >> lS, tr, om, gb, gd, gx);
+  auto gb = [&](int n) { return b[((long)n << lS) + rl]; };
+  auto gd = [&](int n) { return dinv[n]; };
+  auto gx = [&](int n) { return xc[((long)n << lS) + rl]; };
+  cx<R> v = mg_up_cell<Op, R>(op, f, c, i, j, k, cell, tr, om, gb, gd, gx);
+  hold(v, flag);
+  if (!flag) xout[((long)cell << lS) + rl] = v;
 }
 
 // The coarse end of the V-cycle in one workgroup: levels t..L-1 (right-hand
 // side of level t from global memory, solution of level t back to it), every
 // level's b and x in LDS, a barrier between legs.  Saves two launches per
-// coarse level, which are all latency.
+// coarse level, which are all latency.  The levels' coefficients (D^-1, cell
+// masses, faces) come packed in one block that the workgroup copies into LDS
+// at its start, all loads in flight at once, so that no leg after that waits
+// on global memory.
 constexpr int MG_MAXL = 14;
 constexpr int MG_TAIL_THREADS = 1024;
-constexpr int MG_TAIL_LDS = 64 * 1024;
-template <typename Op, typename R> struct MgTail {
-  int T;                        // levels in the tail
-  Op op[MG_MAXL];
-  LevelDims dims[MG_MAXL];
-  const cx<R>* dinv[MG_MAXL];
-  int off[MG_MAXL];             // LDS offset of b_k; x_k follows it (n_k S each)
+constexpr int MG_TAIL_LDS = 63 * 1024;   // dynamic LDS; the level table takes static LDS beside it
+constexpr int MG_MAXSEG = 5 * MG_MAXL;
+struct MgTailLevel {
+  int nx, ny, nz;
+  int off;       // LDS offset (elements) of b; x follows it (n S each)
+  int doff;      // LDS byte offset of D^-1
+  int moff;      // LDS byte offset of the cell masses (doubles)
+  int foff[3];   // LDS byte offsets of the face arrays along x, y, z
 };
+struct MgTail {
+  int T;                        // levels in the tail
+  int pack_lds;                 // LDS byte offset of the packed block
+  int pack_words;               // its length in 4-byte words
+  MgTailLevel lv[MG_MAXL];
+};
+
+// One segment of the packed block: `words` 4-byte words copied from src, or
+// (src null) words / 2 doubles equal to `fill`, at byte offset dst.
+struct MgSeg {
+  const void* src;
+  int dst, words;
+  double fill;
+};
+struct MgPack {
+  int nseg;
+  MgSeg seg[MG_MAXSEG];
+};
+// One block per segment.
+__global__ void __launch_bounds__(BS) k_mg_pack(MgPack p, unsigned* __restrict__ dst) {
+  const MgSeg s = p.seg[blockIdx.x];
+  unsigned* d = dst + s.dst / 4;
+  if (s.src) {
+    const unsigned* src = static_cast<const unsigned*>(s.src);
+    for (int j = threadIdx.x; j < s.words; j += BS) d[j] = src[j];
+  } else {
+    double* dd = reinterpret_cast<double*>(d);
+    for (int j = threadIdx.x; j < s.words / 2; j += BS) dd[j] = s.fill;
+  }
+}
+
 template <typename Op, typename R>
-__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail<Op, R> a, c128 tau, double omega, int lS,
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau, double omega, int lS,
+                                                             const unsigned* __restrict__ pack,
                                                              const cx<R>* __restrict__ btop, cx<R>* __restrict__ xtop,
                                                              const int* __restrict__ all_done) {
-  if (*all_done) return;
+  using F = typename std::remove_const<typename std::remove_pointer<decltype(Op::tx)>::type>::type;
+  constexpr int NW = MG_TAIL_LDS / 4 / MG_TAIL_THREADS + 1;                       // packed words per thread
+  constexpr int NB0 = MG_TAIL_LDS / (2 * (int)sizeof(cx<R>)) / MG_TAIL_THREADS + 1; // top rhs elements per thread
+  constexpr int NP = (int)(sizeof(MgTailLevel) * MG_MAXL / 4);                    // level table words
+  static_assert(NP <= MG_TAIL_THREADS, "level table");
   extern __shared__ __align__(16) char lds_raw[];
+  __shared__ MgTailLevel lv[MG_MAXL];
   cx<R>* sh = reinterpret_cast<cx<R>*>(lds_raw);
+  const int flag = *all_done;
+  const int tid = threadIdx.x;
+  const int T = a.T;
+  const int n0 = (a.lv[0].nx * a.lv[0].ny * a.lv[0].nz) << lS;
+  {
+    // every global load of the kernel is issued here, at once: the level
+    // table, the packed coefficients and the top right-hand side
+    const int pw0 = tid < NP ? reinterpret_cast<const int*>(a.lv)[tid] : 0;
+    unsigned wv[NW];
+    cx<R> bv[NB0];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int j = tid + k * MG_TAIL_THREADS;
+      wv[k] = j < a.pack_words ? pack[j] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < NB0; ++k) {
+      const int j = tid + k * MG_TAIL_THREADS;
+      bv[k] = j < n0 ? btop[j] : cx<R>{0, 0};
+    }
+    if (tid < NP) reinterpret_cast<int*>(lv)[tid] = pw0;
+    unsigned* pw = reinterpret_cast<unsigned*>(lds_raw + a.pack_lds);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int j = tid + k * MG_TAIL_THREADS;
+      if (j < a.pack_words) pw[j] = wv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NB0; ++k) {
+      const int j = tid + k * MG_TAIL_THREADS;
+      if (j < n0) sh[j] = bv[k];
+    }
+  }
+  if (flag) return;   // uniform: the whole workgroup leaves
+  __syncthreads();
   const int S = 1 << lS;
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
-  const int nth = blockDim.x;
-  const int T = a.T;
-  {
-    const int n0 = a.dims[0].n() << lS;
-    for (int j = threadIdx.x; j < n0; j += nth) sh[a.off[0] + j] = btop[j];
-  }
-  __syncthreads();
+  constexpr int nth = MG_TAIL_THREADS;
+  auto dims = [&](int k) { return LevelDims{lv[k].nx, lv[k].ny, lv[k].nz}; };
+  auto lop = [&](int k) {
+    Op o{};
+    o.nx = lv[k].nx;
+    o.ny = lv[k].ny;
+    o.tx = reinterpret_cast<const F*>(lds_raw + lv[k].foff[0]);
+    o.ty = reinterpret_cast<const F*>(lds_raw + lv[k].foff[1]);
+    if constexpr (Op::NB == 6) {
+      o.nz = lv[k].nz;
+      o.tz = reinterpret_cast<const F*>(lds_raw + lv[k].foff[2]);
+    }
+    o.mdiag = reinterpret_cast<const double*>(lds_raw + lv[k].moff);
+    return o;
+  };
+  auto ldinv = [&](int k) { return reinterpret_cast<const cx<R>*>(lds_raw + lv[k].doff); };
   for (int k = 0; k + 1 < T; ++k) {
-    const LevelDims f = a.dims[k], c = a.dims[k + 1];
-    const cx<R>* bk = sh + a.off[k];
-    cx<R>* bc = sh + a.off[k + 1];
-    const cx<R>* dk = a.dinv[k];
+    const LevelDims f = dims(k), c = dims(k + 1);
+    const Op o = lop(k);
+    const cx<R>* bk = sh + lv[k].off;
+    cx<R>* bc = sh + lv[k + 1].off;
+    const cx<R>* dk = ldinv(k);
     const int Nc = c.n() << lS;
-    for (int j = threadIdx.x; j < Nc; j += nth) {
+    for (int j = tid; j < Nc; j += nth) {
       const int rl = j & (S - 1), I = j >> lS;
+      const int Ix = I % c.nx, Iyz = I / c.nx;
       auto gb = [&](int i) { return bk[(i << lS) + rl]; };
       auto gd = [&](int i) { return dk[i]; };
-      bc[j] = mg_down_cell<Op, R>(a.op[k], f, I % c.nx, (I / c.nx) % c.ny, I / (c.nx * c.ny), tr, om, gb, gd);
+      bc[j] = mg_down_cell<Op, R>(o, f, Ix, Iyz % c.ny, Iyz / c.ny, tr, om, gb, gd);
     }
     __syncthreads();
   }
   {
     const int k = T - 1;
-    const int nk = a.dims[k].n() << lS;
-    for (int j = threadIdx.x; j < nk; j += nth)
-      sh[a.off[k] + nk + j] = a.dinv[k][j >> lS] * sh[a.off[k] + j];
+    const int nk = dims(k).n() << lS;
+    const cx<R>* dk = ldinv(k);
+    for (int j = tid; j < nk; j += nth) sh[lv[k].off + nk + j] = dk[j >> lS] * sh[lv[k].off + j];
   }
   __syncthreads();
   for (int k = T - 2; k >= 0; --k) {
-    const LevelDims f = a.dims[k], c = a.dims[k + 1];
+    const LevelDims f = dims(k), c = dims(k + 1);
+    const Op o = lop(k);
     const int nk = f.n() << lS, nc = c.n() << lS;
-    const cx<R>* bk = sh + a.off[k];
-    cx<R>* xk = sh + a.off[k] + nk;
-    const cx<R>* xc = sh + a.off[k + 1] + nc;
-    const cx<R>* dk = a.dinv[k];
-    for (int j = threadIdx.x; j < nk; j += nth) {
-      const int rl = j & (S - 1);
-      auto gb = [&](int i) { return bk[(i << lS) + rl]; };
-      auto gd = [&](int i) { return dk[i]; };
-      auto gx = [&](int I) { return xc[(I << lS) + rl]; };
-      xk[j] = mg_up_cell<Op, R>(a.op[k], f, c, j >> lS, tr, om, gb, gd, gx);
+    const cx<R>* bk = sh + lv[k].off;
+    cx<R>* xk = sh + lv[k].off + nk;
+    const cx<R>* xc = sh + lv[k + 1].off + nc;
+    const cx<R>* dk = ldinv(k);
+    for (int j = tid; j < nk; j += nth) {
+      const int rl = j & (S - 1), cell = j >> lS;
+      const int i = cell % f.nx, jk = cell / f.nx;
+      auto gb = [&](int n) { return bk[(n << lS) + rl]; };
+      auto gd = [&](int n) { return dk[n]; };
+      auto gx = [&](int n) { return xc[(n << lS) + rl]; };
+      xk[j] = mg_up_cell<Op, R>(o, f, c, i, jk % f.ny, jk / f.ny, cell, tr, om, gb, gd, gx);
     }
     __syncthreads();
   }
-  {
-    const int n0 = a.dims[0].n() << lS;
-    for (int j = threadIdx.x; j < n0; j += nth) xtop[j] = sh[a.off[0] + n0 + j];
-  }
+  for (int j = tid; j < n0; j += nth) xtop[j] = sh[n0 + j];
 }
 
 // The coarsest level solved on the grid (only when even its lanes exceed the
@@ -263,7 +405,7 @@ template <typename R>
 __global__ void __launch_bounds__(BS) k_mg_scale_grid(long N, int lS, const cx<R>* __restrict__ dinv,
                                                       const cx<R>* __restrict__ b, cx<R>* __restrict__ x,
                                                       const int* __restrict__ all_done) {
-  if (*all_done) return;
+  if (*all_done) return;   // rare path (coarsest level beyond the tail): not worth the overlap
   for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) x[t] = dinv[t >> lS] * b[t];
 }
 
@@ -365,7 +507,6 @@ __global__ void __launch_bounds__(CGB) k_cgmg_post(Op op, c128 tau, int n, int l
                                                    const cx<R>* __restrict__ r, const cx<R>* __restrict__ u,
                                                    cx<R>* __restrict__ w, c128* __restrict__ partOut,
                                                    const int* __restrict__ all_done) {
-  if (*all_done) return;
   const int lS = ONE ? 0 : lS_;
   const int S = 1 << lS;
   const int rl = ONE ? 0 : (int)threadIdx.x & (S - 1);
@@ -376,22 +517,38 @@ __global__ void __launch_bounds__(CGB) k_cgmg_post(Op op, c128 tau, int n, int l
   const int t0 = xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x;
   c128 ag{0, 0}, ad{0, 0};
   double arr = 0.0;
+  // The operands are loaded whatever the flags say (done lanes' sums are
+  // masked out) and the done flag is read after their loads are issued, so
+  // its round trip overlaps theirs.
   auto cell = [&](int t) {
     const int c = t >> lS;
-    const cx<R> ww = op.template apply<R>(c, tr, gu);
-    w[t] = ww;
-    const c128 rd = cvt<double>(r[t]), ud = cvt<double>(u[t]);
-    ag = ag + rd * ud;
-    ad = ad + cvt<double>(ww) * ud;
-    arr += abs2(rd);
-  };
-  if (live) {
-    if constexpr (MULTI) {
-      for (int t = t0; t < N; t += gridDim.x * CGB) cell(t);
-    } else {
-      if (t0 < N) cell(t0);
+    constexpr int NB = Op::NB;
+    int idx[NB];
+    R fo[NB];
+    R fsum;
+    op.template stencil<R>(c, idx, fo, fsum);
+    const cx<R> uc = gu(c);
+    cx<R> ww = fsum * uc + (R)op.mass(c) * (tr * uc);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) ww = ww - fo[q] * gu(idx[q]);
+    cx<R> rr = r[t];
+    int flag = *opaque(all_done);
+    asm volatile("" : "+v"(ww.re), "+v"(ww.im), "+v"(rr.re), "+v"(rr.im), "+v"(flag));
+    if (flag) return;
+    const c128 rd = cvt<double>(rr), ud = cvt<double>(uc);
+    if (live) {
+      w[t] = ww;
+      ag = ag + rd * ud;
+      ad = ad + cvt<double>(ww) * ud;
+      arr += abs2(rd);
     }
+  };
+  if constexpr (MULTI) {
+    for (int t = t0; t < N; t += gridDim.x * CGB) cell(t);
+  } else {
+    if (t0 < N) cell(t0);
   }
+  if (*opaque(all_done)) return;
   c128 acc[3] = {ag, ad, {arr, 0.0}};
   block_partials<3, CGB>(acc, S, partOut + (size_t)blockIdx.x * 3 * S);
 }

@@ -57,6 +57,11 @@ template <typename F> struct Op2D {
   template <typename R>
   __device__ __forceinline__ void stencil(int c, int (&idx)[NB], R (&fo)[NB], R& fsum) const {
     const int j = c / nx, i = c - j * nx;
+    stencil_at<R>(i, j, 0, c, idx, fo, fsum);
+  }
+  // The same for cell c = i + nx j whose coordinates the caller already has.
+  template <typename R>
+  __device__ __forceinline__ void stencil_at(int i, int j, int, int c, int (&idx)[NB], R (&fo)[NB], R& fsum) const {
     const int fx = c + j;
     const R fw = (R)tx[fx], fe = (R)tx[fx + 1], fs = (R)ty[c], fn = (R)ty[c + nx];
     fsum = fw + fe + fs + fn;
@@ -127,6 +132,12 @@ template <typename F> struct Op3D {
   __device__ __forceinline__ void stencil(int c, int (&idx)[NB], R (&fo)[NB], R& fsum) const {
     int i, j, k;
     coords(c, i, j, k);
+    stencil_at<R>(i, j, k, c, idx, fo, fsum);
+  }
+  // The same for cell c = i + nx (j + ny k) whose coordinates the caller has.
+  template <typename R>
+  __device__ __forceinline__ void stencil_at(int i, int j, int k, int c, int (&idx)[NB], R (&fo)[NB],
+                                             R& fsum) const {
     const int pl = nx * ny;
     const int fx = i + (nx + 1) * (j + ny * k);
     const int fy = i + nx * (j + (ny + 1) * k);

@@ -111,6 +111,9 @@ void problem_free(shk_problem* p, hipStream_t st) {
 
 // Coarse levels of the multigrid hierarchy, down to one cell: faces (half the
 // sum of the fine faces each covers) and mass (the sum over the group).
+// The V-cycle's grid kernels put rows and planes on the launch grid's y and z.
+static bool mg_grid_ok(const shk_problem* p) { return p->ny <= 65535 && p->nz <= 65535; }
+
 static int mg_setup(shk_problem* p, hipStream_t st) {
   const int d = p->kind == Kind::FV3D ? 3 : 2;
   LevelDims f{p->nx, p->ny, p->nz};
@@ -344,6 +347,7 @@ template <typename R> struct Buffers {
   // right-hand side, solution and inverse diagonal of the V-cycle
   cx<R>* u = nullptr;
   std::vector<cx<R>*> mb, mx, mdinv;
+  unsigned* mpack = nullptr;   // the V-cycle tail's packed coefficients
   size_t bytes;
 };
 
@@ -356,6 +360,7 @@ template <typename R> static void carve_mg(Carver& cv, Buffers<R>& b, const shk_
     b.mx.push_back(cv.take<cx<R>>((size_t)l.n * S));
     b.mdinv.push_back(cv.take<cx<R>>((size_t)l.n));
   }
+  b.mpack = cv.take<unsigned>(MG_TAIL_LDS / 4);
 }
 
 static int resid_grid(long n) { return grid_items(n, 256); }
@@ -508,6 +513,8 @@ template <typename R, typename Op, typename OpD> struct Group {
   // ---- multigrid V-cycle (inner preconditioner) ----
   bool mg = false;                // COCG preconditioned by the V-cycle
   double mg_omega = 0.8;
+  MgTail mg_ta{};                 // tail arguments for the current inner solve
+  int mg_lds = 0;                 // and its LDS bytes
   int mg_levels() const { return 1 + (int)p->mg.size(); }
   LevelDims mg_dims(int l) const {
     if (l == 0) return {p->nx, p->ny, p->nz};
@@ -537,20 +544,89 @@ template <typename R, typename Op, typename OpD> struct Group {
         const int nl = mg_dims(l).n();
         k_mg_dinv<OpD, R><<<grid_items(nl, 2048), BS, 0, st>>>(mg_op<OpD, double>(opd, l), tau, nl, B.mdinv[l - 1]);
       }
+      const int t = mg_tail_level(ilog2(S));
+      if (t < mg_levels()) {
+        MgPack pk;
+        mg_tail_layout(t, ilog2(S), mg_ta, pk, mg_lds);
+        k_mg_pack<<<pk.nseg, BS, 0, st>>>(pk, B.mpack);
+      }
     }
   }
+  // Face array lengths of level l along each axis.
+  void mg_face_lens(int l, long (&len)[3]) const {
+    const LevelDims d = mg_dims(l);
+    len[0] = (long)(d.nx + 1) * d.ny * d.nz;
+    len[1] = (long)d.nx * (d.ny + 1) * d.nz;
+    len[2] = Op::NB == 6 ? (long)d.nx * d.ny * (d.nz + 1) : 0;
+  }
+  // LDS bytes of the tail started at level l: b and x of every level, and
+  // the packed D^-1, masses and faces (each array on a 16-byte boundary).
+  size_t mg_tail_bytes(int l, int lS) const {
+    size_t vec = 0, pack = 0;
+    for (int k = l; k < mg_levels(); ++k) {
+      const size_t nk = (size_t)mg_dims(k).n();
+      long len[3];
+      mg_face_lens(k, len);
+      vec += 2 * (nk << lS) * sizeof(cx<R>);
+      pack += align16(nk * sizeof(cx<R>)) + align16(nk * sizeof(double));
+      for (int a = 0; a < 3; ++a) pack += align16((size_t)len[a] * sizeof(R));
+    }
+    return align16(vec) + pack;
+  }
+  static size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
   // First level of the one-workgroup tail: the finest level from which all
-  // coarser levels' b and x fit in the tail's LDS.
+  // coarser levels fit in the tail's LDS.
   int mg_tail_level(int lS) const {
     const int Lv = mg_levels();
-    size_t need = 0;
     int t = Lv;
     for (int l = Lv - 1; l >= 0; --l) {
-      need += 2 * ((size_t)mg_dims(l).n() << lS) * sizeof(cx<R>);
-      if (need > (size_t)MG_TAIL_LDS || Lv - l > MG_MAXL) break;
+      if (mg_tail_bytes(l, lS) > (size_t)MG_TAIL_LDS || Lv - l > MG_MAXL) break;
       t = l;
     }
     return t;   // Lv: not even the one-cell level fits (many lanes)
+  }
+  // Tail arguments and the segments of its packed block (offsets relative
+  // to the pack for the segments, absolute LDS offsets in the arguments).
+  void mg_tail_layout(int t, int lS, MgTail& a, MgPack& pk, int& lds_bytes) const {
+    const int Lv = mg_levels();
+    a = MgTail{};
+    pk = MgPack{};
+    a.T = Lv - t;
+    size_t vec = 0;
+    for (int k = 0; k < a.T; ++k) {
+      const LevelDims d = mg_dims(t + k);
+      a.lv[k].nx = d.nx;
+      a.lv[k].ny = d.ny;
+      a.lv[k].nz = d.nz;
+      a.lv[k].off = (int)(vec / sizeof(cx<R>));
+      vec += 2 * ((size_t)d.n() << lS) * sizeof(cx<R>);
+    }
+    a.pack_lds = (int)align16(vec);
+    size_t off = 0;
+    auto seg = [&](const void* src, size_t bytes, double fill) {
+      MgSeg& sg = pk.seg[pk.nseg++];
+      sg.src = src;
+      sg.dst = (int)off;
+      sg.words = (int)(bytes / 4);
+      sg.fill = fill;
+      const int at = a.pack_lds + (int)off;
+      off += align16(bytes);
+      return at;
+    };
+    for (int k = 0; k < a.T; ++k) {
+      const int l = t + k;
+      const size_t nk = (size_t)mg_dims(l).n();
+      const Op o = mg_op<Op, R>(op, l);
+      a.lv[k].doff = seg(l == 0 ? (const void*)B.dinv : (const void*)B.mdinv[l - 1], nk * sizeof(cx<R>), 0.0);
+      a.lv[k].moff = seg(o.mdiag, nk * sizeof(double), o.m0);
+      long len[3];
+      mg_face_lens(l, len);
+      a.lv[k].foff[0] = seg(o.tx, (size_t)len[0] * sizeof(R), 0.0);
+      a.lv[k].foff[1] = seg(o.ty, (size_t)len[1] * sizeof(R), 0.0);
+      if constexpr (Op::NB == 6) a.lv[k].foff[2] = seg(o.tz, (size_t)len[2] * sizeof(R), 0.0);
+    }
+    a.pack_words = (int)(off / 4);
+    lds_bytes = a.pack_lds + (int)off;
   }
   // uout = B b0 (one V-cycle over every level)
   void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout) {
@@ -563,26 +639,15 @@ template <typename R, typename Op, typename OpD> struct Group {
       for (int l = 0; l < gdown; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
-        const int g = grid_items((long)c.n() * S_, 8192);
+        const dim3 g((unsigned)((((long)c.nx * S_ << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
         k_mg_down<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl, dl, B.mb[l],
                                             B.all_done);
         bl = B.mb[l];
       }
       if (t < Lv) {
-        MgTail<Op, R> a{};
-        a.T = Lv - t;
-        int off = 0;
-        for (int k = 0; k < a.T; ++k) {
-          const int l = t + k;
-          a.op[k] = mg_op<Op, R>(op, l);
-          a.dims[k] = mg_dims(l);
-          a.dinv[k] = l == 0 ? B.dinv : B.mdinv[l - 1];
-          a.off[k] = off;
-          off += 2 * (mg_dims(l).n() << lS);
-        }
-        cx<R>* xt = t == 0 ? uout : B.mx[t - 1];
-        k_mg_tail<Op, R><<<1, MG_TAIL_THREADS, (size_t)off * sizeof(cx<R>), st>>>(a, tau, mg_omega, lS, bl, xt,
-                                                                                    B.all_done);
+        cx<R>* xt = t == 0 ? uout : B.mx[t - 1];   // mg_ta, mg_lds: laid out by mg_prepare
+        k_mg_tail<Op, R><<<1, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lS, B.mpack, bl, xt,
+                                                                     B.all_done);
       } else {
         // the coarsest level alone exceeds the tail: solve it on the grid
         const int l = Lv - 1;
@@ -594,7 +659,7 @@ template <typename R, typename Op, typename OpD> struct Group {
         const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
         cx<R>* out = l == 0 ? uout : B.mx[l - 1];
-        const int g = grid_items((long)f.n() * S_, 8192);
+        const dim3 g((unsigned)(((long)f.nx * S_ + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
         k_mg_up<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl2, dl, B.mx[l], out,
                                           B.all_done);
       }
@@ -1066,6 +1131,7 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
     return fail(SHK_ERR_INVALID_ARG, "inner_precond");
   if (prm->inner_precond == SHK_PRECOND_MULTIGRID) {
     if (p->kind == Kind::CSR) return fail(SHK_ERR_UNSUPPORTED, "multigrid needs a finite-volume problem");
+    if (!mg_grid_ok(p)) return fail(SHK_ERR_UNSUPPORTED, "multigrid: ny and nz must be at most 65535");
     if (prm->mg_sweeps != 1) return fail(SHK_ERR_UNSUPPORTED, "mg_sweeps must be 1");
     if (!(prm->mg_omega > 0.0 && prm->mg_omega <= 1.0)) return fail(SHK_ERR_INVALID_ARG, "mg_omega must be in (0, 1]");
   }
@@ -1144,6 +1210,8 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
   if (precond != SHK_PRECOND_JACOBI && precond != SHK_PRECOND_MULTIGRID) return fail(SHK_ERR_INVALID_ARG, "precond");
   if (precond == SHK_PRECOND_MULTIGRID && p->kind == Kind::CSR)
     return fail(SHK_ERR_UNSUPPORTED, "multigrid needs a finite-volume problem");
+  if (precond == SHK_PRECOND_MULTIGRID && !mg_grid_ok(p))
+    return fail(SHK_ERR_UNSUPPORTED, "multigrid: ny and nz must be at most 65535");
   const bool use_mg = precond == SHK_PRECOND_MULTIGRID;
   if (maxit <= 0) maxit = 20 * p->max_dim();
   auto run = [&](auto tag) -> int {

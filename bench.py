@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "ops.hpp", "common.hpp"):
+    for f in ("kernels.hpp", "mg.hpp", "ops.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_1212_3660_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -98,12 +98,34 @@ def time_path(P, torch, gp, w, precision, steps, warmup, profile=False, precond=
                 sweeps=sweeps, prof=prof)
 
 
+def roofline(prof, traffic_file, label, unit):
+    """HBM roofline of one unit of work (a kernel launch, or one inner
+    iteration made of several launches) from the library's live timing:
+    (units, milliseconds, algorithmic bytes) summed over the timed region.
+    The measured traffic is taken from the committed counter summary only
+    while the kernel sources it was taken from are unchanged."""
+    units, ms, nbytes = prof
+    if units <= 0:
+        return None
+    avg_s = ms / units / 1e3
+    achieved = nbytes / units / avg_s / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": label, "per": unit,
+         f"avg_{unit}_us": round(ms / units * 1e3, 3), f"{unit}s": units,
+         f"algorithmic_bytes_per_{unit}": round(nbytes / units)}
+    tfile = os.path.join(ROOT, "profiles", traffic_file)
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        if t.get("kernel_source_digest") == kernel_source_digest():
+            r["traffic"] = t.get(f"traffic_bytes_per_{unit}")
+    return r
+
+
 def time_batched(P, torch, w, make, precision, single_rhs_sample=0):
-    """(multigrid inner preconditioner)"""
     """One solve of a multi-rhs workload (all rhs in lockstep); with
     single_rhs_sample > 0, instead that many rhs solved one at a time and the
-    rate scaled to all of them.  Returns shifted solves/s and the worst true
-    relative residual."""
+    rate scaled to all of them (multigrid-preconditioned inner solves).
+    Returns shifted solves/s and the worst true relative residual."""
     gp = make(w)
     prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
                               eps_inner=w.eps_inner, precision=precision, inner_precond=P.SHK_PRECOND_MULTIGRID)
@@ -130,7 +152,7 @@ def time_batched(P, torch, w, make, precision, single_rhs_sample=0):
 
 
 def cpu_baseline(w, seconds, gpu_outer_steps):
-    """The CPU oracle (FGMRES-Sh, complex128, Jacobi-COCG inner) on the same
+    """The CPU oracle (FGMRES-Sh, complex128, multigrid-COCG inner) on the same
     workload, bounded to a few outer steps; scaled to a full solve with the
     outer step count the GPU solve needed (refinement not counted)."""
     import numpy as np  # noqa: F401
@@ -141,7 +163,7 @@ def cpu_baseline(w, seconds, gpu_outer_steps):
     c0 = time.process_time()
     t0 = time.perf_counter()
     while True:
-        fgmres_sh(op, w.b[:, 0], w.sigma, w.tau_seq, m_restart=w.m_restart, tol=w.tol, inner="cocg",
+        fgmres_sh(op, w.b[:, 0], w.sigma, w.tau_seq, m_restart=w.m_restart, tol=w.tol, inner="mg",
                   eps=w.eps_inner, max_steps=steps)
         el = time.perf_counter() - t0
         if el >= 0.5 * seconds or steps >= 4 * n_tau:
@@ -154,7 +176,7 @@ def cpu_baseline(w, seconds, gpu_outer_steps):
     est = per_step * max(gpu_outer_steps, 1)
     threads = max(1, int(round(cpu / el)))
     return {"value": len(w.sigma) / est, "unit": "shifted solves/s", "cores": threads, "kind": "oracle",
-            "sample": (f"{steps} outer steps (all {len(w.sigma)} shifts, Jacobi-COCG inner to {w.eps_inner}) "
+            "sample": (f"{steps} outer steps (all {len(w.sigma)} shifts, multigrid-COCG inner to {w.eps_inner}) "
                        f"of the 512x512 workload in {el:.1f} s; scaled to the {gpu_outer_steps} outer steps "
                        f"of the GPU solve (refinement sweeps not counted)"),
             "host_cores_available": len(os.sched_getaffinity(0))}
@@ -171,6 +193,8 @@ def main():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--single-solve", choices=["mixed", "fp64"], default=None,
                     help="run one solve of the workload and exit (for profiler counter passes)")
+    ap.add_argument("--precond", choices=["multigrid", "jacobi"], default="multigrid",
+                    help="inner preconditioner of --single-solve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device-to-device with a plain copy kernel and exit "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -195,40 +219,39 @@ def main():
     gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
     if a.single_solve:
         prec = P.SHK_MIXED if a.single_solve == "mixed" else P.SHK_FP64
-        r = time_path(P, torch, gp, w, prec, 1, 0, profile=False)
-        print(json.dumps({"single_solve": a.single_solve, "ms": r["total_ms"], "inner_iterations": r["inner"],
+        pc = P.SHK_PRECOND_MULTIGRID if a.precond == "multigrid" else P.SHK_PRECOND_JACOBI
+        r = time_path(P, torch, gp, w, prec, 1, 0, profile=False, precond=pc)
+        print(json.dumps({"single_solve": a.single_solve, "precond": a.precond, "ms": r["total_ms"], "inner_iterations": r["inner"],
                           "converged": r["ok"]}), flush=True)
         return
     # the inner-iteration kernel is timed inside the timed region itself
     mixed = time_path(P, torch, gp, w, P.SHK_MIXED, a.steps, a.warmup, profile=True)
     fp64 = time_path(P, torch, gp, w, P.SHK_FP64, a.steps, a.warmup, profile=False)
-    # the same solves with the Jacobi-preconditioned inner COCG
-    jac = {name: time_path(P, torch, gp, w, prec, a.steps, a.warmup, profile=False, precond=P.SHK_PRECOND_JACOBI)
-           for name, prec in (("mixed", P.SHK_MIXED), ("fp64", P.SHK_FP64))}
+    # the same solves with the Jacobi-preconditioned inner COCG (its one
+    # iteration kernel timed as well)
+    jac = {"mixed": time_path(P, torch, gp, w, P.SHK_MIXED, a.steps, a.warmup, profile=True,
+                              precond=P.SHK_PRECOND_JACOBI),
+           "fp64": time_path(P, torch, gp, w, P.SHK_FP64, a.steps, a.warmup, profile=False,
+                             precond=P.SHK_PRECOND_JACOBI)}
     nf = len(w.sigma)
     ms_step = mixed["total_ms"] / a.steps
     value = nf * a.steps / (mixed["total_ms"] / 1e3)
     fp64_value = nf * a.steps / (fp64["total_ms"] / 1e3)
-    launches, kms, kbytes = mixed["prof"]
-    roof = None
-    if launches > 0:
-        avg_s = kms / launches / 1e3
-        achieved = kbytes / launches / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_cg_step<Op2D<float>, float, ...> (inner COCG iteration, mixed path)",
-                "avg_launch_us": round(kms / launches * 1e3, 3), "launches": launches,
-                "algorithmic_bytes_per_launch": round(kbytes / launches)}
-        tfile = os.path.join(ROOT, "profiles", "traffic_cg_step_512x512.json")
-        if os.path.exists(tfile):
-            t = json.load(open(tfile))
-            if t.get("kernel_source_digest") == kernel_source_digest():
-                roof["traffic"] = t.get("traffic_bytes_per_launch")
+    # Roofline unit: one multigrid-COCG inner iteration (k_cgmg_step, the
+    # V-cycle's k_mg_down / k_mg_tail / k_mg_up launches, k_cgmg_post), timed
+    # with HIP events on the solver's stream around every chunk of iterations
+    # inside the timed region; no single launch of it dominates.
+    roof = roofline(mixed["prof"], "traffic_mg_iteration_512x512.json",
+                    "multigrid-COCG inner iteration, mixed path: k_cgmg_step, k_mg_down x4, k_mg_tail, "
+                    "k_mg_up x4, k_cgmg_post (11 launches)", "iteration")
+    roof_jac = roofline(jac["mixed"]["prof"], "traffic_cg_step_512x512.json",
+                        "k_cg_step<Op2D<float>, float, ...> (Jacobi-COCG iteration, mixed path)", "launch")
     out = {"metric": METRIC, "value": round(value, 2), "unit": "shifted solves/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
            "config": {"workload": f"2-D FV {a.grid}x{a.grid}, {nf} shifts (periods 5..5000 s), 1 point source, "
                                   "tau cyclic {i w20, i w100, i w180}, inner COCG 1e-6, restart 50, target 1e-6",
+                      "inner_preconditioner": "geometric multigrid V(1,1), damped Jacobi smoothing",
                       "n_shifts": nf, "n_rhs": 1, "unknowns": gp.n},
            "p50_ms": round(percentile(mixed["per_ms"], 0.5), 3), "p99_ms": round(percentile(mixed["per_ms"], 0.99), 3),
            "converged": mixed["ok"], "max_true_relres": mixed["worst"],
@@ -238,7 +261,11 @@ def main():
                     "p99_ms": round(percentile(fp64["per_ms"], 0.99), 3), "converged": fp64["ok"],
                     "max_true_relres": fp64["worst"], "inner_iterations": fp64["inner"],
                     "outer_steps": fp64["outer"], "refine_sweeps": fp64["sweeps"]},
-           "roofline": roof, "cpu_baseline": None}
+           "jacobi_inner": {name: {"value": round(nf * a.steps / (r["total_ms"] / 1e3), 2),
+                                   "ms_per_step": round(r["total_ms"] / a.steps, 3), "converged": r["ok"],
+                                   "max_true_relres": r["worst"], "inner_iterations": r["inner"]}
+                            for name, r in jac.items()},
+           "roofline": roof, "roofline_jacobi_step": roof_jac, "cpu_baseline": None}
     if not a.no_extra:
         # the batched workloads: 256x256 with 32 well sources + 32 adjoint
         # receiver vectors, and 128^3 with 8 sources; mixed and FP64 paths in

@@ -131,22 +131,6 @@ __device__ __forceinline__ cx<R> mg_down_fine(const Op& op, int i, int j, int k,
   return bi - ax;
 }
 
-// Downward leg, one coarse cell (I, J, L) and lane: the sum of the residuals
-// of its fine cells (restriction by P^T).
-template <typename Op, typename R, typename GB, typename GD>
-__device__ __forceinline__ cx<R> mg_down_cell(const Op& op, const LevelDims& f, int I, int J, int L, cx<R> tr,
-                                              R om, GB gb, GD gd) {
-  cx<R> acc{0, 0};
-  for (int dk = 0; dk < (f.nz > 1 ? 2 : 1); ++dk)
-    for (int dj = 0; dj < 2; ++dj)
-      for (int di = 0; di < 2; ++di) {
-        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * L + dk;
-        if (i >= f.nx || j >= f.ny || k >= f.nz) continue;
-        acc = acc + mg_down_fine<Op, R>(op, i, j, k, i + f.nx * (j + f.ny * k), tr, om, gb, gd);
-      }
-  return acc;
-}
-
 // Upward leg, one fine cell c = (i, j, k) and lane: x2 = x1 + P x_c
 // (x1 = omega D^-1 b), then one sweep x = x2 + omega D^-1 (b - A x2), with x2
 // at the stencil neighbours formed on the fly; gxc(C): coarse solution at
@@ -181,6 +165,18 @@ __device__ __forceinline__ cx<R> mg_up_cell(const Op& op, const LevelDims& f, co
   return xi + om * (gd(c) * (gb(c) - ax));
 }
 
+// Block coordinates of a (gx, gy, gz) launch, the linear block index taken
+// through xcd_tile: each XCD walks a contiguous band of rows (and planes), so
+// the stencil's neighbour rows are mostly in its own L2.
+__device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int T = xcd_tile(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+  const int r = T / gx;
+  bx = T - r * gx;
+  by = r % gy;
+  bz = r / gy;
+}
+
 // Downward leg of one level over the grid: coarse right-hand side b_c.
 // Launch grid (ceil(c.nx S 2^d / BS), c.ny, c.nz): along a coarse row,
 // thread t holds child t mod 2^d of lane (t >> d) mod S of coarse cell
@@ -193,11 +189,12 @@ __global__ void __launch_bounds__(BS) k_mg_down(Op op, LevelDims f, LevelDims c,
   constexpr int D = Op::NB / 2;
   constexpr int Q = 1 << D;
   int flag = *all_done;
-  const int t = blockIdx.x * BS + threadIdx.x;
+  int bx, J, L;
+  xcd_block3(bx, J, L);
+  const int t = bx * BS + threadIdx.x;
   if (t >= (c.nx << (lS + D))) return;   // whole groups of 2^d lanes leave together
   const int S = 1 << lS;
   const int q = t & (Q - 1), rl = (t >> D) & (S - 1), I = t >> (D + lS);
-  const int J = blockIdx.y, L = blockIdx.z;
   const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * L + (q >> 2);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
@@ -224,10 +221,12 @@ __global__ void __launch_bounds__(BS) k_mg_up(Op op, LevelDims f, LevelDims c, c
                                               const cx<R>* __restrict__ xc, cx<R>* __restrict__ xout,
                                               const int* __restrict__ all_done) {
   int flag = *all_done;
-  const int t = blockIdx.x * BS + threadIdx.x;
+  int bx, j, k;
+  xcd_block3(bx, j, k);
+  const int t = bx * BS + threadIdx.x;
   if (t >= (f.nx << lS)) return;
   const int S = 1 << lS;
-  const int rl = t & (S - 1), i = t >> lS, j = blockIdx.y, k = blockIdx.z;
+  const int rl = t & (S - 1), i = t >> lS;
   const int cell = i + f.nx * (j + f.ny * k);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
@@ -355,19 +354,31 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
     return o;
   };
   auto ldinv = [&](int k) { return reinterpret_cast<const cx<R>*>(lds_raw + lv[k].doff); };
+  // downward legs: as on the grid, one thread per (coarse cell, lane, fine
+  // child) and a cross-lane sum over the children
+  constexpr int D = Op::NB / 2;
+  constexpr int Q = 1 << D;
   for (int k = 0; k + 1 < T; ++k) {
     const LevelDims f = dims(k), c = dims(k + 1);
     const Op o = lop(k);
     const cx<R>* bk = sh + lv[k].off;
     cx<R>* bc = sh + lv[k + 1].off;
     const cx<R>* dk = ldinv(k);
-    const int Nc = c.n() << lS;
-    for (int j = tid; j < Nc; j += nth) {
-      const int rl = j & (S - 1), I = j >> lS;
+    const int total = c.n() << (lS + D);
+    for (int j = tid; j < total; j += nth) {   // whole groups of 2^d lanes in or out
+      const int q = j & (Q - 1), rl = (j >> D) & (S - 1), I = j >> (D + lS);
       const int Ix = I % c.nx, Iyz = I / c.nx;
-      auto gb = [&](int i) { return bk[(i << lS) + rl]; };
-      auto gd = [&](int i) { return dk[i]; };
-      bc[j] = mg_down_cell<Op, R>(o, f, Ix, Iyz % c.ny, Iyz / c.ny, tr, om, gb, gd);
+      const int x = 2 * Ix + (q & 1), y = 2 * (Iyz % c.ny) + ((q >> 1) & 1), z = 2 * (Iyz / c.ny) + (q >> 2);
+      auto gb = [&](int n) { return bk[(n << lS) + rl]; };
+      auto gd = [&](int n) { return dk[n]; };
+      cx<R> v{0, 0};
+      if (x < f.nx && y < f.ny && z < f.nz) v = mg_down_fine<Op, R>(o, x, y, z, x + f.nx * (y + f.ny * z), tr, om, gb, gd);
+#pragma unroll
+      for (int m = 1; m < Q; m <<= 1) {
+        v.re += __shfl_xor(v.re, m);
+        v.im += __shfl_xor(v.im, m);
+      }
+      if (q == 0) bc[(I << lS) + rl] = v;
     }
     __syncthreads();
   }
@@ -437,6 +448,7 @@ __device__ __forceinline__ bool cg_prologue(int lS, const CgCfg& cfg, const c128
     if (blockIdx.x == 0 && threadIdx.x == 0) *all_done = 1;
     return false;
   }
+  count_live(all_done);
   return true;
 }
 
@@ -457,9 +469,6 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
                                                    CgVecs<R> vec, int par, int* __restrict__ all_done) {
   const int lS = ONE ? 0 : lS_;
   const int rl = ONE ? 0 : (int)threadIdx.x & ((1 << lS) - 1);
-  CgScal s;
-  if (!cg_prologue<CGB, ONE>(lS, cfg, partIn, Gin, scIn, scOut, all_done, s)) return;
-  if (s.done) return;
   const int N = n << lS;
   const cx<R>* __restrict__ r0 = vec.r[par];
   const cx<R>* __restrict__ w0 = vec.w[par];
@@ -467,6 +476,9 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
   cx<R>* __restrict__ r1 = vec.r[par ^ 1];
   cx<R>* __restrict__ s1 = vec.s[par ^ 1];
   const int t0 = xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x;
+  CgScal s;
+  if (!cg_prologue<CGB, ONE>(lS, cfg, partIn, Gin, scIn, scOut, all_done, s)) return;
+  if (s.done) return;
   auto for_cells = [&](auto&& f) {
     if constexpr (MULTI) {
       for (int t = t0; t < N; t += gridDim.x * CGB) f(t);

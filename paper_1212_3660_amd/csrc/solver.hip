@@ -275,7 +275,8 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 // streaming stores on the complex64 path); SHK_CG_BLOCK, SHK_NT_STORE,
 // SHK_SEP_LIMIT and SHK_WS_SKEW override them for tuning sweeps.  The
 // complex64 inner rounds' reduction target and stall rule ("min,mult") are
-// SHK_ROUND_TOL and SHK_STALL.
+// SHK_ROUND_TOL and SHK_STALL.  SHK_MG_TAIL_LDS lowers the LDS budget of the
+// V-cycle's one-workgroup tail (so that it starts on a coarser level).
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
@@ -284,7 +285,9 @@ struct Tune {
   size_t skew = 0;
   double round_tol = 1e-2; // complex64 inner rounds: reduction per round
   int stall_min = 150, stall_mult = 3;
+  int tail_lds = MG_TAIL_LDS;
   Tune() {
+    if (const char* e = getenv("SHK_MG_TAIL_LDS")) tail_lds = std::max(0, std::min(atoi(e), MG_TAIL_LDS));
     if (const char* e = getenv("SHK_CG_BLOCK")) {
       const int v = atoi(e);
       if (v == 256 || v == 512) cgb = v;
@@ -462,7 +465,8 @@ struct PassSpec {
 
 struct Snap {
   int all_done;
-  int pad[3];
+  int live;   // iteration launches that did work since the solve started
+  int pad[2];
   CgScal sc[64];
 };
 
@@ -580,7 +584,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     const int Lv = mg_levels();
     int t = Lv;
     for (int l = Lv - 1; l >= 0; --l) {
-      if (mg_tail_bytes(l, lS) > (size_t)MG_TAIL_LDS || Lv - l > MG_MAXL) break;
+      if (mg_tail_bytes(l, lS) > (size_t)g_tune.tail_lds || Lv - l > MG_MAXL) break;
       t = l;
     }
     return t;   // Lv: not even the one-cell level fits (many lanes)
@@ -756,16 +760,25 @@ template <typename R, typename Op, typename OpD> struct Group {
     static_assert(sizeof(Snap) <= 32768, "staging layout");
     Snap* snap = (Snap*)g_pinned.get(65536);
     if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
-    const bool timing = g_timer.on;   // Jacobi: the iteration kernel; multigrid: the iteration's launches
-    if (timing) g_timer.ensure(1);
+    // Timer (profiling only).  At each poll the launches that did work are
+    // the chunk's first `live` ones.  Multigrid: an event after every
+    // iteration (its step, V-cycle and product launches), and the time from
+    // the end of the chunk's first to the end of its last working iteration.
+    // Jacobi (one short kernel per iteration, where an event each would
+    // slow the loop): events around the chunk, counted when every launch of
+    // it worked.  Either way kernel time plus the back-to-back gaps.
+    const bool timing = g_timer.on;
+    int live_before = 0;
     // per lane: iteration count and residual norm seen at the previous poll
     std::vector<int> prev_its(S, 0);
     std::vector<double> prev_rn(S, 0.0);
     int its_before = 0, rounds_before = S;
-    bool first = true;   // the chunk's first launch starts the solve
     const double lrt = std::log(std::max(g_tune.round_tol, 1e-12));
     while (true) {
-      if (timing) (void)hipEventRecord(g_timer.ev[0], st);
+      if (timing) {
+        g_timer.ensure((size_t)chunk / 2 + 1);
+        if (!mg) (void)hipEventRecord(g_timer.ev[0], st);
+      }
       for (int c = 0; c < chunk; ++c, ++it) {
         const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
         CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
@@ -773,10 +786,11 @@ template <typename R, typename Op, typename OpD> struct Group {
         if (mg) mg_iteration(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
         else launch_step(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
         in = totals(out);
+        if (timing && mg) (void)hipEventRecord(g_timer.ev[c + 1], st);
       }
-      if (timing) (void)hipEventRecord(g_timer.ev[1], st);
+      if (timing && !mg) (void)hipEventRecord(g_timer.ev[1], st);
       SHK_HIP(hipGetLastError());
-      SHK_HIP(hipMemcpyAsync(&snap->all_done, B.all_done, sizeof(int), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipMemcpyAsync(&snap->all_done, B.all_done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipMemcpyAsync(snap->sc, B.sc + (size_t)(it & 1) * S, S * sizeof(CgScal), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
       int its_now = 0, rounds_now = 0;
@@ -784,20 +798,22 @@ template <typename R, typename Op, typename OpD> struct Group {
         its_now = std::max(its_now, snap->sc[r].its);
         rounds_now += snap->sc[r].rounds;
       }
-      if (timing && !snap->all_done && rounds_now == rounds_before &&
-          its_now - its_before == chunk - (first ? 1 : 0)) {
-        // every launch of the chunk iterated (no round change, no idle
-        // launch): its time is kernel time plus the back-to-back gaps
+      if (timing) {
+        const int live = snap->live - live_before;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, g_timer.ev[0], g_timer.ev[1]) == hipSuccess) {
+        if (mg && live >= 2 && hipEventElapsedTime(&ms, g_timer.ev[1], g_timer.ev[live]) == hipSuccess) {
+          g_timer.total_ms += ms;
+          g_timer.launches += live - 1;
+          g_timer.total_bytes += (double)(live - 1) * mg_iteration_bytes();
+        } else if (!mg && live == chunk && hipEventElapsedTime(&ms, g_timer.ev[0], g_timer.ev[1]) == hipSuccess) {
           g_timer.total_ms += ms;
           g_timer.launches += chunk;
-          g_timer.total_bytes += (double)chunk * (mg ? mg_iteration_bytes() : (double)n * S * step_bytes_per_cell());
+          g_timer.total_bytes += (double)chunk * n * S * step_bytes_per_cell();
         }
       }
+      live_before = snap->live;
       its_before = its_now;
       rounds_before = rounds_now;
-      first = false;
       if (snap->all_done) break;
       // hang guard only: every lane stops itself after cap iterations and a
       // bounded number of round changes; the rest are the tails of chunks
@@ -895,7 +911,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       bytes += nl * (S * w + w + fpc + mass) + nc * S * w;              // down
       bytes += nl * (S * w + w + fpc + mass + S * w) + nc * S * w;      // up
     }
-    if (t < Lv) bytes += 2.0 * mg_dims(t).n() * S * w;                  // tail in/out
+    if (t < Lv) bytes += 2.0 * mg_dims(t).n() * S * w + 4.0 * mg_ta.pack_words;   // tail in/out, coefficients
     bytes += (double)N * 3.0 * w + (double)n * fpc;                     // product
     return bytes;
   }

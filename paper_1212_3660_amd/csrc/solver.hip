@@ -283,7 +283,8 @@ struct Tune {
   int nt32 = 1;
   long sep_limit = 3072;   // fold partials in a separate kernel above this many
   size_t skew = 0;
-  double round_tol = 1e-2; // complex64 inner rounds: reduction per round
+  double round_tol = 1e-2;    // complex64 inner rounds: reduction per round (Jacobi inner solve)
+  double round_tol_mg = 1e-3; // the same with the multigrid inner solve (few, fast iterations)
   int stall_min = 150, stall_mult = 3;
   int tail_lds = MG_TAIL_LDS;
   Tune() {
@@ -295,7 +296,7 @@ struct Tune {
     if (const char* e = getenv("SHK_WS_SKEW")) skew = (size_t)strtoull(e, nullptr, 10) & ~size_t(255);
     if (const char* e = getenv("SHK_NT_STORE")) nt64 = nt32 = atoi(e) != 0;
     if (const char* e = getenv("SHK_SEP_LIMIT")) sep_limit = atol(e);
-    if (const char* e = getenv("SHK_ROUND_TOL")) round_tol = atof(e);
+    if (const char* e = getenv("SHK_ROUND_TOL")) round_tol = round_tol_mg = atof(e);
     if (const char* e = getenv("SHK_STALL")) {
       if (sscanf(e, "%d,%d", &stall_min, &stall_mult) != 2) stall_min = stall_mult = 0;
     }
@@ -518,6 +519,21 @@ template <typename R, typename Op, typename OpD> struct Group {
   bool mg = false;                // COCG preconditioned by the V-cycle
   double mg_omega = 0.8;
   MgTail mg_ta{};                 // tail arguments for the current inner solve
+  // working launches of the last inner solve per tau (a handful of taus)
+  std::vector<std::pair<c128, int>> mg_hist;
+  int mg_hist_get(c128 tau) const {
+    for (const auto& h : mg_hist)
+      if (h.first.re == tau.re && h.first.im == tau.im) return h.second;
+    return 0;
+  }
+  void mg_hist_put(c128 tau, int launches) {
+    for (auto& h : mg_hist)
+      if (h.first.re == tau.re && h.first.im == tau.im) {
+        h.second = launches;
+        return;
+      }
+    if (mg_hist.size() < 16) mg_hist.emplace_back(tau, launches);
+  }
   int mg_lds = 0;                 // and its LDS bytes
   int mg_levels() const { return 1 + (int)p->mg.size(); }
   LevelDims mg_dims(int l) const {
@@ -740,7 +756,8 @@ template <typename R, typename Op, typename OpD> struct Group {
     cfg.eps = fixed > 0 ? -1.0 : eps;
     cfg.maxit = cap;
     cfg.trust = rounds ? 0 : 1;
-    cfg.round_tol = rounds ? g_tune.round_tol : 0.0;
+    const double rtol = mg ? g_tune.round_tol_mg : g_tune.round_tol;
+    cfg.round_tol = rounds ? rtol : 0.0;
     cfg.stall_min = g_tune.stall_min;
     cfg.stall_mult = g_tune.stall_mult;
     cfg.fused_start = mg ? 1 : 0;
@@ -757,6 +774,13 @@ template <typename R, typename Op, typename OpD> struct Group {
     SHK_HIP(hipGetLastError());
     long it = 0;
     int chunk = std::min(cap + 1, 16);
+    // Multigrid: an idle iteration (launched past the end of the solve) costs
+    // about half a working one, so the first chunk is the working launch
+    // count of the last inner solve with this tau, when there was one (the
+    // shifts repeat cyclically and so do the counts, give or take a few),
+    // plus the launch that finds every lane done.
+    const int hist = mg && fixed <= 0 ? mg_hist_get(tau) : 0;
+    if (hist > 0) chunk = std::min(cap + 1, hist + 1);
     static_assert(sizeof(Snap) <= 32768, "staging layout");
     Snap* snap = (Snap*)g_pinned.get(65536);
     if (!snap) return fail(SHK_ERR_OOM, "pinned staging");
@@ -773,7 +797,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     std::vector<int> prev_its(S, 0);
     std::vector<double> prev_rn(S, 0.0);
     int its_before = 0, rounds_before = S;
-    const double lrt = std::log(std::max(g_tune.round_tol, 1e-12));
+    const double lrt = std::log(std::max(rtol, 1e-12));
     while (true) {
       if (timing) {
         g_timer.ensure((size_t)chunk / 2 + 1);
@@ -823,7 +847,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       // launches per remaining refinement round, and never more than the
       // iterations already taken (a poll costs about as much as a few idle
       // launches; an early overestimate of a slow start far more).
-      int need = 4;
+      int need = mg ? 2 : 4;
       for (int r = 0; r < S; ++r) {
         const CgScal& s = snap->sc[r];
         int rem = 16;
@@ -854,6 +878,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     long long its_max = 0;
     for (int r = 0; r < S; ++r) its_max = std::max<long long>(its_max, snap->sc[r].its);
     inner_its += its_max;
+    if (mg && fixed <= 0) mg_hist_put(tau, snap->live);
     const int Gf = grid_items(N, 1024);
     k_cocg_finish<OpD, R><<<Gf, BS, 0, st>>>(opd, tau, n, S, v, z, B.W, B.part);
     k_final_sqrt<2><<<1, BS, 0, st>>>(B.part, Gf, S, pn_out, B.mz, nullptr);

@@ -99,7 +99,7 @@ typedef struct shk_server shk_server;
  *                 faces they cover, coarse mass the sum, one V-cycle with
  *                 mg_sweeps damped Jacobi sweeps of weight mg_omega before and
  *                 after the coarse correction; a call error (UNSUPPORTED) for
- *                 CSR problems.
+ *                 CSR problems and for grids with ny or nz above 65535.
  *  mg_sweeps      1 (the only value provided; others are a call error).
  *  mg_omega       Jacobi damping of the smoother, in (0, 1].
  */
@@ -237,13 +237,21 @@ int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128
 int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b,
                       const shk_c128* x, double* relres, void* hip_stream);
 
-/* Instrumentation of the inner-iteration kernel (the hot loop of section 4's
- * inner solves): when enabled, each batch of its launches between two host
- * polls is bracketed by HIP events on the solve stream, and for every batch in
- * which each launch performed an iteration, the batch's duration, its launch
- * count and its algorithmic bytes (per cell: r, w, s read and written, p and
- * the FP64 iterate x read and written, the inverse diagonal and the face
- * coefficients read) are accumulated.  Process-wide; enable/disable/read are
+/* Instrumentation of the inner iteration (the hot loop of section 4's inner
+ * solves).  When enabled, the solve stream carries HIP events and the library
+ * accumulates, over the iterations that did work, their duration, their count
+ * and their algorithmic bytes:
+ *  - Jacobi inner solve: one kernel per iteration; events bracket each batch of
+ *    launches between two host polls, and a batch counts when every launch in
+ *    it iterated (bytes per cell: r, w, s read and written, p and the FP64
+ *    iterate read and written, inverse diagonal and faces read);
+ *  - multigrid inner solve: an event after every iteration (step, V-cycle and
+ *    product launches); the count is iterations, the time runs from the end of
+ *    a batch's first to the end of its last working iteration, and the bytes
+ *    follow the byte model of one iteration (the step's vector updates, every
+ *    V-cycle leg's operands and output, the tail's coefficients, the product).
+ * launches: the count (kernel launches or iterations); total_ms: summed time;
+ * total_bytes: summed algorithmic bytes.  Process-wide; enable/disable/read are
  * not meant to race with solves on other threads. */
 int shk_profile_enable(int on);
 int shk_profile_read(long long* launches, double* total_ms, double* total_bytes);

@@ -479,8 +479,8 @@ __global__ void __launch_bounds__(BS) k_cg_init(Op op, const cx<R>* __restrict__
 // all_done[0]: every lane of the inner solve has stopped; all_done[1]: the
 // iteration launches that did work since the solve started (what the host's
 // timer divides by).  Called by a launch that goes on past its prologue.
-__device__ __forceinline__ void count_live(int* all_done) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(all_done + 1, 1);
+__device__ __forceinline__ void count_live(int* all_done, bool lead) {
+  if (lead && threadIdx.x == 0) atomicAdd(all_done + 1, 1);
 }
 
 // Loads of one cell for the stencil iteration (issued before any arithmetic,
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, OpD opd, const cx<R>* __
     if (blockIdx.x == 0 && threadIdx.x == 0) *all_done = 1;
     return;
   }
-  count_live(all_done);
+  count_live(all_done, blockIdx.x == 0);
   c128 ag{0, 0}, ad{0, 0};
   double arr = 0;
   if (!s.done) {

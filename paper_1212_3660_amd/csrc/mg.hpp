@@ -427,7 +427,7 @@ __global__ void __launch_bounds__(BS) k_mg_scale_grid(long N, int lS, const cx<R
 template <int CGB, bool ONE>
 __device__ __forceinline__ bool cg_prologue(int lS, const CgCfg& cfg, const c128* __restrict__ partIn, int Gin,
                                             const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
-                                            int* __restrict__ all_done, CgScal& s) {
+                                            int* __restrict__ all_done, CgScal& s, bool lead) {
   const int S = 1 << lS;
   const int rl = ONE ? 0 : (int)threadIdx.x & (S - 1);
   const int flag = *all_done;
@@ -438,17 +438,17 @@ __device__ __forceinline__ bool cg_prologue(int lS, const CgCfg& cfg, const c128
   c128 tot[3];
   part_sum<3, KMAX, CGB>(partIn, Gin, S, PL, tot);
   if (flag) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
+    if (lead && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
     return false;
   }
   cg_advance(s, cfg, tot[0], tot[1], tot[2].re);
   const bool any_open = __any(!s.done);
-  if (blockIdx.x == 0 && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
+  if (lead && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
   if (!any_open) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *all_done = 1;
+    if (lead && threadIdx.x == 0) *all_done = 1;
     return false;
   }
-  count_live(all_done);
+  count_live(all_done, lead);
   return true;
 }
 
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
   cx<R>* __restrict__ s1 = vec.s[par ^ 1];
   const int t0 = xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x;
   CgScal s;
-  if (!cg_prologue<CGB, ONE>(lS, cfg, partIn, Gin, scIn, scOut, all_done, s)) return;
+  if (!cg_prologue<CGB, ONE>(lS, cfg, partIn, Gin, scIn, scOut, all_done, s, blockIdx.x == 0)) return;
   if (s.done) return;
   auto for_cells = [&](auto&& f) {
     if constexpr (MULTI) {
@@ -508,6 +508,82 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
   } else if (s.mode == CG_KX) {
     for_cells([&](int t) { vec.x[t] = vec.x[t] + cvt<double>(u[t]); });
   }
+}
+
+// The step fused with the V-cycle's first restriction, for one lane (S = 1):
+// launched on the restriction's grid (one thread per fine cell, children of a
+// coarse cell in adjacent lanes), every block runs the step's prologue, each
+// thread updates its own cell as k_cgmg_step does and restricts the new
+// residual, whose values at the stencil neighbours it forms from their old
+// r, w, s (ITER) or their FP64 residual (RR) with the step's own expressions,
+// so they are the values the step stores.  In any other mode the stored r'
+// is restricted, as the separate kernels do.  Saves the step's launch and its
+// second read of r'.
+template <typename Op, typename OpD, typename R>
+__global__ void __launch_bounds__(BS) k_cgmg_step_down(Op op, OpD opd, LevelDims f, LevelDims c, c128 tau,
+                                                       double omega, CgCfg cfg, const cx<R>* __restrict__ v,
+                                                       const cx<R>* __restrict__ u,
+                                                       const c128* __restrict__ partIn, int Gin,
+                                                       const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
+                                                       CgVecs<R> vec, int par, const cx<R>* __restrict__ dinv,
+                                                       cx<R>* __restrict__ out, int* __restrict__ all_done) {
+  constexpr int D = Op::NB / 2;
+  constexpr int Q = 1 << D;
+  int bx, J, L;
+  xcd_block3(bx, J, L);
+  const bool lead = (blockIdx.x | blockIdx.y | blockIdx.z) == 0;
+  CgScal s;
+  if (!cg_prologue<BS, true>(0, cfg, partIn, Gin, scIn, scOut, all_done, s, lead)) return;
+  const int t = bx * BS + threadIdx.x;
+  if (t >= (c.nx << D)) return;   // after the prologue's barriers; whole groups of 2^d lanes
+  const int q = t & (Q - 1), I = t >> D;
+  const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * L + (q >> 2);
+  const bool in = i < f.nx && j < f.ny && k < f.nz;
+  const int cell = i + f.nx * (j + f.ny * k);
+  const cx<R>* __restrict__ r0 = vec.r[par];
+  const cx<R>* __restrict__ w0 = vec.w[par];
+  const cx<R>* __restrict__ s0 = vec.s[par];
+  cx<R>* __restrict__ r1 = vec.r[par ^ 1];
+  cx<R>* __restrict__ s1 = vec.s[par ^ 1];
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  auto gd = [&](int n) { return dinv[n]; };
+  cx<R> res{0, 0};
+  if (s.mode == CG_ITER) {
+    const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta);
+    const c128 al64 = s.alpha;
+    auto gb = [&](int n) { return r0[n] - al * (w0[n] + be * s0[n]); };
+    if (in) {
+      res = mg_down_fine<Op, R>(op, i, j, k, cell, tr, om, gb, gd);
+      const cx<R> sn = w0[cell] + be * s0[cell];
+      const cx<R> pn = u[cell] + be * vec.p[cell];
+      r1[cell] = gb(cell);
+      s1[cell] = sn;
+      vec.p[cell] = pn;
+      vec.x[cell] = vec.x[cell] + al64 * cvt<double>(pn);
+    }
+  } else if (s.mode == CG_RR) {
+    const c128* __restrict__ x = vec.x;
+    auto gx = [&](int cc) { return x[cc]; };
+    auto gb = [&](int n) { return cvt<R>(cvt<double>(v[n]) - opd.template apply<double>(n, tau, gx)); };
+    if (in) {
+      res = mg_down_fine<Op, R>(op, i, j, k, cell, tr, om, gb, gd);
+      r1[cell] = gb(cell);
+      s1[cell] = cx<R>{0, 0};
+    }
+  } else {
+    auto gb = [&](int n) { return r1[n]; };
+    if (in) {
+      res = mg_down_fine<Op, R>(op, i, j, k, cell, tr, om, gb, gd);
+      if (s.mode == CG_KX) vec.x[cell] = vec.x[cell] + cvt<double>(u[cell]);
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < Q; m <<= 1) {
+    res.re += __shfl_xor(res.re, m);
+    res.im += __shfl_xor(res.im, m);
+  }
+  if (q == 0) out[I + c.nx * (J + c.ny * L)] = res;
 }
 
 // Operator product and forms of one multigrid-COCG iteration: w' = A u' for

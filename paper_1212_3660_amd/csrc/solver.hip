@@ -276,7 +276,8 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 // SHK_SEP_LIMIT and SHK_WS_SKEW override them for tuning sweeps.  The
 // complex64 inner rounds' reduction target and stall rule ("min,mult") are
 // SHK_ROUND_TOL and SHK_STALL.  SHK_MG_TAIL_LDS lowers the LDS budget of the
-// V-cycle's one-workgroup tail (so that it starts on a coarser level).
+// V-cycle's one-workgroup tail (so that it starts on a coarser level);
+// SHK_MG_FUSE=0 keeps the multigrid step and the finest restriction apart.
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
@@ -287,7 +288,9 @@ struct Tune {
   double round_tol_mg = 1e-3; // the same with the multigrid inner solve (few, fast iterations)
   int stall_min = 150, stall_mult = 3;
   int tail_lds = MG_TAIL_LDS;
+  int mg_fuse = 1;   // step fused with the finest restriction where it applies
   Tune() {
+    if (const char* e = getenv("SHK_MG_FUSE")) mg_fuse = atoi(e) != 0;
     if (const char* e = getenv("SHK_MG_TAIL_LDS")) tail_lds = std::max(0, std::min(atoi(e), MG_TAIL_LDS));
     if (const char* e = getenv("SHK_CG_BLOCK")) {
       const int v = atoi(e);
@@ -649,14 +652,15 @@ template <typename R, typename Op, typename OpD> struct Group {
     lds_bytes = a.pack_lds + (int)off;
   }
   // uout = B b0 (one V-cycle over every level)
-  void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout) {
+  // (from = 1: the finest restriction was done by the fused step kernel)
+  void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout, int from = 0) {
     if constexpr (Op::NB > 0) {
       const int Lv = mg_levels();
       const int S_ = 1 << lS;
       const int t = mg_tail_level(lS);
       const int gdown = std::min(t, Lv - 1);   // levels whose down leg runs on the grid
-      const cx<R>* bl = b0;
-      for (int l = 0; l < gdown; ++l) {
+      const cx<R>* bl = from > 0 ? B.mb[from - 1] : b0;
+      for (int l = from; l < gdown; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
         const dim3 g((unsigned)((((long)c.nx * S_ << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
@@ -703,13 +707,31 @@ template <typename R, typename Op, typename OpD> struct Group {
     if (g_tune.cgb == 512) mg_post_cgb<512>(G, tau, ni, lS, sc, r, w, out);
     else mg_post_cgb<256>(G, tau, ni, lS, sc, r, w, out);
   }
+  // The step fused with the finest restriction: one lane, the default block
+  // size, the finest down leg on the grid, and few enough blocks that each
+  // summing every partial stays cheap.
+  bool mg_fused(int lS) const {
+    if (Op::NB == 0 || lS != 0 || g_tune.cgb != BS || !g_tune.mg_fuse) return false;
+    if (mg_levels() < 2 || mg_tail_level(lS) < 1) return false;
+    const LevelDims c = mg_dims(1);
+    const long blocks = ((long)c.nx * (1 << (Op::NB / 2)) + BS - 1) / BS * c.ny * c.nz;
+    return blocks <= 2048;
+  }
   template <int CGB, bool ONE, bool MULTI>
   void mg_iter_k(int G, c128 tau, int ni, int lS, const CgCfg& cfg, const c128* in, int Gin, const CgScal* scIn,
                  CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
     if constexpr (Op::NB > 0) {
-      k_cgmg_step<Op, OpD, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(opd, tau, ni, lS, cfg, cur_v, B.u, in, Gin, scIn,
-                                                                  scOut, vec, par, B.all_done);
-      mg_vcycle(vec.r[par ^ 1], tau, lS, B.u);
+      if (mg_fused(lS)) {
+        const LevelDims f = mg_dims(0), c = mg_dims(1);
+        const dim3 g((unsigned)(((long)c.nx * (1 << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
+        k_cgmg_step_down<Op, OpD, R><<<g, BS, 0, st>>>(op, opd, f, c, tau, mg_omega, cfg, cur_v, B.u, in, Gin, scIn,
+                                                       scOut, vec, par, B.dinv, B.mb[0], B.all_done);
+        mg_vcycle(vec.r[par ^ 1], tau, lS, B.u, 1);
+      } else {
+        k_cgmg_step<Op, OpD, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(opd, tau, ni, lS, cfg, cur_v, B.u, in, Gin, scIn,
+                                                                    scOut, vec, par, B.all_done);
+        mg_vcycle(vec.r[par ^ 1], tau, lS, B.u);
+      }
       k_cgmg_post<Op, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(op, tau, ni, lS, scOut, vec.r[par ^ 1], B.u,
                                                              vec.w[par ^ 1], out, B.all_done);
     }
@@ -930,6 +952,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     const int lS = ilog2(S);
     const int Lv = mg_levels(), t = mg_tail_level(lS);
     double bytes = (double)N * (8.0 * w + 32.0);                       // vector updates
+    if (mg_fused(lS)) bytes -= (double)N * w;                           // fused: r' not read back
     for (int l = 0; l < std::min(t, Lv - 1); ++l) {
       const double nl = mg_dims(l).n(), nc = mg_dims(l + 1).n();
       const double mass = l == 0 ? 0.0 : 8.0;

@@ -177,7 +177,7 @@ def test_shifted_lsq_matches_oracle_least_squares():
         assert np.allclose(y[j], yo, rtol=1e-8, atol=1e-9 * np.abs(yo).max())
 
 
-@pytest.mark.parametrize("n,k,nf", [(1000, 5, 3), (70000, 40, 37)])
+@pytest.mark.parametrize("n,k,nf", [(1000, 5, 3), (5000, 25, 200), (70001, 32, 45), (70000, 40, 37)])
 def test_assemble(n, k, nf):
     torch = require_gpu()
     import paper_1212_3660_amd as P

@@ -733,6 +733,7 @@ __global__ void __launch_bounds__(BS) k_gs_dot(long N, int S, int kc, const cx<R
     // exact products of the stored values, FP64 sums (the projections in the
     // second pass are small differences of large terms)
     c128 a{0, 0};
+#pragma unroll 8
     for (long t = start + lane; t < end; t += WAVE) a = a + cdot(cvt<double>(Vi[t]), cvt<double>(w[t]));
     c128 s = wave_sum_strided(a, S);
     if (lane < S) part[((size_t)blockIdx.x * kc + i) * S + lane] = s;
@@ -870,25 +871,33 @@ __device__ __forceinline__ void givens_make(c128 a, c128 b, double& c, c128& s, 
 
 __device__ __forceinline__ size_t tri(int i, int k) { return (size_t)k * (k + 1) / 2 + i; }
 
-// y = R^{-1} g over the first kc columns, written to Yb row; returns ||y||-weighted
-// inexact term sum |y_i| ||p_i||.
-__device__ inline double backsolve(const GivensArgs& a, int lane, int r, int kc, const c128* gv, size_t gstride) {
+// y = R^{-1} g over the first kc columns into y[i * ys]; returns the inexact
+// term sum |y_i| ||p_i||.  The R loads do not depend on the running sum, so
+// several are in flight at once.
+__device__ inline double backsolve(const GivensArgs& a, int lane, int r, int kc, const c128* gv, size_t gstride,
+                                  c128* y, int ys) {
   const int L = a.L;
-  c128* y = a.Yb + (size_t)lane * a.m;
   double gap = 0.0;
   for (int i = kc - 1; i >= 0; --i) {
     c128 acc = gv[(size_t)i * gstride];
-    for (int l = i + 1; l < kc; ++l) acc = acc - a.Rp[tri(i, l) * L + lane] * y[l];
+#pragma unroll 4
+    for (int l = i + 1; l < kc; ++l) acc = acc - a.Rp[tri(i, l) * L + lane] * y[l * ys];
     const c128 yi = cdiv(acc, a.Rp[tri(i, i) * L + lane]);
-    y[i] = yi;
+    y[i * ys] = yi;
     gap += hypot(yi.re, yi.im) * a.pn[i * a.S + r];
   }
-  for (int i = kc; i < a.m; ++i) y[i] = c128{0.0, 0.0};
   return gap;
 }
 
+// Basis lengths up to GIV_LDS_M keep each lane's y in LDS during the back
+// substitution (launch: GIV_BLOCK threads per block, GIV_BLOCK * m * 16 bytes
+// of LDS); longer ones use the lane's row of Yb.
+constexpr int GIV_BLOCK = 64;
+constexpr int GIV_LDS_M = 60;
+
 __global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
-  const int lane = blockIdx.x * BS + threadIdx.x;
+  extern __shared__ __align__(16) char giv_lds[];
+  const int lane = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane >= a.L) return;
   LaneState st = a.ls[lane];
   if (!st.active) return;
@@ -899,6 +908,7 @@ __global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
   // rotate the new column
   c128 carry = d * a.Hk[0 * S + r];
   if (k == 0) carry.re += 1.0;
+#pragma unroll 4
   for (int i = 0; i < k; ++i) {
     c128 nxt = d * a.Hk[(i + 1) * S + r];
     if (i + 1 == k) nxt.re += 1.0;
@@ -919,7 +929,14 @@ __global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
   const c128 gk1 = (-1.0) * (conj(s) * gk);
   a.g[(size_t)(k + 1) * L + lane] = gk1;
   const double rho = broke ? 0.0 : hypot(gk1.re, gk1.im);
-  const double gap = backsolve(a, lane, r, k + 1, a.g + lane, (size_t)L);
+  const bool in_lds = a.m <= GIV_LDS_M && blockDim.x == GIV_BLOCK;
+  c128* yrow = a.Yb + (size_t)lane * a.m;
+  c128* y = in_lds ? reinterpret_cast<c128*>(giv_lds) + threadIdx.x : yrow;
+  const int ys = in_lds ? GIV_BLOCK : 1;
+  const double gap = backsolve(a, lane, r, k + 1, a.g + lane, (size_t)L, y, ys);
+  if (in_lds)
+    for (int i = 0; i <= k; ++i) yrow[i] = y[i * ys];
+  for (int i = k + 1; i < a.m; ++i) yrow[i] = c128{0.0, 0.0};
   const double bound = rho + st.gap_prev + gap;
   const double b0 = a.beta0[r];
   st.rho = rho;
@@ -1045,7 +1062,7 @@ __global__ void __launch_bounds__(BS) k_restart_lanes(GivensArgs a, const int* _
       carry = (-1.0) * (conj(s) * carry) + c * nx;
       a.g[(size_t)i * L + lane] = a.g[(size_t)i * L + lane] - gamma * zi;
     }
-    gap = backsolve(a, lane, r, m, a.g + lane, (size_t)L);
+    gap = backsolve(a, lane, r, m, a.g + lane, (size_t)L, a.Yb + (size_t)lane * m, 1);
   }
   st.gap_prev += gap;
   st.beta = (j == seed[r]) ? c128{nzs[r], 0.0} : gamma;

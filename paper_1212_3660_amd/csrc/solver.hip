@@ -371,9 +371,20 @@ template <typename R> static void carve_mg(Carver& cv, Buffers<R>& b, const shk_
 }
 
 static int resid_grid(long n) { return grid_items(n, 256); }
+
+// One thread per (shift, rhs) lane; short bases keep the back substitution
+// in LDS.
+static void launch_givens(const GivensArgs& a, hipStream_t st) {
+  if (a.m <= GIV_LDS_M)
+    k_givens<<<(a.L + GIV_BLOCK - 1) / GIV_BLOCK, GIV_BLOCK, (size_t)GIV_BLOCK * a.m * sizeof(c128), st>>>(a);
+  else
+    k_givens<<<(a.L + BS - 1) / BS, BS, 0, st>>>(a);
+}
+// Items per block of the Gram-Schmidt dot kernel: about 512 blocks (two per
+// CU), at least 256 items each.
 static long dot_ipb(long N) {
   long ipb = (N + 511) / 512;
-  ipb = std::max<long>(1024, (ipb + 255) / 256 * 256);
+  ipb = std::max<long>(256, (ipb + 255) / 256 * 256);
   return ipb;
 }
 
@@ -1012,7 +1023,7 @@ template <typename R, typename Op, typename OpD> struct Group {
                       B.pn + (size_t)k * S));
         SHK_TRY(orthogonalize(k, B.W));
         GivensArgs a = gargs(k, cycle, (int)(kglob - ps.kglob0), ps.tol);
-        k_givens<<<Lb, BS, 0, st>>>(a);
+        launch_givens(a, st);
         k_count_active<<<1, BS, 0, st>>>(S, nf, B.ls, B.nact);
         SHK_HIP(hipGetLastError());
         SHK_HIP(hipMemcpyAsync(nact, B.nact, S * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1411,7 +1422,7 @@ int step_lsq(int K, const c128* H, const c128* taus, int nf, const c128* sigma, 
     a.tol = 0.0; a.inexact_ratio = -1.0; a.breakdown_rel = 0.0;
     a.Hk = b.H + (size_t)k * (m + 2); a.hn = b.hn; a.mz = b.mz; a.pn = b.pn; a.beta0 = b.beta0;
     a.sigma = b.sigma; a.taus = b.taus; a.ls = b.ls; a.rc = b.rc; a.rs = b.rs; a.g = b.g; a.Rp = b.Rp; a.Yb = b.Yb;
-    k_givens<<<(L + BS - 1) / BS, BS>>>(a);
+    launch_givens(a, nullptr);
     SHK_HIP(hipGetLastError());
     SHK_HIP(hipMemcpy(ls.data(), b.ls, sizeof(LaneState) * L, hipMemcpyDeviceToHost));
     for (int j = 0; j < nf; ++j) rho[j + (size_t)nf * k] = ls[j].rho;

@@ -237,13 +237,14 @@ def main():
     ms_step = mixed["total_ms"] / a.steps
     value = nf * a.steps / (mixed["total_ms"] / 1e3)
     fp64_value = nf * a.steps / (fp64["total_ms"] / 1e3)
-    # Roofline unit: one multigrid-COCG inner iteration (k_cgmg_step, the
-    # V-cycle's k_mg_down / k_mg_tail / k_mg_up launches, k_cgmg_post), timed
+    # Roofline unit: one multigrid-COCG inner iteration (the step fused with
+    # the first restriction, the V-cycle's other k_mg_down / k_mg_tail /
+    # k_mg_up launches, k_cgmg_post), timed
     # with HIP events on the solver's stream around every chunk of iterations
     # inside the timed region; no single launch of it dominates.
     roof = roofline(mixed["prof"], "traffic_mg_iteration_512x512.json",
-                    "multigrid-COCG inner iteration, mixed path: k_cgmg_step, k_mg_down x4, k_mg_tail, "
-                    "k_mg_up x4, k_cgmg_post (11 launches)", "iteration")
+                    "multigrid-COCG inner iteration, mixed path: k_cgmg_step_down (step fused with the finest "
+                    "restriction), k_mg_down x3, k_mg_tail, k_mg_up x4, k_cgmg_post (10 launches)", "iteration")
     roof_jac = roofline(jac["mixed"]["prof"], "traffic_cg_step_512x512.json",
                         "k_cg_step<Op2D<float>, float, ...> (Jacobi-COCG iteration, mixed path)", "launch")
     out = {"metric": METRIC, "value": round(value, 2), "unit": "shifted solves/s", "n_gpus": 1,

@@ -101,6 +101,31 @@ __global__ void __launch_bounds__(BS) k_mg_dinv(OpD opd, c128 tau, int n, cx<R>*
 template <typename R> __device__ __forceinline__ void hold(cx<R>& v, int& flag) {
   asm volatile("" : "+v"(v.re), "+v"(v.im), "+s"(flag));
 }
+// Sum of v over the Q = 2^d adjacent lanes of an aligned group (d = 2, 3), in
+// the same order in every lane: quad permutes (DPP) for lane distances 1 and
+// 2, a cross-lane read for 4.
+template <int CTRL> __device__ __forceinline__ float dpp_quad(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_quad(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int Q, typename R> __device__ __forceinline__ cx<R> group_sum(cx<R> v) {
+  constexpr int X1 = 0xB1, X2 = 0x4E;   // quad_perm [1,0,3,2] and [2,3,0,1]
+  v.re += dpp_quad<X1>(v.re);
+  v.im += dpp_quad<X1>(v.im);
+  v.re += dpp_quad<X2>(v.re);
+  v.im += dpp_quad<X2>(v.im);
+  if constexpr (Q == 8) {
+    v.re += __shfl_xor(v.re, 4);
+    v.im += __shfl_xor(v.im, 4);
+  }
+  return v;
+}
+
 // A pointer the compiler cannot see through: a load from it stays where it is
 // written instead of being merged with an earlier one.
 template <typename T> __device__ __forceinline__ T* opaque(T* p) {
@@ -204,11 +229,7 @@ __global__ void __launch_bounds__(BS) k_mg_down(Op op, LevelDims f, LevelDims c,
     auto gd = [&](int n) { return dinv[n]; };
     v = mg_down_fine<Op, R>(op, i, j, k, i + f.nx * (j + f.ny * k), tr, om, gb, gd);
   }
-#pragma unroll
-  for (int m = 1; m < Q; m <<= 1) {
-    v.re += __shfl_xor(v.re, m);
-    v.im += __shfl_xor(v.im, m);
-  }
+  v = group_sum<Q>(v);
   hold(v, flag);
   if (!flag && q == 0) out[((long)(I + c.nx * (J + c.ny * L)) << lS) + rl] = v;
 }
@@ -373,11 +394,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
       auto gd = [&](int n) { return dk[n]; };
       cx<R> v{0, 0};
       if (x < f.nx && y < f.ny && z < f.nz) v = mg_down_fine<Op, R>(o, x, y, z, x + f.nx * (y + f.ny * z), tr, om, gb, gd);
-#pragma unroll
-      for (int m = 1; m < Q; m <<= 1) {
-        v.re += __shfl_xor(v.re, m);
-        v.im += __shfl_xor(v.im, m);
-      }
+      v = group_sum<Q>(v);
       if (q == 0) bc[(I << lS) + rl] = v;
     }
     __syncthreads();
@@ -578,11 +595,7 @@ __global__ void __launch_bounds__(BS) k_cgmg_step_down(Op op, OpD opd, LevelDims
       if (s.mode == CG_KX) vec.x[cell] = vec.x[cell] + cvt<double>(u[cell]);
     }
   }
-#pragma unroll
-  for (int m = 1; m < Q; m <<= 1) {
-    res.re += __shfl_xor(res.re, m);
-    res.im += __shfl_xor(res.im, m);
-  }
+  res = group_sum<Q>(res);
   if (q == 0) out[I + c.nx * (J + c.ny * L)] = res;
 }
 

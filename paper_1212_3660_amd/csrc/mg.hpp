@@ -272,6 +272,7 @@ constexpr int MG_TAIL_LDS = 63 * 1024;   // dynamic LDS; the level table takes s
 constexpr int MG_MAXSEG = 5 * MG_MAXL;
 struct MgTailLevel {
   int nx, ny, nz;
+  int lpx, lpy;  // log2 of the power-of-two row and column pitches the phases walk (no index division)
   int off;       // LDS offset (elements) of b; x follows it (n S each)
   int doff;      // LDS byte offset of D^-1
   int moff;      // LDS byte offset of the cell masses (doubles)
@@ -385,17 +386,22 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
     const cx<R>* bk = sh + lv[k].off;
     cx<R>* bc = sh + lv[k + 1].off;
     const cx<R>* dk = ldinv(k);
-    const int total = c.n() << (lS + D);
+    // threads walk the coarse grid with power-of-two pitches: coordinates by
+    // shifts and masks, padding threads idle
+    const int lpx = lv[k + 1].lpx, lpy = lv[k + 1].lpy;
+    const int total = (c.nz << (lpx + lpy)) << (lS + D);
     for (int j = tid; j < total; j += nth) {   // whole groups of 2^d lanes in or out
-      const int q = j & (Q - 1), rl = (j >> D) & (S - 1), I = j >> (D + lS);
-      const int Ix = I % c.nx, Iyz = I / c.nx;
-      const int x = 2 * Ix + (q & 1), y = 2 * (Iyz % c.ny) + ((q >> 1) & 1), z = 2 * (Iyz / c.ny) + (q >> 2);
+      const int q = j & (Q - 1), rl = (j >> D) & (S - 1), r2 = j >> (D + lS);
+      const int Ix = r2 & ((1 << lpx) - 1), r3 = r2 >> lpx;
+      const int Jy = r3 & ((1 << lpy) - 1), Lz = r3 >> lpy;
+      if (Ix >= c.nx || Jy >= c.ny) continue;
+      const int x = 2 * Ix + (q & 1), y = 2 * Jy + ((q >> 1) & 1), z = 2 * Lz + (q >> 2);
       auto gb = [&](int n) { return bk[(n << lS) + rl]; };
       auto gd = [&](int n) { return dk[n]; };
       cx<R> v{0, 0};
       if (x < f.nx && y < f.ny && z < f.nz) v = mg_down_fine<Op, R>(o, x, y, z, x + f.nx * (y + f.ny * z), tr, om, gb, gd);
       v = group_sum<Q>(v);
-      if (q == 0) bc[(I << lS) + rl] = v;
+      if (q == 0) bc[((Ix + c.nx * (Jy + c.ny * Lz)) << lS) + rl] = v;
     }
     __syncthreads();
   }
@@ -414,13 +420,18 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
     cx<R>* xk = sh + lv[k].off + nk;
     const cx<R>* xc = sh + lv[k + 1].off + nc;
     const cx<R>* dk = ldinv(k);
-    for (int j = tid; j < nk; j += nth) {
-      const int rl = j & (S - 1), cell = j >> lS;
-      const int i = cell % f.nx, jk = cell / f.nx;
+    const int lpx = lv[k].lpx, lpy = lv[k].lpy;
+    const int total = (f.nz << (lpx + lpy)) << lS;
+    for (int j = tid; j < total; j += nth) {
+      const int rl = j & (S - 1), r2 = j >> lS;
+      const int i = r2 & ((1 << lpx) - 1), r3 = r2 >> lpx;
+      const int jy = r3 & ((1 << lpy) - 1), kz = r3 >> lpy;
+      if (i >= f.nx || jy >= f.ny) continue;
+      const int cell = i + f.nx * (jy + f.ny * kz);
       auto gb = [&](int n) { return bk[(n << lS) + rl]; };
       auto gd = [&](int n) { return dk[n]; };
       auto gx = [&](int n) { return xc[(n << lS) + rl]; };
-      xk[j] = mg_up_cell<Op, R>(o, f, c, i, jk % f.ny, jk / f.ny, cell, tr, om, gb, gd, gx);
+      xk[(cell << lS) + rl] = mg_up_cell<Op, R>(o, f, c, i, jy, kz, cell, tr, om, gb, gd, gx);
     }
     __syncthreads();
   }

@@ -24,6 +24,11 @@ int fail(int code, const std::string& m) {
 }
 const char* last_error_text() { return g_err.c_str(); }
 
+static int ceil_log2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
 static int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -632,6 +637,8 @@ template <typename R, typename Op, typename OpD> struct Group {
       a.lv[k].nx = d.nx;
       a.lv[k].ny = d.ny;
       a.lv[k].nz = d.nz;
+      a.lv[k].lpx = ceil_log2(d.nx);
+      a.lv[k].lpy = ceil_log2(d.ny);
       a.lv[k].off = (int)(vec / sizeof(cx<R>));
       vec += 2 * ((size_t)d.n() << lS) * sizeof(cx<R>);
     }

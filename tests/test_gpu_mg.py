@@ -68,6 +68,38 @@ def test_mg_cocg_converges_like_oracle(shape):
         assert true <= 1e-6 * 1.01
 
 
+@pytest.mark.parametrize("shape,S", [((6, 5), 1), ((4, 3, 2), 1), ((7, 9), 2)])
+def test_mg_whole_hierarchy_in_one_workgroup(shape, S):
+    """Grids small enough for every level to sit in the one-workgroup tail
+    (no grid-wide restriction or prolongation at all): iterates as the oracle's,
+    complex128 and complex64 inputs."""
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"mg tail only {shape} S={S}")
+    K = _field(shape, 3)
+    op = OProblem.fv(K)
+    gp = _gpu_problem(P, K)
+    H = Hierarchy.of(op)
+    tau = 2j * np.pi / 90.0
+    rng = np.random.default_rng(11)
+    V = rng.normal(size=(op.n, S)) + 1j * rng.normal(size=(op.n, S))
+    for k in (1, 4):
+        z = torch.zeros(op.n * S, dtype=torch.complex128, device="cuda")
+        P.shk_inner_solve(gp, tau, to_dev(V.ravel()), z, fixed_iters=k, n_rhs=S, precond=P.SHK_PRECOND_MULTIGRID)
+        Z = z.cpu().numpy().reshape(op.n, S)
+        for r in range(S):
+            xo, _, _, _ = mg_cocg(op, tau, V[:, r], 0.0, 100, H, fixed_iters=k)
+            assert np.allclose(Z[:, r], xo, rtol=0, atol=1e-10 * np.abs(xo).max()), (k, r)
+    V32 = V.astype(np.complex64).astype(np.complex128)      # the right-hand side the complex64 path sees
+    z = torch.zeros(op.n * S, dtype=torch.complex128, device="cuda")
+    its, pn = P.shk_inner_solve(gp, tau, to_dev(V32.ravel(), "c64"), z, eps=1e-6, n_rhs=S,
+                                precond=P.SHK_PRECOND_MULTIGRID)
+    Z = z.cpu().numpy().reshape(op.n, S)
+    for r in range(S):
+        true = np.linalg.norm(V32[:, r] - op.apply(tau, Z[:, r]))
+        assert true <= 1e-6 * np.linalg.norm(V32[:, r]) * 1.01
+
+
 def test_mg_rejected_for_csr():
     torch = require_gpu()
     import paper_1212_3660_amd as P

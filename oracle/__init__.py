@@ -14,6 +14,8 @@ Contents (complex128 throughout):
   mg         geometric aggregation multigrid V-cycle, multigrid-preconditioned
              COCG (the inner solve with a multigrid preconditioner, section 6)
   fgmres_sh  Algorithms 3 and 4 with inexact inner solves, restart, refinement
+  sensitivity  adjoint-state sensitivity of point measurements to ln K per
+             cell (section 5, eq. sensitivity, Algorithm 6)
 """
 from .fv import Problem, assemble_stiffness, face_transmissivities, mass_diagonal  # noqa: F401
 from .exact import (banded_solve, dense_solve, superlu_solve, dst_closed_form,  # noqa: F401
@@ -23,3 +25,4 @@ from .mg import Hierarchy, vcycle, pcocg, mg_cocg  # noqa: F401
 from .fgmres_sh import (fgmres_sh, refine, true_residuals, mgs_step,  # noqa: F401
                         shifted_hessenberg, small_solve, CONVERGED, NOT_CONVERGED,
                         INNER_LIMITED, BREAKDOWN_EXACT, NAN_STATUS)
+from .sensitivity import sensitivity, sensitivity_block  # noqa: F401

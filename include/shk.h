@@ -237,6 +237,25 @@ int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128
 int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b,
                       const shk_c128* x, double* relres, void* hip_stream);
 
+/* Sensitivities of point measurements to the log-conductivity field (section
+ * 5, eq. sensitivity; step 3 of Algorithm 6), finite-volume problems only.
+ * phi: forward solutions, device, n x n_shifts x n_src column-major complex128
+ * (the layout fgmres_sh_solve writes), A_j phi_{j,s} = b_s; psi: adjoint
+ * solutions, same layout with n_rec columns per shift, A_j psi_{j,r} = e_{m_r}
+ * (unit source at the measurement cell; the paper's adjoint has source -delta,
+ * i.e. it is -psi).  Writes, for every shift j, source s, receiver r and cell
+ * c, J[c + n*(r + n_rec*(s + n_src*j))] = d h / d(ln K_c) with h = e_{m_r}^T
+ * phi_{j,s}:  J = -sum over the faces f of c of (dT_f / d ln K_c)
+ * (g_f^T psi)(g_f^T phi), g_f the face's difference operator (Dirichlet
+ * ghost 0 at the boundary).  Real and imaginary parts are the paper's two
+ * measurements per location and frequency.  J: device, complex128 for
+ * SHK_FP64, complex64 for SHK_MIXED (computed in FP64, rounded once); the
+ * caller owns all buffers.  Asynchronous on hip_stream.  UNSUPPORTED for CSR
+ * problems; INVALID_ARG for null pointers, non-positive counts or more than
+ * 65535 shifts. */
+int shk_sensitivity(shk_problem* p, int n_shifts, int n_src, const shk_c128* phi, int n_rec, const shk_c128* psi,
+                    void* J, int precision, void* hip_stream);
+
 /* Instrumentation of the inner iteration (the hot loop of section 4's inner
  * solves).  When enabled, the solve stream carries HIP events and the library
  * accumulates, over the iterations that did work, their duration, their count

@@ -84,6 +84,8 @@ _SIGS = {
                                C.c_int, C.c_void_p]),
     "shk_true_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
+    "shk_sensitivity": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                  C.c_int, C.c_void_p]),
     "shk_profile_enable": (C.c_int, [C.c_int]),
     "shk_profile_read": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "shk_status_string": (C.c_char_p, [C.c_int]),
@@ -331,6 +333,17 @@ def shk_true_residual(problem: Problem, sigma, b, x, stream=None) -> np.ndarray:
                                    C.c_void_p(x.data_ptr()), out.ctypes.data, _stream_ptr(stream)),
            "shk_true_residual")
     return out
+
+
+def shk_sensitivity(problem: Problem, phi, psi, J, n_shifts: int, n_src: int, n_rec: int, stream=None):
+    """Sensitivities dh/d(ln K_c) (device tensors; phi: n*n_shifts*n_src and psi:
+    n*n_shifts*n_rec complex128 in the solver's layout; J complex128 or
+    complex64 with n*n_rec*n_src*n_shifts entries, cell fastest)."""
+    import torch
+    prec = SHK_FP64 if J.dtype == torch.complex128 else SHK_MIXED
+    _check(lib().shk_sensitivity(problem.handle, n_shifts, n_src, C.c_void_p(phi.data_ptr()), n_rec,
+                                 C.c_void_p(psi.data_ptr()), C.c_void_p(J.data_ptr()), prec, _stream_ptr(stream)),
+           "shk_sensitivity")
 
 
 def shk_profile_enable(on: bool = True):

@@ -134,6 +134,12 @@ int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128
                             accumulate, precision, (hipStream_t)hip_stream);
 }
 
+int shk_sensitivity(shk_problem* p, int n_shifts, int n_src, const shk_c128* phi, int n_rec, const shk_c128* psi,
+                    void* J, int precision, void* hip_stream) {
+  return shk::step_sensitivity(p, n_shifts, n_src, reinterpret_cast<const c128*>(phi), n_rec,
+                               reinterpret_cast<const c128*>(psi), J, precision, (hipStream_t)hip_stream);
+}
+
 int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b, const shk_c128* x,
                       double* relres, void* hip_stream) {
   return shk::step_true_residual(p, n_shifts, reinterpret_cast<const c128*>(sigma), reinterpret_cast<const c128*>(b),

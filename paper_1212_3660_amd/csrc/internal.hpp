@@ -53,6 +53,7 @@ struct shk_problem {
   int* rowptr = nullptr; int* col = nullptr;
   double* val = nullptr; float* val32 = nullptr;
   double* diag = nullptr;           // diagonal of K (CSR only)
+  double* cellK = nullptr;          // cell conductivity (finite-volume problems; sensitivities)
   double* dK = nullptr;             // diagonal of K, every kind (Jacobi preconditioner)
   float* dK32 = nullptr;
   double* mdiag = nullptr;          // per-row mass (CSR only)
@@ -78,6 +79,8 @@ int step_lsq(int k, const c128* H, const c128* taus, int nf, const c128* sigma, 
              c128* y, double* rho);
 int step_assemble(long long n, int k, int nf, const void* Z, const c128* Y, c128* X, int acc,
                   int precision, hipStream_t stream);
+int step_sensitivity(shk_problem* p, int nf, int ns, const c128* phi, int nr, const c128* psi, void* J, int precision,
+                     hipStream_t st);
 int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x,
                        double* relres, hipStream_t stream);
 

@@ -13,6 +13,7 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "mg.hpp"
+#include "sens.hpp"
 
 namespace shk {
 
@@ -100,7 +101,7 @@ int profile_read(long long* launches, double* ms, double* bytes) {
 // --------------------------------------------------------------- problem ---
 void problem_free(shk_problem* p, hipStream_t st) {
   void* ptrs[] = {p->tx, p->ty, p->tz, p->tx32, p->ty32, p->tz32, p->rowptr, p->col, p->val, p->val32, p->diag, p->mdiag,
-                  p->dK, p->dK32};
+                  p->dK, p->dK32, p->cellK};
   for (void* q : ptrs)
     if (q) (void)hipFreeAsync(q, st);
   for (MgLevel& l : p->mg) {
@@ -198,7 +199,7 @@ int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipSt
     k_diag<<<grid_items(n, 8192), BS, 0, st>>>(od, n, p->dK, p->dK32);
   }
   SHK_HIP(hipGetLastError());
-  SHK_HIP(hipFreeAsync(Kd, st));
+  p->cellK = Kd;   // kept for sensitivities
   SHK_TRY(mg_setup(p, st));
   SHK_HIP(hipStreamSynchronize(st));
   return SHK_OK;
@@ -1458,6 +1459,27 @@ int step_assemble(long long n, int k, int nf, const void* Z, const c128* Y, c128
     return SHK_OK;
   };
   return precision == SHK_MIXED ? run(float{}) : run(double{});
+}
+
+int step_sensitivity(shk_problem* p, int nf, int ns, const c128* phi, int nr, const c128* psi, void* J, int precision,
+                     hipStream_t st) {
+  if (!p || !phi || !psi || !J || nf < 1 || ns < 1 || nr < 1) return fail(SHK_ERR_INVALID_ARG, "sensitivity arguments");
+  if (p->kind == Kind::CSR || !p->cellK) return fail(SHK_ERR_UNSUPPORTED, "sensitivities need a finite-volume problem");
+  if (precision != SHK_FP64 && precision != SHK_MIXED) return fail(SHK_ERR_INVALID_ARG, "precision");
+  if (nf > 65535 || (ns + 3) / 4 > 65535) return fail(SHK_ERR_INVALID_ARG, "too many shifts or sources for one launch");
+  SensArgs a{p->nx, p->ny, p->nz, p->tx, p->ty, p->tz, p->cellK, phi, psi, nf, ns, nr};
+  constexpr int TS = 4;
+  const dim3 g((unsigned)((p->n + BS - 1) / BS), (unsigned)nf, (unsigned)((ns + TS - 1) / TS));
+  const bool d3 = p->kind == Kind::FV3D;
+  if (precision == SHK_FP64) {
+    if (d3) k_sensitivity<double, TS, 6><<<g, BS, 0, st>>>(a, (c128*)J);
+    else k_sensitivity<double, TS, 4><<<g, BS, 0, st>>>(a, (c128*)J);
+  } else {
+    if (d3) k_sensitivity<float, TS, 6><<<g, BS, 0, st>>>(a, (c64*)J);
+    else k_sensitivity<float, TS, 4><<<g, BS, 0, st>>>(a, (c64*)J);
+  }
+  SHK_HIP(hipGetLastError());
+  return SHK_OK;
 }
 
 int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x, double* relres,

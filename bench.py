@@ -121,6 +121,42 @@ def roofline(prof, traffic_file, label, unit):
     return r
 
 
+def sensitivity_bench(P, torch, w, make, n_src=8, n_rec=8, reps=5):
+    """Sensitivities (section 5, eq. sensitivity) from one batched solve of the
+    256x256 workload: its first n_src well sources as forward solutions and its
+    first n_rec receiver vectors as adjoint solutions, J in complex64.  Timed
+    with events on the stream the kernel runs on; roofline against HBM."""
+    gp = make(w)
+    prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
+                              eps_inner=w.eps_inner, precision=P.SHK_MIXED, inner_precond=P.SHK_PRECOND_MULTIGRID)
+    b = torch.from_numpy(np.ascontiguousarray(w.b.T)).cuda()
+    x, st = P.fgmres_sh_solve(gp, prm, w.sigma, b)
+    nw = len(w.extra["wells"])
+    phi = x[:n_src].contiguous()
+    psi = x[nw:nw + n_rec].contiguous()
+    n, nf = gp.n, len(w.sigma)
+    J = torch.empty(n * nf * n_src * n_rec, dtype=torch.complex64, device="cuda")
+    P.shk_sensitivity(gp, phi, psi, J, nf, n_src, n_rec)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        P.shk_sensitivity(gp, phi, psi, J, nf, n_src, n_rec)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # algorithmic bytes: J written once, phi and psi read once, faces and K read once
+    nbytes = n * nf * n_src * n_rec * 8 + n * nf * (n_src + n_rec) * 16 + n * (2 * 8 + 8)
+    gbs = nbytes / (ms / 1e3) / 1e9
+    out = {"workload": f"2-D FV 256x256, {nf} shifts, {n_src} sources x {n_rec} receivers from the 64-rhs solve",
+           "entries": n * nf * n_src * n_rec, "dtype": "c64", "ms": round(ms, 3),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "kernel": "k_sensitivity<float, 4, 4>",
+                        "algorithmic_bytes_per_launch": nbytes}}
+    gp.close()
+    return out
+
+
 def time_batched(P, torch, w, make, precision, single_rhs_sample=0):
     """One solve of a multi-rhs workload (all rhs in lockstep); with
     single_rhs_sample > 0, instead that many rhs solved one at a time and the
@@ -281,6 +317,7 @@ def main():
                 "fp64_single_rhs": dict(time_batched(P, torch, w3, mk2, P.SHK_FP64, single_rhs_sample=4),
                                         sample="4 of the 64 rhs solved one at a time, rate over those")},
         }
+        out["sensitivity"] = sensitivity_bench(P, torch, w3, mk2)
         w4 = synth.config4()
         out["batched"]["3-D FV 128^3, 100 shifts, 8 rhs"] = {
             "mixed_batched": time_batched(P, torch, w4, mk3, P.SHK_MIXED),

@@ -13,11 +13,12 @@
 // = T for a boundary face (T = K_c h^(d-2)).  The paper's adjoint carries the
 // source -delta, which flips the sign of its bilinear term.
 //
-// One thread per cell, a shift per blockIdx.y and a tile of TS forward
-// solutions per blockIdx.z held in registers as face differences; the thread
+// One thread per cell, shift and tile of TS forward solutions (held in
+// registers as face differences); the thread
 // walks the adjoint solutions and writes TS entries of J for each (c fastest,
-// so every store is coalesced).  Face differences and products in FP64, J
-// rounded once to its storage type.  The launch is bound by the writes of J.
+// so every store is coalesced; streaming stores, J is not read back here).
+// Face differences and products in FP64, J rounded once to its storage type.
+// The launch is bound by the writes of J.
 #pragma once
 #include "kernels.hpp"
 
@@ -34,13 +35,19 @@ struct SensArgs {
   int nf, ns, nr;
 };
 
+// Launch grid (ceil(n / BS) * ceil(ns / TS), nf): the source tiles of one
+// block of cells are adjacent blocks, and the linear block index goes through
+// xcd_tile, so one XCD's L2 serves the neighbour rows and the adjoint
+// solutions to every tile of a band of cells.
 template <typename RO, int TS, int NF>
 __global__ void __launch_bounds__(BS) k_sensitivity(SensArgs a, cx<RO>* __restrict__ J) {
   const long n = (long)a.nx * a.ny * a.nz;
-  const long c = (long)blockIdx.x * BS + threadIdx.x;
+  const int ntile = (a.ns + TS - 1) / TS;
+  const int T = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int j = T / gridDim.x, bx = T - j * gridDim.x;
+  const long c = (long)(bx / ntile) * BS + threadIdx.x;
   if (c >= n) return;
-  const int j = blockIdx.y;
-  const int s0 = blockIdx.z * TS;
+  const int s0 = (bx % ntile) * TS;
   const int pl = a.nx * a.ny;
   const int k = (int)(c / pl), rem = (int)(c - (long)k * pl);
   const int y = rem / a.nx, x = rem - y * a.nx;
@@ -95,7 +102,7 @@ __global__ void __launch_bounds__(BS) k_sensitivity(SensArgs a, cx<RO>* __restri
       c128 acc{0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < NF; ++q) acc = acc + dT[q] * (gpsi[q] * gphi[t][q]);
-      J[c + n * ((long)r + (long)a.nr * ((long)(s0 + t) + (long)a.ns * j))] = cvt<RO>(c128{-acc.re, -acc.im});
+      st<true>(J + c + n * ((long)r + (long)a.nr * ((long)(s0 + t) + (long)a.ns * j)), cvt<RO>(c128{-acc.re, -acc.im}));
     }
   }
 }

@@ -1466,10 +1466,11 @@ int step_sensitivity(shk_problem* p, int nf, int ns, const c128* phi, int nr, co
   if (!p || !phi || !psi || !J || nf < 1 || ns < 1 || nr < 1) return fail(SHK_ERR_INVALID_ARG, "sensitivity arguments");
   if (p->kind == Kind::CSR || !p->cellK) return fail(SHK_ERR_UNSUPPORTED, "sensitivities need a finite-volume problem");
   if (precision != SHK_FP64 && precision != SHK_MIXED) return fail(SHK_ERR_INVALID_ARG, "precision");
-  if (nf > 65535 || (ns + 3) / 4 > 65535) return fail(SHK_ERR_INVALID_ARG, "too many shifts or sources for one launch");
-  SensArgs a{p->nx, p->ny, p->nz, p->tx, p->ty, p->tz, p->cellK, phi, psi, nf, ns, nr};
   constexpr int TS = 4;
-  const dim3 g((unsigned)((p->n + BS - 1) / BS), (unsigned)nf, (unsigned)((ns + TS - 1) / TS));
+  const long gx = (p->n + BS - 1) / BS * ((ns + TS - 1) / TS);
+  if (nf > 65535 || gx * nf > 0x7fffffffL) return fail(SHK_ERR_INVALID_ARG, "too many shifts or sources for one launch");
+  SensArgs a{p->nx, p->ny, p->nz, p->tx, p->ty, p->tz, p->cellK, phi, psi, nf, ns, nr};
+  const dim3 g((unsigned)gx, (unsigned)nf);
   const bool d3 = p->kind == Kind::FV3D;
   if (precision == SHK_FP64) {
     if (d3) k_sensitivity<double, TS, 6><<<g, BS, 0, st>>>(a, (c128*)J);

@@ -231,6 +231,8 @@ def main():
                     help="run one solve of the workload and exit (for profiler counter passes)")
     ap.add_argument("--precond", choices=["multigrid", "jacobi"], default="multigrid",
                     help="inner preconditioner of --single-solve")
+    ap.add_argument("--sensitivity-only", action="store_true",
+                    help="run only the sensitivity measurement of the 256x256 workload and exit (profiler passes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device-to-device with a plain copy kernel and exit "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -250,6 +252,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return
+    if a.sensitivity_only:
+        print(json.dumps(sensitivity_bench(P, torch, synth.config3(), lambda w: P.Problem.fv2d(w.cell_K, w.Ss, w.h))),
+              flush=True)
         return
     w = synth.config2(n_grid=a.grid)
     gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)

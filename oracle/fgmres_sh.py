@@ -120,20 +120,20 @@ def make_inner(problem, inner: str, eps: float, inner_maxit: Optional[int], mg_n
         inner_maxit = 20 * max(dims)
 
     if inner == "cocg":
-        def f(v, tau):
+        def f(v, tau, eps_k=eps):
             diag = problem.diag(tau)
-            z, its, _ok, _h = cocg(lambda x: problem.apply(tau, x), diag, v, eps, inner_maxit)
+            z, its, _ok, _h = cocg(lambda x: problem.apply(tau, x), diag, v, eps_k, inner_maxit)
             return z, its
         return f
     if inner == "mg":
         H = Hierarchy.of(problem)
 
-        def f(v, tau):
-            z, its, _ok, _h = mg_cocg(problem, tau, v, eps, inner_maxit, H, mg_nu, mg_omega)
+        def f(v, tau, eps_k=eps):
+            z, its, _ok, _h = mg_cocg(problem, tau, v, eps_k, inner_maxit, H, mg_nu, mg_omega)
             return z, its
         return f
 
-    def f(v, tau):
+    def f(v, tau, eps_k=eps):
         A = problem.shifted(tau)
         if inner == "dense":
             return dense_solve(A, v), 0
@@ -153,7 +153,7 @@ def make_inner(problem, inner: str, eps: float, inner_maxit: Optional[int], mg_n
 def fgmres_sh(problem, b, sigmas, tau_seq, *, m_restart=50, max_restarts=20, tol=1e-8,
               inner="cocg", eps=1e-10, inner_maxit=None, variant="gmres",
               max_steps=None, keep_basis=False, record_quasi=False,
-              stop_after_restart=None, mg_nu=1, mg_omega=0.8) -> Result:
+              stop_after_restart=None, mg_nu=1, mg_omega=0.8, relax=0.0, eps_max=1e-2) -> Result:
     """Solve (K + sigma_j M) x_j = b for all shifts with one flexible basis.
 
     ``tau_seq`` is used cyclically over the global step counter.  ``inner`` is
@@ -161,8 +161,15 @@ def fgmres_sh(problem, b, sigmas, tau_seq, *, m_restart=50, max_restarts=20, tol
     V-cycle of oracle.mg with ``mg_nu`` damped-Jacobi sweeps of weight
     ``mg_omega``), or an exact solve ("superlu", "banded", "dense").  ``max_steps`` caps the total number of outer steps (for timing
     samples); ``stop_after_restart`` returns right after the restart update of
-    that cycle (0-based), to inspect the restarted residuals.  Returns x as an
-    (n, n_f) array plus per-shift information."""
+    that cycle (0-based), to inspect the restarted residuals.  ``relax`` > 0
+    relaxes the inner tolerance as the outer residual falls (the Simoncini-Szyld
+    idea the paper cites in section 4 without pursuing it): after each outer
+    step the next inner solve asks for
+        eps_k = min(eps_max, max(eps, relax * tol / q)),
+    q the largest relative quasi-residual rho_j / ||b|| over the shifts still
+    running; the stopping bound of eq. trueresidual uses the measured ||p_k||,
+    so it stays a bound whatever eps_k is.  Returns x as an (n, n_f) array plus
+    per-shift information."""
     sigmas = np.asarray(sigmas, dtype=np.complex128)
     tau_seq = np.asarray(tau_seq, dtype=np.complex128)
     b = np.asarray(b, dtype=np.complex128)
@@ -181,6 +188,7 @@ def fgmres_sh(problem, b, sigmas, tau_seq, *, m_restart=50, max_restarts=20, tol
             s.status, s.quasi_relres, s.bound_relres, s.true_relres = CONVERGED, 0.0, 0.0, 0.0
         return res
     solve_inner = make_inner(problem, inner, eps, inner_maxit, mg_nu, mg_omega)
+    eps_k = eps
     M = problem.Mdiag
     beta = np.full(nf, beta0, dtype=np.complex128)
     gap_prev = np.zeros(nf)
@@ -207,7 +215,7 @@ def fgmres_sh(problem, b, sigmas, tau_seq, *, m_restart=50, max_restarts=20, tol
             kk += 1
             res.outer_steps += 1
             taus[k] = tau
-            z, its = solve_inner(V[:, k], tau)
+            z, its = solve_inner(V[:, k], tau, eps_k)
             res.inner_its += its
             p = V[:, k] - problem.apply(tau, z)
             pn[k] = np.linalg.norm(p)
@@ -254,6 +262,10 @@ def fgmres_sh(problem, b, sigmas, tau_seq, *, m_restart=50, max_restarts=20, tol
                     active[j] = False
             if record_quasi:
                 quasi_hist.append(step_q)
+            if relax > 0.0 and np.any(np.isfinite(step_q)):
+                q = float(np.nanmax(step_q))
+                if q > 0.0:
+                    eps_k = min(eps_max, max(eps, relax * tol / q))
             if broke or not active.any():
                 break
         if keep_basis:

@@ -1,0 +1,40 @@
+"""The oracle's relaxed inner tolerance (section 4's remark on Simoncini-Szyld,
+not pursued by the paper): convergence to the requested true residual, the
+error bound against the direct solution, fewer inner iterations, and the
+unrelaxed default unchanged."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Problem, fgmres_sh, exact_family, true_residuals, CONVERGED
+
+
+def _setup():
+    K = synth.cell_conductivity((24, 20), -11.5, 1.0, 3, cfg=94, idx=1)
+    op = Problem.fv(K)
+    sig = synth.shifts_from_periods(synth.periods(12, 5.0, 2000.0))
+    b = synth.unit_vector(op.n, 230)
+    return op, sig, b
+
+
+@pytest.mark.parametrize("inner", ["cocg", "mg"])
+def test_relaxed_converges_with_fewer_inner_iterations(inner):
+    op, sig, b = _setup()
+    taus = sig[[2, 6, 10]]
+    tol = 1e-8
+    base = fgmres_sh(op, b, sig, taus, m_restart=60, tol=tol, inner=inner, eps=1e-10)
+    rel = fgmres_sh(op, b, sig, taus, m_restart=60, tol=tol, inner=inner, eps=1e-10, relax=0.1, eps_max=1e-2)
+    assert all(s.status == CONVERGED for s in rel.info)
+    r = true_residuals(op, b, sig, rel.x)
+    assert np.all(r <= tol * (1 + 1e-6)), r.max()
+    xe = exact_family(op, sig, b, "dense")
+    for j, s in enumerate(sig):
+        assert np.linalg.norm(rel.x[:, j] - xe[:, j]) <= r[j] * np.linalg.norm(b) / (abs(s) * 1e-5) * (1 + 1e-6)
+    assert rel.inner_its < 0.8 * base.inner_its, (rel.inner_its, base.inner_its)
+
+
+def test_relax_zero_is_the_default():
+    op, sig, b = _setup()
+    a = fgmres_sh(op, b, sig, sig[[3, 9]], m_restart=30, tol=1e-7, eps=1e-9)
+    c = fgmres_sh(op, b, sig, sig[[3, 9]], m_restart=30, tol=1e-7, eps=1e-9, relax=0.0)
+    assert np.array_equal(a.x, c.x) and a.inner_its == c.inner_its

@@ -51,10 +51,11 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def time_path(P, torch, gp, w, precision, steps, warmup, profile=False, precond=None):
+def time_path(P, torch, gp, w, precision, steps, warmup, profile=False, precond=None, relax=0.0):
     prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
                               eps_inner=w.eps_inner, precision=precision,
-                              inner_precond=P.SHK_PRECOND_MULTIGRID if precond is None else precond)
+                              inner_precond=P.SHK_PRECOND_MULTIGRID if precond is None else precond,
+                              inner_relax=relax, inner_eps_max=1e-2)
     nf = len(w.sigma)
     ws = torch.empty(P.shk_workspace_bytes(gp, prm, nf, 1), dtype=torch.uint8, device="cuda")
     b = torch.from_numpy(w.b[:, 0]).cuda()[None, :].contiguous()
@@ -275,6 +276,9 @@ def main():
                               precond=P.SHK_PRECOND_JACOBI),
            "fp64": time_path(P, torch, gp, w, P.SHK_FP64, a.steps, a.warmup, profile=False,
                              precond=P.SHK_PRECOND_JACOBI)}
+    # the same workload with the relaxed inner tolerance (an option, not the
+    # configuration the metric is quoted on: its inner tolerance is fixed)
+    relaxed = time_path(P, torch, gp, w, P.SHK_MIXED, a.steps, a.warmup, profile=False, relax=0.1)
     nf = len(w.sigma)
     ms_step = mixed["total_ms"] / a.steps
     value = nf * a.steps / (mixed["total_ms"] / 1e3)
@@ -308,6 +312,11 @@ def main():
                                    "ms_per_step": round(r["total_ms"] / a.steps, 3), "converged": r["ok"],
                                    "max_true_relres": r["worst"], "inner_iterations": r["inner"]}
                             for name, r in jac.items()},
+           "relaxed_inner": {"inner_relax": 0.1, "inner_eps_max": 1e-2,
+                             "value": round(nf * a.steps / (relaxed["total_ms"] / 1e3), 2),
+                             "ms_per_step": round(relaxed["total_ms"] / a.steps, 3), "converged": relaxed["ok"],
+                             "max_true_relres": relaxed["worst"], "inner_iterations": relaxed["inner"],
+                             "outer_steps": relaxed["outer"], "refine_sweeps": relaxed["sweeps"]},
            "roofline": roof, "roofline_jacobi_step": roof_jac, "cpu_baseline": None}
     if not a.no_extra:
         # the batched workloads: 256x256 with 32 well sources + 32 adjoint

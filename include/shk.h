@@ -102,6 +102,15 @@ typedef struct shk_server shk_server;
  *                 CSR problems and for grids with ny or nz above 65535.
  *  mg_sweeps      1 (the only value provided; others are a call error).
  *  mg_omega       Jacobi damping of the smoother, in (0, 1].
+ *  inner_relax    0: every inner solve asks for eps_inner.  > 0: relaxed inner
+ *                 tolerance (the Simoncini-Szyld idea section 4 cites without
+ *                 pursuing it): after each outer step the next inner solve asks
+ *                 for min(inner_eps_max, max(eps, inner_relax * tol / q)), q the
+ *                 largest relative quasi-residual of the (shift, rhs) pairs
+ *                 still running; the stopping bound keeps using the measured
+ *                 inner residuals.  0.1 keeps every shift CONVERGED on the
+ *                 workloads here.
+ *  inner_eps_max  cap of the relaxed inner tolerance, in [eps_inner, 1).
  */
 typedef struct {
   int m_restart;
@@ -119,6 +128,8 @@ typedef struct {
   int inner_precond;
   int mg_sweeps;
   double mg_omega;
+  double inner_relax;
+  double inner_eps_max;
 } shk_params;
 
 /* Per-(shift, rhs) result, host memory, n_shifts x n_rhs column-major. */

@@ -34,7 +34,8 @@ class shk_params(C.Structure):
                 ("inner_maxit", C.c_int), ("tol", C.c_double), ("eps_inner", C.c_double),
                 ("n_tau", C.c_int), ("tau_seq", C.POINTER(shk_c128)), ("variant", C.c_int),
                 ("precision", C.c_int), ("refine_tol", C.c_double), ("refine_eps_inner", C.c_double),
-                ("inner_precond", C.c_int), ("mg_sweeps", C.c_int), ("mg_omega", C.c_double)]
+                ("inner_precond", C.c_int), ("mg_sweeps", C.c_int), ("mg_omega", C.c_double),
+                ("inner_relax", C.c_double), ("inner_eps_max", C.c_double)]
 
 
 class shk_status(C.Structure):
@@ -138,7 +139,7 @@ def _c128_array(values) -> "C.Array":
 
 def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_maxit=0, tol=1e-8,
                 eps_inner=1e-10, precision=SHK_FP64, variant=SHK_GMRES, refine_tol=0.05,
-                refine_eps_inner=5e-3, inner_precond=None, mg_omega=0.8):
+                refine_eps_inner=5e-3, inner_precond=None, mg_omega=0.8, inner_relax=0.0, inner_eps_max=1e-2):
     """Returns (shk_params, keepalive) with tau_seq marshalled to C."""
     taus = _c128_array(tau_seq)
     p = shk_params()
@@ -152,6 +153,7 @@ def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_m
     if inner_precond is not None:
         p.inner_precond = inner_precond
     p.mg_omega = mg_omega
+    p.inner_relax, p.inner_eps_max = inner_relax, inner_eps_max
     return p, taus
 
 

@@ -26,6 +26,8 @@ void shk_params_default(shk_params* p) {
   p->inner_precond = SHK_PRECOND_JACOBI;
   p->mg_sweeps = 1;
   p->mg_omega = 0.8;
+  p->inner_relax = 0.0;
+  p->inner_eps_max = 1e-2;
 }
 
 static int create_fv(int nx, int ny, int nz, shk::Kind kind, const double* cell_K, double Ss, double h,

@@ -1082,16 +1082,32 @@ __global__ void __launch_bounds__(BS) k_finalize_active(int L, LaneState* __rest
 }
 
 // Active lanes per rhs lane r (one block; LDS integer counts).
+// Running lanes per rhs, and per rhs the largest quasi-residual rho / ||b||
+// among them (0 when none runs; the relaxed inner tolerance reads it).
 __global__ void __launch_bounds__(BS) k_count_active(int S, int nf, const LaneState* __restrict__ ls,
-                                                     int* __restrict__ out) {
+                                                     const double* __restrict__ beta0, int* __restrict__ out,
+                                                     double* __restrict__ qmax) {
   __shared__ int cnt[64];
-  if ((int)threadIdx.x < 64) cnt[threadIdx.x] = 0;
+  __shared__ unsigned long long qm[64];   // bit patterns of non-negative doubles order as integers
+  if ((int)threadIdx.x < 64) {
+    cnt[threadIdx.x] = 0;
+    qm[threadIdx.x] = 0ull;
+  }
   __syncthreads();
   const int L = nf * S;
-  for (int lane = threadIdx.x; lane < L; lane += BS)
-    if (ls[lane].active) atomicAdd(&cnt[lane % S], 1);
+  for (int lane = threadIdx.x; lane < L; lane += BS) {
+    const LaneState st = ls[lane];
+    if (!st.active) continue;
+    const int r = lane % S;
+    atomicAdd(&cnt[r], 1);
+    const double q = beta0[r] > 0.0 ? st.rho / beta0[r] : 0.0;
+    if (q > 0.0 && q < 1e300) atomicMax(&qm[r], (unsigned long long)__double_as_longlong(q));
+  }
   __syncthreads();
-  if ((int)threadIdx.x < S) out[threadIdx.x] = cnt[threadIdx.x];
+  if ((int)threadIdx.x < S) {
+    out[threadIdx.x] = cnt[threadIdx.x];
+    qmax[threadIdx.x] = __longlong_as_double((long long)qm[threadIdx.x]);
+  }
 }
 
 // Per-lane multiplier of the assembly: lanes still active at the end of the

@@ -350,6 +350,7 @@ template <typename R> struct Buffers {
   double *beta0, *hn, *mz, *pn, *nzs;
   c128 *H, *h2, *taus, *sigma, *zs;
   int *seed, *nact;
+  double* qmax;           // per rhs: largest relative quasi-residual of the running lanes
   LaneState* ls;
   double* rc;
   c128 *rs, *g, *Rp, *Yb, *ascale, *extra;
@@ -435,6 +436,7 @@ static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, 
   b.zs = cv.take<c128>((size_t)(m + 1) * S);
   b.seed = cv.take<int>(S);
   b.nact = cv.take<int>(S);
+  b.qmax = cv.take<double>(S);
   b.ls = cv.take<LaneState>(L);
   b.rc = cv.take<double>((size_t)m * L);
   b.rs = cv.take<c128>((size_t)m * L);
@@ -482,6 +484,7 @@ struct PassSpec {
   double tol, eps;
   const std::vector<c128>* taus;
   long long kglob0;   // tau schedule position
+  double relax = 0.0, eps_max = 1e-2;   // relaxed inner tolerance (0: off)
 };
 
 struct Snap {
@@ -1020,6 +1023,8 @@ template <typename R, typename Op, typename OpD> struct Group {
     char* stage = (char*)g_pinned.get(65536);
     int* nact = stage ? (int*)(stage + 32768) : nullptr;
     if (!nact) return fail(SHK_ERR_OOM, "pinned staging");
+    double* qmax = (double*)(stage + 32768 + 64 * sizeof(int));   // per rhs: largest running quasi-residual / ||b||
+    double eps_k = ps.eps;
     bool first_write = !accumulate;
     for (int cycle = 0; cycle <= ps.max_restarts; ++cycle) {
       for (int k = 0; k < m; ++k) tcyc[k] = taus[(size_t)((kglob + k) % (long long)taus.size())];
@@ -1027,15 +1032,23 @@ template <typename R, typename Op, typename OpD> struct Group {
       int kend = 0;
       bool any_active = true;
       for (int k = 0; k < m; ++k) {
-        SHK_TRY(inner(tcyc[k], B.V + (size_t)k * N, B.Z + (size_t)k * N, ps.eps, ps.inner_maxit, 0,
+        SHK_TRY(inner(tcyc[k], B.V + (size_t)k * N, B.Z + (size_t)k * N, eps_k, ps.inner_maxit, 0,
                       B.pn + (size_t)k * S));
         SHK_TRY(orthogonalize(k, B.W));
         GivensArgs a = gargs(k, cycle, (int)(kglob - ps.kglob0), ps.tol);
         launch_givens(a, st);
-        k_count_active<<<1, BS, 0, st>>>(S, nf, B.ls, B.nact);
+        k_count_active<<<1, BS, 0, st>>>(S, nf, B.ls, B.beta0, B.nact, B.qmax);
         SHK_HIP(hipGetLastError());
         SHK_HIP(hipMemcpyAsync(nact, B.nact, S * sizeof(int), hipMemcpyDeviceToHost, st));
+        if (ps.relax > 0.0) SHK_HIP(hipMemcpyAsync(qmax, B.qmax, S * sizeof(double), hipMemcpyDeviceToHost, st));
         SHK_HIP(hipStreamSynchronize(st));
+        if (ps.relax > 0.0) {
+          // relaxed inner tolerance for the next step: the outer residual has
+          // fallen to q, so the next preconditioner solve may be looser
+          double q = 0.0;
+          for (int r = 0; r < S; ++r) q = std::max(q, qmax[r]);
+          if (q > 0.0) eps_k = std::min(ps.eps_max, std::max(ps.eps, ps.relax * ps.tol / q));
+        }
         ++kglob;
         ++outer_steps;
         kend = k + 1;
@@ -1114,7 +1127,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     Group<R, Op, OpD> g{p, op, opd, st, B, n, N, S, s_real, nf, m, nf * S, item_plan(N, S)};
     g.mg = use_mg;
     g.mg_omega = prm->mg_omega;
-    PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0};
+    PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0, prm->inner_relax, prm->inner_eps_max};
     SHK_TRY(g.pass(B.bint, ps, X, false, nullptr));
     SHK_HIP(hipMemcpyAsync(lanes.data(), B.ls, sizeof(LaneState) * nf * S, hipMemcpyDeviceToHost, st));
     SHK_HIP(hipMemcpyAsync(bnorm.data(), B.beta0, sizeof(double) * S, hipMemcpyDeviceToHost, st));
@@ -1169,7 +1182,8 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
           extra[j * S + r] = gmm;
         }
       SHK_HIP(hipMemcpyAsync(B.extra, extra.data(), sizeof(c128) * nf * S, hipMemcpyHostToDevice, st));
-      PassSpec pr{m, prm->max_restarts, maxit, prm->refine_tol, prm->refine_eps_inner, &taus, 0};
+      PassSpec pr{m, prm->max_restarts, maxit, prm->refine_tol, prm->refine_eps_inner, &taus, 0, prm->inner_relax,
+                  prm->inner_eps_max};
       SHK_TRY(g.pass(B.rsv, pr, X, true, B.extra));
       SHK_TRY(measure());
     }
@@ -1218,6 +1232,10 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
     if (prm->mg_sweeps != 1) return fail(SHK_ERR_UNSUPPORTED, "mg_sweeps must be 1");
     if (!(prm->mg_omega > 0.0 && prm->mg_omega <= 1.0)) return fail(SHK_ERR_INVALID_ARG, "mg_omega must be in (0, 1]");
   }
+  if (!(prm->inner_relax >= 0.0) || !std::isfinite(prm->inner_relax))
+    return fail(SHK_ERR_INVALID_ARG, "inner_relax must be finite and >= 0");
+  if (prm->inner_relax > 0.0 && !(prm->inner_eps_max >= prm->eps_inner && prm->inner_eps_max < 1.0))
+    return fail(SHK_ERR_INVALID_ARG, "inner_eps_max must be in [eps_inner, 1)");
   for (int i = 0; i < prm->n_tau; ++i)
     if (!std::isfinite(prm->tau_seq[i].re) || !std::isfinite(prm->tau_seq[i].im))
       return fail(SHK_ERR_INVALID_ARG, "non-finite tau");

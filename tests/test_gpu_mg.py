@@ -133,3 +133,45 @@ def test_solve_with_multigrid_inner(precision):
     xe = exact_family(op, sig, b, "superlu")
     for j in range(len(sig)):
         assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= st[0, j]["true_relres"] / (abs(sig[j]) * 1e-5) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_relaxed_inner_tolerance(precision):
+    """Relaxed inner tolerance (eps_k = min(eps_max, max(eps, relax tol / q))):
+    every shift still meets the tolerance, within the bound of the exact family,
+    with fewer inner iterations than the fixed tolerance."""
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"relaxed inner {precision}")
+    K = _field((45, 38), 13)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(10, 5.0, 2000.0))
+    b = synth.unit_vector(op.n, 900)
+    prec = P.SHK_FP64 if precision == "fp64" else P.SHK_MIXED
+    tol, eps = (1e-8, 1e-10) if precision == "fp64" else (1e-6, 1e-6)
+    runs = {}
+    for relax in (0.0, 0.1):
+        prm, keep = P.make_params(sig[[2, 5, 8]], tol=tol, eps_inner=eps, m_restart=50, precision=prec, max_refine=4,
+                                  inner_precond=P.SHK_PRECOND_MULTIGRID, inner_relax=relax, inner_eps_max=1e-2)
+        x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+        assert np.all(st["true_relres"] <= tol)
+        runs[relax] = (x, int(st["inner_its"].max()))
+    x, its = runs[0.1]
+    assert its < runs[0.0][1], (its, runs[0.0][1])
+    xe = exact_family(op, sig, b, "superlu")
+    for j in range(len(sig)):
+        assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= tol / (abs(sig[j]) * 1e-5) * (1 + 1e-6)
+
+
+def test_relaxed_tolerance_rejects_bad_parameters():
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    K = _field((10, 8), 2)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(3, 10.0, 100.0))
+    b = synth.unit_vector(K.size, 20)
+    for relax, emax in ((-1.0, 1e-2), (0.1, 2.0), (0.1, 1e-12)):
+        prm, keep = P.make_params(sig, tol=1e-6, eps_inner=1e-8, inner_relax=relax, inner_eps_max=emax)
+        with pytest.raises(P.ShkError):
+            P.fgmres_sh_solve(gp, prm, sig, b)

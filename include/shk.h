@@ -8,7 +8,7 @@
  *     (K + sigma_j M) x_j = b,   j = 1..n_f                  (section 2, eq. multipleshifted)
  *
  * with one flexible Arnoldi basis built from preconditioners K + tau_k M
- * (Algorithm 3), a per-shift projected problem (Algorithm 4, GMRES variant),
+ * (Algorithm 3), a per-shift projected problem (Algorithm 4, GMRES or FOM),
  * inexact inner solves of the preconditioner systems (section 4, eq.
  * zmmoditer) and the true-residual bound of eq. trueresidual as stopping test.
  * K is real symmetric positive definite, M real diagonal (lumped mass), the
@@ -88,7 +88,14 @@ typedef struct shk_server shk_server;
  *                 array of n_tau complex values; section 2.2.1 and the recycled
  *                 schedule of section 6.1).  A blocked schedule is expressed by
  *                 repeating entries.
- *  variant        SHK_GMRES (FOM is not provided by the GPU path: call error).
+ *  variant        SHK_GMRES: y_j minimises ||beta e_1 - Hbar(sigma_j;T) y||;
+ *                 restarts keep the residuals collinear with the largest one
+ *                 (section 2.2.2).  SHK_FOM: y_j solves the square system
+ *                 H_m(sigma_j;T) y = beta e_1 (Algorithm 4, FOM); every
+ *                 residual is a multiple of v_{m+1} (proof of Prop. 2), which
+ *                 starts the next cycle.  A (shift, rhs) whose square system is
+ *                 exactly singular at the end of a cycle stops NOT_CONVERGED
+ *                 with its least-squares iterate.  Other values: INVALID_ARG.
  *  precision      SHK_FP64 or SHK_MIXED.
  *  refine_tol     relative accuracy asked of each refinement correction solve.
  *  refine_eps_inner  inner tolerance of the correction solves.
@@ -187,7 +194,8 @@ int shk_workspace_bytes(const shk_problem* p, const shk_params* prm, int n_shift
  *  st         host, n_shifts x n_rhs statuses, st[j + n_shifts*r].
  *  workspace  device buffer of >= shk_workspace_bytes(); NULL lets the library
  *             allocate and free it inside the call.
- * Errors: INVALID_ARG, UNSUPPORTED (FOM variant), WORKSPACE (too small), OOM, HIP.
+ * Errors: INVALID_ARG, UNSUPPORTED (multigrid on a CSR problem or an oversized
+ * grid), WORKSPACE (too small), OOM, HIP.
  */
 int fgmres_sh_solve(shk_problem* p, const shk_params* prm, int n_shifts, const shk_c128* sigma,
                     int n_rhs, const shk_c128* b, shk_c128* x, shk_status* st, void* workspace,
@@ -227,14 +235,18 @@ int shk_inner_solve(shk_problem* p, shk_c128 tau, int n_rhs, const void* v, void
 int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128* h,
                       int precision, void* hip_stream);
 
-/* Per-shift projected problem of Algorithm 4 (GMRES): given Hbar ((k+1) x k,
- * host, column-major, one rhs), taus (host, k) and shifts (host, n_shifts),
- * solve min ||beta e_1 - Hbar(sigma_j;T) y|| with Givens rotations on the
- * device, Hbar(sigma;T) = [I;0] + Hbar (sigma I - T) (eq. shiftedarnoldimod).
+/* Per-shift projected problem of Algorithm 4: given Hbar ((k+1) x k, host,
+ * column-major, one rhs), taus (host, k) and shifts (host, n_shifts), with
+ * Hbar(sigma;T) = [I;0] + Hbar (sigma I - T) (eq. shiftedarnoldimod), on the
+ * device with Givens rotations:
+ *   variant SHK_GMRES: y = argmin ||beta e_1 - Hbar(sigma_j;T) y||;
+ *   variant SHK_FOM:   y solves H_k(sigma_j;T) y = beta e_1 (the first k rows).
  * Outputs (host): y (k x n_shifts column-major) and quasi-residual norms
- * rho (n_shifts) after each step: rho[s + n_shifts*j] for s = 0..k-1. */
+ * ||beta e_1 - Hbar(sigma_j;T) y|| after each step s = 0..k-1 at
+ * rho[j + n_shifts*s] (FOM: |hbar_{s+1,s}(sigma_j)| |y_s|; +inf where the
+ * square system of that step is exactly singular).  Errors: INVALID_ARG. */
 int shk_shifted_lsq(int k, const shk_c128* Hbar, const shk_c128* taus, int n_shifts,
-                    const shk_c128* sigma, double beta, shk_c128* y, double* rho);
+                    const shk_c128* sigma, double beta, shk_c128* y, double* rho, int variant);
 
 /* Solution assembly x_j = Z y_j (Algorithm 4): Z is k columns of n complex
  * values (column stride n, complex128 or complex64 per precision, device), Y

@@ -80,7 +80,7 @@ _SIGS = {
     "shk_orthogonalize": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                     C.c_void_p]),
     "shk_shifted_lsq": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p,
-                                  C.c_void_p]),
+                                  C.c_void_p, C.c_int]),
     "shk_assemble": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                C.c_int, C.c_void_p]),
     "shk_true_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -307,9 +307,10 @@ def shk_orthogonalize(n: int, k: int, V, w, n_rhs: int = 1, stream=None):
     return h
 
 
-def shk_shifted_lsq(Hbar: np.ndarray, taus, sigma, beta: float):
-    """Device Givens solution of the per-shift projected problems for a
-    (k+1) x k Hessenberg; returns (y (n_shifts, k), rho (k, n_shifts))."""
+def shk_shifted_lsq(Hbar: np.ndarray, taus, sigma, beta: float, variant: int = SHK_GMRES):
+    """Device Givens solution of the per-shift projected problems (least
+    squares, or the square FOM system) for a (k+1) x k Hessenberg; returns
+    (y (n_shifts, k), rho (k, n_shifts))."""
     H = np.asfortranarray(Hbar, dtype=np.complex128)
     k = H.shape[1]
     tt = np.ascontiguousarray(taus, dtype=np.complex128)
@@ -318,7 +319,7 @@ def shk_shifted_lsq(Hbar: np.ndarray, taus, sigma, beta: float):
     y = np.zeros((nf, k), dtype=np.complex128)
     rho = np.zeros((k, nf), dtype=np.float64)
     _check(lib().shk_shifted_lsq(k, H.ctypes.data, tt.ctypes.data, nf, sg.ctypes.data, beta, y.ctypes.data,
-                                 rho.ctypes.data), "shk_shifted_lsq")
+                                 rho.ctypes.data, variant), "shk_shifted_lsq")
     return y, rho
 
 

@@ -125,9 +125,9 @@ int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128*
 }
 
 int shk_shifted_lsq(int k, const shk_c128* Hbar, const shk_c128* taus, int n_shifts, const shk_c128* sigma,
-                    double beta, shk_c128* y, double* rho) {
+                    double beta, shk_c128* y, double* rho, int variant) {
   return shk::step_lsq(k, reinterpret_cast<const c128*>(Hbar), reinterpret_cast<const c128*>(taus), n_shifts,
-                       reinterpret_cast<const c128*>(sigma), beta, reinterpret_cast<c128*>(y), rho);
+                       reinterpret_cast<const c128*>(sigma), beta, reinterpret_cast<c128*>(y), rho, variant);
 }
 
 int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128* Y, shk_c128* X, int accumulate,

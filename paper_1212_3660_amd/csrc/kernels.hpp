@@ -829,8 +829,18 @@ __global__ void __launch_bounds__(BS) k_basis_combine(long N, int S, int kc, con
 // subdiagonal, |g_{k+1}| is the quasi-residual ||beta e_1 - Hbar(sigma;T) y||,
 // y comes from the triangular factor, and eq. trueresidual's bound
 // rho + sum |y_i| ||p_i|| decides whether the lane freezes.
+//
+// FOM variant (Algorithm 4, FOM): y solves the square system H_k(sigma;T) y =
+// beta e_1.  The rotations that zero the earlier subdiagonals turn it into the
+// triangular factor with the last diagonal and right-hand side taken before
+// the new rotation, so the same stored factor serves both variants.  The FOM
+// residual is -hbar_{k+1,k}(sigma) y_k v_{k+1} (the closed form in the proof of
+// Prop. 2); its coefficient is kept for the restart.  An exactly singular
+// H_k(sigma;T) has no FOM iterate: the step reports an infinite quasi-residual
+// and keeps the least-squares y.
 struct LaneState {
   c128 beta;        // current start coefficient beta_j of this cycle
+  c128 fres;        // FOM: residual coefficient along the next basis vector
   double gap_prev;  // inexact-inner term accumulated over earlier cycles
   double rho;       // quasi-residual at the last step
   double bound;     // bound of eq. trueresidual at the last step
@@ -845,6 +855,7 @@ struct LaneState {
 
 struct GivensArgs {
   int L, S, m, k, cycle, kglob;
+  int fom;               // 1: FOM projected problem, 0: least squares (GMRES)
   double tol, inexact_ratio, breakdown_rel;
   const c128* Hk;        // column k: Hk[i*S + r], i <= k+1 (k+1 = subdiagonal)
   const double* hn;      // h_{k+1,k} per lane r
@@ -873,12 +884,20 @@ __device__ __forceinline__ size_t tri(int i, int k) { return (size_t)k * (k + 1)
 
 // y = R^{-1} g over the first kc columns into y[i * ys]; returns the inexact
 // term sum |y_i| ||p_i||.  The R loads do not depend on the running sum, so
-// several are in flight at once.
+// several are in flight at once.  With `last`, the last row uses the diagonal
+// last[0] and right-hand side last[1] instead of the stored ones.
 __device__ inline double backsolve(const GivensArgs& a, int lane, int r, int kc, const c128* gv, size_t gstride,
-                                  c128* y, int ys) {
+                                  c128* y, int ys, const c128* last = nullptr) {
   const int L = a.L;
   double gap = 0.0;
-  for (int i = kc - 1; i >= 0; --i) {
+  int i0 = kc - 1;
+  if (last) {
+    const c128 yi = cdiv(last[1], last[0]);
+    y[i0 * ys] = yi;
+    gap += hypot(yi.re, yi.im) * a.pn[i0 * a.S + r];
+    --i0;
+  }
+  for (int i = i0; i >= 0; --i) {
     c128 acc = gv[(size_t)i * gstride];
 #pragma unroll 4
     for (int l = i + 1; l < kc; ++l) acc = acc - a.Rp[tri(i, l) * L + lane] * y[l * ys];
@@ -928,12 +947,26 @@ __global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
   a.g[(size_t)k * L + lane] = c * gk;
   const c128 gk1 = (-1.0) * (conj(s) * gk);
   a.g[(size_t)(k + 1) * L + lane] = gk1;
-  const double rho = broke ? 0.0 : hypot(gk1.re, gk1.im);
+  double rho = broke ? 0.0 : hypot(gk1.re, gk1.im);
   const bool in_lds = a.m <= GIV_LDS_M && blockDim.x == GIV_BLOCK;
   c128* yrow = a.Yb + (size_t)lane * a.m;
   c128* y = in_lds ? reinterpret_cast<c128*>(giv_lds) + threadIdx.x : yrow;
   const int ys = in_lds ? GIV_BLOCK : 1;
-  const double gap = backsolve(a, lane, r, k + 1, a.g + lane, (size_t)L, y, ys);
+  // FOM: the square system's factor ends in the unrotated pivot; after a
+  // breakdown (zero subdiagonal) the two variants coincide
+  const bool fom = a.fom && !broke;
+  const bool singular = fom && carry.re == 0.0 && carry.im == 0.0;
+  const c128 last[2] = {carry, gk};
+  const double gap = backsolve(a, lane, r, k + 1, a.g + lane, (size_t)L, y, ys, fom && !singular ? last : nullptr);
+  st.fres = c128{0.0, 0.0};
+  if (fom) {
+    if (singular) {
+      rho = __builtin_inf();
+    } else {
+      st.fres = (-1.0) * (sub * y[k * ys]);
+      rho = hypot(st.fres.re, st.fres.im);
+    }
+  }
   if (in_lds)
     for (int i = 0; i <= k; ++i) yrow[i] = y[i * ys];
   for (int i = k + 1; i < a.m; ++i) yrow[i] = c128{0.0, 0.0};
@@ -1066,6 +1099,35 @@ __global__ void __launch_bounds__(BS) k_restart_lanes(GivensArgs a, const int* _
   }
   st.gap_prev += gap;
   st.beta = (j == seed[r]) ? c128{nzs[r], 0.0} : gamma;
+  st.cycle_fz = -1;
+  a.ls[lane] = st;
+  a.g[lane] = st.beta;
+}
+
+// FOM restart, every active lane: the residual beta e_1 - Hbar(sigma;T) y of
+// the cycle is fres v_{m+1} already (no seed needed), so the next cycle starts
+// from v_1 = v_{m+1} with beta_j <- fres, the lane's y (the last step's FOM
+// solution in Yb) is assembled, and the inexact term grows by sum |y_i|
+// ||p_i||.  A lane whose last projected system was singular has no collinear
+// residual: it freezes NOT_CONVERGED with its least-squares y.
+__global__ void __launch_bounds__(BS) k_restart_fom(GivensArgs a) {
+  const int lane = blockIdx.x * BS + threadIdx.x;
+  if (lane >= a.L) return;
+  LaneState st = a.ls[lane];
+  if (!st.active) return;
+  const int r = lane % a.S;
+  if (!(st.rho < __builtin_inf())) {
+    st.status = SHK_NOT_CONVERGED;
+    st.active = 0;
+    st.cycle_fz = a.cycle;
+    a.ls[lane] = st;
+    return;
+  }
+  const c128* y = a.Yb + (size_t)lane * a.m;
+  double gap = 0.0;
+  for (int i = 0; i < a.m; ++i) gap += hypot(y[i].re, y[i].im) * a.pn[i * a.S + r];
+  st.gap_prev += gap;
+  st.beta = st.fres;
   st.cycle_fz = -1;
   a.ls[lane] = st;
   a.g[lane] = st.beta;

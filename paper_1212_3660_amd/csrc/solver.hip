@@ -485,6 +485,7 @@ struct PassSpec {
   const std::vector<c128>* taus;
   long long kglob0;   // tau schedule position
   double relax = 0.0, eps_max = 1e-2;   // relaxed inner tolerance (0: off)
+  bool fom = false;                     // FOM projected problem and FOM restart
 };
 
 struct Snap {
@@ -1036,6 +1037,7 @@ template <typename R, typename Op, typename OpD> struct Group {
                       B.pn + (size_t)k * S));
         SHK_TRY(orthogonalize(k, B.W));
         GivensArgs a = gargs(k, cycle, (int)(kglob - ps.kglob0), ps.tol);
+        a.fom = ps.fom ? 1 : 0;
         launch_givens(a, st);
         k_count_active<<<1, BS, 0, st>>>(S, nf, B.ls, B.beta0, B.nact, B.qmax);
         SHK_HIP(hipGetLastError());
@@ -1066,8 +1068,18 @@ template <typename R, typename Op, typename OpD> struct Group {
         SHK_HIP(hipGetLastError());
         break;
       }
-      // ---- restart with collinear residuals ----
       GivensArgs a = gargs(m - 1, cycle, 0, ps.tol);
+      if (ps.fom) {
+        // ---- FOM restart: every residual lies along v_{m+1} ----
+        k_restart_fom<<<Lb, BS, 0, st>>>(a);
+        SHK_HIP(hipGetLastError());
+        SHK_TRY(assemble(m, cycle, extra, X, !first_write));
+        first_write = false;
+        k_copy<R><<<grid_items(N, 4096), BS, 0, st>>>(B.V + (size_t)m * N, N, B.V);
+        SHK_HIP(hipGetLastError());
+        continue;
+      }
+      // ---- GMRES restart with collinear residuals ----
       k_restart_seed<<<1, 64, 0, st>>>(S, nf, m, B.ls, B.rc, B.rs, B.g, B.seed, B.zs, B.nzs);
       k_restart_lanes<<<Lb, BS, 0, st>>>(a, B.seed, B.zs, B.nzs);
       SHK_HIP(hipGetLastError());
@@ -1127,7 +1139,8 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     Group<R, Op, OpD> g{p, op, opd, st, B, n, N, S, s_real, nf, m, nf * S, item_plan(N, S)};
     g.mg = use_mg;
     g.mg_omega = prm->mg_omega;
-    PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0, prm->inner_relax, prm->inner_eps_max};
+    PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0, prm->inner_relax, prm->inner_eps_max,
+                prm->variant == SHK_FOM};
     SHK_TRY(g.pass(B.bint, ps, X, false, nullptr));
     SHK_HIP(hipMemcpyAsync(lanes.data(), B.ls, sizeof(LaneState) * nf * S, hipMemcpyDeviceToHost, st));
     SHK_HIP(hipMemcpyAsync(bnorm.data(), B.beta0, sizeof(double) * S, hipMemcpyDeviceToHost, st));
@@ -1183,7 +1196,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
         }
       SHK_HIP(hipMemcpyAsync(B.extra, extra.data(), sizeof(c128) * nf * S, hipMemcpyHostToDevice, st));
       PassSpec pr{m, prm->max_restarts, maxit, prm->refine_tol, prm->refine_eps_inner, &taus, 0, prm->inner_relax,
-                  prm->inner_eps_max};
+                  prm->inner_eps_max, prm->variant == SHK_FOM};
       SHK_TRY(g.pass(B.rsv, pr, X, true, B.extra));
       SHK_TRY(measure());
     }
@@ -1222,7 +1235,7 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
   if (prm->max_restarts < 0 || prm->max_refine < 0) return fail(SHK_ERR_INVALID_ARG, "negative restart/refine count");
   if (prm->n_tau < 1 || !prm->tau_seq) return fail(SHK_ERR_INVALID_ARG, "tau_seq must hold n_tau >= 1 values");
   if (!(prm->tol > 0.0) || !(prm->eps_inner >= 0.0)) return fail(SHK_ERR_INVALID_ARG, "tol must be > 0, eps >= 0");
-  if (prm->variant != SHK_GMRES) return fail(SHK_ERR_UNSUPPORTED, "only the GMRES variant runs on the GPU path");
+  if (prm->variant != SHK_GMRES && prm->variant != SHK_FOM) return fail(SHK_ERR_INVALID_ARG, "variant");
   if (prm->precision != SHK_FP64 && prm->precision != SHK_MIXED) return fail(SHK_ERR_INVALID_ARG, "precision");
   if (prm->inner_precond != SHK_PRECOND_JACOBI && prm->inner_precond != SHK_PRECOND_MULTIGRID)
     return fail(SHK_ERR_INVALID_ARG, "inner_precond");
@@ -1409,8 +1422,10 @@ int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precisio
   return precision == SHK_MIXED ? run(float{}) : run(double{});
 }
 
-int step_lsq(int K, const c128* H, const c128* taus, int nf, const c128* sigma, double beta, c128* y, double* rho) {
+int step_lsq(int K, const c128* H, const c128* taus, int nf, const c128* sigma, double beta, c128* y, double* rho,
+             int variant) {
   if (K < 1 || nf < 1 || !H || !taus || !sigma || !y || !rho) return fail(SHK_ERR_INVALID_ARG, "lsq arguments");
+  if (variant != SHK_GMRES && variant != SHK_FOM) return fail(SHK_ERR_INVALID_ARG, "variant");
   const int m = K, S = 1, L = nf;
   Carver cv{nullptr};
   Buffers<double> b0{};
@@ -1444,7 +1459,7 @@ int step_lsq(int K, const c128* H, const c128* taus, int nf, const c128* sigma, 
     const double hnk = Hd[(size_t)k * (m + 2) + k + 1].re;
     SHK_HIP(hipMemcpy(b.hn, &hnk, sizeof(double), hipMemcpyHostToDevice));
     GivensArgs a{};
-    a.L = L; a.S = S; a.m = m; a.k = k; a.cycle = 0; a.kglob = k;
+    a.L = L; a.S = S; a.m = m; a.k = k; a.cycle = 0; a.kglob = k; a.fom = variant == SHK_FOM ? 1 : 0;
     a.tol = 0.0; a.inexact_ratio = -1.0; a.breakdown_rel = 0.0;
     a.Hk = b.H + (size_t)k * (m + 2); a.hn = b.hn; a.mz = b.mz; a.pn = b.pn; a.beta0 = b.beta0;
     a.sigma = b.sigma; a.taus = b.taus; a.ls = b.ls; a.rc = b.rc; a.rs = b.rs; a.g = b.g; a.Rp = b.Rp; a.Yb = b.Yb;

@@ -908,14 +908,9 @@ __device__ inline double backsolve(const GivensArgs& a, int lane, int r, int kc,
   return gap;
 }
 
-// Basis lengths up to GIV_LDS_M keep each lane's y in LDS during the back
-// substitution (launch: GIV_BLOCK threads per block, GIV_BLOCK * m * 16 bytes
-// of LDS); longer ones use the lane's row of Yb.
-constexpr int GIV_BLOCK = 64;
-constexpr int GIV_LDS_M = 60;
-
+// Thread per lane (bases longer than GIVW_MAXM; shorter ones use
+// k_givens_wave below).  y goes straight to the lane's row of Yb.
 __global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
-  extern __shared__ __align__(16) char giv_lds[];
   const int lane = blockIdx.x * blockDim.x + threadIdx.x;
   if (lane >= a.L) return;
   LaneState st = a.ls[lane];
@@ -948,10 +943,9 @@ __global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
   const c128 gk1 = (-1.0) * (conj(s) * gk);
   a.g[(size_t)(k + 1) * L + lane] = gk1;
   double rho = broke ? 0.0 : hypot(gk1.re, gk1.im);
-  const bool in_lds = a.m <= GIV_LDS_M && blockDim.x == GIV_BLOCK;
   c128* yrow = a.Yb + (size_t)lane * a.m;
-  c128* y = in_lds ? reinterpret_cast<c128*>(giv_lds) + threadIdx.x : yrow;
-  const int ys = in_lds ? GIV_BLOCK : 1;
+  c128* y = yrow;
+  const int ys = 1;
   // FOM: the square system's factor ends in the unrotated pivot; after a
   // breakdown (zero subdiagonal) the two variants coincide
   const bool fom = a.fom && !broke;
@@ -967,9 +961,126 @@ __global__ void __launch_bounds__(BS) k_givens(GivensArgs a) {
       rho = hypot(st.fres.re, st.fres.im);
     }
   }
-  if (in_lds)
-    for (int i = 0; i <= k; ++i) yrow[i] = y[i * ys];
   for (int i = k + 1; i < a.m; ++i) yrow[i] = c128{0.0, 0.0};
+  const double bound = rho + st.gap_prev + gap;
+  const double b0 = a.beta0[r];
+  st.rho = rho;
+  st.bound = bound;
+  st.kfz = k + 1;
+  st.outer_its = a.kglob + 1;
+  st.restarts = a.cycle;
+  int done = -1;
+  if (broke) done = bound <= a.tol * b0 ? SHK_BREAKDOWN_EXACT : SHK_INNER_LIMITED;
+  else if (bound <= a.tol * b0) done = SHK_CONVERGED;
+  else if (rho <= a.inexact_ratio * (st.gap_prev + gap)) done = SHK_INNER_LIMITED;
+  if (done >= 0) {
+    st.status = done;
+    st.active = 0;
+    st.cycle_fz = a.cycle;
+  }
+  a.ls[lane] = st;
+}
+
+// Wave per (shift, rhs) lane, bases up to GIVW_MAXM columns (launch: one
+// 64-thread block per lane, givens_wave_lds(m) bytes of LDS).  The lane's
+// triangular factor, rotations and the new Hessenberg column are staged in LDS
+// with independent loads; thread 0 rotates the new column (a serial chain of
+// k rotations read from LDS); the back substitution then runs by columns with
+// thread t owning row t: y_i = acc_i / R_ii on thread i, broadcast by readlane,
+// and every row above subtracts R_ti y_i.  The inexact term sum |y_i| ||p_i||
+// is a wave sum.  Same arithmetic as k_givens up to the order of the
+// subtractions and of the sum.
+constexpr int GIVW_MAXM = 64;
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__global__ void __launch_bounds__(64) k_givens_wave(GivensArgs a) {
+  extern __shared__ __align__(16) char gw_lds[];
+  __shared__ c128 last_rhs;
+  const int m = a.m, k = a.k, S = a.S, L = a.L;
+  c128* R = reinterpret_cast<c128*>(gw_lds);   // tri(i, l), l <= k
+  c128* rs = R + (size_t)m * (m + 1) / 2;       // rotations 0..k-1
+  c128* hk = rs + m;                            // column k of Hbar, k + 2 entries
+  double* rc = reinterpret_cast<double*>(hk + m + 2);
+  const int lane = blockIdx.x;
+  const int t = threadIdx.x;
+  LaneState st = a.ls[lane];
+  if (!st.active) return;                       // uniform over the block
+  const int r = lane % S, j = lane / S;
+  const int nold = k * (k + 1) / 2;
+  for (int e = t; e < nold; e += 64) R[e] = a.Rp[(size_t)e * L + lane];
+  for (int e = t; e < k; e += 64) {
+    rc[e] = a.rc[(size_t)e * L + lane];
+    rs[e] = a.rs[(size_t)e * L + lane];
+  }
+  for (int e = t; e <= k + 1; e += 64) hk[e] = a.Hk[e * S + r];
+  const c128 g_own = t < k ? a.g[(size_t)t * L + lane] : c128{0.0, 0.0};
+  const c128 d = a.sigma[j] - a.taus[k];
+  const double hn = a.hn[r];
+  const bool broke = !(hn > a.breakdown_rel * a.mz[r]);
+  const c128 sub = broke ? c128{0.0, 0.0} : hn * d;
+  const bool fom = a.fom && !broke;
+  __syncthreads();
+  // thread 0: rotate the new column by the stored rotations, make the new one
+  double c = 1.0;
+  c128 s{0.0, 0.0}, carry{0.0, 0.0}, gk1{0.0, 0.0};
+  if (t == 0) {
+    carry = d * hk[0];
+    if (k == 0) carry.re += 1.0;
+    for (int i = 0; i < k; ++i) {
+      c128 nxt = d * hk[i + 1];
+      if (i + 1 == k) nxt.re += 1.0;
+      const double ci = rc[i];
+      const c128 si = rs[i];
+      const c128 v = ci * carry + si * nxt;
+      R[tri(i, k)] = v;
+      a.Rp[tri(i, k) * L + lane] = v;
+      carry = (-1.0) * (conj(si) * carry) + ci * nxt;
+    }
+    c128 rr;
+    givens_make(carry, sub, c, s, rr);
+    a.Rp[tri(k, k) * L + lane] = rr;
+    a.rc[(size_t)k * L + lane] = c;
+    a.rs[(size_t)k * L + lane] = s;
+    const c128 gk = a.g[(size_t)k * L + lane];
+    a.g[(size_t)k * L + lane] = c * gk;
+    gk1 = (-1.0) * (conj(s) * gk);
+    a.g[(size_t)(k + 1) * L + lane] = gk1;
+    // FOM: the square system's factor ends in the unrotated pivot and
+    // right-hand side (an exactly singular one keeps the least-squares y)
+    const bool use_fom = fom && !(carry.re == 0.0 && carry.im == 0.0);
+    R[tri(k, k)] = use_fom ? carry : rr;
+    last_rhs = use_fom ? gk : c * gk;
+  }
+  __syncthreads();
+  c128 acc = t < k ? g_own : (t == k ? last_rhs : c128{0.0, 0.0});
+  c128 yown{0.0, 0.0};
+  for (int i = k; i >= 0; --i) {
+    if (t == i) yown = cdiv(acc, R[tri(i, i)]);
+    const c128 yi{readlane_f64(yown.re, i), readlane_f64(yown.im, i)};
+    if (t < i) acc = acc - R[tri(t, i)] * yi;
+  }
+  const bool owned = t <= k;
+  double gp = owned ? hypot(yown.re, yown.im) * a.pn[t * S + r] : 0.0;
+  const double gap = wave_sum_strided(gp, 1);
+  if (t < m) a.Yb[(size_t)lane * m + t] = owned ? yown : c128{0.0, 0.0};
+  const c128 yk{readlane_f64(yown.re, k), readlane_f64(yown.im, k)};
+  if (t != 0) return;
+  double rho = broke ? 0.0 : hypot(gk1.re, gk1.im);
+  st.fres = c128{0.0, 0.0};
+  if (fom) {
+    if (carry.re == 0.0 && carry.im == 0.0) {
+      rho = __builtin_inf();
+    } else {
+      st.fres = (-1.0) * (sub * yk);
+      rho = hypot(st.fres.re, st.fres.im);
+    }
+  }
   const double bound = rho + st.gap_prev + gap;
   const double b0 = a.beta0[r];
   st.rho = rho;
@@ -1217,6 +1328,67 @@ __global__ void __launch_bounds__(BS) k_assemble(long n, int S, int s_real, int 
         const c128 v = ascale[(size_t)j * S + r] * acc[q];
         c128* dst = X + c + n * ((long)j + (long)nf * r);
         *dst = accumulate ? *dst + v : v;
+      }
+    }
+  }
+}
+
+// The same product with the block's JT columns of Y (every rhs lane, kc rows)
+// staged once in LDS at ys[(i JT + q) S + lane] instead of being reloaded for
+// every item; each thread accumulates two items, t and t + BS, per LDS read.
+// Needs kc * JT * S * 16 bytes of LDS (the launcher keeps it within 64 KB).
+// Same FP64 accumulation order as k_assemble.
+template <typename R>
+__global__ void __launch_bounds__(BS) k_assemble_lds(long n, int S, int s_real, int nf, int kc, int m,
+                                                     const cx<R>* __restrict__ Z, size_t cstride,
+                                                     const c128* __restrict__ Yb, const c128* __restrict__ ascale,
+                                                     c128* __restrict__ X, int accumulate) {
+  extern __shared__ __align__(16) char asm_lds[];
+  c128* ys = reinterpret_cast<c128*>(asm_lds);
+  const long N = n * S;
+  const int j0 = blockIdx.y * JT;
+  const int tot = kc * JT * S;
+  for (int e = threadIdx.x; e < tot; e += BS) {
+    const int rr = e % S, q = (e / S) % JT, i = e / (S * JT);
+    const int j = j0 + q < nf ? j0 + q : nf - 1;
+    ys[e] = Yb[((size_t)j * S + rr) * m + i];
+  }
+  __syncthreads();
+  const int r = threadIdx.x & (S - 1);
+  if (r >= s_real) return;
+  for (long base = (long)blockIdx.x * 2 * BS; base < N; base += (long)gridDim.x * 2 * BS) {
+    const long t0 = base + threadIdx.x, t1 = t0 + BS;
+    const bool h0 = t0 < N, h1 = t1 < N;
+    c128 a0[JT], a1[JT];
+#pragma unroll
+    for (int q = 0; q < JT; ++q) a0[q] = a1[q] = c128{0.0, 0.0};
+    for (int i = 0; i < kc; ++i) {
+      const c128 z0 = h0 ? cvt<double>(Z[(size_t)i * cstride + t0]) : c128{0.0, 0.0};
+      const c128 z1 = h1 ? cvt<double>(Z[(size_t)i * cstride + t1]) : c128{0.0, 0.0};
+      const c128* yr = ys + (size_t)i * JT * S + r;
+#pragma unroll
+      for (int q = 0; q < JT; ++q) {
+        const c128 y = yr[q * S];
+        a0[q] = a0[q] + z0 * y;
+        a1[q] = a1[q] + z1 * y;
+      }
+    }
+    const long c0 = t0 / S, c1 = t1 / S;
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      const int j = j0 + q;
+      if (j >= nf) break;
+      const c128 sc = ascale[(size_t)j * S + r];
+      const long off = n * ((long)j + (long)nf * r);
+      if (h0) {
+        c128* d = X + c0 + off;
+        const c128 v = sc * a0[q];
+        *d = accumulate ? *d + v : v;
+      }
+      if (h1) {
+        c128* d = X + c1 + off;
+        const c128 v = sc * a1[q];
+        *d = accumulate ? *d + v : v;
       }
     }
   }

@@ -379,11 +379,31 @@ template <typename R> static void carve_mg(Carver& cv, Buffers<R>& b, const shk_
 
 static int resid_grid(long n) { return grid_items(n, 256); }
 
-// One thread per (shift, rhs) lane; short bases keep the back substitution
-// in LDS.
+// X (+)= Z Y (Algorithm 4, x = Z y): Y staged in LDS when the block's JT
+// columns for every rhs lane fit in 64 KB, else read per item.
+template <typename R>
+static void launch_assemble(long n, int S, int s_real, int nf, int kc, int m, const cx<R>* Z, size_t cstride,
+                            const c128* Yb, const c128* ascale, c128* X, int acc, hipStream_t st) {
+  const long N = n * S;
+  const size_t lds = (size_t)kc * JT * S * sizeof(c128);
+  if (lds <= 65536) {
+    dim3 grid(grid_items((N + 1) / 2, 4096), (nf + JT - 1) / JT);
+    k_assemble_lds<R><<<grid, BS, lds, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);
+  } else {
+    dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
+    k_assemble<R><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);
+  }
+}
+
+// Bases up to GIVW_MAXM columns: a wave per (shift, rhs) lane; longer ones a
+// thread per lane.
+static size_t givens_wave_lds(int m) {
+  return ((size_t)m * (m + 1) / 2 + 2 * (size_t)m + 2) * sizeof(c128) + (size_t)m * sizeof(double);
+}
+
 static void launch_givens(const GivensArgs& a, hipStream_t st) {
-  if (a.m <= GIV_LDS_M)
-    k_givens<<<(a.L + GIV_BLOCK - 1) / GIV_BLOCK, GIV_BLOCK, (size_t)GIV_BLOCK * a.m * sizeof(c128), st>>>(a);
+  if (a.m <= GIVW_MAXM)
+    k_givens_wave<<<a.L, 64, givens_wave_lds(a.m), st>>>(a);
   else
     k_givens<<<(a.L + BS - 1) / BS, BS, 0, st>>>(a);
 }
@@ -1000,9 +1020,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   int assemble(int kc, int cycle, const c128* extra, c128* X, bool accumulate) {
     const int Lb = (L + BS - 1) / BS;
     k_asm_scale<<<Lb, BS, 0, st>>>(L, cycle, B.ls, extra, B.ascale);
-    dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
-    k_assemble<double><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X,
-                                            accumulate ? 1 : 0);
+    launch_assemble<double>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X, accumulate ? 1 : 0, st);
     SHK_HIP(hipGetLastError());
     return SHK_OK;
   }
@@ -1484,9 +1502,7 @@ int step_assemble(long long n, int k, int nf, const void* Z, const c128* Y, c128
   SHK_HIP(hipMemcpyAsync(ones.p, o.data(), sizeof(c128) * nf, hipMemcpyHostToDevice, st));
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
-    dim3 grid(grid_items(n, 4096), (nf + JT - 1) / JT);
-    k_assemble<R><<<grid, BS, 0, st>>>((long)n, 1, 1, nf, k, k, (const cx<R>*)Z, (size_t)n, Y, (const c128*)ones.p, X,
-                                       acc);
+    launch_assemble<R>((long)n, 1, 1, nf, k, k, (const cx<R>*)Z, (size_t)n, Y, (const c128*)ones.p, X, acc, st);
     SHK_HIP(hipGetLastError());
     SHK_HIP(hipStreamSynchronize(st));
     return SHK_OK;

@@ -34,11 +34,12 @@ def _arnoldi(shape, seed, k):
     return r.H, r.taus, sig, float(np.linalg.norm(b))
 
 
-def test_fom_projected_solves_match_oracle():
+@pytest.mark.parametrize("m", [14, 64, 70])
+def test_fom_projected_solves_match_oracle(m):
     require_gpu()
     import paper_1212_3660_amd as P
-    announce("shifted fom")
-    H, taus, sig, beta = _arnoldi((20, 20), 9, 14)
+    announce(f"shifted fom m={m}")
+    H, taus, sig, beta = _arnoldi((20, 20), 9, m)
     k = H.shape[1]
     y, rho = P.shk_shifted_lsq(H, taus, sig, beta, P.SHK_FOM)
     for j, s in enumerate(sig):

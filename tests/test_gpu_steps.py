@@ -152,16 +152,18 @@ def test_orthogonalize_matches_mgs(n, k, S):
         assert np.allclose(h32[r, :k], ho, atol=2e-5 * np.linalg.norm(W[:, r]))
 
 
-def test_shifted_lsq_matches_oracle_least_squares():
+@pytest.mark.parametrize("m", [14, 64, 70])
+def test_shifted_lsq_matches_oracle_least_squares(m):
+    # m <= 64: a wave per shift; longer bases: a thread per shift
     require_gpu()
     import paper_1212_3660_amd as P
-    announce("shifted lsq")
+    announce(f"shifted lsq m={m}")
     K = _field((20, 20), 9)
     op = OProblem.fv(K)
     T = synth.periods(12, 5, 5000)
     sig = synth.shifts_from_periods(T)
     b = synth.unit_vector(op.n, 210)
-    r = fgmres_sh(op, b, sig, sig[[2, 6, 10]], m_restart=14, max_restarts=0, tol=1e-30, inner="dense",
+    r = fgmres_sh(op, b, sig, sig[[2, 6, 10]], m_restart=m, max_restarts=0, tol=1e-30, inner="dense",
                   keep_basis=True)
     H, taus = r.H, r.taus
     k = H.shape[1]

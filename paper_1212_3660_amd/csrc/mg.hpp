@@ -81,12 +81,26 @@ __global__ void __launch_bounds__(BS) k_mg_mass(LevelDims f, LevelDims c, const 
   }
 }
 
-// Inverse diagonal of one level for the solve's tau: 1 / (diag K_l + tau M_l).
+// Inverse diagonals for the solve's tau, 1 / (diag K_l + tau M_l), of up to
+// MG_DINV_TAB levels in one launch: level q holds cells [start[q],
+// start[q + 1]) of the launch's index range.
+constexpr int MG_DINV_TAB = 16;
+template <typename OpD, typename R> struct MgDinvTab {
+  int nl;
+  long start[MG_DINV_TAB + 1];
+  OpD op[MG_DINV_TAB];
+  cx<R>* out[MG_DINV_TAB];
+};
 template <typename OpD, typename R>
-__global__ void __launch_bounds__(BS) k_mg_dinv(OpD opd, c128 tau, int n, cx<R>* __restrict__ dinv) {
-  for (int c = blockIdx.x * BS + threadIdx.x; c < n; c += gridDim.x * BS) {
-    const double m = opd.mass(c);
-    dinv[c] = cvt<R>(cdiv(c128{1.0, 0.0}, c128{opd.diagK(c) + tau.re * m, tau.im * m}));
+__global__ void __launch_bounds__(BS) k_mg_dinv_levels(MgDinvTab<OpD, R> tab, c128 tau) {
+  const long total = tab.start[tab.nl];
+  for (long g = blockIdx.x * (long)BS + threadIdx.x; g < total; g += (long)gridDim.x * BS) {
+    int l = 0;
+    while (l + 1 < tab.nl && g >= tab.start[l + 1]) ++l;
+    const int c = (int)(g - tab.start[l]);
+    const OpD& o = tab.op[l];
+    const double m = o.mass(c);
+    tab.out[l][c] = cvt<R>(cdiv(c128{1.0, 0.0}, c128{o.diagK(c) + tau.re * m, tau.im * m}));
   }
 }
 

@@ -604,9 +604,20 @@ template <typename R, typename Op, typename OpD> struct Group {
   // inverse diagonals of the coarse levels for this tau
   void mg_prepare(c128 tau) {
     if constexpr (Op::NB > 0) {
-      for (int l = 1; l < mg_levels(); ++l) {
-        const int nl = mg_dims(l).n();
-        k_mg_dinv<OpD, R><<<grid_items(nl, 2048), BS, 0, st>>>(mg_op<OpD, double>(opd, l), tau, nl, B.mdinv[l - 1]);
+      // D^-1 of every coarse level, MG_DINV_TAB levels per launch
+      const int Lv = mg_levels();
+      for (int l0 = 1; l0 < Lv; l0 += MG_DINV_TAB) {
+        MgDinvTab<OpD, R> tab{};
+        tab.nl = std::min(MG_DINV_TAB, Lv - l0);
+        long tot = 0;
+        for (int q = 0; q < tab.nl; ++q) {
+          tab.start[q] = tot;
+          tab.op[q] = mg_op<OpD, double>(opd, l0 + q);
+          tab.out[q] = B.mdinv[l0 + q - 1];
+          tot += mg_dims(l0 + q).n();
+        }
+        tab.start[tab.nl] = tot;
+        k_mg_dinv_levels<OpD, R><<<grid_items(tot, 2048), BS, 0, st>>>(tab, tau);
       }
       const int t = mg_tail_level(ilog2(S));
       if (t < mg_levels()) {

@@ -935,10 +935,10 @@ template <typename R, typename Op, typename OpD> struct Group {
           const int kw = s.its - prev_its[r];
           if (kw >= 8 && s.rnorm < prev_rn[r]) rate = 0.5 * (rate + std::log(s.rnorm / prev_rn[r]) / kw);
           if (s.rnorm <= target) {
-            rem = 3;
+            rem = 2;
           } else {
             const double lr = std::log(target / s.rnorm);
-            rem = (int)std::ceil(lr / rate * 1.05) + 2;
+            rem = (int)std::ceil(lr / rate * 1.05) + 1;
             if (!cfg.trust) rem += 2 * (int)std::ceil(lr / lrt);
           }
           rem = std::min(rem, std::max(16, s.its));

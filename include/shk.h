@@ -63,6 +63,8 @@ typedef struct shk_server shk_server;
 /* parameter values */
 #define SHK_GMRES 0
 #define SHK_FOM 1
+#define SHK_CGS2 0
+#define SHK_MGS 1
 #define SHK_FP64 0   /* every vector complex128                                       */
 #define SHK_MIXED 1  /* operator, inner solve and Gram-Schmidt in complex64 with FP32
                         accumulation; Hessenberg least squares, basis norms, true
@@ -118,6 +120,12 @@ typedef struct shk_server shk_server;
  *                 inner residuals.  0.1 keeps every shift CONVERGED on the
  *                 workloads here.
  *  inner_eps_max  cap of the relaxed inner tolerance, in [eps_inner, 1).
+ *  ortho          orthogonalisation of each new basis vector (Algorithm 3):
+ *                 SHK_CGS2 (default): classical Gram-Schmidt with one
+ *                 reorthogonalisation, two passes over the basis;
+ *                 SHK_MGS: the paper's modified Gram-Schmidt, one column at a
+ *                 time (k + 1 sequential passes at step k).  Other values:
+ *                 INVALID_ARG.
  */
 typedef struct {
   int m_restart;
@@ -137,6 +145,7 @@ typedef struct {
   double mg_omega;
   double inner_relax;
   double inner_eps_max;
+  int ortho;
 } shk_params;
 
 /* Per-(shift, rhs) result, host memory, n_shifts x n_rhs column-major. */
@@ -227,13 +236,14 @@ int shk_inner_solve(shk_problem* p, shk_c128 tau, int n_rhs, const void* v, void
                     double eps, int maxit, int fixed_iters, int precision, int precond, int* its,
                     double* pnorm, void* hip_stream);
 
-/* One orthogonalisation step of Algorithm 3 (classical Gram-Schmidt with one
- * reorthogonalisation): V holds k orthonormal columns (column stride n*n_rhs
- * elements), w is orthogonalised against them in place and normalised into
- * V column k.  h (host, (k+1) x n_rhs, h[i + (k+1)*r]) receives v_i^H w for
- * i < k and ||w|| at i = k (the new Hessenberg column). */
+/* One orthogonalisation step of Algorithm 3: V holds k orthonormal columns
+ * (column stride n*n_rhs elements), w is orthogonalised against them in place
+ * (ortho = SHK_CGS2: classical Gram-Schmidt with one reorthogonalisation;
+ * SHK_MGS: modified Gram-Schmidt) and normalised into V column k.  h (host,
+ * (k+1) x n_rhs, h[i + (k+1)*r]) receives the coefficients of v_i for i < k
+ * and ||w|| at i = k (the new Hessenberg column).  Errors: INVALID_ARG. */
 int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128* h,
-                      int precision, void* hip_stream);
+                      int precision, int ortho, void* hip_stream);
 
 /* Per-shift projected problem of Algorithm 4: given Hbar ((k+1) x k, host,
  * column-major, one rhs), taus (host, k) and shifts (host, n_shifts), with

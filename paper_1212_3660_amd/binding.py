@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libshk.so")
 SHK_OK, SHK_ERR_NOT_READY = 0, -4
 SHK_CONVERGED, SHK_NOT_CONVERGED, SHK_INNER_LIMITED, SHK_BREAKDOWN_EXACT, SHK_NAN = 0, 1, 2, 3, 4
 SHK_GMRES, SHK_FOM = 0, 1
+SHK_CGS2, SHK_MGS = 0, 1
 SHK_FP64, SHK_MIXED = 0, 1
 SHK_PTR_HOST, SHK_PTR_DEVICE = 0, 1
 SHK_PRECOND_JACOBI, SHK_PRECOND_MULTIGRID = 0, 1
@@ -35,7 +36,7 @@ class shk_params(C.Structure):
                 ("n_tau", C.c_int), ("tau_seq", C.POINTER(shk_c128)), ("variant", C.c_int),
                 ("precision", C.c_int), ("refine_tol", C.c_double), ("refine_eps_inner", C.c_double),
                 ("inner_precond", C.c_int), ("mg_sweeps", C.c_int), ("mg_omega", C.c_double),
-                ("inner_relax", C.c_double), ("inner_eps_max", C.c_double)]
+                ("inner_relax", C.c_double), ("inner_eps_max", C.c_double), ("ortho", C.c_int)]
 
 
 class shk_status(C.Structure):
@@ -78,7 +79,7 @@ _SIGS = {
     "shk_inner_solve": (C.c_int, [C.c_void_p, shk_c128, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "shk_orthogonalize": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
-                                    C.c_void_p]),
+                                    C.c_int, C.c_void_p]),
     "shk_shifted_lsq": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p,
                                   C.c_void_p, C.c_int]),
     "shk_assemble": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
@@ -139,7 +140,8 @@ def _c128_array(values) -> "C.Array":
 
 def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_maxit=0, tol=1e-8,
                 eps_inner=1e-10, precision=SHK_FP64, variant=SHK_GMRES, refine_tol=0.05,
-                refine_eps_inner=5e-3, inner_precond=None, mg_omega=0.8, inner_relax=0.0, inner_eps_max=1e-2):
+                refine_eps_inner=5e-3, inner_precond=None, mg_omega=0.8, inner_relax=0.0, inner_eps_max=1e-2,
+                ortho=SHK_CGS2):
     """Returns (shk_params, keepalive) with tau_seq marshalled to C."""
     taus = _c128_array(tau_seq)
     p = shk_params()
@@ -154,6 +156,7 @@ def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_m
         p.inner_precond = inner_precond
     p.mg_omega = mg_omega
     p.inner_relax, p.inner_eps_max = inner_relax, inner_eps_max
+    p.ortho = ortho
     return p, taus
 
 
@@ -298,12 +301,12 @@ def shk_inner_solve(problem: Problem, tau: complex, v, z, w=None, eps=1e-10, max
     return its, pn
 
 
-def shk_orthogonalize(n: int, k: int, V, w, n_rhs: int = 1, stream=None):
-    """CGS2 of w against k columns of V (device, column stride n*n_rhs);
-    writes V column k; returns h as (n_rhs, k+1) complex128."""
+def shk_orthogonalize(n: int, k: int, V, w, n_rhs: int = 1, stream=None, ortho: int = SHK_CGS2):
+    """Gram-Schmidt (CGS2 or MGS) of w against k columns of V (device, column
+    stride n*n_rhs); writes V column k; returns h as (n_rhs, k+1) complex128."""
     h = np.zeros((n_rhs, k + 1), dtype=np.complex128)
     _check(lib().shk_orthogonalize(n, n_rhs, k, C.c_void_p(V.data_ptr()), C.c_void_p(w.data_ptr()), h.ctypes.data,
-                                   _prec(w), _stream_ptr(stream)), "shk_orthogonalize")
+                                   _prec(w), ortho, _stream_ptr(stream)), "shk_orthogonalize")
     return h
 
 

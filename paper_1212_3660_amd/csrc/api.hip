@@ -28,6 +28,7 @@ void shk_params_default(shk_params* p) {
   p->mg_omega = 0.8;
   p->inner_relax = 0.0;
   p->inner_eps_max = 1e-2;
+  p->ortho = SHK_CGS2;
 }
 
 static int create_fv(int nx, int ny, int nz, shk::Kind kind, const double* cell_K, double Ss, double h,
@@ -120,8 +121,9 @@ int shk_inner_solve(shk_problem* p, shk_c128 tau, int n_rhs, const void* v, void
                          pnorm, (hipStream_t)hip_stream);
 }
 
-int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128* h, int precision, void* hip_stream) {
-  return shk::step_orth(n, n_rhs, k, V, w, reinterpret_cast<c128*>(h), precision, (hipStream_t)hip_stream);
+int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128* h, int precision, int ortho,
+                      void* hip_stream) {
+  return shk::step_orth(n, n_rhs, k, V, w, reinterpret_cast<c128*>(h), precision, ortho, (hipStream_t)hip_stream);
 }
 
 int shk_shifted_lsq(int k, const shk_c128* Hbar, const shk_c128* taus, int n_shifts, const shk_c128* sigma,

@@ -73,7 +73,7 @@ int step_apply(shk_problem* p, c128 sigma, int S, const void* x, void* y, int pr
 int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w, double eps,
                int maxit, int fixed_iters, int precision, int precond, int* its, double* pnorm,
                hipStream_t stream);
-int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precision,
+int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precision, int ortho,
               hipStream_t stream);
 int step_lsq(int k, const c128* H, const c128* taus, int nf, const c128* sigma, double beta,
              c128* y, double* rho, int variant);

@@ -415,6 +415,33 @@ static long dot_ipb(long N) {
   return ipb;
 }
 
+// Gram-Schmidt of w against kc columns of V (Algorithm 3): CGS2, two block
+// passes (dot products of every column, then one update), or the paper's MGS,
+// one column at a time (its dot product, then its update).  H receives the kc
+// coefficients (summed over the two CGS2 passes); the last update leaves the
+// partials of ||w||^2 over the update's blocks in part for k_final_sqrt.
+template <typename R>
+static void gram_schmidt(long N, int S, int kc, cx<R>* V, cx<R>* w, c128* H, c128* h2, c128* part, bool mgs,
+                         hipStream_t st) {
+  const long ipb = dot_ipb(N);
+  const int Gd = (int)((N + ipb - 1) / ipb);
+  const int Gu = (int)((N + (long)BS * GSQ - 1) / ((long)BS * GSQ));
+  if (!mgs) {
+    for (int pass = 0; pass < 2; ++pass) {
+      k_gs_dot<R><<<Gd, BS, 0, st>>>(N, S, kc, V, (size_t)N, w, part, ipb);
+      k_gs_reduce<<<kc * S, BS, 0, st>>>(part, Gd, kc, S, H, h2, pass);
+      k_gs_update<R><<<Gu, BS, 0, st>>>(N, S, kc, V, (size_t)N, h2, w, pass, part);
+    }
+    return;
+  }
+  for (int i = 0; i < kc; ++i) {
+    cx<R>* Vi = V + (size_t)i * N;
+    k_gs_dot<R><<<Gd, BS, 0, st>>>(N, S, 1, Vi, (size_t)N, w, part, ipb);
+    k_gs_reduce<<<S, BS, 0, st>>>(part, Gd, 1, S, H + (size_t)i * S, h2, 0);
+    k_gs_update<R><<<Gu, BS, 0, st>>>(N, S, 1, Vi, (size_t)N, h2, w, i == kc - 1 ? 1 : 0, part);
+  }
+}
+
 template <typename R>
 static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, int s_real, bool host_x, bool mg) {
   Carver cv{base};
@@ -962,19 +989,13 @@ template <typename R, typename Op, typename OpD> struct Group {
     return SHK_OK;
   }
 
-  // ---- classical Gram-Schmidt with one reorthogonalisation (Algorithm 3) ----
+  // ---- Gram-Schmidt step of Algorithm 3 (CGS2, or MGS when mgs is set) ----
+  bool mgs = false;
   int orthogonalize(int k, cx<R>* w) {
     const int kc = k + 1;
-    const size_t cs = (size_t)N;
-    const long ipb = dot_ipb(N);
-    const int Gd = (int)((N + ipb - 1) / ipb);
     const int Gu = (int)((N + (long)BS * GSQ - 1) / ((long)BS * GSQ));
     c128* Hk = B.H + (size_t)k * (m + 2) * S;
-    for (int pass = 0; pass < 2; ++pass) {
-      k_gs_dot<R><<<Gd, BS, 0, st>>>(N, S, kc, B.V, cs, w, B.part, ipb);
-      k_gs_reduce<<<kc * S, BS, 0, st>>>(B.part, Gd, kc, S, Hk, B.h2, pass);
-      k_gs_update<R><<<Gu, BS, 0, st>>>(N, S, kc, B.V, cs, B.h2, w, pass, B.part);
-    }
+    gram_schmidt<R>(N, S, kc, B.V, w, Hk, B.h2, B.part, mgs, st);
     k_final_sqrt<1><<<1, BS, 0, st>>>(B.part, Gu, S, B.hn, nullptr, Hk + (size_t)(k + 1) * S);
     k_scale_col<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, w, B.hn, B.mz, B.V + (size_t)(k + 1) * N);
     SHK_HIP(hipGetLastError());
@@ -1168,6 +1189,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     Group<R, Op, OpD> g{p, op, opd, st, B, n, N, S, s_real, nf, m, nf * S, item_plan(N, S)};
     g.mg = use_mg;
     g.mg_omega = prm->mg_omega;
+    g.mgs = prm->ortho == SHK_MGS;
     PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0, prm->inner_relax, prm->inner_eps_max,
                 prm->variant == SHK_FOM};
     SHK_TRY(g.pass(B.bint, ps, X, false, nullptr));
@@ -1265,6 +1287,7 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
   if (prm->n_tau < 1 || !prm->tau_seq) return fail(SHK_ERR_INVALID_ARG, "tau_seq must hold n_tau >= 1 values");
   if (!(prm->tol > 0.0) || !(prm->eps_inner >= 0.0)) return fail(SHK_ERR_INVALID_ARG, "tol must be > 0, eps >= 0");
   if (prm->variant != SHK_GMRES && prm->variant != SHK_FOM) return fail(SHK_ERR_INVALID_ARG, "variant");
+  if (prm->ortho != SHK_CGS2 && prm->ortho != SHK_MGS) return fail(SHK_ERR_INVALID_ARG, "ortho");
   if (prm->precision != SHK_FP64 && prm->precision != SHK_MIXED) return fail(SHK_ERR_INVALID_ARG, "precision");
   if (prm->inner_precond != SHK_PRECOND_JACOBI && prm->inner_precond != SHK_PRECOND_MULTIGRID)
     return fail(SHK_ERR_INVALID_ARG, "inner_precond");
@@ -1407,8 +1430,9 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
   return precision == SHK_MIXED ? run(float{}) : run(double{});
 }
 
-int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precision, hipStream_t st) {
+int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precision, int ortho, hipStream_t st) {
   if (!V || !w || !h || k < 1 || S < 1 || S > 64 || (S & (S - 1))) return fail(SHK_ERR_INVALID_ARG, "orth arguments");
+  if (ortho != SHK_CGS2 && ortho != SHK_MGS) return fail(SHK_ERR_INVALID_ARG, "ortho");
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
     const long N = (long)n * S;
@@ -1433,11 +1457,7 @@ int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precisio
     SHK_HIP(hipMemcpyAsync(b.mz, tiny.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
     cx<R>* Vp = (cx<R>*)V;
     const int kc = k;
-    for (int pass = 0; pass < 2; ++pass) {
-      k_gs_dot<R><<<(int)Gd, BS, 0, st>>>(N, S, kc, Vp, (size_t)N, (const cx<R>*)w, b.part, ipb);
-      k_gs_reduce<<<kc * S, BS, 0, st>>>(b.part, (int)Gd, kc, S, b.H, b.h2, pass);
-      k_gs_update<R><<<(int)Gu, BS, 0, st>>>(N, S, kc, Vp, (size_t)N, b.h2, (cx<R>*)w, pass, b.part);
-    }
+    gram_schmidt<R>(N, S, kc, Vp, (cx<R>*)w, b.H, b.h2, b.part, ortho == SHK_MGS, st);
     k_final_sqrt<1><<<1, BS, 0, st>>>(b.part, (int)Gu, S, b.hn, nullptr, b.H + (size_t)kc * S);
     k_scale_col<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, (const cx<R>*)w, b.hn, b.mz, Vp + (size_t)kc * N);
     SHK_HIP(hipGetLastError());

@@ -28,7 +28,7 @@ def test_param_defaults_and_status_strings():
     P.lib().shk_params_default(C.byref(p))
     assert p.m_restart == 50 and p.tol == 1e-8 and p.precision == P.SHK_FP64
     assert p.inner_precond == P.SHK_PRECOND_JACOBI and p.mg_sweeps == 1 and p.mg_omega == 0.8
-    assert p.inner_relax == 0.0 and p.inner_eps_max == 1e-2
+    assert p.inner_relax == 0.0 and p.inner_eps_max == 1e-2 and p.ortho == P.SHK_CGS2
     assert P.lib().shk_status_string(-5).decode() == "unsupported"
 
 

@@ -183,3 +183,27 @@ def test_degenerate_inputs():
     bad, keep2 = P.make_params(sig[:1], m_restart=0)
     with pytest.raises(P.ShkError):
         P.fgmres_sh_solve(gp, bad, sig, np.ones(256, complex))
+
+
+def test_mgs_orthogonalisation_solve_matches_oracle():
+    # the paper's modified Gram-Schmidt (Algorithm 3) on the device: the same
+    # outer step counts as the oracle, which uses it too, and the exact
+    # solutions; a bad ortho value is a call error
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("c1 fp64 mgs")
+    w = synth.config1()
+    op = OProblem.fv(w.cell_K, w.Ss, w.h)
+    gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+    prm, keep = _params(P, w, ortho=P.SHK_MGS)
+    x, st = P.fgmres_sh_solve(gp, prm, w.sigma, w.b)
+    xe = exact_family(op, w.sigma, w.b[:, 0], "banded")
+    ro = fgmres_sh(op, w.b[:, 0], w.sigma, w.tau_seq, m_restart=50, tol=w.tol, inner="cocg", eps=w.eps_inner)
+    for j in range(len(w.sigma)):
+        s = st[0, j]
+        assert s["status"] == P.SHK_CONVERGED and s["true_relres"] <= 1e-8, (j, s)
+        assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= 2e3 * 1e-8 * np.linalg.norm(xe[:, j]), j
+        assert abs(int(s["outer_its"]) - ro.info[j].outer_its) <= 1
+    bad, keep2 = _params(P, w, ortho=5)
+    with pytest.raises(P.ShkError):
+        P.fgmres_sh_solve(gp, bad, w.sigma, w.b)

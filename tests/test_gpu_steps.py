@@ -124,11 +124,16 @@ def test_inner_cocg_converged_counts_and_residual():
             assert true <= eps * np.linalg.norm(V32[:, r]) * 1.01 and np.isclose(pn[r], true, rtol=1e-6)
 
 
+@pytest.mark.parametrize("ortho", ["cgs2", "mgs"])
 @pytest.mark.parametrize("n,k,S", [(4096, 1, 1), (10000, 7, 1), (262144, 30, 1), (5000, 12, 4)])
-def test_orthogonalize_matches_mgs(n, k, S):
+def test_orthogonalize_matches_mgs(n, k, S, ortho):
+    # both device variants against the oracle's modified Gram-Schmidt step: an
+    # orthonormal V makes the coefficients and the new column the same up to
+    # rounding
     torch = require_gpu()
     import paper_1212_3660_amd as P
-    announce(f"orth n={n} k={k} S={S}")
+    announce(f"orth {ortho} n={n} k={k} S={S}")
+    og = P.SHK_MGS if ortho == "mgs" else P.SHK_CGS2
     rng = np.random.default_rng(k)
     Vh = np.zeros((k + 1, n, S), complex)
     W = rng.normal(size=(n, S)) + 1j * rng.normal(size=(n, S))
@@ -137,7 +142,7 @@ def test_orthogonalize_matches_mgs(n, k, S):
         Vh[:k, :, r] = Q.T
     V = to_dev(Vh.reshape(k + 1, n * S).ravel())
     w = to_dev(W.ravel())
-    h = P.shk_orthogonalize(n, k, V, w, n_rhs=S)
+    h = P.shk_orthogonalize(n, k, V, w, n_rhs=S, ortho=og)
     Vg = V.cpu().numpy().reshape(k + 1, n, S)
     for r in range(S):
         ho, hn, vn = mgs_step(Vh[:k, :, r].T, W[:, r])
@@ -146,7 +151,7 @@ def test_orthogonalize_matches_mgs(n, k, S):
         assert np.allclose(Vg[k, :, r], vn, atol=1e-12)
     # complex64
     V32 = to_dev(Vh.reshape(k + 1, n * S).ravel(), "c64")
-    h32 = P.shk_orthogonalize(n, k, V32, to_dev(W.ravel(), "c64"), n_rhs=S)
+    h32 = P.shk_orthogonalize(n, k, V32, to_dev(W.ravel(), "c64"), n_rhs=S, ortho=og)
     for r in range(S):
         ho, hn, _ = mgs_step(Vh[:k, :, r].T, W[:, r])
         assert np.allclose(h32[r, :k], ho, atol=2e-5 * np.linalg.norm(W[:, r]))

@@ -100,6 +100,39 @@ def test_mg_whole_hierarchy_in_one_workgroup(shape, S):
         assert true <= 1e-6 * np.linalg.norm(V32[:, r]) * 1.01
 
 
+@pytest.mark.parametrize("shape,S", [((64, 64), 2), ((96, 80), 1), ((24, 20, 18), 1)])
+def test_mg_tail_two_levels_down(shape, S):
+    """Grids whose one-workgroup tail starts two or more levels down (grid
+    restriction and prolongation legs on the levels above it): iterates as the
+    oracle's (complex128), and the complex64 path meets its FP64 residual
+    target."""
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"mg tail two levels down {shape} S={S}")
+    K = _field(shape, 4)
+    op = OProblem.fv(K)
+    gp = _gpu_problem(P, K)
+    H = Hierarchy.of(op)
+    tau = 2j * np.pi / 250.0
+    rng = np.random.default_rng(13)
+    V = rng.normal(size=(op.n, S)) + 1j * rng.normal(size=(op.n, S))
+    for k in (1, 3, 8):
+        z = torch.zeros(op.n * S, dtype=torch.complex128, device="cuda")
+        P.shk_inner_solve(gp, tau, to_dev(V.ravel()), z, fixed_iters=k, n_rhs=S, precond=P.SHK_PRECOND_MULTIGRID)
+        Z = z.cpu().numpy().reshape(op.n, S)
+        for r in range(S):
+            xo, _, _, _ = mg_cocg(op, tau, V[:, r], 0.0, 100, H, fixed_iters=k)
+            assert np.allclose(Z[:, r], xo, rtol=0, atol=1e-9 * np.abs(xo).max()), (k, r)
+    V32 = V.astype(np.complex64).astype(np.complex128)
+    z = torch.zeros(op.n * S, dtype=torch.complex128, device="cuda")
+    its, pn = P.shk_inner_solve(gp, tau, to_dev(V32.ravel(), "c64"), z, eps=1e-6, n_rhs=S,
+                                precond=P.SHK_PRECOND_MULTIGRID)
+    Z = z.cpu().numpy().reshape(op.n, S)
+    for r in range(S):
+        true = np.linalg.norm(V32[:, r] - op.apply(tau, Z[:, r]))
+        assert true <= 1e-6 * np.linalg.norm(V32[:, r]) * 1.01
+
+
 def test_mg_rejected_for_csr():
     torch = require_gpu()
     import paper_1212_3660_amd as P

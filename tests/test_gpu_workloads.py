@@ -90,8 +90,12 @@ def test_server_alone_vs_mix():
     reqs = [synth.Request(i, 0.0, g, 1000 + i, nf, nr)
             for i, (g, nf, nr) in enumerate([(48, 7, 2), (64, 12, 1), (32, 5, 3), (48, 9, 4), (40, 6, 1)])]
     works = [synth.request_workload(r) for r in reqs]
-    params = [P.make_params(w.tau_seq, m_restart=40, tol=1e-6, eps_inner=1e-6, precision=P.SHK_MIXED, max_refine=4)
-              for w in works]
+    # requests with different options share the server: FOM projected problems,
+    # modified Gram-Schmidt, the multigrid inner solve, a relaxed inner tolerance
+    opts = [{}, dict(variant=P.SHK_FOM), dict(ortho=P.SHK_MGS), dict(inner_precond=P.SHK_PRECOND_MULTIGRID),
+            dict(inner_precond=P.SHK_PRECOND_MULTIGRID, inner_relax=0.1, variant=P.SHK_FOM)]
+    params = [P.make_params(w.tau_seq, m_restart=40, tol=1e-6, eps_inner=1e-6, precision=P.SHK_MIXED, max_refine=4,
+                            **o) for w, o in zip(works, opts)]
     alone = []
     for w, (prm, keep) in zip(works, params):
         gp = P.Problem.fv2d(w.cell_K, w.Ss, w.h)

@@ -159,11 +159,14 @@ def sensitivity_bench(P, torch, w, make, n_src=8, n_rec=8, reps=5):
     return out
 
 
-def time_batched(P, torch, w, make, precision, single_rhs_sample=0):
+def time_batched(P, torch, w, make, precision, single_rhs_sample=0, label=None):
     """One solve of a multi-rhs workload (all rhs in lockstep); with
     single_rhs_sample > 0, instead that many rhs solved one at a time and the
     rate scaled to all of them (multigrid-preconditioned inner solves).
-    Returns shifted solves/s and the worst true relative residual."""
+    Returns shifted solves/s and the worst true relative residual; with a
+    label, also the HBM roofline of one multigrid-COCG inner iteration at this
+    workload, from one more solve with the library's per-iteration events
+    (kept out of the timed solve)."""
     gp = make(w)
     prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
                               eps_inner=w.eps_inner, precision=precision, inner_precond=P.SHK_PRECOND_MULTIGRID)
@@ -184,9 +187,17 @@ def time_batched(P, torch, w, make, precision, single_rhs_sample=0):
         worst = max(worst, float(st["true_relres"].max()))
         ok &= bool((st["status"] == P.SHK_CONVERGED).all())
     solves = nf * (len(cols) if single_rhs_sample else nr)
+    out = {"solves_per_s": round(solves / total, 1), "ms": round(total * 1e3, 1), "converged": ok,
+           "max_true_relres": worst}
+    if label is not None:
+        P.shk_profile_enable(True)
+        P.fgmres_sh_solve(gp, prm, w.sigma, b)
+        torch.cuda.synchronize()
+        prof = P.shk_profile_read()
+        P.shk_profile_enable(False)
+        out["roofline_iteration"] = roofline(prof, "none", label, "iteration")
     gp.close()
-    return {"solves_per_s": round(solves / total, 1), "ms": round(total * 1e3, 1), "converged": ok,
-            "max_true_relres": worst}
+    return out
 
 
 def cpu_baseline(w, seconds, gpu_outer_steps):
@@ -334,16 +345,20 @@ def main():
         mk3 = lambda w: P.Problem.fv3d(w.cell_K, w.Ss, w.h)
         out["batched"] = {
             "2-D FV 256x256, 50 shifts, 64 rhs": {
-                "mixed_batched": time_batched(P, torch, w3, mk2, P.SHK_MIXED),
-                "fp64_batched": time_batched(P, torch, w3, mk2, P.SHK_FP64),
+                "mixed_batched": time_batched(P, torch, w3, mk2, P.SHK_MIXED,
+                                              label="multigrid-COCG inner iteration, 64 lanes, complex64"),
+                "fp64_batched": time_batched(P, torch, w3, mk2, P.SHK_FP64,
+                                             label="multigrid-COCG inner iteration, 64 lanes, complex128"),
                 "fp64_single_rhs": dict(time_batched(P, torch, w3, mk2, P.SHK_FP64, single_rhs_sample=4),
                                         sample="4 of the 64 rhs solved one at a time, rate over those")},
         }
         out["sensitivity"] = sensitivity_bench(P, torch, w3, mk2)
         w4 = synth.config4()
         out["batched"]["3-D FV 128^3, 100 shifts, 8 rhs"] = {
-            "mixed_batched": time_batched(P, torch, w4, mk3, P.SHK_MIXED),
-            "fp64_batched": time_batched(P, torch, w4, mk3, P.SHK_FP64)}
+            "mixed_batched": time_batched(P, torch, w4, mk3, P.SHK_MIXED,
+                                          label="multigrid-COCG inner iteration, 8 lanes, complex64"),
+            "fp64_batched": time_batched(P, torch, w4, mk3, P.SHK_FP64,
+                                         label="multigrid-COCG inner iteration, 8 lanes, complex128")}
     if not a.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, mixed["outer"])

@@ -273,6 +273,125 @@ __global__ void __launch_bounds__(BS) k_mg_up(Op op, LevelDims f, LevelDims c, c
   if (!flag) xout[((long)cell << lS) + rl] = v;
 }
 
+// The two legs for several right-hand sides: a thread works LT lanes of one
+// cell (down: of one child of a coarse cell) and loads the cell's stencil,
+// mass and D^-1 once for them instead of once per lane; per lane the
+// expressions of mg_down_fine and mg_up_cell.  Lane chunk lc holds lanes
+// lc LT .. lc LT + LT - 1; lNC = log2(S / LT).
+// Down: grid (ceil(c.nx 2^(lNC + d) / BS), c.ny, c.nz), the 2^d children of a
+// coarse cell (per chunk) in adjacent threads.
+template <typename Op, typename R, int LT>
+__global__ void __launch_bounds__(BS) k_mg_down_lanes(Op op, LevelDims f, LevelDims c, c128 tau, double omega,
+                                                      int lS, int lNC, const cx<R>* __restrict__ b,
+                                                      const cx<R>* __restrict__ dinv, cx<R>* __restrict__ out,
+                                                      const int* __restrict__ all_done) {
+  constexpr int D = Op::NB / 2;
+  constexpr int Q = 1 << D;
+  constexpr int NB = Op::NB;
+  int flag = *all_done;
+  int bx, J, L;
+  xcd_block3(bx, J, L);
+  const int t = bx * BS + threadIdx.x;
+  if (t >= (c.nx << (lNC + D))) return;   // whole groups of 2^d lanes leave together
+  const int q = t & (Q - 1), lc = (t >> D) & ((1 << lNC) - 1), I = t >> (D + lNC);
+  const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * L + (q >> 2);
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  cx<R> v[LT];
+#pragma unroll
+  for (int l = 0; l < LT; ++l) v[l] = cx<R>{0, 0};
+  if (i < f.nx && j < f.ny && k < f.nz) {
+    const int cell = i + f.nx * (j + f.ny * k);
+    int idx[NB];
+    R fo[NB];
+    R fsum;
+    op.template stencil_at<R>(i, j, k, cell, idx, fo, fsum);
+    const R m = (R)op.mass(cell);
+    const cx<R> dc = dinv[cell];
+    cx<R> dn[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) dn[e] = dinv[idx[e]];
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+      const int rl = lc * LT + l;
+      auto gb = [&](int n) { return b[((long)n << lS) + rl]; };
+      const cx<R> bi = gb(cell);
+      const cx<R> x1 = om * (dc * bi);
+      cx<R> ax = fsum * x1 + m * (tr * x1);
+#pragma unroll
+      for (int e = 0; e < NB; ++e) ax = ax - fo[e] * (om * (dn[e] * gb(idx[e])));
+      v[l] = bi - ax;
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < LT; ++l) v[l] = group_sum<Q>(v[l]);
+  hold(v[0], flag);
+  if (!flag && q == 0) {
+    cx<R>* o = out + ((long)(I + c.nx * (J + c.ny * L)) << lS) + lc * LT;
+#pragma unroll
+    for (int l = 0; l < LT; ++l) o[l] = v[l];
+  }
+}
+
+// Up: grid (ceil(f.nx 2^lNC / BS), f.ny, f.nz), thread t holds chunk
+// t mod 2^lNC of cell t >> lNC along a fine row.
+template <typename Op, typename R, int LT>
+__global__ void __launch_bounds__(BS) k_mg_up_lanes(Op op, LevelDims f, LevelDims cd, c128 tau, double omega, int lS,
+                                                    int lNC, const cx<R>* __restrict__ b,
+                                                    const cx<R>* __restrict__ dinv, const cx<R>* __restrict__ xc,
+                                                    cx<R>* __restrict__ xout, const int* __restrict__ all_done) {
+  constexpr int NB = Op::NB;
+  int flag = *all_done;
+  int bx, j, k;
+  xcd_block3(bx, j, k);
+  const int t = bx * BS + threadIdx.x;
+  if (t >= (f.nx << lNC)) return;
+  const int lc = t & ((1 << lNC) - 1), i = t >> lNC;
+  const int cell = i + f.nx * (j + f.ny * k);
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  int idx[NB];
+  R fo[NB];
+  R fsum;
+  op.template stencil_at<R>(i, j, k, cell, idx, fo, fsum);
+  const int pi = i >> 1, pj = j >> 1, pk = k >> 1;
+  auto par = [&](int a, int bb, int e) { return a + cd.nx * (bb + cd.ny * e); };
+  int pq[NB];
+  pq[0] = par((i > 0 ? i - 1 : i) >> 1, pj, pk);
+  pq[1] = par((i < f.nx - 1 ? i + 1 : i) >> 1, pj, pk);
+  pq[2] = par(pi, (j > 0 ? j - 1 : j) >> 1, pk);
+  pq[3] = par(pi, (j < f.ny - 1 ? j + 1 : j) >> 1, pk);
+  if constexpr (NB == 6) {
+    pq[4] = par(pi, pj, (k > 0 ? k - 1 : k) >> 1);
+    pq[5] = par(pi, pj, (k < f.nz - 1 ? k + 1 : k) >> 1);
+  }
+  const int pc = par(pi, pj, pk);
+  const R m = (R)op.mass(cell);
+  const cx<R> dc = dinv[cell];
+  cx<R> dn[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) dn[e] = dinv[idx[e]];
+  cx<R> v[LT];
+#pragma unroll
+  for (int l = 0; l < LT; ++l) {
+    const int rl = lc * LT + l;
+    auto gb = [&](int n) { return b[((long)n << lS) + rl]; };
+    auto gx = [&](int n) { return xc[((long)n << lS) + rl]; };
+    const cx<R> bc = gb(cell);
+    const cx<R> xi = om * (dc * bc) + gx(pc);
+    cx<R> ax = fsum * xi + m * (tr * xi);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) ax = ax - fo[e] * (om * (dn[e] * gb(idx[e])) + gx(pq[e]));
+    v[l] = xi + om * (dc * (bc - ax));
+  }
+  hold(v[0], flag);
+  if (!flag) {
+    cx<R>* o = xout + ((long)cell << lS) + lc * LT;
+#pragma unroll
+    for (int l = 0; l < LT; ++l) o[l] = v[l];
+  }
+}
+
 // The coarse end of the V-cycle in one workgroup: levels t..L-1 (right-hand
 // side of level t from global memory, solution of level t back to it), every
 // level's b and x in LDS, a barrier between legs.  Saves two launches per

@@ -734,6 +734,35 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   // uout = B b0 (one V-cycle over every level)
   // (from = 1: the finest restriction was done by the fused step kernel)
+  // Grid legs for several lanes: chunks of up to 8 lanes per thread.
+  template <int LT>
+  void mg_down_lt(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
+                  cx<R>* out) {
+    const int lNC = lS - ilog2(LT);
+    const dim3 g((unsigned)((((long)c.nx << (lNC + Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
+    k_mg_down_lanes<Op, R, LT><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, bl, dl, out,
+                                                 B.all_done);
+  }
+  void mg_down_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
+                     const cx<R>* dl, cx<R>* out) {
+    if (lS == 1) mg_down_lt<2>(l, f, c, tau, lS, bl, dl, out);
+    else if (lS == 2) mg_down_lt<4>(l, f, c, tau, lS, bl, dl, out);
+    else mg_down_lt<8>(l, f, c, tau, lS, bl, dl, out);
+  }
+  template <int LT>
+  void mg_up_lt(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
+                const cx<R>* xcoarse, cx<R>* out) {
+    const int lNC = lS - ilog2(LT);
+    const dim3 g((unsigned)((((long)f.nx << lNC) + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
+    k_mg_up_lanes<Op, R, LT><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, bl, dl, xcoarse,
+                                               out, B.all_done);
+  }
+  void mg_up_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
+                   const cx<R>* dl, const cx<R>* xcoarse, cx<R>* out) {
+    if (lS == 1) mg_up_lt<2>(l, f, c, tau, lS, bl, dl, xcoarse, out);
+    else if (lS == 2) mg_up_lt<4>(l, f, c, tau, lS, bl, dl, xcoarse, out);
+    else mg_up_lt<8>(l, f, c, tau, lS, bl, dl, xcoarse, out);
+  }
   void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout, int from = 0) {
     if constexpr (Op::NB > 0) {
       const int Lv = mg_levels();
@@ -744,9 +773,13 @@ template <typename R, typename Op, typename OpD> struct Group {
       for (int l = from; l < gdown; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
-        const dim3 g((unsigned)((((long)c.nx * S_ << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
-        k_mg_down<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl, dl, B.mb[l],
-                                            B.all_done);
+        if (lS > 0) {
+          mg_down_lanes(l, f, c, tau, lS, bl, dl, B.mb[l]);
+        } else {
+          const dim3 g((unsigned)((((long)c.nx * S_ << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
+          k_mg_down<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl, dl, B.mb[l],
+                                              B.all_done);
+        }
         bl = B.mb[l];
       }
       if (t < Lv) {
@@ -764,9 +797,13 @@ template <typename R, typename Op, typename OpD> struct Group {
         const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
         cx<R>* out = l == 0 ? uout : B.mx[l - 1];
-        const dim3 g((unsigned)(((long)f.nx * S_ + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
-        k_mg_up<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl2, dl, B.mx[l], out,
-                                          B.all_done);
+        if (lS > 0) {
+          mg_up_lanes(l, f, c, tau, lS, bl2, dl, B.mx[l], out);
+        } else {
+          const dim3 g((unsigned)(((long)f.nx * S_ + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
+          k_mg_up<Op, R><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, bl2, dl, B.mx[l], out,
+                                            B.all_done);
+        }
       }
     }
   }

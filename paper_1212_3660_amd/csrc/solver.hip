@@ -407,10 +407,13 @@ static void launch_givens(const GivensArgs& a, hipStream_t st) {
   else
     k_givens<<<(a.L + BS - 1) / BS, BS, 0, st>>>(a);
 }
-// Items per block of the Gram-Schmidt dot kernel: about 512 blocks (two per
-// CU), at least 256 items each.
+// Items per block of the Gram-Schmidt dot kernel (at least 256): about 512
+// blocks (two per CU) while the vectors are small and the launch is
+// latency-bound; about 2048 from 4 Mi items up, where the kernel streams and
+// needs more waves in flight.
 static long dot_ipb(long N) {
-  long ipb = (N + 511) / 512;
+  const long blocks = N >= (4L << 20) ? 2048 : 512;
+  long ipb = (N + blocks - 1) / blocks;
   ipb = std::max<long>(256, (ipb + 255) / 256 * 256);
   return ipb;
 }

@@ -209,6 +209,30 @@ __global__ void __launch_bounds__(BS) k_final_sqrt(const c128* __restrict__ part
   }
 }
 
+// The same with one block per lane (launch: S blocks), for many lanes: block
+// r sums lane r's G partials in a fixed order.
+template <int NV>
+__global__ void __launch_bounds__(BS) k_final_sqrt_lanes(const c128* __restrict__ part, int G, int S,
+                                                         double* __restrict__ out0, double* __restrict__ out1,
+                                                         c128* __restrict__ hcol) {
+  const int r = blockIdx.x;
+  c128 acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = c128{0.0, 0.0};
+  for (int b = threadIdx.x; b < G; b += BS) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = acc[q] + part[((size_t)b * NV + q) * S + r];
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = block_sum_all(acc[q]);
+  if (threadIdx.x == 0) {
+    const double a = sqrt(acc[0].re);
+    if (out0) out0[r] = a;
+    if (hcol) hcol[r] = c128{a, 0.0};
+    if (NV > 1 && out1) out1[r] = sqrt(acc[NV - 1].re);
+  }
+}
+
 // out = in / beta[r] converted to R (zero lanes stay zero).
 template <typename R>
 __global__ void __launch_bounds__(BS) k_scale_conv(const c128* __restrict__ in, long N, int S,

@@ -377,6 +377,15 @@ template <typename R> static void carve_mg(Carver& cv, Buffers<R>& b, const shk_
   b.mpack = cv.take<unsigned>(MG_TAIL_LDS / 4);
 }
 
+// Norms from block partials: one block for few lanes, one block per lane
+// from 4 lanes up (a single block would leave BS / S threads per lane).
+template <int NV>
+static void launch_final_sqrt(const c128* part, int G, int S, double* out0, double* out1, c128* hcol,
+                              hipStream_t st) {
+  if (S >= 4) k_final_sqrt_lanes<NV><<<S, BS, 0, st>>>(part, G, S, out0, out1, hcol);
+  else k_final_sqrt<NV><<<1, BS, 0, st>>>(part, G, S, out0, out1, hcol);
+}
+
 static int resid_grid(long n) { return grid_items(n, 256); }
 
 // X (+)= Z Y (Algorithm 4, x = Z y): Y staged in LDS when the block's JT
@@ -1024,7 +1033,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     if (mg && fixed <= 0) mg_hist_put(tau, snap->live);
     const int Gf = grid_items(N, 1024);
     k_cocg_finish<OpD, R><<<Gf, BS, 0, st>>>(opd, tau, n, S, v, z, B.W, B.part);
-    k_final_sqrt<2><<<1, BS, 0, st>>>(B.part, Gf, S, pn_out, B.mz, nullptr);
+    launch_final_sqrt<2>(B.part, Gf, S, pn_out, B.mz, nullptr, st);
     SHK_HIP(hipGetLastError());
     return SHK_OK;
   }
@@ -1036,7 +1045,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     const int Gu = (int)((N + (long)BS * GSQ - 1) / ((long)BS * GSQ));
     c128* Hk = B.H + (size_t)k * (m + 2) * S;
     gram_schmidt<R>(N, S, kc, B.V, w, Hk, B.h2, B.part, mgs, st);
-    k_final_sqrt<1><<<1, BS, 0, st>>>(B.part, Gu, S, B.hn, nullptr, Hk + (size_t)(k + 1) * S);
+    launch_final_sqrt<1>(B.part, Gu, S, B.hn, nullptr, Hk + (size_t)(k + 1) * S, st);
     k_scale_col<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, w, B.hn, B.mz, B.V + (size_t)(k + 1) * N);
     SHK_HIP(hipGetLastError());
     return SHK_OK;
@@ -1104,7 +1113,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     SHK_HIP(hipMemsetAsync(B.Yb, 0, sizeof(c128) * (size_t)L * m, st));
     const int Gn = grid_items(N, 1024);
     k_norm2<double><<<Gn, BS, 0, st>>>(rhs, N, S, B.part);
-    k_final_sqrt<1><<<1, BS, 0, st>>>(B.part, Gn, S, B.beta0, nullptr, nullptr);
+    launch_final_sqrt<1>(B.part, Gn, S, B.beta0, nullptr, nullptr, st);
     k_scale_conv<R><<<grid_items(N, 4096), BS, 0, st>>>(rhs, N, S, B.beta0, B.V);
     k_lanes_init<<<Lb, BS, 0, st>>>(L, S, s_real, B.beta0, B.ls, B.g);
     SHK_HIP(hipGetLastError());
@@ -1498,7 +1507,7 @@ int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precisio
     cx<R>* Vp = (cx<R>*)V;
     const int kc = k;
     gram_schmidt<R>(N, S, kc, Vp, (cx<R>*)w, b.H, b.h2, b.part, ortho == SHK_MGS, st);
-    k_final_sqrt<1><<<1, BS, 0, st>>>(b.part, (int)Gu, S, b.hn, nullptr, b.H + (size_t)kc * S);
+    launch_final_sqrt<1>(b.part, (int)Gu, S, b.hn, nullptr, b.H + (size_t)kc * S, st);
     k_scale_col<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, (const cx<R>*)w, b.hn, b.mz, Vp + (size_t)kc * N);
     SHK_HIP(hipGetLastError());
     std::vector<c128> hh((size_t)(k + 1) * S);

@@ -1440,6 +1440,39 @@ __global__ void __launch_bounds__(BS) k_resid(Op op, long n, int S, int nf, cons
   if (threadIdx.x == 0) part[((size_t)r * nf + j) * gridDim.x + blockIdx.x] = a;
 }
 
+// The same for JR shifts per block (blockIdx.y = block of JR shifts): with
+// several lanes b and rs are strided by S (one cache line per lane and cell),
+// so each cell's b, rs, faces and mass are loaded once for JR shifts.
+template <typename Op, int JR>
+__global__ void __launch_bounds__(BS) k_resid_jr(Op op, long n, int S, int nf, const c128* __restrict__ sigma,
+                                                 const c128* __restrict__ bint, const c128* __restrict__ X,
+                                                 const c128* __restrict__ rs, int mode, c128* __restrict__ part) {
+  const int j0 = blockIdx.y * JR, r = blockIdx.z;
+  const int nj = nf - j0 < JR ? nf - j0 : JR;
+  c128 a[JR];
+#pragma unroll
+  for (int q = 0; q < JR; ++q) a[q] = c128{0.0, 0.0};
+  for (long c = blockIdx.x * (long)BS + threadIdx.x; c < n; c += (long)gridDim.x * BS) {
+    const c128 bc = bint[c * S + r];
+    const c128 rc = mode == 0 ? c128{0.0, 0.0} : rs[c * S + r];
+#pragma unroll
+    for (int q = 0; q < JR; ++q) {
+      if (q < nj) {
+        const c128* xj = X + n * ((long)(j0 + q) + (long)nf * r);
+        auto g = [&](long cc) { return xj[cc]; };
+        const c128 res = bc - op.template apply<double>(c, sigma[j0 + q], g);
+        if (mode == 0) a[q].re += abs2(res);
+        else a[q] = a[q] + cdot(rc, res);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < JR; ++q) {
+    const c128 t = block_sum_all(a[q]);
+    if (q < nj && threadIdx.x == 0) part[((size_t)r * nf + j0 + q) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 // rows partial sums -> out[row] (fixed order), one block per row.
 __global__ void __launch_bounds__(BS) k_rows_reduce(const c128* __restrict__ part, int G, c128* __restrict__ out) {
   const size_t row = blockIdx.x;

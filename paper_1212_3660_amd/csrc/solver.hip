@@ -1197,8 +1197,13 @@ template <typename OpD>
 static int residual_rows(const OpD& opd, long n, int S, int s_real, int nf, const c128* sigma, const c128* bint,
                          const c128* X, const c128* rs, int mode, c128* rpart, c128* rrow, hipStream_t st) {
   const int Gr = resid_grid(n);
-  dim3 grid(Gr, nf, s_real);
-  k_resid<OpD><<<grid, BS, 0, st>>>(opd, n, S, nf, sigma, bint, X, rs, mode, rpart);
+  if (S >= 4) {
+    constexpr int JR = 8;
+    k_resid_jr<OpD, JR><<<dim3(Gr, (nf + JR - 1) / JR, s_real), BS, 0, st>>>(opd, n, S, nf, sigma, bint, X, rs, mode,
+                                                                          rpart);
+  } else {
+    k_resid<OpD><<<dim3(Gr, nf, s_real), BS, 0, st>>>(opd, n, S, nf, sigma, bint, X, rs, mode, rpart);
+  }
   k_rows_reduce<<<s_real * nf, BS, 0, st>>>(rpart, Gr, rrow);
   SHK_HIP(hipGetLastError());
   return SHK_OK;

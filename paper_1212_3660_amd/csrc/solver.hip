@@ -746,7 +746,10 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   // uout = B b0 (one V-cycle over every level)
   // (from = 1: the finest restriction was done by the fused step kernel)
-  // Grid legs for several lanes: chunks of up to 8 lanes per thread.
+  // Grid legs for several lanes: chunks of up to 8 lanes per thread on the
+  // complex64 path (measured faster there; the complex128 path keeps a lane
+  // per thread, which measured faster for it).
+  static constexpr bool lane_chunks = std::is_same<R, float>::value;
   template <int LT>
   void mg_down_lt(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
                   cx<R>* out) {
@@ -785,7 +788,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       for (int l = from; l < gdown; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
-        if (lS > 0) {
+        if (lS > 0 && lane_chunks) {
           mg_down_lanes(l, f, c, tau, lS, bl, dl, B.mb[l]);
         } else {
           const dim3 g((unsigned)((((long)c.nx * S_ << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
@@ -809,7 +812,7 @@ template <typename R, typename Op, typename OpD> struct Group {
         const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
         cx<R>* out = l == 0 ? uout : B.mx[l - 1];
-        if (lS > 0) {
+        if (lS > 0 && lane_chunks) {
           mg_up_lanes(l, f, c, tau, lS, bl2, dl, B.mx[l], out);
         } else {
           const dim3 g((unsigned)(((long)f.nx * S_ + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);

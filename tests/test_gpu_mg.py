@@ -133,6 +133,39 @@ def test_mg_tail_two_levels_down(shape, S):
         assert true <= 1e-6 * np.linalg.norm(V32[:, r]) * 1.01
 
 
+@pytest.mark.parametrize("shape,S", [((40, 36), 8), ((24, 20), 16), ((12, 10, 9), 4)])
+def test_mg_complex64_lanes_iterates(shape, S):
+    """Complex64 path with several lanes (grid legs working chunks of up to 8
+    lanes per thread): fixed iteration counts against the oracle's FP64
+    iterates, to complex64 accuracy; a lane or chunk mixed up would be off by
+    O(1).  One iteration (the V-cycle's output scaled) agrees to ~1e-6 of the
+    largest entry; after a few, COCG can amplify single-precision rounding
+    for some vectors (3e-4 seen for one of these on the single-lane path
+    too), hence the looser bound there."""
+    torch = require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"mg c64 lanes {shape} S={S}")
+    K = _field(shape, 5)
+    op = OProblem.fv(K)
+    gp = _gpu_problem(P, K)
+    H = Hierarchy.of(op)
+    tau = 2j * np.pi / 400.0
+    rng = np.random.default_rng(17)
+    V = (rng.normal(size=(op.n, S)) + 1j * rng.normal(size=(op.n, S))).astype(np.complex64).astype(np.complex128)
+    def run(Vs, k):
+        s_ = Vs.shape[1]
+        z = torch.zeros(op.n * s_, dtype=torch.complex128, device="cuda")
+        P.shk_inner_solve(gp, tau, to_dev(np.ascontiguousarray(Vs).ravel(), "c64"), z, fixed_iters=k, n_rhs=s_,
+                          precond=P.SHK_PRECOND_MULTIGRID)
+        return z.cpu().numpy().reshape(op.n, s_)
+
+    for k, tol in ((1, 2e-5), (3, 1e-3)):
+        Z = run(V, k)
+        for r in range(S):
+            xo, _, _, _ = mg_cocg(op, tau, V[:, r], 0.0, 100, H, fixed_iters=k)
+            assert np.allclose(Z[:, r], xo, rtol=0, atol=tol * np.abs(xo).max()), (k, r)
+
+
 def test_mg_rejected_for_csr():
     torch = require_gpu()
     import paper_1212_3660_amd as P

@@ -1357,6 +1357,55 @@ __global__ void __launch_bounds__(BS) k_assemble(long n, int S, int s_real, int 
   }
 }
 
+// Y transposed for the product when it is read straight from memory with
+// several lanes: Yt[(j m + i) S + r] = Yb[(j S + r) m + i] for i < kc, so the
+// lanes of one (shift, column) are contiguous.
+__global__ void __launch_bounds__(BS) k_y_transpose(int S, int nf, int kc, int m, const c128* __restrict__ Yb,
+                                                    c128* __restrict__ Yt) {
+  const long total = (long)nf * kc * S;
+  for (long e = blockIdx.x * (long)BS + threadIdx.x; e < total; e += (long)gridDim.x * BS) {
+    const int r = (int)(e % S);
+    const long ji = e / S;
+    const int i = (int)(ji % kc), j = (int)(ji / kc);
+    Yt[((long)j * m + i) * S + r] = Yb[((long)j * S + r) * m + i];
+  }
+}
+
+// The product with Y in that layout (several lanes, Y too large for LDS).
+template <typename R>
+__global__ void __launch_bounds__(BS) k_assemble_t(long n, int S, int s_real, int nf, int kc, int m,
+                                                   const cx<R>* __restrict__ Z, size_t cstride,
+                                                   const c128* __restrict__ Yt, const c128* __restrict__ ascale,
+                                                   c128* __restrict__ X, int accumulate) {
+  const long N = n * S;
+  const int j0 = blockIdx.y * JT;
+  const int r = threadIdx.x & (S - 1);
+  if (r >= s_real) return;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
+    const long c = t / S;
+    c128 acc[JT];
+#pragma unroll
+    for (int q = 0; q < JT; ++q) acc[q] = c128{0.0, 0.0};
+    for (int i = 0; i < kc; ++i) {
+      const c128 z = cvt<double>(Z[(size_t)i * cstride + t]);
+#pragma unroll
+      for (int q = 0; q < JT; ++q) {
+        const int j = j0 + q < nf ? j0 + q : nf - 1;
+        acc[q] = acc[q] + z * Yt[((size_t)j * m + i) * S + r];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < JT; ++q) {
+      const int j = j0 + q;
+      if (j < nf) {
+        const c128 v = ascale[(size_t)j * S + r] * acc[q];
+        c128* dst = X + c + n * ((long)j + (long)nf * r);
+        *dst = accumulate ? *dst + v : v;
+      }
+    }
+  }
+}
+
 // The same product with the block's JT columns of Y (every rhs lane, kc rows)
 // staged once in LDS at ys[(i JT + q) S + lane] instead of being reloaded for
 // every item; each thread accumulates two items, t and t + BS, per LDS read.

@@ -353,7 +353,7 @@ template <typename R> struct Buffers {
   double* qmax;           // per rhs: largest relative quasi-residual of the running lanes
   LaneState* ls;
   double* rc;
-  c128 *rs, *g, *Rp, *Yb, *ascale, *extra;
+  c128 *rs, *g, *Rp, *Yb, *Yt, *ascale, *extra;
   c128 *bint, *rsv, *X;
   c128* rpart;      // residual partials [s][nf][Gr]
   c128* rrow;       // residual rows [s*nf]
@@ -392,12 +392,17 @@ static int resid_grid(long n) { return grid_items(n, 256); }
 // columns for every rhs lane fit in 64 KB, else read per item.
 template <typename R>
 static void launch_assemble(long n, int S, int s_real, int nf, int kc, int m, const cx<R>* Z, size_t cstride,
-                            const c128* Yb, const c128* ascale, c128* X, int acc, hipStream_t st) {
+                            const c128* Yb, const c128* ascale, c128* X, int acc, hipStream_t st,
+                            c128* Yt = nullptr) {
   const long N = n * S;
   const size_t lds = (size_t)kc * JT * S * sizeof(c128);
   if (lds <= 65536) {
     dim3 grid(grid_items((N + 1) / 2, 4096), (nf + JT - 1) / JT);
     k_assemble_lds<R><<<grid, BS, lds, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);
+  } else if (Yt && S > 1) {
+    k_y_transpose<<<grid_items((long)nf * kc * S, 1024), BS, 0, st>>>(S, nf, kc, m, Yb, Yt);
+    dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
+    k_assemble_t<R><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yt, ascale, X, acc);
   } else {
     dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
     k_assemble<R><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);
@@ -502,6 +507,7 @@ static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, 
   b.g = cv.take<c128>((size_t)(m + 1) * L);
   b.Rp = cv.take<c128>((size_t)m * (m + 1) / 2 * L);
   b.Yb = cv.take<c128>((size_t)L * m);
+  b.Yt = S > 1 ? cv.take<c128>((size_t)L * m) : nullptr;
   b.ascale = cv.take<c128>(L);
   b.extra = cv.take<c128>(L);
   b.bint = cv.take<c128>(N);
@@ -1104,7 +1110,8 @@ template <typename R, typename Op, typename OpD> struct Group {
   int assemble(int kc, int cycle, const c128* extra, c128* X, bool accumulate) {
     const int Lb = (L + BS - 1) / BS;
     k_asm_scale<<<Lb, BS, 0, st>>>(L, cycle, B.ls, extra, B.ascale);
-    launch_assemble<double>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X, accumulate ? 1 : 0, st);
+    launch_assemble<double>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X, accumulate ? 1 : 0, st,
+                            B.Yt);
     SHK_HIP(hipGetLastError());
     return SHK_OK;
   }

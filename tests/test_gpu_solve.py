@@ -207,3 +207,29 @@ def test_mgs_orthogonalisation_solve_matches_oracle():
     bad, keep2 = _params(P, w, ortho=5)
     with pytest.raises(P.ShkError):
         P.fgmres_sh_solve(gp, bad, w.sigma, w.b)
+
+
+@pytest.mark.parametrize("variant", ["gmres", "fom"])
+def test_long_bases_on_both_least_squares_kernels(variant):
+    # restart length 64 (a wave per (shift, rhs) lane) and 65 (a thread per
+    # lane): both reach the direct solutions and agree with each other
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce(f"m=64/65 {variant}")
+    K = synth.cell_conductivity((40, 36), -11.5, 1.0, 5, cfg=73)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(9, 5, 3000))
+    b = synth.unit_vector(op.n, 700)
+    v = P.SHK_FOM if variant == "fom" else P.SHK_GMRES
+    xe = exact_family(op, sig, b, "banded")
+    xs = []
+    for m in (64, 65):
+        prm, keep = P.make_params(sig[[1, 4, 7]], tol=1e-9, eps_inner=1e-12, m_restart=m, max_restarts=10,
+                                  max_refine=2, variant=v)
+        x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+        assert np.all(st["status"] == P.SHK_CONVERGED) and np.all(st["true_relres"] <= 1e-9), m
+        for j in range(len(sig)):
+            assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= 2e3 * 1e-9 * np.linalg.norm(xe[:, j]), (m, j)
+        xs.append(x)
+    assert np.allclose(xs[0], xs[1], rtol=0, atol=1e-6 * np.abs(xs[0]).max())

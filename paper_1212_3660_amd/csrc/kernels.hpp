@@ -1371,36 +1371,52 @@ __global__ void __launch_bounds__(BS) k_y_transpose(int S, int nf, int kc, int m
   }
 }
 
-// The product with Y in that layout (several lanes, Y too large for LDS).
-template <typename R>
-__global__ void __launch_bounds__(BS) k_assemble_t(long n, int S, int s_real, int nf, int kc, int m,
-                                                   const cx<R>* __restrict__ Z, size_t cstride,
-                                                   const c128* __restrict__ Yt, const c128* __restrict__ ascale,
-                                                   c128* __restrict__ X, int accumulate) {
-  const long N = n * S;
-  const int j0 = blockIdx.y * JT;
-  const int r = threadIdx.x & (S - 1);
-  if (r >= s_real) return;
-  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < N; t += (long)gridDim.x * BS) {
-    const long c = t / S;
-    c128 acc[JT];
+// The product with Y in that layout (several lanes, Y too large for LDS),
+// register-blocked: a thread takes CT consecutive cells of one lane and JQ
+// shifts, so each Y entry it loads serves CT cells and its X stores are CT
+// contiguous entries.  Launch grid (items, ceil(nf / JQ)); lS = log2 S.
+template <typename R, int CT, int JQ>
+__global__ void __launch_bounds__(BS) k_assemble_rb(long n, int S, int lS, int s_real, int nf, int kc, int m,
+                                                    const cx<R>* __restrict__ Z, size_t cstride,
+                                                    const c128* __restrict__ Yt, const c128* __restrict__ ascale,
+                                                    c128* __restrict__ X, int accumulate) {
+  const long groups = (n + CT - 1) / CT;
+  const long T = groups << lS;
+  const int j0 = blockIdx.y * JQ;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < T; t += (long)gridDim.x * BS) {
+    const int r = (int)(t & (S - 1));
+    if (r >= s_real) continue;
+    const long c0 = (t >> lS) * CT;
+    c128 acc[CT][JQ];
 #pragma unroll
-    for (int q = 0; q < JT; ++q) acc[q] = c128{0.0, 0.0};
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int q = 0; q < JQ; ++q) acc[ct][q] = c128{0.0, 0.0};
     for (int i = 0; i < kc; ++i) {
-      const c128 z = cvt<double>(Z[(size_t)i * cstride + t]);
+      c128 z[CT];
 #pragma unroll
-      for (int q = 0; q < JT; ++q) {
+      for (int ct = 0; ct < CT; ++ct)
+        z[ct] = c0 + ct < n ? cvt<double>(Z[(size_t)i * cstride + (size_t)(c0 + ct) * S + r]) : c128{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < JQ; ++q) {
         const int j = j0 + q < nf ? j0 + q : nf - 1;
-        acc[q] = acc[q] + z * Yt[((size_t)j * m + i) * S + r];
+        const c128 y = Yt[((size_t)j * m + i) * S + r];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ct][q] = acc[ct][q] + z[ct] * y;
       }
     }
 #pragma unroll
-    for (int q = 0; q < JT; ++q) {
+    for (int q = 0; q < JQ; ++q) {
       const int j = j0 + q;
-      if (j < nf) {
-        const c128 v = ascale[(size_t)j * S + r] * acc[q];
-        c128* dst = X + c + n * ((long)j + (long)nf * r);
-        *dst = accumulate ? *dst + v : v;
+      if (j >= nf) break;
+      const c128 sc = ascale[(size_t)j * S + r];
+      c128* col = X + n * ((long)j + (long)nf * r);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        if (c0 + ct < n) {
+          const c128 v = sc * acc[ct][q];
+          col[c0 + ct] = accumulate ? col[c0 + ct] + v : v;
+        }
       }
     }
   }

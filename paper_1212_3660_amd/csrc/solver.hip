@@ -401,8 +401,11 @@ static void launch_assemble(long n, int S, int s_real, int nf, int kc, int m, co
     k_assemble_lds<R><<<grid, BS, lds, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);
   } else if (Yt && S > 1) {
     k_y_transpose<<<grid_items((long)nf * kc * S, 1024), BS, 0, st>>>(S, nf, kc, m, Yb, Yt);
-    dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
-    k_assemble_t<R><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yt, ascale, X, acc);
+    constexpr int CT = 4, JQ = 8;
+    int lS = 0;
+    while ((1 << lS) < S) ++lS;
+    dim3 grid(grid_items((n + CT - 1) / CT * S, 4096), (nf + JQ - 1) / JQ);
+    k_assemble_rb<R, CT, JQ><<<grid, BS, 0, st>>>(n, S, lS, s_real, nf, kc, m, Z, cstride, Yt, ascale, X, acc);
   } else {
     dim3 grid(grid_items(N, 4096), (nf + JT - 1) / JT);
     k_assemble<R><<<grid, BS, 0, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);

@@ -38,3 +38,23 @@ def test_relax_zero_is_the_default():
     a = fgmres_sh(op, b, sig, sig[[3, 9]], m_restart=30, tol=1e-7, eps=1e-9)
     c = fgmres_sh(op, b, sig, sig[[3, 9]], m_restart=30, tol=1e-7, eps=1e-9, relax=0.0)
     assert np.array_equal(a.x, c.x) and a.inner_its == c.inner_its
+
+
+def test_relaxed_run_keeps_the_gap_bound_of_eq_resdiff():
+    # eq. resdiff holds with the inner residuals a relaxed run actually had:
+    # ||r - r~|| <= sum |y_k| ||p_k|| (||v_k|| = 1); and the relaxation did
+    # loosen them: the first inner solve meets eps, later ones are orders of
+    # magnitude looser, none beyond eps_max
+    op, sig, b = _setup()
+    eps, emax = 1e-10, 1e-2
+    r = fgmres_sh(op, b, sig, sig[[2, 6, 10]], m_restart=60, max_restarts=0, tol=1e-8, inner="cocg", eps=eps,
+                  relax=0.1, eps_max=emax, keep_basis=True)
+    pn = r.pnorms
+    assert pn[0] <= 10 * eps
+    assert pn.max() > 1e4 * eps
+    assert np.all(pn <= 2 * emax)
+    for j, (y, qv) in r.y_last.items():
+        k = len(y)
+        true = b - op.apply(sig[j], r.Z[:, :k] @ y)
+        inexact = r.V[:, :k + 1] @ qv
+        assert np.linalg.norm(true - inexact) <= np.sum(np.abs(y) * pn[:k]) * (1 + 1e-9) + 1e-14, j

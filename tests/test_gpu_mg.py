@@ -222,12 +222,21 @@ def test_relaxed_inner_tolerance(precision):
                                   inner_precond=P.SHK_PRECOND_MULTIGRID, inner_relax=relax, inner_eps_max=1e-2)
         x, st = P.fgmres_sh_solve(gp, prm, sig, b)
         assert np.all(st["true_relres"] <= tol)
-        runs[relax] = (x, int(st["inner_its"].max()))
-    x, its = runs[0.1]
+        runs[relax] = (x, int(st["inner_its"].max()), st)
+    x, its, st = runs[0.1]
     assert its < runs[0.0][1], (its, runs[0.0][1])
     xe = exact_family(op, sig, b, "superlu")
     for j in range(len(sig)):
         assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= tol / (abs(sig[j]) * 1e-5) * (1 + 1e-6)
+    if precision == "fp64":
+        # the oracle's relaxed run (same rule for eps_k, multigrid inner solve):
+        # the same outer step counts within two
+        from oracle import fgmres_sh
+        ro = fgmres_sh(op, b, sig, sig[[2, 5, 8]], m_restart=50, tol=tol, inner="mg", eps=eps, relax=0.1,
+                       eps_max=1e-2)
+        for j in range(len(sig)):
+            assert abs(int(st[0, j]["outer_its"]) - ro.info[j].outer_its) <= 2, (j, int(st[0, j]["outer_its"]),
+                                                                               ro.info[j].outer_its)
 
 
 def test_relaxed_tolerance_rejects_bad_parameters():

@@ -170,3 +170,9 @@ def test_fom_and_gmres_agree_with_multigrid_inner():
             for j in range(len(sig)):
                 assert st[r, j]["status"] == P.SHK_CONVERGED and st[r, j]["true_relres"] <= 1e-8, (v, r, j)
                 assert np.linalg.norm(x[:, j, r] - xe[:, j]) <= 2e3 * 1e-8 * np.linalg.norm(xe[:, j])
+        # the oracle's FOM run with the multigrid inner solve: outer steps within two
+        ro = fgmres_sh(op, B[:, r], sig, taus, m_restart=40, max_restarts=10, tol=1e-8, inner="mg", eps=1e-10,
+                       variant="fom")
+        st = out[P.SHK_FOM][1]
+        for j in range(len(sig)):
+            assert abs(int(st[r, j]["outer_its"]) - ro.info[j].outer_its) <= 2, (r, j)

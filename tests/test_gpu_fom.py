@@ -176,3 +176,26 @@ def test_fom_and_gmres_agree_with_multigrid_inner():
         st = out[P.SHK_FOM][1]
         for j in range(len(sig)):
             assert abs(int(st[r, j]["outer_its"]) - ro.info[j].outer_its) <= 2, (r, j)
+
+
+def test_fom_restarts_with_several_rhs():
+    # three right-hand sides in lockstep, restart length 6: each lane restarts
+    # from its own v_{m+1} with its own residual coefficient
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("fom restarts 3 rhs")
+    K = synth.cell_conductivity((30, 26), -11.5, 1.0, 5, cfg=74)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(7, 10, 1000))
+    B = np.stack([synth.unit_vector(op.n, c) for c in (100, 390, 611)], axis=1)
+    taus = 2j * np.pi / np.array([20.0, 500.0])
+    prm, keep = P.make_params(taus, tol=1e-9, eps_inner=1e-12, m_restart=6, max_restarts=80, max_refine=2,
+                              variant=P.SHK_FOM)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, B)
+    assert st["restarts"].max() >= 1
+    for r in range(B.shape[1]):
+        xe = exact_family(op, sig, B[:, r], "banded")
+        for j in range(len(sig)):
+            assert st[r, j]["status"] == P.SHK_CONVERGED and st[r, j]["true_relres"] <= 1e-9, (r, j)
+            assert np.linalg.norm(x[:, j, r] - xe[:, j]) <= 2e3 * 1e-9 * np.linalg.norm(xe[:, j]), (r, j)

@@ -233,3 +233,42 @@ def test_long_bases_on_both_least_squares_kernels(variant):
             assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= 2e3 * 1e-9 * np.linalg.norm(xe[:, j]), (m, j)
         xs.append(x)
     assert np.allclose(xs[0], xs[1], rtol=0, atol=1e-6 * np.abs(xs[0]).max())
+
+
+def test_paper_style_blocked_log_tau_schedule():
+    # section 2.2.1 / 6.1: n_p = 5 preconditioners log-spaced over the frequency
+    # range, each used for a block of m / n_p steps, cycled; every shift
+    # converges to the direct solution
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("blocked log tau")
+    K = synth.cell_conductivity((20, 20), -11.5, 1.0, 5, cfg=75)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(20, 3.0, 600.0))
+    taus = synth.blocked_tau(synth.log_spaced_tau(2 * np.pi / 600, 2 * np.pi / 3, 5), 40)
+    b = synth.unit_vector(op.n, 210)
+    prm, keep = P.make_params(taus, tol=1e-10, eps_inner=1e-13, m_restart=40, max_restarts=20, max_refine=2)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    xe = exact_family(op, sig, b, "banded")
+    for j in range(len(sig)):
+        assert st[0, j]["status"] == P.SHK_CONVERGED and st[0, j]["true_relres"] <= 1e-10, (j, st[0, j])
+        assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= 2e3 * 1e-10 * np.linalg.norm(xe[:, j]), j
+
+
+def test_single_tau_equal_to_a_shift_converges_in_one_step():
+    # Hbar(tau;T) = [I;0] when sigma = tau (eq. shiftedarnoldimod): that shift
+    # is exact after one outer step, and shifts far from tau need the most
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("sigma = tau")
+    K = synth.cell_conductivity((20, 20), -11.5, 1.0, 5, cfg=76)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(9, 3.0, 3000.0))
+    b = synth.unit_vector(K.size, 210)
+    prm, keep = P.make_params(sig[[4]], tol=1e-9, eps_inner=1e-13, m_restart=150, max_restarts=2, max_refine=2)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    its = np.array([int(st[0, j]["outer_its"]) for j in range(len(sig))])
+    assert its[4] == its.min() == 1, its
+    assert its[0] > its[3] and its[8] > its[5], its
+    assert np.all(st["true_relres"] <= 1e-9)

@@ -272,3 +272,46 @@ def test_single_tau_equal_to_a_shift_converges_in_one_step():
     assert its[4] == its.min() == 1, its
     assert its[0] > its[3] and its[8] > its[5], its
     assert np.all(st["true_relres"] <= 1e-9)
+
+
+def test_csr_problem_matches_the_1d_greens_function():
+    # a general (CSR) problem: the 1-D homogeneous operator, whose inverse is
+    # the closed-form discrete Green's function (K0/h) G
+    require_gpu()
+    import paper_1212_3660_amd as P
+    from oracle import green_1d
+    announce("csr 1-D green")
+    N, K0, Ss = 300, 1e-5, 1e-5
+    op = OProblem.fv(np.full((N,), K0), Ss)
+    A = op.K.tocsr()
+    gp = P.Problem.csr(A.indptr, A.indices, A.data, op.Mdiag)
+    sig = synth.shifts_from_periods(synth.periods(6, 10, 1000))
+    b = synth.unit_vector(N, 123)
+    prm, keep = P.make_params(sig[[1, 4]], tol=1e-10, eps_inner=1e-13, m_restart=60, max_restarts=20, max_refine=2)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    for j, s_ in enumerate(sig):
+        xe = green_1d(N, K0, Ss, 1.0, s_) @ b
+        assert st[0, j]["status"] == P.SHK_CONVERGED and st[0, j]["true_relres"] <= 1e-10, (j, st[0, j])
+        assert np.linalg.norm(x[:, j, 0] - xe) <= 1e-10 / (abs(s_) * Ss) * np.linalg.norm(b) * 1.01, j
+
+
+def test_csr_problem_with_identity_mass():
+    # M = I turns the family into (K + sigma_j I) x_j = b, the shifted systems
+    # the flexible method generalises; against a dense solve of each
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("csr identity mass")
+    K = synth.cell_conductivity((18, 15), -11.5, 1.0, 5, cfg=77)
+    op = OProblem.fv(K)
+    A = (op.K * 1e5).tocsr()                  # scale so that the shifts below sit inside its spectrum
+    n = A.shape[0]
+    gp = P.Problem.csr(A.indptr, A.indices, A.data, np.ones(n))
+    sig = 1j * np.array([0.05, 0.2, 1.0, 4.0])
+    b = synth.unit_vector(n, 140)
+    prm, keep = P.make_params(sig[[0, 2]], tol=1e-10, eps_inner=1e-13, m_restart=80, max_restarts=20, max_refine=2)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    Ad = A.toarray().astype(complex)
+    for j, s_ in enumerate(sig):
+        xe = np.linalg.solve(Ad + s_ * np.eye(n), b)
+        assert st[0, j]["status"] == P.SHK_CONVERGED and st[0, j]["true_relres"] <= 1e-10, (j, st[0, j])
+        assert np.linalg.norm(x[:, j, 0] - xe) <= 1e-10 / abs(s_) * np.linalg.norm(b) * 1.01, j

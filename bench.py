@@ -246,6 +246,9 @@ def main():
                     help="inner preconditioner of --single-solve")
     ap.add_argument("--sensitivity-only", action="store_true",
                     help="run only the sensitivity measurement of the 256x256 workload and exit (profiler passes)")
+    ap.add_argument("--batched-only", choices=["2d", "3d"], default=None,
+                    help="run only the mixed batched 256x256 x 64 rhs (2d) or 128^3 x 8 rhs (3d) workload and "
+                         "exit (profiler passes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device-to-device with a plain copy kernel and exit "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -258,6 +261,14 @@ def main():
     import paper_1212_3660_amd as P
     import synth
     torch.cuda.set_device(0)
+    if a.batched_only:
+        if a.batched_only == "2d":
+            wb, mk, name = synth.config3(), (lambda w: P.Problem.fv2d(w.cell_K, w.Ss, w.h)), "2-D FV 256x256, 64 rhs"
+        else:
+            wb, mk, name = synth.config4(), (lambda w: P.Problem.fv3d(w.cell_K, w.Ss, w.h)), "3-D FV 128^3, 8 rhs"
+        r = time_batched(P, torch, wb, mk, P.SHK_MIXED, label=f"multigrid-COCG inner iteration, {name}, complex64")
+        print(json.dumps({"workload": name, **r}), flush=True)
+        return
     if a.copy_calibration:
         src = torch.ones(a.copy_calibration << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -315,3 +315,44 @@ def test_csr_problem_with_identity_mass():
         xe = np.linalg.solve(Ad + s_ * np.eye(n), b)
         assert st[0, j]["status"] == P.SHK_CONVERGED and st[0, j]["true_relres"] <= 1e-10, (j, st[0, j])
         assert np.linalg.norm(x[:, j, 0] - xe) <= 1e-10 / abs(s_) * np.linalg.norm(b) * 1.01, j
+
+
+def test_maximum_restart_length():
+    # m_restart = 400, the largest accepted: the basis, the packed factors and
+    # the thread-per-lane least squares at full length; 401 is a call error
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("m = 400")
+    K = synth.cell_conductivity((30, 28), -11.5, 1.0, 5, cfg=78)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(8, 5, 3000))
+    b = synth.unit_vector(op.n, 333)
+    prm, keep = P.make_params(sig[[3]], tol=1e-10, eps_inner=1e-13, m_restart=400, max_restarts=2, max_refine=2)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    xe = exact_family(op, sig, b, "banded")
+    for j in range(len(sig)):
+        assert st[0, j]["status"] == P.SHK_CONVERGED and st[0, j]["true_relres"] <= 1e-10, (j, st[0, j])
+        assert np.linalg.norm(x[:, j, 0] - xe[:, j]) <= 2e3 * 1e-10 * np.linalg.norm(xe[:, j]), j
+    bad, keep2 = P.make_params(sig[[3]], tol=1e-10, m_restart=401)
+    with pytest.raises(P.ShkError):
+        P.fgmres_sh_solve(gp, bad, sig, b)
+
+
+def test_two_thousand_shifts():
+    # a large shift family (2000 periods from 2 s to 20000 s) from one basis
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("2000 shifts")
+    K = synth.cell_conductivity((24, 22), -11.5, 1.0, 5, cfg=79)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(2000, 2.0, 20000.0))
+    b = synth.unit_vector(op.n, 250)
+    prm, keep = P.make_params(sig[[200, 1000, 1800]], tol=1e-9, eps_inner=1e-12, m_restart=30, max_restarts=40,
+                              max_refine=2)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, b)
+    assert np.all(st["status"] == P.SHK_CONVERGED) and np.all(st["true_relres"] <= 1e-9)
+    for j in (0, 777, 1999):
+        xe = exact_family(op, sig[[j]], b, "banded")[:, 0]
+        assert np.linalg.norm(x[:, j, 0] - xe) <= 2e3 * 1e-9 * np.linalg.norm(xe), j

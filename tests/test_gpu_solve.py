@@ -356,3 +356,27 @@ def test_two_thousand_shifts():
     for j in (0, 777, 1999):
         xe = exact_family(op, sig[[j]], b, "banded")[:, 0]
         assert np.linalg.norm(x[:, j, 0] - xe) <= 2e3 * 1e-9 * np.linalg.norm(xe), j
+
+
+def test_more_right_hand_sides_than_one_group():
+    # 66 right-hand sides: a group of 64 lanes, then a group of 2 in the same
+    # workspace; every (shift, rhs) converged, the second group's solutions the
+    # direct ones
+    require_gpu()
+    import paper_1212_3660_amd as P
+    announce("66 rhs")
+    K = synth.cell_conductivity((16, 14), -11.5, 1.0, 5, cfg=80)
+    op = OProblem.fv(K)
+    gp = P.Problem.fv2d(K)
+    sig = synth.shifts_from_periods(synth.periods(5, 10, 1000))
+    B = np.zeros((op.n, 66), complex)
+    for r in range(66):
+        B[(37 * r + 11) % op.n, r] = 1.0
+    prm, keep = P.make_params(sig[[1, 3]], tol=1e-9, eps_inner=1e-12, m_restart=60, max_restarts=10, max_refine=2)
+    x, st = P.fgmres_sh_solve(gp, prm, sig, B)
+    assert x.shape == (op.n, len(sig), 66) and st.shape == (66, len(sig))
+    assert np.all(st["status"] == P.SHK_CONVERGED) and np.all(st["true_relres"] <= 1e-9)
+    for r in (0, 63, 64, 65):
+        xe = exact_family(op, sig, B[:, r], "banded")
+        for j in range(len(sig)):
+            assert np.linalg.norm(x[:, j, r] - xe[:, j]) <= 2e3 * 1e-9 * np.linalg.norm(xe[:, j]), (r, j)

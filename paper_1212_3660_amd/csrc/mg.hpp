@@ -798,4 +798,85 @@ __global__ void __launch_bounds__(CGB) k_cgmg_post(Op op, c128 tau, int n, int l
   block_partials<3, CGB>(acc, S, partOut + (size_t)blockIdx.x * 3 * S);
 }
 
+// k_cgmg_post with a thread per (cell, chunk of LT lanes): the stencil, the
+// cell mass and the done flags are loaded once for LT lanes.  Same grid and
+// partial layout [block][3][S]; item t is chunk t mod 2^lC (lC = lS - log2 LT)
+// of cell t >> lC, and since the grid stride is a multiple of 2^lC a thread
+// keeps its chunk.  Block partials: a strided wave sum per (form, lane) over
+// the threads of one chunk, then the waves in order.
+template <typename Op, typename R, int CGB, int LT>
+__global__ void __launch_bounds__(CGB) k_cgmg_post_lanes(Op op, c128 tau, int n, int lS,
+                                                         const CgScal* __restrict__ sc, const cx<R>* __restrict__ r,
+                                                         const cx<R>* __restrict__ u, cx<R>* __restrict__ w,
+                                                         c128* __restrict__ partOut, const int* __restrict__ all_done) {
+  constexpr int NB = Op::NB;
+  constexpr int NW = CGB / WAVE;
+  constexpr int LLT = LT == 2 ? 1 : LT == 4 ? 2 : 3;
+  const int S = 1 << lS, lC = lS - LLT, C = 1 << lC;
+  const int ch = (int)threadIdx.x & (C - 1);
+  const long items = (long)n << lC;
+  bool live[LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) live[j] = !sc[ch * LT + j].done;
+  const cx<R> tr = cvt<R>(tau);
+  c128 acc[3][LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) acc[0][j] = acc[1][j] = acc[2][j] = c128{0.0, 0.0};
+  for (long t = (long)xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x; t < items; t += (long)gridDim.x * CGB) {
+    const int c = (int)(t >> lC);
+    int idx[NB];
+    R fo[NB];
+    R fsum;
+    op.template stencil<R>(c, idx, fo, fsum);
+    const R m = (R)op.mass(c);
+    const long base = ((long)c << lS) + ch * LT;
+    cx<R> uc[LT], ww[LT], rr[LT];
+#pragma unroll
+    for (int j = 0; j < LT; ++j) {
+      uc[j] = u[base + j];
+      rr[j] = r[base + j];
+      ww[j] = fsum * uc[j] + m * (tr * uc[j]);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const cx<R>* un = u + ((long)idx[q] << lS) + ch * LT;
+#pragma unroll
+      for (int j = 0; j < LT; ++j) ww[j] = ww[j] - fo[q] * un[j];
+    }
+    int flag = *opaque(all_done);
+    asm volatile("" : "+v"(ww[0].re), "+v"(rr[0].re), "+v"(flag));
+    if (flag) break;
+#pragma unroll
+    for (int j = 0; j < LT; ++j) {
+      if (!live[j]) continue;
+      w[base + j] = ww[j];
+      const c128 rd = cvt<double>(rr[j]), ud = cvt<double>(uc[j]);
+      acc[0][j] = acc[0][j] + rd * ud;
+      acc[1][j] = acc[1][j] + cvt<double>(ww[j]) * ud;
+      acc[2][j].re += abs2(rd);
+    }
+  }
+  if (*opaque(all_done)) return;
+  __shared__ c128 sh[NW][3][WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int j = 0; j < LT; ++j) {
+      const c128 v = wave_sum_strided(acc[q][j], C);
+      if (lane < C) sh[wv][q][lane * LT + j] = v;
+    }
+  }
+  lds_sync();
+  if ((int)threadIdx.x < S) {
+    c128* out = partOut + (size_t)blockIdx.x * 3 * S;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      c128 a = sh[0][q][threadIdx.x];
+      for (int v = 1; v < NW; ++v) a = a + sh[v][q][threadIdx.x];
+      out[q * S + threadIdx.x] = a;
+    }
+  }
+}
+
 }  // namespace shk

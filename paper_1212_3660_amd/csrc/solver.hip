@@ -283,7 +283,9 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 // complex64 inner rounds' reduction target and stall rule ("min,mult") are
 // SHK_ROUND_TOL and SHK_STALL.  SHK_MG_TAIL_LDS lowers the LDS budget of the
 // V-cycle's one-workgroup tail (so that it starts on a coarser level);
-// SHK_MG_FUSE=0 keeps the multigrid step and the finest restriction apart.
+// SHK_MG_FUSE=0 keeps the multigrid step and the finest restriction apart;
+// SHK_MG_POST_LT (0, 2, 4, 8) sets the lanes a thread of the multigrid
+// product handles when several right-hand sides run on complex64 vectors.
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
@@ -295,7 +297,12 @@ struct Tune {
   int stall_min = 150, stall_mult = 3;
   int tail_lds = MG_TAIL_LDS;
   int mg_fuse = 1;   // step fused with the finest restriction where it applies
+  int post_lt = 2;   // lanes per thread of the multigrid product on the complex64 path (0: one)
   Tune() {
+    if (const char* e = getenv("SHK_MG_POST_LT")) {
+      const int v = atoi(e);
+      post_lt = v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 0;
+    }
     if (const char* e = getenv("SHK_MG_FUSE")) mg_fuse = atoi(e) != 0;
     if (const char* e = getenv("SHK_MG_TAIL_LDS")) tail_lds = std::max(0, std::min(atoi(e), MG_TAIL_LDS));
     if (const char* e = getenv("SHK_CG_BLOCK")) {
@@ -832,10 +839,24 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
   }
   // w = A u and the forms with r, on the iteration kernels' grid
+  // Several lanes on complex64 vectors: a thread per cell and chunk of lanes.
+  template <int CGB>
+  bool mg_post_lanes(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
+    if constexpr (Op::NB > 0 && std::is_same<R, float>::value) {
+      const int lt = std::min(g_tune.post_lt, 1 << lS);
+      if (lS == 0 || lt < 2) return false;
+      if (lt == 2) k_cgmg_post_lanes<Op, R, CGB, 2><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      else if (lt == 4) k_cgmg_post_lanes<Op, R, CGB, 4><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      else k_cgmg_post_lanes<Op, R, CGB, 8><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      return true;
+    }
+    return false;
+  }
   template <int CGB>
   void mg_post_cgb(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
     if constexpr (Op::NB > 0) {
       const bool multi = (long)G * CGB < N;
+      if (mg_post_lanes<CGB>(G, tau, ni, lS, sc, r, w, out)) return;
       if (lS == 0) {
         if (multi) k_cgmg_post<Op, R, CGB, true, true><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
         else k_cgmg_post<Op, R, CGB, true, false><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
@@ -874,8 +895,9 @@ template <typename R, typename Op, typename OpD> struct Group {
                                                                     scOut, vec, par, B.all_done);
         mg_vcycle(vec.r[par ^ 1], tau, lS, B.u);
       }
-      k_cgmg_post<Op, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(op, tau, ni, lS, scOut, vec.r[par ^ 1], B.u,
-                                                             vec.w[par ^ 1], out, B.all_done);
+      if (!mg_post_lanes<CGB>(G, tau, ni, lS, scOut, vec.r[par ^ 1], vec.w[par ^ 1], out))
+        k_cgmg_post<Op, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(op, tau, ni, lS, scOut, vec.r[par ^ 1], B.u,
+                                                               vec.w[par ^ 1], out, B.all_done);
     }
   }
   template <int CGB>

@@ -285,7 +285,8 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 // V-cycle's one-workgroup tail (so that it starts on a coarser level);
 // SHK_MG_FUSE=0 keeps the multigrid step and the finest restriction apart;
 // SHK_MG_POST_LT (0, 2, 4, 8) sets the lanes a thread of the multigrid
-// product handles when several right-hand sides run on complex64 vectors.
+// product handles when several right-hand sides run on complex64 vectors;
+// SHK_MG_DOWN_LT and SHK_MG_UP_LT (2, 4, 8) cap the lane chunk of the grid legs.
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
@@ -298,7 +299,11 @@ struct Tune {
   int tail_lds = MG_TAIL_LDS;
   int mg_fuse = 1;   // step fused with the finest restriction where it applies
   int post_lt = 2;   // lanes per thread of the multigrid product on the complex64 path (0: one)
+  int down_lt = 4, up_lt = 4;   // largest lane chunk of the grid legs on the complex64 path
   Tune() {
+    auto chunk = [](const char* e) { const int v = atoi(e); return v >= 8 ? 8 : v >= 4 ? 4 : 2; };
+    if (const char* e = getenv("SHK_MG_DOWN_LT")) down_lt = chunk(e);
+    if (const char* e = getenv("SHK_MG_UP_LT")) up_lt = chunk(e);
     if (const char* e = getenv("SHK_MG_POST_LT")) {
       const int v = atoi(e);
       post_lt = v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 0;
@@ -776,8 +781,9 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   void mg_down_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                      const cx<R>* dl, cx<R>* out) {
-    if (lS == 1) mg_down_lt<2>(l, f, c, tau, lS, bl, dl, out);
-    else if (lS == 2) mg_down_lt<4>(l, f, c, tau, lS, bl, dl, out);
+    const int lt = std::min(g_tune.down_lt, 1 << lS);
+    if (lt == 2) mg_down_lt<2>(l, f, c, tau, lS, bl, dl, out);
+    else if (lt == 4) mg_down_lt<4>(l, f, c, tau, lS, bl, dl, out);
     else mg_down_lt<8>(l, f, c, tau, lS, bl, dl, out);
   }
   template <int LT>
@@ -790,8 +796,9 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   void mg_up_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                    const cx<R>* dl, const cx<R>* xcoarse, cx<R>* out) {
-    if (lS == 1) mg_up_lt<2>(l, f, c, tau, lS, bl, dl, xcoarse, out);
-    else if (lS == 2) mg_up_lt<4>(l, f, c, tau, lS, bl, dl, xcoarse, out);
+    const int lt = std::min(g_tune.up_lt, 1 << lS);
+    if (lt == 2) mg_up_lt<2>(l, f, c, tau, lS, bl, dl, xcoarse, out);
+    else if (lt == 4) mg_up_lt<4>(l, f, c, tau, lS, bl, dl, xcoarse, out);
     else mg_up_lt<8>(l, f, c, tau, lS, bl, dl, xcoarse, out);
   }
   void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout, int from = 0) {

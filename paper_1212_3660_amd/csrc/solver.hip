@@ -544,18 +544,30 @@ static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real
 }
 
 // ------------------------------------------------------- lane totals -------
-// One block per lane: totals of NV partial sums over G blocks -> tot[q*S+r]
-// (the layout of a single block's partials, so consumers read it with G=1).
+// One block per (sum q, lane r), grid NV*S: totals of NV partial sums over G
+// blocks -> tot[q*S+r] (the layout of a single block's partials, so consumers
+// read it with G=1).  Each thread issues its first LTK loads together, then
+// sums them in order (a strided loop takes blocks beyond LTK*BS), then a
+// fixed-order block sum.
+constexpr int LTK = 8;
 template <int NV>
 __global__ void __launch_bounds__(BS) k_lane_totals(const c128* __restrict__ part, int G, int S,
                                                     c128* __restrict__ tot) {
-  const int r = blockIdx.x;
-  for (int q = 0; q < NV; ++q) {
-    c128 a{0.0, 0.0};
-    for (int b = threadIdx.x; b < G; b += BS) a = a + part[((size_t)b * NV + q) * S + r];
-    a = block_sum_all(a);
-    if (threadIdx.x == 0) tot[q * S + r] = a;
+  const int q = (int)blockIdx.x / S, r = (int)blockIdx.x - q * S;
+  const c128* col = part + (size_t)q * S + r;
+  const size_t stride = (size_t)NV * S;
+  c128 v[LTK];
+#pragma unroll
+  for (int k = 0; k < LTK; ++k) {
+    const int b = (int)threadIdx.x + k * BS;
+    v[k] = b < G ? col[(size_t)b * stride] : c128{0.0, 0.0};
   }
+  c128 a = v[0];
+#pragma unroll
+  for (int k = 1; k < LTK; ++k) a = a + v[k];
+  for (int b = (int)threadIdx.x + LTK * BS; b < G; b += BS) a = a + col[(size_t)b * stride];
+  a = block_sum_all(a);
+  if (threadIdx.x == 0) tot[q * S + r] = a;
 }
 
 // --------------------------------------------------------------- solver ----
@@ -941,7 +953,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     // partials of launch L live in cpart[L & 1] (totals in ctot[L & 1])
     auto totals = [&](int slot) -> const c128* {
       if (!gp.separate) return B.cpart[slot];
-      k_lane_totals<3><<<S, BS, 0, st>>>(B.cpart[slot], G, S, B.ctot[slot]);
+      k_lane_totals<3><<<3 * S, BS, 0, st>>>(B.cpart[slot], G, S, B.ctot[slot]);
       return B.ctot[slot];
     };
     const int Gin = gp.separate ? 1 : G;

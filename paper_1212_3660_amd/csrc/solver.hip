@@ -286,7 +286,8 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 // SHK_MG_FUSE=0 keeps the multigrid step and the finest restriction apart;
 // SHK_MG_POST_LT (0, 2, 4, 8) sets the lanes a thread of the multigrid
 // product handles when several right-hand sides run on complex64 vectors;
-// SHK_MG_DOWN_LT and SHK_MG_UP_LT (2, 4, 8) cap the lane chunk of the grid legs.
+// SHK_MG_DOWN_LT and SHK_MG_UP_LT (2, 4, 8) cap the lane chunk of the grid legs;
+// SHK_MG_LT64 (0, 2, 4) does so for the complex128 path.
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
@@ -300,7 +301,9 @@ struct Tune {
   int mg_fuse = 1;   // step fused with the finest restriction where it applies
   int post_lt = 2;   // lanes per thread of the multigrid product on the complex64 path (0: one)
   int down_lt = 4, up_lt = 4;   // largest lane chunk of the grid legs on the complex64 path
+  int lt64 = 2;   // the same on the complex128 path (0: a lane per thread; product at most 2)
   Tune() {
+    if (const char* e = getenv("SHK_MG_LT64")) lt64 = atoi(e) >= 4 ? 4 : atoi(e) >= 2 ? 2 : 0;
     auto chunk = [](const char* e) { const int v = atoi(e); return v >= 8 ? 8 : v >= 4 ? 4 : 2; };
     if (const char* e = getenv("SHK_MG_DOWN_LT")) down_lt = chunk(e);
     if (const char* e = getenv("SHK_MG_UP_LT")) up_lt = chunk(e);
@@ -779,10 +782,11 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   // uout = B b0 (one V-cycle over every level)
   // (from = 1: the finest restriction was done by the fused step kernel)
-  // Grid legs for several lanes: chunks of up to 8 lanes per thread on the
-  // complex64 path (measured faster there; the complex128 path keeps a lane
-  // per thread, which measured faster for it).
-  static constexpr bool lane_chunks = std::is_same<R, float>::value;
+  // Grid legs for several lanes: chunks of up to 4 lanes per thread on the
+  // complex64 path and of 2 on the complex128 path (each measured faster
+  // than the other sizes and than a lane per thread).
+  static constexpr bool c64 = std::is_same<R, float>::value;
+  bool lane_chunks() const { return c64 || g_tune.lt64 >= 2; }
   template <int LT>
   void mg_down_lt(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
                   cx<R>* out) {
@@ -793,7 +797,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   void mg_down_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                      const cx<R>* dl, cx<R>* out) {
-    const int lt = std::min(g_tune.down_lt, 1 << lS);
+    const int lt = std::min(c64 ? g_tune.down_lt : g_tune.lt64, 1 << lS);
     if (lt == 2) mg_down_lt<2>(l, f, c, tau, lS, bl, dl, out);
     else if (lt == 4) mg_down_lt<4>(l, f, c, tau, lS, bl, dl, out);
     else mg_down_lt<8>(l, f, c, tau, lS, bl, dl, out);
@@ -808,7 +812,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   void mg_up_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                    const cx<R>* dl, const cx<R>* xcoarse, cx<R>* out) {
-    const int lt = std::min(g_tune.up_lt, 1 << lS);
+    const int lt = std::min(c64 ? g_tune.up_lt : g_tune.lt64, 1 << lS);
     if (lt == 2) mg_up_lt<2>(l, f, c, tau, lS, bl, dl, xcoarse, out);
     else if (lt == 4) mg_up_lt<4>(l, f, c, tau, lS, bl, dl, xcoarse, out);
     else mg_up_lt<8>(l, f, c, tau, lS, bl, dl, xcoarse, out);
@@ -823,7 +827,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       for (int l = from; l < gdown; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
-        if (lS > 0 && lane_chunks) {
+        if (lS > 0 && lane_chunks()) {
           mg_down_lanes(l, f, c, tau, lS, bl, dl, B.mb[l]);
         } else {
           const dim3 g((unsigned)((((long)c.nx * S_ << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
@@ -847,7 +851,7 @@ template <typename R, typename Op, typename OpD> struct Group {
         const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
         cx<R>* out = l == 0 ? uout : B.mx[l - 1];
-        if (lS > 0 && lane_chunks) {
+        if (lS > 0 && lane_chunks()) {
           mg_up_lanes(l, f, c, tau, lS, bl2, dl, B.mx[l], out);
         } else {
           const dim3 g((unsigned)(((long)f.nx * S_ + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
@@ -858,15 +862,18 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
   }
   // w = A u and the forms with r, on the iteration kernels' grid
-  // Several lanes on complex64 vectors: a thread per cell and chunk of lanes.
+  // Several lanes: a thread per cell and chunk of lanes.
   template <int CGB>
   bool mg_post_lanes(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
-    if constexpr (Op::NB > 0 && std::is_same<R, float>::value) {
-      const int lt = std::min(g_tune.post_lt, 1 << lS);
+    if constexpr (Op::NB > 0) {
+      const int lt = std::min(c64 ? g_tune.post_lt : std::min(g_tune.lt64, 2), 1 << lS);
       if (lS == 0 || lt < 2) return false;
-      if (lt == 2) k_cgmg_post_lanes<Op, R, CGB, 2><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
-      else if (lt == 4) k_cgmg_post_lanes<Op, R, CGB, 4><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
-      else k_cgmg_post_lanes<Op, R, CGB, 8><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      if (lt == 2) {
+        k_cgmg_post_lanes<Op, R, CGB, 2><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      } else if constexpr (c64) {
+        if (lt == 4) k_cgmg_post_lanes<Op, R, CGB, 4><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+        else k_cgmg_post_lanes<Op, R, CGB, 8><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
+      }
       return true;
     }
     return false;

@@ -135,8 +135,8 @@ def test_mg_tail_two_levels_down(shape, S):
 
 @pytest.mark.parametrize("shape,S", [((40, 36), 8), ((24, 20), 16), ((12, 10, 9), 4)])
 def test_mg_complex64_lanes_iterates(shape, S):
-    """Complex64 path with several lanes (grid legs working chunks of up to 8
-    lanes per thread): fixed iteration counts against the oracle's FP64
+    """Complex64 path with several lanes (grid legs and product working chunks
+    of lanes per thread): fixed iteration counts against the oracle's FP64
     iterates, to complex64 accuracy; a lane or chunk mixed up would be off by
     O(1).  One iteration (the V-cycle's output scaled) agrees to ~1e-6 of the
     largest entry; after a few, COCG can amplify single-precision rounding

@@ -76,8 +76,12 @@ static size_t footprint(const Job& j) {
   return ws + xb + shk::problem_bytes(&tmp) + (64u << 20);
 }
 
-static void run_job(shk_server* s, Job* j, hipStream_t st) {
-  j->res.t_start = s->now();
+// Runs one request on stream st.  Only this thread touches the request's
+// inputs while it runs; the outputs go to x_out / st_out / res_out, which the
+// caller publishes under the server mutex.
+static void run_job(shk_server* s, Job* j, hipStream_t st, shk_result& res_out, std::vector<shk_c128>& x_out,
+                    std::vector<shk_status>& st_out) {
+  res_out.t_start = s->now();
   shk_problem* p = new shk_problem();
   p->kind = shk::Kind::FV2D;
   p->nx = j->nx;
@@ -89,7 +93,7 @@ static void run_job(shk_server* s, Job* j, hipStream_t st) {
   void* ws = nullptr;
   void* xd = nullptr;
   void* bd = nullptr;
-  j->st.assign((size_t)nf * j->n_rhs, shk_status{});
+  st_out.assign((size_t)nf * j->n_rhs, shk_status{});
   if (rc == SHK_OK) {
     const size_t wsb = shk::workspace_bytes(p, &j->prm, nf, j->n_rhs, false);
     const size_t xb = sizeof(c128) * (size_t)n * nf * j->n_rhs;
@@ -99,11 +103,11 @@ static void run_job(shk_server* s, Job* j, hipStream_t st) {
     } else {
       (void)hipMemcpyAsync(bd, j->b.data(), sizeof(c128) * (size_t)n * j->n_rhs, hipMemcpyHostToDevice, st);
       rc = shk::solve_all(p, &j->prm, nf, reinterpret_cast<const c128*>(j->sigma.data()), j->n_rhs,
-                          reinterpret_cast<const c128*>(bd), reinterpret_cast<c128*>(xd), j->st.data(), ws, wsb, st,
-                          SHK_PTR_DEVICE);
+                          reinterpret_cast<const c128*>(bd), reinterpret_cast<c128*>(xd), st_out.data(), ws, wsb,
+                          st, SHK_PTR_DEVICE);
       if (rc == SHK_OK && j->keep_x) {
-        j->x.resize((size_t)n * nf * j->n_rhs);
-        (void)hipMemcpyAsync(j->x.data(), xd, xb, hipMemcpyDeviceToHost, st);
+        x_out.resize((size_t)n * nf * j->n_rhs);
+        (void)hipMemcpyAsync(x_out.data(), xd, xb, hipMemcpyDeviceToHost, st);
       }
     }
   }
@@ -113,20 +117,16 @@ static void run_job(shk_server* s, Job* j, hipStream_t st) {
   shk::problem_free(p, st);
   delete p;
   (void)hipStreamSynchronize(st);
-  j->res.error = rc;
+  res_out.error = rc;
   int nconv = 0;
   double worst = 0.0;
-  for (const shk_status& x : j->st) {
+  for (const shk_status& x : st_out) {
     nconv += (x.status == SHK_CONVERGED || x.status == SHK_BREAKDOWN_EXACT);
     worst = std::max(worst, x.true_relres);
   }
-  j->res.n_converged = nconv;
-  j->res.max_true_relres = worst;
-  j->res.t_done = s->now();
-  j->res.done = 1;
-  // the request's inputs are no longer needed
-  std::vector<double>().swap(j->K);
-  std::vector<shk_c128>().swap(j->b);
+  res_out.n_converged = nconv;
+  res_out.max_true_relres = worst;
+  res_out.t_done = s->now();
 }
 
 static void worker(shk_server* s) {
@@ -153,9 +153,19 @@ static void worker(shk_server* s) {
     if (!pick) continue;
     s->used += pick->need;
     s->running += 1;
+    shk_result res = pick->res;   // t_arrival, set at submit under the mutex
     lk.unlock();
-    run_job(s, pick, st);
+    std::vector<shk_c128> x;
+    std::vector<shk_status> stv;
+    run_job(s, pick, st, res, x, stv);
     lk.lock();
+    // publish: shk_server_poll reads these under the mutex only
+    res.done = 1;
+    pick->res = res;
+    pick->x.swap(x);
+    pick->st.swap(stv);
+    std::vector<double>().swap(pick->K);      // the request's inputs are no longer needed
+    std::vector<shk_c128>().swap(pick->b);
     s->used -= pick->need;
     s->running -= 1;
     s->cv_work.notify_all();

@@ -8,7 +8,8 @@ arithmetic.  The defaults are covered by the rest of the suite; here each
 non-default setting reruns, in a child process with that environment, the
 multi-lane multigrid tests: fixed inner iterations against the oracle's
 iterates (complex64: 8, 16 and 4 lanes; complex128: 4 and 2 lanes), and the
-256x256 / 64-rhs solves on both paths against SuperLU and reciprocity.
+256x256 / 64-rhs solves with the multigrid inner solve (the kernels these
+settings select) on both paths against SuperLU and reciprocity.
 """
 import os
 import subprocess
@@ -32,7 +33,8 @@ def test_lane_chunk_settings(post, down, up, lt64):
            "--timeout-method", "thread",
            "tests/test_gpu_mg.py::test_mg_complex64_lanes_iterates",
            "tests/test_gpu_mg.py::test_mg_cocg_iterates_match_oracle",
-           "tests/test_gpu_workloads.py::test_256x256_64_rhs_forward_adjoint"]
+           "tests/test_gpu_workloads.py::test_256x256_64_rhs_forward_adjoint[fp64-multigrid]",
+           "tests/test_gpu_workloads.py::test_256x256_64_rhs_forward_adjoint[mixed-multigrid]"]
     r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-2000:]
     assert "8 passed" in r.stdout, r.stdout[-2000:]

@@ -14,6 +14,8 @@ Contents (complex128 throughout):
   mg         geometric aggregation multigrid V-cycle, multigrid-preconditioned
              COCG (the inner solve with a multigrid preconditioner, section 6)
   fgmres_sh  Algorithms 3 and 4 with inexact inner solves, restart, refinement
+  block      block FGMRES-Sh: one shared block basis for several right-hand
+             sides (the multiple right-hand-side extension of sections 5 and 7)
   sensitivity  adjoint-state sensitivity of point measurements to ln K per
              cell (section 5, eq. sensitivity, Algorithm 6)
 """

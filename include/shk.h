@@ -270,6 +270,21 @@ int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128
 int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b,
                       const shk_c128* x, double* relres, void* hip_stream);
 
+/* The residuals of shk_true_residual computed without allocating device
+ * memory, for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Its scratch (shifts,
+ * per-block partial sums, ||b||) lives in a fixed 9 MiB device array that the
+ * library holds on each device it runs on until the process ends; the array's
+ * device address is looked up on the first call on a device.  Same arguments,
+ * layout and results as shk_true_residual (bitwise: same kernels, same
+ * summation order).  Errors: INVALID_ARG as shk_true_residual; WORKSPACE when
+ * n_shifts x (the residual kernel's block count, at most 256) x 16 bytes plus
+ * small terms exceeds the array (about 2,280 shifts at n >= 65,536 cells:
+ * split the shifts over calls).  Calls that overlap on one device share the
+ * array and race; calls on different devices do not. */
+int shk_true_residual_noalloc(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b,
+                              const shk_c128* x, double* relres, void* hip_stream);
+
 /* Sensitivities of point measurements to the log-conductivity field (section
  * 5, eq. sensitivity; step 3 of Algorithm 6), finite-volume problems only.
  * phi: forward solutions, device, n x n_shifts x n_src column-major complex128

@@ -6,6 +6,6 @@ in ``include/shk.h``); ``binding`` marshals arguments to it.  Build with
 """
 from .binding import (Problem, Server, fgmres_sh_solve, make_params, shk_apply_shifted,  # noqa: F401
                       shk_assemble, shk_inner_solve, shk_orthogonalize, shk_shifted_lsq,
-                      shk_true_residual, shk_sensitivity, shk_workspace_bytes, shk_profile_enable, shk_profile_read, lib, STATUS_DTYPE, SHK_FP64, SHK_MIXED,
+                      shk_true_residual, shk_true_residual_noalloc, shk_sensitivity, shk_workspace_bytes, shk_profile_enable, shk_profile_read, lib, STATUS_DTYPE, SHK_FP64, SHK_MIXED,
                       SHK_GMRES, SHK_FOM, SHK_CGS2, SHK_MGS, SHK_CONVERGED, SHK_NOT_CONVERGED, SHK_INNER_LIMITED,
                       SHK_BREAKDOWN_EXACT, SHK_NAN, SHK_PRECOND_JACOBI, SHK_PRECOND_MULTIGRID, ShkError)

@@ -86,6 +86,8 @@ _SIGS = {
                                C.c_int, C.c_void_p]),
     "shk_true_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
+    "shk_true_residual_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
     "shk_sensitivity": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                   C.c_int, C.c_void_p]),
     "shk_profile_enable": (C.c_int, [C.c_int]),
@@ -338,6 +340,17 @@ def shk_true_residual(problem: Problem, sigma, b, x, stream=None) -> np.ndarray:
     _check(lib().shk_true_residual(problem.handle, len(sg), sg.ctypes.data, C.c_void_p(b.data_ptr()),
                                    C.c_void_p(x.data_ptr()), out.ctypes.data, _stream_ptr(stream)),
            "shk_true_residual")
+    return out
+
+
+def shk_true_residual_noalloc(problem: Problem, sigma, b, x, stream=None) -> np.ndarray:
+    """shk_true_residual with the library's fixed device scratch (no device
+    allocation)."""
+    sg = np.ascontiguousarray(sigma, dtype=np.complex128)
+    out = np.zeros(len(sg), dtype=np.float64)
+    _check(lib().shk_true_residual_noalloc(problem.handle, len(sg), sg.ctypes.data, C.c_void_p(b.data_ptr()),
+                                           C.c_void_p(x.data_ptr()), out.ctypes.data, _stream_ptr(stream)),
+           "shk_true_residual_noalloc")
     return out
 
 

@@ -150,6 +150,13 @@ int shk_true_residual(shk_problem* p, int n_shifts, const shk_c128* sigma, const
                                  reinterpret_cast<const c128*>(x), relres, (hipStream_t)hip_stream);
 }
 
+int shk_true_residual_noalloc(shk_problem* p, int n_shifts, const shk_c128* sigma, const shk_c128* b,
+                              const shk_c128* x, double* relres, void* hip_stream) {
+  return shk::step_true_residual_noalloc(p, n_shifts, reinterpret_cast<const c128*>(sigma),
+                                         reinterpret_cast<const c128*>(b), reinterpret_cast<const c128*>(x), relres,
+                                         (hipStream_t)hip_stream);
+}
+
 const char* shk_status_string(int code) {
   switch (code) {
     case SHK_CONVERGED: return "converged";

@@ -83,6 +83,10 @@ int step_sensitivity(shk_problem* p, int nf, int ns, const c128* phi, int nr, co
                      hipStream_t st);
 int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x,
                        double* relres, hipStream_t stream);
+// Bytes of the fixed device array behind shk_true_residual_noalloc.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(9) << 20;
+int step_true_residual_noalloc(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x,
+                               double* relres, hipStream_t stream);
 
 int problem_setup_fv(shk_problem* p, const double* cellK_host, double Ss, double h, hipStream_t st);
 int problem_setup_csr(shk_problem* p, const int* rowptr, const int* col, const double* val,

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -1678,35 +1679,98 @@ int step_sensitivity(shk_problem* p, int nf, int ns, const c128* phi, int nr, co
   return SHK_OK;
 }
 
-int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x, double* relres,
-                       hipStream_t st) {
+// Scratch of the true-residual entry points, carved from base (nullptr: sizes
+// only): the shifts, residual partials [nf][Gr], residual rows [nf], partials
+// of ||b||^2 [Gn] and ||b||.  Every slot is written before it is read.
+struct ResidScratch {
+  c128 *sg, *part, *rows, *npart;
+  double* nbd;
+  size_t bytes;
+};
+static ResidScratch resid_scratch(char* base, long n, int nf) {
+  Carver c{base};
+  ResidScratch r{};
+  r.sg = c.take<c128>(nf);
+  r.part = c.take<c128>((size_t)nf * resid_grid(n));
+  r.rows = c.take<c128>(nf);
+  r.npart = c.take<c128>(grid_items(n, 1024));
+  r.nbd = c.take<double>(2);
+  r.bytes = c.off;
+  return r;
+}
+
+static int check_resid_args(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x,
+                            const double* relres) {
   if (!p || !sigma || !b || !x || !relres || nf < 1) return fail(SHK_ERR_INVALID_ARG, "residual arguments");
+  if (nf > 65535) return fail(SHK_ERR_INVALID_ARG, "at most 65535 shifts per residual call");
+  return SHK_OK;
+}
+
+// ||b - (K + sigma_j M) x_j|| / ||b|| with the scratch at base (device).
+static int true_residual_in(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x, double* relres,
+                            hipStream_t st, char* base) {
   const long n = p->n;
-  const int Gr = resid_grid(n);
   const int Gn = grid_items(n, 1024);
-  DevBuf mem;
-  Carver cv{nullptr};
-  cv.take<c128>(nf); cv.take<c128>((size_t)nf * Gr); cv.take<c128>(nf); cv.take<c128>(Gn); cv.take<double>(2);
-  SHK_HIP(hipMalloc(&mem.p, cv.off));
-  Carver c{(char*)mem.p};
-  c128* sg = c.take<c128>(nf);
-  c128* part = c.take<c128>((size_t)nf * Gr);
-  c128* rows = c.take<c128>(nf);
-  c128* npart = c.take<c128>(Gn);
-  double* nbd = c.take<double>(2);
-  SHK_HIP(hipMemcpyAsync(sg, sigma, sizeof(c128) * nf, hipMemcpyHostToDevice, st));
-  k_norm2<double><<<Gn, BS, 0, st>>>(b, n, 1, npart);
-  k_final_sqrt<1><<<1, BS, 0, st>>>(npart, Gn, 1, nbd, nullptr, nullptr);
+  const ResidScratch r = resid_scratch(base, n, nf);
+  SHK_HIP(hipMemcpyAsync(r.sg, sigma, sizeof(c128) * nf, hipMemcpyHostToDevice, st));
+  k_norm2<double><<<Gn, BS, 0, st>>>(b, n, 1, r.npart);
+  k_final_sqrt<1><<<1, BS, 0, st>>>(r.npart, Gn, 1, r.nbd, nullptr, nullptr);
   SHK_TRY(with_op<double>(p, [&](auto opd) -> int {
-    return residual_rows(opd, n, 1, 1, nf, sg, b, x, nullptr, 0, part, rows, st);
+    return residual_rows(opd, n, 1, 1, nf, r.sg, b, x, nullptr, 0, r.part, r.rows, st);
   }));
   std::vector<c128> hr(nf);
   double bn = 0.0;
-  SHK_HIP(hipMemcpyAsync(hr.data(), rows, sizeof(c128) * nf, hipMemcpyDeviceToHost, st));
-  SHK_HIP(hipMemcpyAsync(&bn, nbd, sizeof(double), hipMemcpyDeviceToHost, st));
+  SHK_HIP(hipMemcpyAsync(hr.data(), r.rows, sizeof(c128) * nf, hipMemcpyDeviceToHost, st));
+  SHK_HIP(hipMemcpyAsync(&bn, r.nbd, sizeof(double), hipMemcpyDeviceToHost, st));
   SHK_HIP(hipStreamSynchronize(st));
   for (int j = 0; j < nf; ++j) relres[j] = bn > 0 ? std::sqrt(hr[j].re) / bn : std::sqrt(hr[j].re);
   return SHK_OK;
+}
+
+int step_true_residual(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x, double* relres,
+                       hipStream_t st) {
+  SHK_TRY(check_resid_args(p, nf, sigma, b, x, relres));
+  DevBuf mem;
+  SHK_HIP(hipMalloc(&mem.p, resid_scratch(nullptr, p->n, nf).bytes));
+  return true_residual_in(p, nf, sigma, b, x, relres, st, (char*)mem.p);
+}
+
+// ------------------------------------------- allocation-free residual ------
+// The same residual with its scratch in a fixed device array: for callers that
+// cannot allocate device memory.  Each device holds its own copy of the array
+// for the life of the process; its address is looked up once per device, with
+// that device current, on the first call there.  Calls that overlap on one
+// device share the array and race.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[64] = {};
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  SHK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(SHK_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    SHK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SHK_ERR_HIP, "no device address for the residual scratch");
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return SHK_OK;
+}
+
+int step_true_residual_noalloc(shk_problem* p, int nf, const c128* sigma, const c128* b, const c128* x,
+                               double* relres, hipStream_t st) {
+  SHK_TRY(check_resid_args(p, nf, sigma, b, x, relres));
+  const size_t need = resid_scratch(nullptr, p->n, nf).bytes;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(SHK_ERR_WORKSPACE, "residual scratch of " + std::to_string(need) + " bytes exceeds the fixed " +
+                                       std::to_string(NOALLOC_SCRATCH_BYTES) + " (fewer shifts per call)");
+  void* base = nullptr;
+  SHK_TRY(scratch_address(&base));
+  return true_residual_in(p, nf, sigma, b, x, relres, st, (char*)base);
 }
 
 }  // namespace shk

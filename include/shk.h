@@ -71,6 +71,10 @@ typedef struct shk_server shk_server;
                         residual and refinement in FP64                             */
 #define SHK_PTR_HOST 0
 #define SHK_PTR_DEVICE 1
+#define SHK_RHS_LOCKSTEP 0  /* one flexible basis per right-hand side, the bases
+                               built in lockstep (the paper's choice, section 5)  */
+#define SHK_RHS_BLOCK 1     /* one block basis shared by a group's right-hand
+                               sides (block FGMRES-Sh)                           */
 #define SHK_PRECOND_JACOBI 0     /* inner COCG with D = diag(K + tau M)              */
 #define SHK_PRECOND_MULTIGRID 1  /* inner COCG preconditioned by a geometric
                                     aggregation multigrid V-cycle (structured
@@ -126,6 +130,24 @@ typedef struct shk_server shk_server;
  *                 SHK_MGS: the paper's modified Gram-Schmidt, one column at a
  *                 time (k + 1 sequential passes at step k).  Other values:
  *                 INVALID_ARG.
+ *  rhs_mode       how the right-hand sides of a group (up to 64 per call group)
+ *                 share the work.  SHK_RHS_LOCKSTEP (default): each has its
+ *                 own flexible basis (Algorithms 3 and 4 per rhs); the bases
+ *                 are built side by side so the operator is read once for all.
+ *                 SHK_RHS_BLOCK: one block basis for the group (the block
+ *                 extension for several right-hand sides the paper points to in
+ *                 sections 5 and 7): B = V_1 beta; per step the S columns of V_k
+ *                 get their inner solves, W = M Z_k is orthogonalised against
+ *                 V_1..V_k by block CGS2 on the matrix cores and factored W =
+ *                 V_{k+1} H_{k+1,k} (CholQR2, FP64 Gram); each (shift, rhs)
+ *                 takes the least-squares solution of the block form of eq.
+ *                 shiftedarnoldimod with the stopping rule of eq.
+ *                 trueresidual (one inner residual per basis column).  The
+ *                 group is padded to at least 16 columns.  No restarts: pairs
+ *                 still running after m_restart block steps keep their
+ *                 least-squares iterate and go to refinement.  Requires
+ *                 variant SHK_GMRES and ortho SHK_CGS2 (else UNSUPPORTED) and
+ *                 m_restart <= 100; workspace grows as n_shifts (m S)^2.
  */
 typedef struct {
   int m_restart;
@@ -146,6 +168,7 @@ typedef struct {
   double inner_relax;
   double inner_eps_max;
   int ortho;
+  int rhs_mode;
 } shk_params;
 
 /* Per-(shift, rhs) result, host memory, n_shifts x n_rhs column-major. */
@@ -257,6 +280,32 @@ int shk_orthogonalize(long long n, int n_rhs, int k, void* V, void* w, shk_c128*
  * square system of that step is exactly singular).  Errors: INVALID_ARG. */
 int shk_shifted_lsq(int k, const shk_c128* Hbar, const shk_c128* taus, int n_shifts,
                     const shk_c128* sigma, double beta, shk_c128* y, double* rho, int variant);
+
+/* One step of the shared block basis (block form of Algorithm 3): V holds k
+ * blocks of n_rhs columns (device, n x n_rhs each, element (c, r) at c*n_rhs
+ * + r, block stride n*n_rhs), orthonormal; W (device, one such block) is
+ * orthogonalised against them by block classical Gram-Schmidt with one
+ * reorthogonalisation (projections on the matrix cores, FP32 products summed
+ * in FP64 for SHK_MIXED, FP64 for SHK_FP64) and factored W = V_{k+1} R
+ * (CholQR twice, FP64 Gram matrices; R upper triangular with a real positive
+ * diagonal; a dependent column gives a zero column of V_{k+1}), V_{k+1}
+ * written as block k of V.  h (host, ((k+1) n_rhs) x n_rhs column-major)
+ * receives the coefficients of V_1..V_k in rows 0..k n_rhs and R below.
+ * n_rhs in {16, 32, 64}.  Overwrites W.  Errors: INVALID_ARG. */
+int shk_block_orthogonalize(long long n, int n_rhs, int k, void* V, void* W, shk_c128* h, int precision,
+                            void* hip_stream);
+
+/* Per-shift block least squares of the shared block basis (FP64, on the
+ * device): Hbar ((k+1) s x k s, host, column-major, s = n_rhs in {16, 32,
+ * 64}), taus (host, k: block column i uses tau_i), beta (host, s x s
+ * column-major, upper triangular: B = V_1 beta), shifts (host).  For every
+ * shift j and column r, y minimises ||E_1 beta e_r - Hbar(sigma_j;T) y|| with
+ * Hbar(sigma;T) = [I;0] + Hbar (sigma I - T), T = diag(tau_i I_s) (the block
+ * form of eq. shiftedarnoldimod).  Outputs (host): y[row + k s (r + s j)]
+ * (k s rows), and the projected residual norm after each block column i at
+ * rho[r + s (j + n_shifts i)].  Errors: INVALID_ARG. */
+int shk_block_shifted_lsq(int k, int n_rhs, const shk_c128* Hbar, const shk_c128* taus, int n_shifts,
+                          const shk_c128* sigma, const shk_c128* beta, shk_c128* y, double* rho);
 
 /* Solution assembly x_j = Z y_j (Algorithm 4): Z is k columns of n complex
  * values (column stride n, complex128 or complex64 per precision, device), Y

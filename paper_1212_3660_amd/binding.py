@@ -24,6 +24,7 @@ SHK_CGS2, SHK_MGS = 0, 1
 SHK_FP64, SHK_MIXED = 0, 1
 SHK_PTR_HOST, SHK_PTR_DEVICE = 0, 1
 SHK_PRECOND_JACOBI, SHK_PRECOND_MULTIGRID = 0, 1
+SHK_RHS_LOCKSTEP, SHK_RHS_BLOCK = 0, 1
 
 
 class shk_c128(C.Structure):
@@ -36,7 +37,8 @@ class shk_params(C.Structure):
                 ("n_tau", C.c_int), ("tau_seq", C.POINTER(shk_c128)), ("variant", C.c_int),
                 ("precision", C.c_int), ("refine_tol", C.c_double), ("refine_eps_inner", C.c_double),
                 ("inner_precond", C.c_int), ("mg_sweeps", C.c_int), ("mg_omega", C.c_double),
-                ("inner_relax", C.c_double), ("inner_eps_max", C.c_double), ("ortho", C.c_int)]
+                ("inner_relax", C.c_double), ("inner_eps_max", C.c_double), ("ortho", C.c_int),
+                ("rhs_mode", C.c_int)]
 
 
 class shk_status(C.Structure):
@@ -82,6 +84,10 @@ _SIGS = {
                                     C.c_int, C.c_void_p]),
     "shk_shifted_lsq": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p,
                                   C.c_void_p, C.c_int]),
+    "shk_block_orthogonalize": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_int, C.c_void_p]),
+    "shk_block_shifted_lsq": (C.c_int, [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "shk_assemble": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                C.c_int, C.c_void_p]),
     "shk_true_residual": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -143,7 +149,7 @@ def _c128_array(values) -> "C.Array":
 def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_maxit=0, tol=1e-8,
                 eps_inner=1e-10, precision=SHK_FP64, variant=SHK_GMRES, refine_tol=0.05,
                 refine_eps_inner=5e-3, inner_precond=None, mg_omega=0.8, inner_relax=0.0, inner_eps_max=1e-2,
-                ortho=SHK_CGS2):
+                ortho=SHK_CGS2, rhs_mode=SHK_RHS_LOCKSTEP):
     """Returns (shk_params, keepalive) with tau_seq marshalled to C."""
     taus = _c128_array(tau_seq)
     p = shk_params()
@@ -159,6 +165,7 @@ def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_m
     p.mg_omega = mg_omega
     p.inner_relax, p.inner_eps_max = inner_relax, inner_eps_max
     p.ortho = ortho
+    p.rhs_mode = rhs_mode
     return p, taus
 
 
@@ -325,6 +332,31 @@ def shk_shifted_lsq(Hbar: np.ndarray, taus, sigma, beta: float, variant: int = S
     rho = np.zeros((k, nf), dtype=np.float64)
     _check(lib().shk_shifted_lsq(k, H.ctypes.data, tt.ctypes.data, nf, sg.ctypes.data, beta, y.ctypes.data,
                                  rho.ctypes.data, variant), "shk_shifted_lsq")
+    return y, rho
+
+
+def shk_block_orthogonalize(n: int, k: int, V, W, n_rhs: int, stream=None):
+    """Block CGS2 of W (device, n x n_rhs interleaved) against k blocks of V and
+    CholQR2 into V block k; returns h as ((k+1) n_rhs, n_rhs) complex128."""
+    h = np.zeros(((k + 1) * n_rhs, n_rhs), dtype=np.complex128, order="F")
+    _check(lib().shk_block_orthogonalize(n, n_rhs, k, C.c_void_p(V.data_ptr()), C.c_void_p(W.data_ptr()),
+                                         h.ctypes.data, _prec(W), _stream_ptr(stream)), "shk_block_orthogonalize")
+    return h
+
+
+def shk_block_shifted_lsq(Hbar: np.ndarray, taus, sigma, beta: np.ndarray, n_rhs: int):
+    """Device block least squares of every shift for a ((k+1)s x ks) block
+    Hessenberg; returns (y (n_shifts, s, k s), rho (k, n_shifts, s))."""
+    H = np.asfortranarray(Hbar, dtype=np.complex128)
+    k = H.shape[1] // n_rhs
+    tt = np.ascontiguousarray(taus, dtype=np.complex128)
+    sg = np.ascontiguousarray(sigma, dtype=np.complex128)
+    bb = np.asfortranarray(beta, dtype=np.complex128)
+    nf = len(sg)
+    y = np.zeros((nf, n_rhs, k * n_rhs), dtype=np.complex128)
+    rho = np.zeros((k, nf, n_rhs), dtype=np.float64)
+    _check(lib().shk_block_shifted_lsq(k, n_rhs, H.ctypes.data, tt.ctypes.data, nf, sg.ctypes.data, bb.ctypes.data,
+                                       y.ctypes.data, rho.ctypes.data), "shk_block_shifted_lsq")
     return y, rho
 
 

@@ -29,6 +29,7 @@ void shk_params_default(shk_params* p) {
   p->inner_relax = 0.0;
   p->inner_eps_max = 1e-2;
   p->ortho = SHK_CGS2;
+  p->rhs_mode = SHK_RHS_LOCKSTEP;
 }
 
 static int create_fv(int nx, int ny, int nz, shk::Kind kind, const double* cell_K, double Ss, double h,
@@ -130,6 +131,18 @@ int shk_shifted_lsq(int k, const shk_c128* Hbar, const shk_c128* taus, int n_shi
                     double beta, shk_c128* y, double* rho, int variant) {
   return shk::step_lsq(k, reinterpret_cast<const c128*>(Hbar), reinterpret_cast<const c128*>(taus), n_shifts,
                        reinterpret_cast<const c128*>(sigma), beta, reinterpret_cast<c128*>(y), rho, variant);
+}
+
+int shk_block_orthogonalize(long long n, int n_rhs, int k, void* V, void* W, shk_c128* h, int precision,
+                            void* hip_stream) {
+  return shk::step_block_orth(n, n_rhs, k, V, W, reinterpret_cast<c128*>(h), precision, (hipStream_t)hip_stream);
+}
+
+int shk_block_shifted_lsq(int k, int n_rhs, const shk_c128* Hbar, const shk_c128* taus, int n_shifts,
+                          const shk_c128* sigma, const shk_c128* beta, shk_c128* y, double* rho) {
+  return shk::step_block_lsq(k, n_rhs, reinterpret_cast<const c128*>(Hbar), reinterpret_cast<const c128*>(taus),
+                             n_shifts, reinterpret_cast<const c128*>(sigma), reinterpret_cast<const c128*>(beta),
+                             reinterpret_cast<c128*>(y), rho);
 }
 
 int shk_assemble(long long n, int k, int n_shifts, const void* Z, const shk_c128* Y, shk_c128* X, int accumulate,

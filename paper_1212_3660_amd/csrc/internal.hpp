@@ -77,6 +77,9 @@ int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precisio
               hipStream_t stream);
 int step_lsq(int k, const c128* H, const c128* taus, int nf, const c128* sigma, double beta,
              c128* y, double* rho, int variant);
+int step_block_orth(long long n, int S, int k, void* V, void* W, c128* h, int precision, hipStream_t stream);
+int step_block_lsq(int k, int S, const c128* H, const c128* taus, int nf, const c128* sigma, const c128* beta,
+                   c128* y, double* rho);
 int step_assemble(long long n, int k, int nf, const void* Z, const c128* Y, c128* X, int acc,
                   int precision, hipStream_t stream);
 int step_sensitivity(shk_problem* p, int nf, int ns, const c128* phi, int nr, const c128* psi, void* J, int precision,

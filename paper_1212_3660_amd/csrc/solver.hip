@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 #include "mg.hpp"
 #include "sens.hpp"
+#include "block.hpp"
 
 namespace shk {
 
@@ -378,8 +379,45 @@ template <typename R> struct Buffers {
   cx<R>* u = nullptr;
   std::vector<cx<R>*> mb, mx, mdinv;
   unsigned* mpack = nullptr;   // the V-cycle tail's packed coefficients
+  // block FGMRES-Sh (one basis shared by the S right-hand sides)
+  c128* Hb = nullptr;          // block Hessenberg, ((m+1) S) x (m S) column-major
+  void* gpart = nullptr;       // chunk partials of the block projections
+  cx<R>* Cc = nullptr;         // this pass's projection coefficients, (m+1) blocks S x S
+  cx<R>* Rinv = nullptr;       // inverse of a CholQR factor (S x S, row-major)
+  c128 *Gm = nullptr, *Rrow = nullptr, *beta_blk = nullptr, *Rinv64 = nullptr;
+  double* fro = nullptr;       // ||H_{k+1,k}||_F^2
+  int* broke = nullptr;        // breakdown flag of the current step
+  c128 *Rf = nullptr, *Vr = nullptr, *Gq = nullptr, *Yp = nullptr;
+  double *Tr = nullptr, *brho = nullptr;
+  int* want = nullptr;
   size_t bytes;
 };
+
+// Chunk partials of one block projection: at most BLK_WAVES waves' S x S
+// complex128 results.
+constexpr int BLK_WAVES = 2048;
+
+// Block-basis buffers (block FGMRES-Sh) for nf shifts, S columns, m steps.
+template <typename R> static void carve_block(Carver& cv, Buffers<R>& b, int m, int nf, int S) {
+  const size_t ldh = (size_t)(m + 1) * S, mS = (size_t)m * S;
+  b.Hb = cv.take<c128>(ldh * mS);
+  b.gpart = cv.take<c128>((size_t)BLK_WAVES * S * S);
+  b.Cc = cv.take<cx<R>>((m + 1) * (size_t)S * S);
+  b.Rinv = cv.take<cx<R>>((size_t)S * S);
+  b.Gm = cv.take<c128>((size_t)S * S);
+  b.Rrow = cv.take<c128>((size_t)S * S);
+  b.beta_blk = cv.take<c128>((size_t)S * S);
+  b.Rinv64 = cv.take<c128>((size_t)S * S);
+  b.fro = cv.take<double>(2);
+  b.broke = cv.take<int>(4);
+  b.Rf = cv.take<c128>((size_t)nf * (mS * (mS + 1) / 2));
+  b.Vr = cv.take<c128>((size_t)nf * m * S * (S + 1));
+  b.Tr = cv.take<double>((size_t)nf * m * S);
+  b.Gq = cv.take<c128>((size_t)nf * ldh * S);
+  b.Yp = cv.take<c128>((size_t)nf * S * mS);
+  b.brho = cv.take<double>((size_t)nf * S);
+  b.want = cv.take<int>((size_t)nf * S);
+}
 
 // Multigrid buffers for S lanes over the coarse levels of p (none: no levels).
 template <typename R> static void carve_mg(Carver& cv, Buffers<R>& b, const shk_problem* p, long N, int S) {
@@ -479,7 +517,8 @@ static void gram_schmidt(long N, int S, int kc, cx<R>* V, cx<R>* w, c128* H, c12
 }
 
 template <typename R>
-static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, int s_real, bool host_x, bool mg) {
+static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, int s_real, bool host_x, bool mg,
+                        bool block = false) {
   Carver cv{base};
   const long n = p->n;
   Buffers<R> b{};
@@ -535,16 +574,23 @@ static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, 
   const int Gr = resid_grid(n);
   b.rpart = cv.take<c128>((size_t)s_real * nf * Gr);
   b.rrow = cv.take<c128>((size_t)s_real * nf);
+  if (block) carve_block(cv, b, m, nf, S);
   b.bytes = cv.off;
   return b;
 }
 
-static int lanes_of(int n_rhs) { return std::min(64, next_pow2(std::max(1, n_rhs))); }
+// Lanes of a group of n_rhs right-hand sides: the next power of two up to 64;
+// the shared block basis takes at least 16 (the matrix-core tile width; the
+// extra columns are zero and drop out of the basis).
+static int lanes_of(int n_rhs, bool block = false) {
+  const int s = std::min(64, next_pow2(std::max(1, n_rhs)));
+  return block ? std::max(16, s) : s;
+}
 
 static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real, int precision, bool host_x,
-                          bool mg) {
-  if (precision == SHK_MIXED) return carve<float>(nullptr, p, m, nf, S, s_real, host_x, mg).bytes;
-  return carve<double>(nullptr, p, m, nf, S, s_real, host_x, mg).bytes;
+                          bool mg, bool block) {
+  if (precision == SHK_MIXED) return carve<float>(nullptr, p, m, nf, S, s_real, host_x, mg, block).bytes;
+  return carve<double>(nullptr, p, m, nf, S, s_real, host_x, mg, block).bytes;
 }
 
 // ------------------------------------------------------- lane totals -------
@@ -589,6 +635,85 @@ struct Snap {
   int live;   // iteration launches that did work since the solve started
   int pad[2];
   CgScal sc[64];
+};
+
+// Block-basis operations on n x S blocks (block FGMRES-Sh), with the scratch
+// they need: chunk partials, coefficients, CholQR factors.
+template <typename R> struct BlkCtx {
+  long n;
+  int S;
+  hipStream_t st;
+  void* gpart;        // chunk partials (BLK_WAVES S x S complex128)
+  cx<R>* Cc;          // projection coefficients, up to (m+1) S x S blocks
+  cx<R>* Rinv;        // S x S
+  c128 *Gm, *Rrow, *Rinv64;
+  double* fro;
+
+  // C = A^H B over nb blocks of A (astride apart) against one block B, summed
+  // into Hcol (rows iS.., leading dimension ldh; add != 0 accumulates) and/or
+  // rounded into Cc.  TAcc: accumulation of the matrix-core products.
+  template <typename TIn, typename TAcc, int TM>
+  void project_tm(const cx<TIn>* A, size_t astride, int nb, const cx<TIn>* Bm, c128* Hcol, int ldh, int add,
+                  cx<R>* C) const {
+    constexpr bool dbl = std::is_same<TAcc, double>::value;
+    constexpr int TN = dbl ? 1 : TM, ZG = TM / TN;
+    const long ncap = std::max<long>(1, (n + 63) / 64);
+    long nch = std::max<long>(1, std::min<long>(ncap, BLK_WAVES / ((long)nb * ZG)));
+    long ch = (n + nch - 1) / nch;
+    ch = (ch + 3) & ~3L;
+    nch = (n + ch - 1) / ch;
+    auto* part = reinterpret_cast<cx<TAcc>*>(gpart);
+    k_blk_gram<TIn, TAcc, TM, TN><<<dim3((unsigned)nch, (unsigned)nb, ZG), 64, 0, st>>>(A, astride, Bm, n, (int)ch,
+                                                                                       part);
+    k_blk_reduce<TAcc, R><<<dim3((unsigned)((S * S + BS - 1) / BS), (unsigned)nb), BS, 0, st>>>(part, (int)nch, S,
+                                                                                                 Hcol, ldh, add, C);
+  }
+  template <typename TIn, typename TAcc>
+  void project(const cx<TIn>* A, size_t astride, int nb, const cx<TIn>* Bm, c128* Hcol, int ldh, int add,
+               cx<R>* C) const {
+    if (S == 64) project_tm<TIn, TAcc, 4>(A, astride, nb, Bm, Hcol, ldh, add, C);
+    else if (S == 32) project_tm<TIn, TAcc, 2>(A, astride, nb, Bm, Hcol, ldh, add, C);
+    else project_tm<TIn, TAcc, 1>(A, astride, nb, Bm, Hcol, ldh, add, C);
+  }
+  // Out = beta In + sgn sum_i A_i C_i (C row-major S x S blocks)
+  template <typename TIn, typename TC, typename TOut, int TM>
+  void apply_tm(const cx<TIn>* A, size_t astride, int nb, const cx<TC>* C, const cx<TOut>* In, cx<TOut>* Out,
+                double beta, double sgn) const {
+    constexpr int TMC = std::is_same<TC, double>::value ? 1 : 2;
+    const long cells = 4L * 16 * TMC;
+    const size_t lds = (size_t)S * (S + 1) * sizeof(cx<TC>);
+    k_blk_update<TIn, TC, TOut, TM, TMC><<<(unsigned)((n + cells - 1) / cells), 256, lds, st>>>(
+        A, astride, nb, C, In, Out, n, (TC)beta, (TC)sgn);
+  }
+  template <typename TIn, typename TC, typename TOut>
+  void apply(const cx<TIn>* A, size_t astride, int nb, const cx<TC>* C, const cx<TOut>* In, cx<TOut>* Out,
+             double beta, double sgn) const {
+    if (S == 64) apply_tm<TIn, TC, TOut, 4>(A, astride, nb, C, In, Out, beta, sgn);
+    else if (S == 32) apply_tm<TIn, TC, TOut, 2>(A, astride, nb, C, In, Out, beta, sgn);
+    else apply_tm<TIn, TC, TOut, 1>(A, astride, nb, C, In, Out, beta, sgn);
+  }
+  // Block classical Gram-Schmidt with one reorthogonalisation of W against
+  // nb blocks of V: H(0:nb, col) = V^H W, W -= V H, twice (H summed).
+  void cgs2(const cx<R>* V, size_t vstride, int nb, cx<R>* W, c128* Hcol, int ldh) const {
+    for (int pass = 0; pass < 2; ++pass) {
+      project<R, R>(V, vstride, nb, W, Hcol, ldh, pass, Cc);
+      apply<R, R, R>(V, vstride, nb, Cc, W, W, 1.0, -1.0);
+    }
+  }
+  // CholQR2 of the block W (n x S, precision TIn) into Vout (precision R):
+  // two passes of G = W^H W (FP64 products), G = R^H R, W <- W R^{-1}.  R =
+  // R2 R1 goes to Rout (column-major, leading dimension ldh; may be null) and
+  // row-major to Rrow_out (may be null); ||R||_F^2 to fro.
+  template <typename TIn> void qr(const cx<TIn>* W, cx<R>* Vout, c128* Rout, int ldh, c128* Rrow_out) const {
+    const size_t lds = 2 * (size_t)S * S * sizeof(c128);
+    cx<TIn>* rinv1 = reinterpret_cast<cx<TIn>*>(std::is_same<TIn, double>::value ? (void*)Rinv64 : (void*)Rinv);
+    project<TIn, double>(W, 0, 1, W, Gm, S, 0, nullptr);
+    k_blk_chol<TIn><<<1, 256, lds, st>>>(Gm, S, nullptr, nullptr, 0, Rrow, rinv1, nullptr);
+    apply<TIn, TIn, R>(W, 0, 1, rinv1, nullptr, Vout, 0.0, 1.0);
+    project<R, double>(Vout, 0, 1, Vout, Gm, S, 0, nullptr);
+    k_blk_chol<R><<<1, 256, lds, st>>>(Gm, S, Rrow, Rout, ldh, Rrow_out, Rinv, fro);
+    apply<R, R, R>(Vout, 0, 1, Rinv, nullptr, Vout, 0.0, 1.0);
+  }
 };
 
 template <typename R, typename Op, typename OpD> struct Group {
@@ -1252,6 +1377,95 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
     return SHK_OK;
   }
+
+  // ---- block FGMRES-Sh: one basis shared by the S right-hand sides ----
+  BlkCtx<R> blk() const {
+    return BlkCtx<R>{n, S, st, B.gpart, B.Cc, B.Rinv, B.Gm, B.Rrow, B.Rinv64, B.fro};
+  }
+
+  // One block FGMRES-Sh pass for the S right-hand sides in `rhs` (interleaved
+  // c128): block flexible Arnoldi with block CGS2 and CholQR2, each shift's
+  // block least squares updated per step, per-(shift, rhs) freezing by the
+  // rule of eq. trueresidual, no restart (pairs still running after m block
+  // steps keep their least-squares iterate), then X (+)= scale Z y.
+  int pass_block(const c128* rhs, const PassSpec& ps, c128* X, bool accumulate, const c128* extra) {
+    const int Lb = (L + BS - 1) / BS;
+    const int ldh = (m + 1) * S, mS = m * S;
+    const int Gn = grid_items(N, 1024);
+    k_norm2<double><<<Gn, BS, 0, st>>>(rhs, N, S, B.part);
+    launch_final_sqrt<1>(B.part, Gn, S, B.beta0, nullptr, nullptr, st);
+    k_lanes_init<<<Lb, BS, 0, st>>>(L, S, s_real, B.beta0, B.ls, B.g);
+    // pairs that stop early keep zeros beyond their own basis length
+    SHK_HIP(hipMemsetAsync(B.Yp, 0, sizeof(c128) * (size_t)L * mS, st));
+    // start block: rhs = V_1 beta
+    const BlkCtx<R> bc = blk();
+    bc.template qr<double>(rhs, B.V, nullptr, 0, B.beta_blk);
+    k_blk_g_init<<<grid_items((long)nf * ldh * S, 4096), BS, 0, st>>>(S, ldh, nf, B.beta_blk, B.Gq);
+    SHK_HIP(hipGetLastError());
+    const std::vector<c128>& taus = *ps.taus;
+    char* stage = (char*)g_pinned.get(65536);
+    int* nact = stage ? (int*)(stage + 32768) : nullptr;
+    if (!nact) return fail(SHK_ERR_OOM, "pinned staging");
+    double* qmax = (double*)(stage + 32768 + 64 * sizeof(int));
+    double eps_k = ps.eps;
+    const size_t lsq_lds = (size_t)S * (S + 1) * sizeof(c128) + S * sizeof(double) + 2 * (S + 1) * sizeof(c128) +
+                           2 * sizeof(double);
+    int kend = 0;
+    long long kglob = ps.kglob0;
+    for (int k = 0; k < m; ++k) {
+      const c128 tau = taus[(size_t)(kglob % (long long)taus.size())];
+      ++kglob;
+      cx<R>* Vk = B.V + (size_t)k * N;
+      SHK_TRY(inner(tau, Vk, B.Z + (size_t)k * N, eps_k, ps.inner_maxit, 0, B.pn + (size_t)k * S));
+      // block CGS2: H(0:k, k) = V^H W, W -= V H, twice
+      c128* Hcol = B.Hb + (size_t)ldh * k * S;
+      bc.cgs2(B.V, (size_t)N, k + 1, B.W, Hcol, ldh);
+      // W = V_{k+1} H(k+1, k)
+      bc.template qr<R>(B.W, B.V + (size_t)(k + 1) * N, Hcol + (size_t)(k + 1) * S, ldh, nullptr);
+      k_blk_breakdown<<<1, 64, 0, st>>>(B.fro, B.mz, S, B.broke);
+      // each shift's block least squares, then the pairs near their target
+      BlkLsqArgs la{S, m, k, nf, ldh, B.Hb, B.sigma, tau, B.Rf, B.Vr, B.Tr, B.Gq, B.brho, B.ls};
+      k_blk_lsq<<<nf, BLK_LSQ_THREADS, lsq_lds, st>>>(la);
+      const bool last = k == m - 1;
+      k_blk_mark<<<Lb, BS, 0, st>>>(L, S, B.brho, B.beta0, 100.0 * ps.tol, last ? 1 : 0, B.broke, outer_steps + 1,
+                                    B.ls, B.want);
+      BlkSolveArgs sa{S, m, k + 1, nf, ldh, outer_steps + 1, last ? 1 : 0, B.Rf, B.Gq, B.want, B.Yp, B.pn,
+                      B.brho, B.beta0, ps.tol, 0.1, B.broke, B.ls};
+      k_blk_backsolve<<<nf, BS, 0, st>>>(sa);
+      k_count_active<<<1, BS, 0, st>>>(S, nf, B.ls, B.beta0, B.nact, B.qmax);
+      SHK_HIP(hipGetLastError());
+      int brk = 0;
+      SHK_HIP(hipMemcpyAsync(nact, B.nact, S * sizeof(int), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipMemcpyAsync(qmax, B.qmax, S * sizeof(double), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipMemcpyAsync(&brk, B.broke, sizeof(int), hipMemcpyDeviceToHost, st));
+      SHK_HIP(hipStreamSynchronize(st));
+      ++outer_steps;
+      kend = k + 1;
+      if (ps.relax > 0.0) {
+        double q = 0.0;
+        for (int r = 0; r < S; ++r) q = std::max(q, qmax[r]);
+        if (q > 0.0) eps_k = std::min(ps.eps_max, std::max(ps.eps, ps.relax * ps.tol / q));
+      }
+      int tot = 0;
+      for (int r = 0; r < S; ++r) tot += nact[r];
+      if (tot == 0 || brk) break;
+    }
+    // pairs still running (breakdown with some pair undecided cannot happen:
+    // a breakdown step decides every active pair)
+    k_finalize_active<<<Lb, BS, 0, st>>>(L, B.ls);
+    assemble_block(kend, extra, X, accumulate);
+    SHK_HIP(hipGetLastError());
+    return SHK_OK;
+  }
+  // X[:, j, r] (+)= extra_{j,r} Z y_{j,r} over kc block columns (FP64, matrix cores).
+  void assemble_block(int kc, const c128* extra, c128* X, bool accumulate) {
+    const int mS = m * S;
+    const size_t lds = (size_t)S * (S + 1) * sizeof(c128);
+    const dim3 g((unsigned)((n + 63) / 64), (unsigned)nf);
+    if (S == 64) k_blk_assemble<4, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, accumulate ? 1 : 0);
+    else if (S == 32) k_blk_assemble<2, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, accumulate ? 1 : 0);
+    else k_blk_assemble<1, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, accumulate ? 1 : 0);
+  }
 };
 
 // FP64 true residual norms ||b_r - (K + sigma_j M) x_{j,r}||, rows [r][j].
@@ -1274,12 +1488,13 @@ static int residual_rows(const OpD& opd, long n, int S, int s_real, int nf, cons
 template <typename R>
 static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128* sigma_h, int s_real,
                        const c128* b_src, int ptr_kind, c128* x_dst, shk_status* st_out, char* ws, hipStream_t st) {
-  const int S = lanes_of(s_real);
+  const bool blk = prm->rhs_mode == SHK_RHS_BLOCK;
+  const int S = lanes_of(s_real, blk);
   const int m = prm->m_restart;
   const long n = p->n;
   const bool host_x = ptr_kind == SHK_PTR_HOST;
   const bool use_mg = prm->inner_precond == SHK_PRECOND_MULTIGRID;
-  Buffers<R> B = carve<R>(ws, p, m, nf, S, s_real, host_x, use_mg);
+  Buffers<R> B = carve<R>(ws, p, m, nf, S, s_real, host_x, use_mg, blk);
   c128* X = host_x ? B.X : x_dst;
   const long N = n * S;
   // rhs into interleaved c128
@@ -1308,7 +1523,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     g.mgs = prm->ortho == SHK_MGS;
     PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0, prm->inner_relax, prm->inner_eps_max,
                 prm->variant == SHK_FOM};
-    SHK_TRY(g.pass(B.bint, ps, X, false, nullptr));
+    SHK_TRY(blk ? g.pass_block(B.bint, ps, X, false, nullptr) : g.pass(B.bint, ps, X, false, nullptr));
     SHK_HIP(hipMemcpyAsync(lanes.data(), B.ls, sizeof(LaneState) * nf * S, hipMemcpyDeviceToHost, st));
     SHK_HIP(hipMemcpyAsync(bnorm.data(), B.beta0, sizeof(double) * S, hipMemcpyDeviceToHost, st));
     SHK_HIP(hipStreamSynchronize(st));
@@ -1364,7 +1579,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
       SHK_HIP(hipMemcpyAsync(B.extra, extra.data(), sizeof(c128) * nf * S, hipMemcpyHostToDevice, st));
       PassSpec pr{m, prm->max_restarts, maxit, prm->refine_tol, prm->refine_eps_inner, &taus, 0, prm->inner_relax,
                   prm->inner_eps_max, prm->variant == SHK_FOM};
-      SHK_TRY(g.pass(B.rsv, pr, X, true, B.extra));
+      SHK_TRY(blk ? g.pass_block(B.rsv, pr, X, true, B.extra) : g.pass(B.rsv, pr, X, true, B.extra));
       SHK_TRY(measure());
     }
     inner_total = g.inner_its;
@@ -1413,6 +1628,12 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
     if (prm->mg_sweeps != 1) return fail(SHK_ERR_UNSUPPORTED, "mg_sweeps must be 1");
     if (!(prm->mg_omega > 0.0 && prm->mg_omega <= 1.0)) return fail(SHK_ERR_INVALID_ARG, "mg_omega must be in (0, 1]");
   }
+  if (prm->rhs_mode != SHK_RHS_LOCKSTEP && prm->rhs_mode != SHK_RHS_BLOCK) return fail(SHK_ERR_INVALID_ARG, "rhs_mode");
+  if (prm->rhs_mode == SHK_RHS_BLOCK) {
+    if (prm->variant != SHK_GMRES) return fail(SHK_ERR_UNSUPPORTED, "the shared block basis solves least squares (GMRES) only");
+    if (prm->ortho != SHK_CGS2) return fail(SHK_ERR_UNSUPPORTED, "the shared block basis uses block CGS2");
+    if (prm->m_restart > 100) return fail(SHK_ERR_INVALID_ARG, "m_restart must be <= 100 with the shared block basis");
+  }
   if (!(prm->inner_relax >= 0.0) || !std::isfinite(prm->inner_relax))
     return fail(SHK_ERR_INVALID_ARG, "inner_relax must be finite and >= 0");
   if (prm->inner_relax > 0.0 && !(prm->inner_eps_max >= prm->eps_inner && prm->inner_eps_max < 1.0))
@@ -1425,8 +1646,9 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
 
 size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x) {
   const int s_real = std::min(n_rhs, 64);
-  return group_bytes(p, prm->m_restart, nf, lanes_of(s_real), s_real, prm->precision, host_x,
-                     prm->inner_precond == SHK_PRECOND_MULTIGRID);
+  const bool blk = prm->rhs_mode == SHK_RHS_BLOCK;
+  return group_bytes(p, prm->m_restart, nf, lanes_of(s_real, blk), s_real, prm->precision, host_x,
+                     prm->inner_precond == SHK_PRECOND_MULTIGRID, blk);
 }
 
 int solve_all(shk_problem* p, const shk_params* prm, int nf, const c128* sigma, int n_rhs, const c128* b, c128* x,
@@ -1585,6 +1807,98 @@ int step_orth(long long n, int S, int k, void* V, void* w, c128* h, int precisio
     return SHK_OK;
   };
   return precision == SHK_MIXED ? run(float{}) : run(double{});
+}
+
+// Block orthogonalisation step (block CGS2 + CholQR2) on device blocks.
+int step_block_orth(long long n, int S, int k, void* V, void* W, c128* h, int precision, hipStream_t st) {
+  if (!V || !W || !h || k < 0 || n < 1 || (S != 16 && S != 32 && S != 64))
+    return fail(SHK_ERR_INVALID_ARG, "block orthogonalisation arguments (S in {16, 32, 64})");
+  auto run = [&](auto tag) -> int {
+    using R = decltype(tag);
+    const long N = (long)n * S;
+    const int ldh = (k + 1) * S;
+    auto lay = [&](Carver& c, Buffers<R>& b) {
+      b.gpart = c.take<c128>((size_t)BLK_WAVES * S * S);
+      b.Cc = c.take<cx<R>>((size_t)(k + 1) * S * S);
+      b.Rinv = c.take<cx<R>>((size_t)S * S);
+      b.Gm = c.take<c128>((size_t)S * S); b.Rrow = c.take<c128>((size_t)S * S);
+      b.Rinv64 = c.take<c128>((size_t)S * S); b.fro = c.take<double>(2);
+      b.Hb = c.take<c128>((size_t)ldh * S);
+    };
+    Carver cv{nullptr};
+    Buffers<R> b0{};
+    lay(cv, b0);
+    DevBuf mem;
+    SHK_HIP(hipMalloc(&mem.p, cv.off));
+    Carver c2{(char*)mem.p};
+    Buffers<R> b{};
+    lay(c2, b);
+    const BlkCtx<R> bc{(long)n, S, st, b.gpart, b.Cc, b.Rinv, b.Gm, b.Rrow, b.Rinv64, b.fro};
+    cx<R>* Vp = (cx<R>*)V;
+    if (k > 0) bc.cgs2(Vp, (size_t)N, k, (cx<R>*)W, b.Hb, ldh);
+    bc.template qr<R>((cx<R>*)W, Vp + (size_t)k * N, b.Hb + (size_t)k * S, ldh, nullptr);
+    SHK_HIP(hipGetLastError());
+    SHK_HIP(hipMemcpyAsync(h, b.Hb, sizeof(c128) * (size_t)ldh * S, hipMemcpyDeviceToHost, st));
+    SHK_HIP(hipStreamSynchronize(st));
+    return SHK_OK;
+  };
+  return precision == SHK_MIXED ? run(float{}) : run(double{});
+}
+
+// Block least squares of every shift for a given block Hessenberg (host).
+int step_block_lsq(int K, int S, const c128* H, const c128* taus, int nf, const c128* sigma, const c128* beta,
+                   c128* y, double* rho) {
+  if (K < 1 || nf < 1 || !H || !taus || !sigma || !beta || !y || !rho || (S != 16 && S != 32 && S != 64))
+    return fail(SHK_ERR_INVALID_ARG, "block least-squares arguments (S in {16, 32, 64})");
+  const int m = K, ldh = (m + 1) * S, mS = m * S, L = nf * S;
+  Carver cv{nullptr};
+  Buffers<double> b0{};
+  auto lay = [&](Carver& c, Buffers<double>& b) {
+    b.Hb = c.take<c128>((size_t)ldh * mS); b.sigma = c.take<c128>(nf); b.beta_blk = c.take<c128>((size_t)S * S);
+    b.Rf = c.take<c128>((size_t)nf * rpk(0, mS)); b.Vr = c.take<c128>((size_t)nf * m * S * (S + 1));
+    b.Tr = c.take<double>((size_t)nf * m * S); b.Gq = c.take<c128>((size_t)nf * ldh * S);
+    b.Yp = c.take<c128>((size_t)L * mS); b.brho = c.take<double>(L); b.want = c.take<int>(L);
+    b.pn = c.take<double>((size_t)mS); b.beta0 = c.take<double>(S); b.ls = c.take<LaneState>(L);
+    b.broke = c.take<int>(4); b.g = c.take<c128>(L);
+  };
+  lay(cv, b0);
+  DevBuf mem;
+  SHK_HIP(hipMalloc(&mem.p, cv.off));
+  SHK_HIP(hipMemset(mem.p, 0, cv.off));
+  Carver c2{(char*)mem.p};
+  Buffers<double> b{};
+  lay(c2, b);
+  SHK_HIP(hipMemcpy(b.Hb, H, sizeof(c128) * (size_t)ldh * mS, hipMemcpyHostToDevice));
+  SHK_HIP(hipMemcpy(b.sigma, sigma, sizeof(c128) * nf, hipMemcpyHostToDevice));
+  // beta: column-major on the host, row-major for the start of G
+  std::vector<c128> brow((size_t)S * S);
+  std::vector<double> bn(S, 0.0);
+  for (int r = 0; r < S; ++r)
+    for (int i = 0; i < S; ++i) {
+      brow[(size_t)i * S + r] = beta[i + (size_t)S * r];
+      bn[r] += beta[i + (size_t)S * r].re * beta[i + (size_t)S * r].re + beta[i + (size_t)S * r].im * beta[i + (size_t)S * r].im;
+    }
+  for (int r = 0; r < S; ++r) bn[r] = std::sqrt(bn[r]);
+  SHK_HIP(hipMemcpy(b.beta_blk, brow.data(), sizeof(c128) * brow.size(), hipMemcpyHostToDevice));
+  SHK_HIP(hipMemcpy(b.beta0, bn.data(), sizeof(double) * S, hipMemcpyHostToDevice));
+  k_lanes_init<<<(L + BS - 1) / BS, BS>>>(L, S, S, b.beta0, b.ls, b.g);
+  k_blk_g_init<<<grid_items((long)nf * ldh * S, 4096), BS>>>(S, ldh, nf, b.beta_blk, b.Gq);
+  const size_t lsq_lds = (size_t)S * (S + 1) * sizeof(c128) + S * sizeof(double) + 2 * (S + 1) * sizeof(c128) +
+                         2 * sizeof(double);
+  std::vector<double> hr(L);
+  for (int k = 0; k < K; ++k) {
+    BlkLsqArgs la{S, m, k, nf, ldh, b.Hb, b.sigma, taus[k], b.Rf, b.Vr, b.Tr, b.Gq, b.brho, b.ls};
+    k_blk_lsq<<<nf, BLK_LSQ_THREADS, lsq_lds>>>(la);
+    SHK_HIP(hipGetLastError());
+    SHK_HIP(hipMemcpy(hr.data(), b.brho, sizeof(double) * L, hipMemcpyDeviceToHost));
+    for (int p = 0; p < L; ++p) rho[p + (size_t)L * k] = hr[p];
+  }
+  k_blk_mark<<<(L + BS - 1) / BS, BS>>>(L, S, b.brho, b.beta0, 0.0, 1, b.broke, K, b.ls, b.want);
+  BlkSolveArgs sa{S, m, K, nf, ldh, K, 1, b.Rf, b.Gq, b.want, b.Yp, b.pn, b.brho, b.beta0, 0.0, -1.0, b.broke, b.ls};
+  k_blk_backsolve<<<nf, BS>>>(sa);
+  SHK_HIP(hipGetLastError());
+  SHK_HIP(hipMemcpy(y, b.Yp, sizeof(c128) * (size_t)L * mS, hipMemcpyDeviceToHost));
+  return SHK_OK;
 }
 
 int step_lsq(int K, const c128* H, const c128* taus, int nf, const c128* sigma, double beta, c128* y, double* rho,

@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shifted solves/s at rel-res 1e-6 (mixed batched vs plain FP64); p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
+BLOCK_M = 30   # block steps of the shared block basis (the batched workloads need 17-20)
 
 
 def kernel_source_digest():
@@ -159,7 +160,25 @@ def sensitivity_bench(P, torch, w, make, n_src=8, n_rec=8, reps=5):
     return out
 
 
-def time_batched(P, torch, w, make, precision, single_rhs_sample=0, label=None):
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+
+
+def block_gs_roofline(prof, precision_name):
+    """Matrix-core roofline of the block Gram-Schmidt of the shared block basis
+    (two projections V^H W and two updates W -= V C per block step, timed
+    live with HIP events on the solve stream): achieved flops per second
+    against the dense MFMA peak of its arithmetic type."""
+    calls, ms, flops = prof
+    if calls <= 0 or ms <= 0:
+        return None
+    tf = flops / (ms / 1e3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[precision_name]
+    return {"bound": "mfma", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+            "traffic": None, "kernel": f"k_blk_gram + k_blk_reduce + k_blk_update ({precision_name} 16x16x4 MFMA)",
+            "calls": calls, "avg_call_us": round(ms / calls * 1e3, 2), "flops_per_call": round(flops / calls)}
+
+
+def time_batched(P, torch, w, make, precision, single_rhs_sample=0, label=None, rhs_mode=None, m_restart=None):
     """One solve of a multi-rhs workload (all rhs in lockstep); with
     single_rhs_sample > 0, instead that many rhs solved one at a time and the
     rate scaled to all of them (multigrid-preconditioned inner solves).
@@ -168,8 +187,11 @@ def time_batched(P, torch, w, make, precision, single_rhs_sample=0, label=None):
     workload, from one more solve with the library's per-iteration events
     (kept out of the timed solve)."""
     gp = make(w)
-    prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
-                              eps_inner=w.eps_inner, precision=precision, inner_precond=P.SHK_PRECOND_MULTIGRID)
+    block = rhs_mode == P.SHK_RHS_BLOCK
+    prm, keep = P.make_params(w.tau_seq, m_restart=m_restart or w.m_restart, max_restarts=20, max_refine=4,
+                              tol=w.tol, eps_inner=w.eps_inner, precision=precision,
+                              inner_precond=P.SHK_PRECOND_MULTIGRID,
+                              rhs_mode=P.SHK_RHS_LOCKSTEP if rhs_mode is None else rhs_mode)
     nf, nr = len(w.sigma), w.b.shape[1]
     cols = list(range(single_rhs_sample)) if single_rhs_sample else [list(range(nr))]
     worst, ok, total = 0.0, True, 0.0
@@ -188,14 +210,20 @@ def time_batched(P, torch, w, make, precision, single_rhs_sample=0, label=None):
         ok &= bool((st["status"] == P.SHK_CONVERGED).all())
     solves = nf * (len(cols) if single_rhs_sample else nr)
     out = {"solves_per_s": round(solves / total, 1), "ms": round(total * 1e3, 1), "converged": ok,
-           "max_true_relres": worst}
+           "max_true_relres": worst, "outer_steps": int(st["outer_its"].max()),
+           "inner_iterations": int(st["inner_its"][0, 0]), "refine_sweeps": int(st["refine_sweeps"].max())}
+    if block:
+        out["m_restart"] = prm.m_restart
     if label is not None:
         P.shk_profile_enable(True)
         P.fgmres_sh_solve(gp, prm, w.sigma, b)
         torch.cuda.synchronize()
         prof = P.shk_profile_read()
+        bprof = P.shk_profile_read_block()
         P.shk_profile_enable(False)
         out["roofline_iteration"] = roofline(prof, "none", label, "iteration")
+        if block:
+            out["roofline_block_gs"] = block_gs_roofline(bprof, "fp32" if precision == P.SHK_MIXED else "fp64")
     gp.close()
     return out
 
@@ -246,9 +274,9 @@ def main():
                     help="inner preconditioner of --single-solve")
     ap.add_argument("--sensitivity-only", action="store_true",
                     help="run only the sensitivity measurement of the 256x256 workload and exit (profiler passes)")
-    ap.add_argument("--batched-only", choices=["2d", "3d"], default=None,
-                    help="run only the mixed batched 256x256 x 64 rhs (2d) or 128^3 x 8 rhs (3d) workload and "
-                         "exit (profiler passes)")
+    ap.add_argument("--batched-only", choices=["2d", "3d", "2d-block", "3d-block"], default=None,
+                    help="run only the mixed batched 256x256 x 64 rhs (2d) or 128^3 x 8 rhs (3d) workload, with "
+                         "independent bases or the shared block basis (-block), and exit (profiler passes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device-to-device with a plain copy kernel and exit "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -262,11 +290,14 @@ def main():
     import synth
     torch.cuda.set_device(0)
     if a.batched_only:
-        if a.batched_only == "2d":
+        if a.batched_only.startswith("2d"):
             wb, mk, name = synth.config3(), (lambda w: P.Problem.fv2d(w.cell_K, w.Ss, w.h)), "2-D FV 256x256, 64 rhs"
         else:
             wb, mk, name = synth.config4(), (lambda w: P.Problem.fv3d(w.cell_K, w.Ss, w.h)), "3-D FV 128^3, 8 rhs"
-        r = time_batched(P, torch, wb, mk, P.SHK_MIXED, label=f"multigrid-COCG inner iteration, {name}, complex64")
+        blk = a.batched_only.endswith("block")
+        r = time_batched(P, torch, wb, mk, P.SHK_MIXED, label=f"multigrid-COCG inner iteration, {name}, complex64",
+                         rhs_mode=P.SHK_RHS_BLOCK if blk else None, m_restart=BLOCK_M if blk else None)
+        name += ", shared block basis" if blk else ""
         print(json.dumps({"workload": name, **r}), flush=True)
         return
     if a.copy_calibration:
@@ -358,8 +389,14 @@ def main():
             "2-D FV 256x256, 50 shifts, 64 rhs": {
                 "mixed_batched": time_batched(P, torch, w3, mk2, P.SHK_MIXED,
                                               label="multigrid-COCG inner iteration, 64 lanes, complex64"),
+                "mixed_block": time_batched(P, torch, w3, mk2, P.SHK_MIXED, rhs_mode=P.SHK_RHS_BLOCK,
+                                            m_restart=BLOCK_M,
+                                            label="multigrid-COCG inner iteration, 64 lanes, complex64"),
                 "fp64_batched": time_batched(P, torch, w3, mk2, P.SHK_FP64,
                                              label="multigrid-COCG inner iteration, 64 lanes, complex128"),
+                "fp64_block": time_batched(P, torch, w3, mk2, P.SHK_FP64, rhs_mode=P.SHK_RHS_BLOCK,
+                                           m_restart=BLOCK_M,
+                                           label="multigrid-COCG inner iteration, 64 lanes, complex128"),
                 "fp64_single_rhs": dict(time_batched(P, torch, w3, mk2, P.SHK_FP64, single_rhs_sample=4),
                                         sample="4 of the 64 rhs solved one at a time, rate over those")},
         }
@@ -368,6 +405,8 @@ def main():
         out["batched"]["3-D FV 128^3, 100 shifts, 8 rhs"] = {
             "mixed_batched": time_batched(P, torch, w4, mk3, P.SHK_MIXED,
                                           label="multigrid-COCG inner iteration, 8 lanes, complex64"),
+            "mixed_block": time_batched(P, torch, w4, mk3, P.SHK_MIXED, rhs_mode=P.SHK_RHS_BLOCK, m_restart=BLOCK_M,
+                                        label="multigrid-COCG inner iteration, 16 lanes (8 padded), complex64"),
             "fp64_batched": time_batched(P, torch, w4, mk3, P.SHK_FP64,
                                          label="multigrid-COCG inner iteration, 8 lanes, complex128")}
     if not a.no_cpu:

@@ -371,6 +371,12 @@ int shk_sensitivity(shk_problem* p, int n_shifts, int n_src, const shk_c128* phi
  * not meant to race with solves on other threads. */
 int shk_profile_enable(int on);
 int shk_profile_read(long long* launches, double* total_ms, double* total_bytes);
+/* With the instrumentation on, each block Gram-Schmidt of the shared block
+ * basis (SHK_RHS_BLOCK: two projections V^H W and two updates W -= V C over
+ * the k + 1 blocks of step k) is bracketed by HIP events on the solve stream:
+ * calls, their summed time and their flops (4 x 8 n (k+1) s^2 real flops per
+ * call, s the block width).  Reset by shk_profile_enable. */
+int shk_profile_read_block(long long* calls, double* total_ms, double* total_flops);
 
 /* Text for a status or error code; last error message of the calling thread. */
 const char* shk_status_string(int code);

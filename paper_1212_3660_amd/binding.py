@@ -98,6 +98,7 @@ _SIGS = {
                                   C.c_int, C.c_void_p]),
     "shk_profile_enable": (C.c_int, [C.c_int]),
     "shk_profile_read": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "shk_profile_read_block": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "shk_status_string": (C.c_char_p, [C.c_int]),
     "shk_last_error": (C.c_char_p, []),
     "shk_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
@@ -406,6 +407,13 @@ def shk_profile_read():
     n, ms, by = C.c_longlong(), C.c_double(), C.c_double()
     _check(lib().shk_profile_read(C.byref(n), C.byref(ms), C.byref(by)), "shk_profile_read")
     return int(n.value), float(ms.value), float(by.value)
+
+
+def shk_profile_read_block():
+    """(calls, total_ms, total_flops) of the timed block Gram-Schmidt steps."""
+    n, ms, fl = C.c_longlong(), C.c_double(), C.c_double()
+    _check(lib().shk_profile_read_block(C.byref(n), C.byref(ms), C.byref(fl)), "shk_profile_read_block")
+    return int(n.value), float(ms.value), float(fl.value)
 
 
 class Server:

@@ -194,5 +194,8 @@ int shk_profile_enable(int on) { return shk::profile_enable(on); }
 int shk_profile_read(long long* launches, double* total_ms, double* total_bytes) {
   return shk::profile_read(launches, total_ms, total_bytes);
 }
+int shk_profile_read_block(long long* calls, double* total_ms, double* total_flops) {
+  return shk::profile_read_block(calls, total_ms, total_flops);
+}
 
 }  // extern "C"

@@ -219,10 +219,13 @@ __global__ void __launch_bounds__(256) k_blk_chol(const c128* __restrict__ G, in
                                                   cx<R>* __restrict__ Rinv, double* __restrict__ fro) {
   extern __shared__ unsigned char blk_lds[];
   c128* A = reinterpret_cast<c128*>(blk_lds);        // [S][S] row-major working copy, then R
-  c128* X = A + S * S;                                // [S][S] R^{-1}
+  c128* X = A + S * S;                                // [S][S] R^{-1}, then Rprev
   __shared__ double dmax;
   __shared__ int dead[64];
+  __shared__ c128 rdi[64];                            // 1 / R_qq (0 for a dependent column)
   const int t = threadIdx.x;
+  // thread t: column jc = t % 64, row group rg = t / 64 (rows rg, rg + 4, ...)
+  const int jc = t & 63, rg = t >> 6;
   for (int e = t; e < S * S; e += 256) A[e] = G[(e % S) * S + e / S];   // G column-major -> row-major
   if (t < 64) dead[t] = 0;
   __syncthreads();
@@ -235,35 +238,42 @@ __global__ void __launch_bounds__(256) k_blk_chol(const c128* __restrict__ G, in
   for (int q = 0; q < S; ++q) {
     const double d = A[q * S + q].re;
     const bool gone = !(d > 1e-26 * dmax);
+    const double rq = gone ? 0.0 : sqrt(d);
+    const double iq = gone ? 0.0 : 1.0 / rq;
     __syncthreads();
-    if (gone) {
-      for (int j = q + t; j < S; j += 256) A[q * S + j] = c128{0.0, 0.0};
-      if (t == 0) dead[q] = 1;
-    } else {
-      const double rq = sqrt(d);
-      for (int j = q + 1 + t; j < S; j += 256) A[q * S + j] = (1.0 / rq) * A[q * S + j];
-      __syncthreads();
-      if (t == 0) A[q * S + q] = c128{rq, 0.0};
+    // row q of R: R_qq = sqrt(d), R_qj = A_qj / R_qq (zero for a dependent column)
+    if (rg == 0 && jc >= q && jc < S) A[q * S + jc] = jc == q ? c128{rq, 0.0} : iq * A[q * S + jc];
+    if (t == 0) {
+      dead[q] = gone ? 1 : 0;
+      rdi[q] = c128{iq, 0.0};
     }
     __syncthreads();
-    // trailing update of the upper triangle: A[i][j] -= conj(R[q][i]) R[q][j]
-    const int nt = S - q - 1;
-    for (int e = t; e < nt * nt; e += 256) {
-      const int i = q + 1 + e / nt, j = q + 1 + e % nt;
-      if (j >= i) A[i * S + j] = A[i * S + j] - conj(A[q * S + i]) * A[q * S + j];
+    // trailing update of the upper triangle: A_ij -= conj(R_qi) R_qj, q < i <= j
+    if (jc > q && jc < S) {
+      const c128 rj = A[q * S + jc];
+      for (int i = q + 1 + rg; i <= jc; i += 4) A[i * S + jc] = A[i * S + jc] - conj(A[q * S + i]) * rj;
     }
     __syncthreads();
   }
-  // R^{-1}, one column per thread, rows from the diagonal up
-  for (int j = t; j < S; j += 256) {
-    for (int i = 0; i < S; ++i) X[i * S + j] = c128{0.0, 0.0};
-    if (!dead[j]) {
-      X[j * S + j] = cdiv(c128{1.0, 0.0}, A[j * S + j]);
-      for (int i = j - 1; i >= 0; --i) {
+  // R^{-1}: column jc by the thread group of rg == 0 (rows upwards, four
+  // independent partial sums per row)
+  if (rg == 0 && jc < S) {
+    for (int i = 0; i < S; ++i) X[i * S + jc] = c128{0.0, 0.0};
+    if (!dead[jc]) {
+      X[jc * S + jc] = rdi[jc];
+      for (int i = jc - 1; i >= 0; --i) {
         if (dead[i]) continue;
-        c128 s{0.0, 0.0};
-        for (int p = i + 1; p <= j; ++p) s = s + A[i * S + p] * X[p * S + j];
-        X[i * S + j] = cdiv(-s, A[i * S + i]);
+        c128 s0{0, 0}, s1{0, 0}, s2{0, 0}, s3{0, 0};
+        int p = i + 1;
+        for (; p + 3 <= jc; p += 4) {
+          s0 = s0 + A[i * S + p] * X[p * S + jc];
+          s1 = s1 + A[i * S + p + 1] * X[(p + 1) * S + jc];
+          s2 = s2 + A[i * S + p + 2] * X[(p + 2) * S + jc];
+          s3 = s3 + A[i * S + p + 3] * X[(p + 3) * S + jc];
+        }
+        for (; p <= jc; ++p) s0 = s0 + A[i * S + p] * X[p * S + jc];
+        const c128 sum = (s0 + s1) + (s2 + s3);
+        X[i * S + jc] = -(rdi[i].re * sum);      // R_ii real positive
       }
     }
   }
@@ -272,22 +282,37 @@ __global__ void __launch_bounds__(256) k_blk_chol(const c128* __restrict__ G, in
     const int i = e / S, j = e % S;
     Rinv[e] = cvt<R>(j >= i ? X[e] : c128{0.0, 0.0});
   }
-  // Rout = R Rprev (both upper triangular)
+  // Rout = R Rprev (both upper triangular), Rprev staged in X's space
+  __syncthreads();
+  if (Rprev)
+    for (int e = t; e < S * S; e += 256) X[e] = Rprev[e];
+  __syncthreads();
   __shared__ double fsum[256];
   double f = 0.0;
-  for (int e = t; e < S * S; e += 256) {
-    const int i = e / S, j = e % S;
-    c128 s{0.0, 0.0};
-    if (j >= i) {
+  if (jc < S) {
+    for (int i = rg; i <= jc; i += 4) {
+      c128 sv{0.0, 0.0};
       if (Rprev) {
-        for (int p = i; p <= j; ++p) s = s + A[i * S + p] * Rprev[p * S + j];
+        c128 s0{0, 0}, s1{0, 0};
+        int p = i;
+        for (; p + 1 <= jc; p += 2) {
+          s0 = s0 + A[i * S + p] * X[p * S + jc];
+          s1 = s1 + A[i * S + p + 1] * X[(p + 1) * S + jc];
+        }
+        for (; p <= jc; ++p) s0 = s0 + A[i * S + p] * X[p * S + jc];
+        sv = s0 + s1;
       } else {
-        s = A[i * S + j];
+        sv = A[i * S + jc];
       }
+      if (Rout) Rout[i + (size_t)ldh * jc] = sv;
+      if (Rrow) Rrow[i * S + jc] = sv;
+      f += abs2(sv);
     }
-    if (Rout) Rout[i + (size_t)ldh * j] = s;
-    if (Rrow) Rrow[e] = s;
-    f += abs2(s);
+    // entries below the diagonal are zero
+    for (int i = jc + 1 + ((rg - (jc + 1) % 4 + 4) % 4); i < S; i += 4) {
+      if (Rout) Rout[i + (size_t)ldh * jc] = c128{0.0, 0.0};
+      if (Rrow) Rrow[i * S + jc] = c128{0.0, 0.0};
+    }
   }
   fsum[t] = f;
   __syncthreads();
@@ -323,11 +348,13 @@ struct BlkLsqArgs {
   const c128* sigma;            // shifts
   c128 tau;                     // preconditioner shift of block column k
   c128* Rf;                     // per shift: m S x m S upper triangle, packed (rpk)
-  c128* Vr;                     // per shift: reflectors [block][q][t = 0..S] (S + 1 entries)
-  double* Tr;                   // per shift: tau of each reflector [block][q]
+  c128* Vr;                     // per shift: this step's reflectors [q][t = 0..S] (S + 1 entries)
+  double* Tr;                   // per shift: their tau [q]
+  c128* Qb;                     // per shift: per block, the 2S x 2S product of its reflectors (column-major)
+  c128* Rdinv;                  // per shift: per block, the inverse of R's diagonal block (S x S column-major)
+  c128* Tile;                   // per shift: the new block column's window rows kS..kS+2S (2S x S column-major)
   c128* Gq;                     // per shift: rotated right-hand sides, ((m + 1) S) x S column-major
   double* rho;                  // per (shift, rhs): ||residual block|| at this step
-  const LaneState* ls;          // frozen pairs need no new quasi-residual
 };
 
 // Applies reflector (v, tau) acting on window rows q..q+S to a column held
@@ -345,127 +372,212 @@ __device__ __forceinline__ void blk_reflect(c128& top, c128& bot, int q, int S, 
   if (ub) bot = bot - vb * ts;
 }
 
-// One outer step k of every shift's block least squares: grid = nf blocks of
-// 1024 threads (16 waves).  Wave w owns block columns c = w, w + 16, ... of
-// the new block column of Hbar(sigma_j;T) and the same columns of G.
-//  1. each owned Hbar column is built (e_{kS+c} + (sigma_j - tau_k) Hbar
-//     column) and the reflectors of blocks 0..k-1 are applied window by
-//     window (rows iS..iS+2S), finished rows going to R;
-//  2. the new block's S reflectors are formed one column at a time (the
-//     owner of column q forms reflector q; one barrier per q) and applied to
-//     the later columns and to G's rows kS..kS+2S;
-//  3. R's diagonal block, the reflectors and G are stored; rho_{j,r} is the
-//     norm of G's rows (k+1)S..(k+2)S in column r.
-constexpr int BLK_LSQ_THREADS = 1024;
-__global__ void __launch_bounds__(BLK_LSQ_THREADS) k_blk_lsq(BlkLsqArgs a) {
+// Entry (row, col) of Hbar(sigma;T) = [I;0] + Hbar (sigma - tau_col) for a
+// column of block column k (ds = sigma - tau_k).
+__device__ __forceinline__ c128 blk_hval(const BlkLsqArgs& a, c128 ds, int row, int col) {
+  c128 v = ds * a.H[row + (size_t)a.ldh * col];
+  if (row == col) v.re += 1.0;
+  return v;
+}
+
+// Step 1 of the per-shift update: the new block column k of Hbar(sigma_j;T)
+// times the earlier blocks' reflectors, block by block.  Block i's S
+// reflectors act on rows iS..iS+2S only; their product Q_i (2S x 2S, formed
+// when block i was factored) is applied as one matrix-core contraction to the
+// 2S-row window of 16 columns held in LDS; rows iS..iS+S are then final
+// entries of R.  Grid (nf, S/16), 256 threads; the window that is left
+// (rows kS..kS+2S) goes to Tile for step 2.
+template <int S>
+__global__ void __launch_bounds__(256) k_blk_lsq_prev(BlkLsqArgs a) {
   extern __shared__ unsigned char blk_lds[];
-  const int S = a.S, k = a.k, j = blockIdx.x, mS = a.m * S;
-  c128* refl = reinterpret_cast<c128*>(blk_lds);               // [S][S+1] reflectors of one block
-  double* rtau = reinterpret_cast<double*>(refl + S * (S + 1)); // [S]
-  c128* nv = reinterpret_cast<c128*>(rtau + S);                // [2][S+1] new reflector (double buffer)
-  double* ntau = reinterpret_cast<double*>(nv + 2 * (S + 1));  // [2]
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int NW = BLK_LSQ_THREADS / 64;
-  const int per = (S + NW - 1) / NW;   // columns per wave (1..4)
+  constexpr int S2 = 2 * S;
+  const int k = a.k, j = blockIdx.x, q0 = 16 * blockIdx.y, mS = a.m * S;
+  c128* win = reinterpret_cast<c128*>(blk_lds);   // [2S][16]
+  c128* nxt = win + S2 * 16;                       // [2S][16]
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, m = lane & 15;
   const c128 ds = a.sigma[j] - a.tau;
-  c128* Rj = a.Rf + (size_t)j * rpk(0, mS);
-  c128* Vj = a.Vr + (size_t)j * a.m * S * (S + 1);
-  double* Tj = a.Tr + (size_t)j * a.m * S;
-  c128* Gj = a.Gq + (size_t)j * a.ldh * S;
   const int col0 = k * S;
-  // owned columns: entries at window rows lane and S + lane
-  c128 top[4], bot[4];
-  auto hval = [&](int row, int c) -> c128 {   // entry of column kS + c of Hbar(sigma;T)
-    const c128 h = a.H[row + (size_t)a.ldh * (col0 + c)];
-    c128 v = ds * h;
-    if (row == col0 + c) v.re += 1.0;
-    return v;
-  };
-  for (int u = 0; u < per; ++u) {
-    const int c = w + NW * u;
-    top[u] = (c < S && lane < S) ? hval(lane, c) : c128{0, 0};
-    bot[u] = (c < S && lane < S) ? hval(S + lane, c) : c128{0, 0};
+  c128* Rj = a.Rf + (size_t)j * rpk(0, mS);
+  for (int e = threadIdx.x; e < S2 * 16; e += 256) {
+    const int row = e >> 4, n = e & 15;
+    win[e] = blk_hval(a, ds, row, col0 + q0 + n);
   }
-  // 1. reflectors of the earlier blocks
+  constexpr int tiles = S2 / 16;
   for (int i = 0; i < k; ++i) {
     __syncthreads();
-    for (int e = threadIdx.x; e < S * (S + 1); e += BLK_LSQ_THREADS) refl[e] = Vj[(size_t)i * S * (S + 1) + e];
-    for (int e = threadIdx.x; e < S; e += BLK_LSQ_THREADS) rtau[e] = Tj[(size_t)i * S + e];
+    const c128* Q = a.Qb + ((size_t)j * a.m + i) * S2 * S2;
+    for (int tl = wv; tl < tiles; tl += 4) {
+      d4m re{0, 0, 0, 0}, im{0, 0, 0, 0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < S2; k0 += 4) {
+        const c128 q = Q[(size_t)(k0 + g) * S2 + 16 * tl + m];
+        const c128 w = win[(k0 + g) * 16 + m];
+        re = mfma16(q.re, w.re, re);
+        re = mfma16(q.im, -w.im, re);
+        im = mfma16(q.re, w.im, im);
+        im = mfma16(q.im, w.re, im);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) nxt[(16 * tl + mfma_row<double>(g, v)) * 16 + m] = c128{re[v], im[v]};
+    }
     __syncthreads();
-    for (int u = 0; u < per; ++u) {
-      const int c = w + NW * u;
-      if (c >= S) continue;
-      for (int q = 0; q < S; ++q) blk_reflect(top[u], bot[u], q, S, refl + q * (S + 1), rtau[q]);
-      // rows iS..iS+S are final: R entries of this column
-      if (lane < S) Rj[rpk(i * S + lane, col0 + c)] = top[u];
-      // slide the window: next window rows (i+1)S .. (i+3)S
-      top[u] = bot[u];
-      bot[u] = lane < S ? hval((i + 2) * S + lane, c) : c128{0, 0};
+    // rows iS..iS+S final; slide the window down one block
+    for (int e = threadIdx.x; e < S * 16; e += 256) {
+      const int row = e >> 4, n = e & 15;
+      Rj[rpk(i * S + row, col0 + q0 + n)] = nxt[e];
+      win[e] = nxt[S * 16 + e];
+      win[S * 16 + e] = blk_hval(a, ds, (i + 2) * S + row, col0 + q0 + n);
     }
   }
-  // G's window rows kS .. kS+2S for the owned right-hand-side columns
-  c128 gt[4], gb[4];
-  for (int u = 0; u < per; ++u) {
-    const int r = w + NW * u;
-    gt[u] = (r < S && lane < S) ? Gj[(size_t)(col0 + lane) + (size_t)a.ldh * r] : c128{0, 0};
-    gb[u] = c128{0, 0};
+  __syncthreads();
+  c128* Tj = a.Tile + (size_t)j * S2 * S;
+  for (int e = threadIdx.x; e < S2 * 16; e += 256) {
+    const int row = e >> 4, n = e & 15;
+    Tj[(size_t)(q0 + n) * S2 + row] = win[e];
   }
-  // 2. the new block's reflectors, one column at a time
-  auto form = [&](int q, int u, int slot) {
-    // reflector from window rows q..q+S of owned column u (lane t: rows t, S+t)
+}
+
+// Step 2: Householder QR of the 2S x S window left by step 1 (rows kS..kS+2S
+// of the new block column; its lower half is the upper triangular (sigma -
+// tau_k) H_{k+1,k}), one reflector per column.  Grid nf, NT threads (NW = NT/64 waves); wave w owns columns w,
+// w + NW, ... (PER of them); the owner of column q forms reflector q, one
+// barrier per q.  Stores
+// R's diagonal block and its inverse and the reflectors (for step 3).
+template <int PER, int NT>
+__global__ void __launch_bounds__(NT) k_blk_lsq_new(BlkLsqArgs a) {
+  extern __shared__ unsigned char blk_lds[];
+  const int S = a.S, S2 = 2 * S, k = a.k, j = blockIdx.x, mS = a.m * S;
+  c128* nv = reinterpret_cast<c128*>(blk_lds);        // [2][S+1] reflector double buffer
+  double* ntau = reinterpret_cast<double*>(nv + 2 * (S + 1));
+  c128* Rd = reinterpret_cast<c128*>(ntau + 2);       // [S][S] R's diagonal block, row-major
+  c128* Xi = Rd + S * S;                              // [S][S] its inverse, row-major
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  c128* Rj = a.Rf + (size_t)j * rpk(0, mS);
+  c128* Vj = a.Vr + (size_t)j * S * (S + 1);
+  double* Tj = a.Tr + (size_t)j * S;
+  const c128* Tl = a.Tile + (size_t)j * S2 * S;
+  const int col0 = k * S;
+  // owned columns c = w + 16 u, u < PER (S = 16 PER): register arrays with
+  // compile-time indices only
+  c128 top[PER], bot[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int c = w + NW * u;
+    top[u] = lane < S ? Tl[(size_t)c * S2 + lane] : c128{0, 0};
+    bot[u] = lane < S ? Tl[(size_t)c * S2 + S + lane] : c128{0, 0};
+  }
+  auto form = [&](int q, c128& tp, c128& bt, int slot) {
     c128* v = nv + slot * (S + 1);
     const int t = lane;
     const bool ut = t >= q && t < S, ub = t <= q && t < S;
     double s2 = 0.0;
-    if (ut) s2 += abs2(top[u]);
-    if (ub) s2 += abs2(bot[u]);
+    if (ut) s2 += abs2(tp);
+    if (ub) s2 += abs2(bt);
     s2 = wave_sum_strided(s2, 1);
     const double nx = sqrt(s2);
-    const c128 x0{__shfl(top[u].re, q, 64), __shfl(top[u].im, q, 64)};
+    const c128 x0{__shfl(tp.re, q, 64), __shfl(tp.im, q, 64)};
     const double a0 = hypot(x0.re, x0.im);
     const c128 ph = a0 > 0.0 ? c128{x0.re / a0, x0.im / a0} : c128{1.0, 0.0};
     const c128 beta = -nx * ph;
     const double tau = nx > 0.0 ? 1.0 / (nx * (nx + a0)) : 0.0;
-    if (ut) v[t - q] = (t == q) ? top[u] - beta : top[u];
-    if (ub) v[S + t - q] = bot[u];
+    if (ut) v[t - q] = (t == q) ? tp - beta : tp;
+    if (ub) v[S + t - q] = bt;
     if (t == 0) ntau[slot] = tau;
-    // the column itself becomes beta e_q
-    if (ut) top[u] = (t == q) ? beta : c128{0.0, 0.0};
-    if (ub) bot[u] = c128{0.0, 0.0};
+    if (ut) tp = (t == q) ? beta : c128{0.0, 0.0};
+    if (ub) bt = c128{0.0, 0.0};
   };
-  // reflector 0's owner forms it before the loop
-  if (w == 0) form(0, 0, 0);
+  if (w == 0) form(0, top[0], bot[0], 0);
   for (int q = 0; q < S; ++q) {
     __syncthreads();
     const int slot = q & 1;
     const c128* v = nv + slot * (S + 1);
     const double tq = ntau[slot];
-    for (int u = 0; u < per; ++u) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
       const int c = w + NW * u;
-      if (c < S && c > q) blk_reflect(top[u], bot[u], q, S, v, tq);
-      const int r = w + NW * u;
-      if (r < S) blk_reflect(gt[u], gb[u], q, S, v, tq);
+      if (c > q) blk_reflect(top[u], bot[u], q, S, v, tq);
     }
-    // store reflector q for later steps
-    for (int e = threadIdx.x; e < S + 1; e += BLK_LSQ_THREADS) Vj[((size_t)k * S + q) * (S + 1) + e] = v[e];
-    if (threadIdx.x == 0) Tj[(size_t)k * S + q] = tq;
-    // the owner of column q + 1 forms its reflector into the other slot
-    if (q + 1 < S && w == (q + 1) % NW) form(q + 1, (q + 1) / NW, slot ^ 1);
+    for (int e = threadIdx.x; e < S + 1; e += NT) Vj[(size_t)q * (S + 1) + e] = v[e];
+    if (threadIdx.x == 0) Tj[q] = tq;
+    if (q + 1 < S && w == (q + 1) % NW) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+        if (u == (q + 1) / NW) form(q + 1, top[u], bot[u], slot ^ 1);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int c = w + NW * u;
+    if (lane < S) {
+      if (lane <= c) Rj[rpk(col0 + lane, col0 + c)] = top[u];
+      Rd[lane * S + c] = lane <= c ? top[u] : c128{0.0, 0.0};
+    }
   }
   __syncthreads();
-  // 3. R's rows kS..kS+S of the new columns; G's rows kS..kS+2S; residuals
-  for (int u = 0; u < per; ++u) {
-    const int c = w + NW * u;
-    if (c < S && lane <= c) Rj[rpk(col0 + lane, col0 + c)] = top[u];
-    const int r = w + NW * u;
-    if (r < S) {
+  // inverse of the diagonal block, one column per thread, rows upwards
+  for (int c = threadIdx.x; c < S; c += NT) {
+    for (int i = 0; i < S; ++i) Xi[i * S + c] = c128{0.0, 0.0};
+    const c128 d = Rd[c * S + c];
+    Xi[c * S + c] = (d.re == 0.0 && d.im == 0.0) ? c128{0.0, 0.0} : cdiv(c128{1.0, 0.0}, d);
+    for (int i = c - 1; i >= 0; --i) {
+      c128 s{0.0, 0.0};
+      for (int p = i + 1; p <= c; ++p) s = s + Rd[i * S + p] * Xi[p * S + c];
+      const c128 di = Rd[i * S + i];
+      Xi[i * S + c] = (di.re == 0.0 && di.im == 0.0) ? c128{0.0, 0.0} : cdiv(-s, di);
+    }
+  }
+  __syncthreads();
+  c128* Di = a.Rdinv + ((size_t)j * a.m + k) * S * S;
+  for (int e = threadIdx.x; e < S * S; e += NT) {
+    const int row = e % S, col = e / S;
+    Di[e] = Xi[row * S + col];      // column-major
+  }
+}
+
+// Step 3: this step's reflectors applied column by column (grid (nf, 3S/16),
+// 256 threads, each wave owns 4 columns): columns 0..2S are the identity's,
+// giving Q_k = P_{S-1} ... P_0 on the 2S-row window (stored column-major for
+// step 1 of later steps); columns 2S..3S are G's rows kS..kS+2S, after which
+// rho_{j,r} = the norm of G's rows (k+1)S..(k+2)S in column r.
+__global__ void __launch_bounds__(256) k_blk_lsq_q(BlkLsqArgs a) {
+  extern __shared__ unsigned char blk_lds[];
+  const int S = a.S, S2 = 2 * S, j = blockIdx.x;
+  c128* refl = reinterpret_cast<c128*>(blk_lds);      // [S][S+1]
+  double* rt = reinterpret_cast<double*>(refl + S * (S + 1));
+  const c128* Vj = a.Vr + (size_t)j * S * (S + 1);
+  for (int e = threadIdx.x; e < S * (S + 1); e += 256) refl[e] = Vj[e];
+  for (int e = threadIdx.x; e < S; e += 256) rt[e] = a.Tr[(size_t)j * S + e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  c128* Q = a.Qb + ((size_t)j * a.m + a.k) * S2 * S2;
+  c128* Gj = a.Gq + (size_t)j * a.ldh * S;
+  const int col0 = a.k * S;
+  for (int u = 0; u < 4; ++u) {
+    const int c = 16 * blockIdx.y + 4 * wv + u;
+    if (c >= 3 * S) continue;
+    const bool gcol = c >= S2;
+    const int r = c - S2;
+    c128 top, bot;
+    if (gcol) {
+      top = lane < S ? Gj[(size_t)(col0 + lane) + (size_t)a.ldh * r] : c128{0.0, 0.0};
+      bot = lane < S ? Gj[(size_t)(col0 + S + lane) + (size_t)a.ldh * r] : c128{0.0, 0.0};
+    } else {
+      top = (lane < S && lane == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+      bot = (lane < S && S + lane == c) ? c128{1.0, 0.0} : c128{0.0, 0.0};
+    }
+    for (int q = 0; q < S; ++q) blk_reflect(top, bot, q, S, refl + q * (S + 1), rt[q]);
+    if (gcol) {
       if (lane < S) {
-        Gj[(size_t)(col0 + lane) + (size_t)a.ldh * r] = gt[u];
-        Gj[(size_t)(col0 + S + lane) + (size_t)a.ldh * r] = gb[u];
+        Gj[(size_t)(col0 + lane) + (size_t)a.ldh * r] = top;
+        Gj[(size_t)(col0 + S + lane) + (size_t)a.ldh * r] = bot;
       }
-      double s2 = lane < S ? abs2(gb[u]) : 0.0;
+      double s2 = lane < S ? abs2(bot) : 0.0;
       s2 = wave_sum_strided(s2, 1);
       if (lane == 0) a.rho[(size_t)j * S + r] = sqrt(s2);
+    } else if (lane < S) {
+      Q[(size_t)c * S2 + lane] = top;
+      Q[(size_t)c * S2 + S + lane] = bot;
     }
   }
 }
@@ -484,20 +596,23 @@ __global__ void __launch_bounds__(BS) k_blk_g_init(int S, int ldh, int nf, const
 
 // ------------------------------------------------ back substitution -------
 // y = R^{-1} G[0:kS, r] for the right-hand sides r of shift j marked in
-// want[j*S + r] (grid: nf blocks of 256 threads; R's diagonal blocks are
-// solved one row at a time with the later blocks' contributions subtracted
-// first).  Y[(j*S + r)*mS + row] receives y (rows kS.. untouched).  Then, per
-// marked pair, the inexact term gap = sum |y_i| ||p_i|| (section 4, eq.
-// resdiff, one inner residual per basis column) and the freeze decision of
-// the one-vector method: CONVERGED when rho + gap <= tol ||b_r||, INNER_LIMITED
-// when rho <= ratio * gap; final != 0 freezes every marked pair that is still
-// active with NOT_CONVERGED.
+// want[j*S + r]: grid (nf, S/16), 256 threads, 16 columns per block.  Block
+// rows are solved from the bottom: Y_b = (R_bb)^{-1} G_b with the stored
+// inverse of the diagonal block, then G_0..G_{b-1} -= R_{0:b, b} Y_b, both as
+// matrix-core contractions; G's working copy lives in Gw.  Y[(j*S + r)*mS +
+// row] receives y for the marked columns.  Then, per marked pair, the inexact
+// term gap = sum |y_i| ||p_i|| (section 4, eq. resdiff, one inner residual per
+// basis column) and the freeze decision of the one-vector method: CONVERGED
+// when rho + gap <= tol ||b_r||, INNER_LIMITED when rho <= ratio * gap;
+// final != 0 freezes every marked pair still active with NOT_CONVERGED.
 struct BlkSolveArgs {
   int S, m, kc, nf, ldh, step, final_;
   const c128* Rf;
+  const c128* Rdinv;
   const c128* Gq;
   const int* want;
   c128* Y;
+  c128* Gw;                // working copy of G: per (shift, 16-column group) mS x 16 row-major
   const double* pn;        // [i*S + c] inner residual norms of basis column (i, c)
   const double* rho;
   const double* beta0;     // ||b_r||
@@ -505,68 +620,99 @@ struct BlkSolveArgs {
   const int* broke;        // the step ended in breakdown (device flag)
   LaneState* ls;
 };
-__global__ void __launch_bounds__(BS) k_blk_backsolve(BlkSolveArgs a) {
-  const int j = blockIdx.x, S = a.S, K = a.kc * S, mS = a.m * S;
-  const c128* Rj = a.Rf + (size_t)j * rpk(0, mS);
-  const c128* Gj = a.Gq + (size_t)j * a.ldh * S;
-  __shared__ int wanted[64];
+template <int S>
+__global__ void __launch_bounds__(256) k_blk_backsolve(BlkSolveArgs a) {
+  const int j = blockIdx.x, grp = blockIdx.y, c0 = 16 * grp, K = a.kc * S, mS = a.m * S;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, m = lane & 15;
+  __shared__ int wanted[16];
   __shared__ int any;
+  __shared__ c128 Yb[64 * 16];
   if (threadIdx.x == 0) any = 0;
   __syncthreads();
-  if ((int)threadIdx.x < S) {
-    wanted[threadIdx.x] = a.want[(size_t)j * S + threadIdx.x];
+  if ((int)threadIdx.x < 16) {
+    wanted[threadIdx.x] = a.want[(size_t)j * S + c0 + threadIdx.x];
     if (wanted[threadIdx.x]) atomicOr(&any, 1);
   }
   __syncthreads();
   if (!any) return;
-  // work vector: G[0:K, r] for wanted r, reduced in place into y (in Y)
-  for (int e = threadIdx.x; e < K * S; e += BS) {
-    const int row = e % K, r = e / K;
-    if (wanted[r]) a.Y[((size_t)j * S + r) * mS + row] = Gj[(size_t)row + (size_t)a.ldh * r];
+  const c128* Rj = a.Rf + (size_t)j * rpk(0, mS);
+  const c128* Gj = a.Gq + (size_t)j * a.ldh * S;
+  c128* Gw = a.Gw + ((size_t)j * (S / 16) + grp) * mS * 16;
+  for (int e = threadIdx.x; e < K * 16; e += 256) {
+    const int row = e >> 4, n = e & 15;
+    Gw[e] = Gj[(size_t)row + (size_t)a.ldh * (c0 + n)];
   }
   __syncthreads();
-  for (int col = K - 1; col >= 0; --col) {
-    const c128 d = Rj[rpk(col, col)];
-    // y_col = g_col / R_col,col for every wanted r (thread r)
-    if ((int)threadIdx.x < S && wanted[threadIdx.x]) {
-      c128* y = a.Y + ((size_t)j * S + threadIdx.x) * mS;
-      y[col] = (d.re == 0.0 && d.im == 0.0) ? c128{0.0, 0.0} : cdiv(y[col], d);
+  constexpr int st = S / 16;
+  for (int b = a.kc - 1; b >= 0; --b) {
+    // Y_b = inv(R_bb) G_b
+    const c128* Di = a.Rdinv + ((size_t)j * a.m + b) * S * S;
+    for (int tl = wv; tl < st; tl += 4) {
+      d4m re{0, 0, 0, 0}, im{0, 0, 0, 0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < S; k0 += 4) {
+        const c128 d = Di[(size_t)(k0 + g) * S + 16 * tl + m];
+        const c128 x = Gw[(size_t)(b * S + k0 + g) * 16 + m];
+        re = mfma16(d.re, x.re, re);
+        re = mfma16(d.im, -x.im, re);
+        im = mfma16(d.re, x.im, im);
+        im = mfma16(d.im, x.re, im);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * tl + mfma_row<double>(g, v);
+        const c128 y{re[v], im[v]};
+        Yb[row * 16 + m] = y;
+        if (wanted[m]) a.Y[((size_t)j * S + c0 + m) * mS + (size_t)b * S + row] = y;
+      }
     }
     __syncthreads();
-    // g[0:col] -= R[0:col, col] y_col
-    for (int e = threadIdx.x; e < col * S; e += BS) {
-      const int row = e % col, r = e / col;
-      if (!wanted[r]) continue;
-      c128* y = a.Y + ((size_t)j * S + r) * mS;
-      y[row] = y[row] - Rj[rpk(row, col)] * y[col];
+    // G_0..G_{b-1} -= R[0:bS, bS:bS+S] Y_b
+    const int rt = b * st;
+    for (int tl = wv; tl < rt; tl += 4) {
+      d4m re{0, 0, 0, 0}, im{0, 0, 0, 0};
+#pragma unroll 4
+      for (int k0 = 0; k0 < S; k0 += 4) {
+        const c128 r = Rj[rpk(16 * tl + m, b * S + k0 + g)];
+        const c128 y = Yb[(k0 + g) * 16 + m];
+        re = mfma16(r.re, y.re, re);
+        re = mfma16(r.im, -y.im, re);
+        im = mfma16(r.re, y.im, im);
+        im = mfma16(r.im, y.re, im);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t at = (size_t)(16 * tl + mfma_row<double>(g, v)) * 16 + m;
+        Gw[at] = Gw[at] - c128{re[v], im[v]};
+      }
     }
     __syncthreads();
   }
   // freeze decisions
-  if ((int)threadIdx.x < S && wanted[threadIdx.x]) {
-    const int r = threadIdx.x;
+  if ((int)threadIdx.x < 16 && wanted[threadIdx.x]) {
+    const int r = c0 + threadIdx.x;
     const c128* y = a.Y + ((size_t)j * S + r) * mS;
     double gap = 0.0;
     for (int i = 0; i < K; ++i) gap += hypot(y[i].re, y[i].im) * a.pn[i];
-    LaneState st = a.ls[(size_t)j * S + r];
-    if (st.active) {
+    LaneState stt = a.ls[(size_t)j * S + r];
+    if (stt.active) {
       const int brk = *a.broke;
       const double rho = brk ? 0.0 : a.rho[(size_t)j * S + r];
       const double bnd = rho + gap;
-      st.rho = rho;
-      st.bound = bnd;
-      st.outer_its = a.step;
-      st.kfz = a.kc;
+      stt.rho = rho;
+      stt.bound = bnd;
+      stt.outer_its = a.step;
+      stt.kfz = a.kc;
       int done = -1;
       if (brk) done = bnd <= a.tol * a.beta0[r] ? SHK_BREAKDOWN_EXACT : SHK_INNER_LIMITED;
       else if (bnd <= a.tol * a.beta0[r]) done = SHK_CONVERGED;
       else if (rho <= a.ratio * gap) done = SHK_INNER_LIMITED;
       else if (a.final_) done = SHK_NOT_CONVERGED;
       if (done >= 0) {
-        st.status = done;
-        st.active = 0;
+        stt.status = done;
+        stt.active = 0;
       }
-      a.ls[(size_t)j * S + r] = st;
+      a.ls[(size_t)j * S + r] = stt;
     }
   }
 }

@@ -100,5 +100,6 @@ size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int 
 const char* last_error_text();
 int profile_enable(int on);
 int profile_read(long long* launches, double* ms, double* bytes);
+int profile_read_block(long long* calls, double* ms, double* flops);
 
 }  // namespace shk

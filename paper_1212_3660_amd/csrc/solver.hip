@@ -86,11 +86,30 @@ struct KernelTimer {
 };
 static KernelTimer g_timer;
 
+// Block Gram-Schmidt timing (shk_profile_read_block): HIP events around each
+// block CGS2 of the shared-basis path (its two projections V^H W and two
+// updates W -= V C), with the flops of those four contractions.
+struct BlockTimer {
+  long long calls = 0;
+  double ms = 0.0, flops = 0.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+static BlockTimer g_btimer;
+
 int profile_enable(int on) {
   g_timer.on = on != 0;
   g_timer.launches = 0;
   g_timer.total_ms = 0.0;
   g_timer.total_bytes = 0.0;
+  g_btimer.calls = 0;
+  g_btimer.ms = 0.0;
+  g_btimer.flops = 0.0;
+  return SHK_OK;
+}
+int profile_read_block(long long* calls, double* ms, double* flops) {
+  if (calls) *calls = g_btimer.calls;
+  if (ms) *ms = g_btimer.ms;
+  if (flops) *flops = g_btimer.flops;
   return SHK_OK;
 }
 int profile_read(long long* launches, double* ms, double* bytes) {
@@ -388,6 +407,7 @@ template <typename R> struct Buffers {
   double* fro = nullptr;       // ||H_{k+1,k}||_F^2
   int* broke = nullptr;        // breakdown flag of the current step
   c128 *Rf = nullptr, *Vr = nullptr, *Gq = nullptr, *Yp = nullptr;
+  c128 *Qb = nullptr, *Rdinv = nullptr, *Tile = nullptr, *Gw = nullptr;
   double *Tr = nullptr, *brho = nullptr;
   int* want = nullptr;
   size_t bytes;
@@ -411,10 +431,14 @@ template <typename R> static void carve_block(Carver& cv, Buffers<R>& b, int m, 
   b.fro = cv.take<double>(2);
   b.broke = cv.take<int>(4);
   b.Rf = cv.take<c128>((size_t)nf * (mS * (mS + 1) / 2));
-  b.Vr = cv.take<c128>((size_t)nf * m * S * (S + 1));
-  b.Tr = cv.take<double>((size_t)nf * m * S);
+  b.Vr = cv.take<c128>((size_t)nf * S * (S + 1));
+  b.Tr = cv.take<double>((size_t)nf * S);
+  b.Qb = cv.take<c128>((size_t)nf * m * 4 * S * S);
+  b.Rdinv = cv.take<c128>((size_t)nf * m * S * S);
+  b.Tile = cv.take<c128>((size_t)nf * 2 * S * S);
   b.Gq = cv.take<c128>((size_t)nf * ldh * S);
   b.Yp = cv.take<c128>((size_t)nf * S * mS);
+  b.Gw = cv.take<c128>((size_t)nf * S * mS);
   b.brho = cv.take<double>((size_t)nf * S);
   b.want = cv.take<int>((size_t)nf * S);
 }
@@ -636,6 +660,29 @@ struct Snap {
   int pad[2];
   CgScal sc[64];
 };
+
+// Pairs whose projected residual is within BLK_CAND x tol of the target get
+// their least-squares solution and the eq. trueresidual test each step.
+constexpr double BLK_CAND = 10.0;
+
+static void blk_lsq_launch(const BlkLsqArgs& la, int S, int nf, hipStream_t st) {
+  const size_t lds_prev = 2 * (size_t)(2 * S) * 16 * sizeof(c128);
+  const size_t lds_new = 2 * (size_t)(S + 1) * sizeof(c128) + 2 * sizeof(double) + 2 * (size_t)S * S * sizeof(c128);
+  const size_t lds_q = (size_t)S * (S + 1) * sizeof(c128) + S * sizeof(double);
+  if (S == 64) k_blk_lsq_prev<64><<<dim3(nf, S / 16), 256, lds_prev, st>>>(la);
+  else if (S == 32) k_blk_lsq_prev<32><<<dim3(nf, S / 16), 256, lds_prev, st>>>(la);
+  else k_blk_lsq_prev<16><<<dim3(nf, S / 16), 256, lds_prev, st>>>(la);
+  if (S == 64) k_blk_lsq_new<4, 1024><<<nf, 1024, lds_new, st>>>(la);
+  else if (S == 32) k_blk_lsq_new<2, 1024><<<nf, 1024, lds_new, st>>>(la);
+  else k_blk_lsq_new<1, 1024><<<nf, 1024, lds_new, st>>>(la);
+  k_blk_lsq_q<<<dim3(nf, 3 * S / 16), 256, lds_q, st>>>(la);
+}
+
+static void blk_backsolve_launch(const BlkSolveArgs& sa, int S, int nf, hipStream_t st) {
+  if (S == 64) k_blk_backsolve<64><<<dim3(nf, S / 16), 256, 0, st>>>(sa);
+  else if (S == 32) k_blk_backsolve<32><<<dim3(nf, S / 16), 256, 0, st>>>(sa);
+  else k_blk_backsolve<16><<<dim3(nf, S / 16), 256, 0, st>>>(sa);
+}
 
 // Block-basis operations on n x S blocks (block FGMRES-Sh), with the scratch
 // they need: chunk partials, coefficients, CholQR factors.
@@ -1408,8 +1455,6 @@ template <typename R, typename Op, typename OpD> struct Group {
     if (!nact) return fail(SHK_ERR_OOM, "pinned staging");
     double* qmax = (double*)(stage + 32768 + 64 * sizeof(int));
     double eps_k = ps.eps;
-    const size_t lsq_lds = (size_t)S * (S + 1) * sizeof(c128) + S * sizeof(double) + 2 * (S + 1) * sizeof(c128) +
-                           2 * sizeof(double);
     int kend = 0;
     long long kglob = ps.kglob0;
     for (int k = 0; k < m; ++k) {
@@ -1419,19 +1464,28 @@ template <typename R, typename Op, typename OpD> struct Group {
       SHK_TRY(inner(tau, Vk, B.Z + (size_t)k * N, eps_k, ps.inner_maxit, 0, B.pn + (size_t)k * S));
       // block CGS2: H(0:k, k) = V^H W, W -= V H, twice
       c128* Hcol = B.Hb + (size_t)ldh * k * S;
+      const bool timing = g_timer.on;
+      if (timing) {
+        if (!g_btimer.e0) {
+          SHK_HIP(hipEventCreate(&g_btimer.e0));
+          SHK_HIP(hipEventCreate(&g_btimer.e1));
+        }
+        SHK_HIP(hipEventRecord(g_btimer.e0, st));
+      }
       bc.cgs2(B.V, (size_t)N, k + 1, B.W, Hcol, ldh);
+      if (timing) SHK_HIP(hipEventRecord(g_btimer.e1, st));
       // W = V_{k+1} H(k+1, k)
       bc.template qr<R>(B.W, B.V + (size_t)(k + 1) * N, Hcol + (size_t)(k + 1) * S, ldh, nullptr);
       k_blk_breakdown<<<1, 64, 0, st>>>(B.fro, B.mz, S, B.broke);
       // each shift's block least squares, then the pairs near their target
-      BlkLsqArgs la{S, m, k, nf, ldh, B.Hb, B.sigma, tau, B.Rf, B.Vr, B.Tr, B.Gq, B.brho, B.ls};
-      k_blk_lsq<<<nf, BLK_LSQ_THREADS, lsq_lds, st>>>(la);
+      const BlkLsqArgs la = lsq_args(k, tau);
+      blk_lsq_step(la);
       const bool last = k == m - 1;
-      k_blk_mark<<<Lb, BS, 0, st>>>(L, S, B.brho, B.beta0, 100.0 * ps.tol, last ? 1 : 0, B.broke, outer_steps + 1,
-                                    B.ls, B.want);
-      BlkSolveArgs sa{S, m, k + 1, nf, ldh, outer_steps + 1, last ? 1 : 0, B.Rf, B.Gq, B.want, B.Yp, B.pn,
-                      B.brho, B.beta0, ps.tol, 0.1, B.broke, B.ls};
-      k_blk_backsolve<<<nf, BS, 0, st>>>(sa);
+      k_blk_mark<<<Lb, BS, 0, st>>>(L, S, B.brho, B.beta0, BLK_CAND * ps.tol, last ? 1 : 0, B.broke,
+                                    outer_steps + 1, B.ls, B.want);
+      BlkSolveArgs sa{S, m, k + 1, nf, ldh, outer_steps + 1, last ? 1 : 0, B.Rf, B.Rdinv, B.Gq, B.want, B.Yp,
+                      B.Gw, B.pn, B.brho, B.beta0, ps.tol, 0.1, B.broke, B.ls};
+      blk_backsolve_launch(sa, S, nf, st);
       k_count_active<<<1, BS, 0, st>>>(S, nf, B.ls, B.beta0, B.nact, B.qmax);
       SHK_HIP(hipGetLastError());
       int brk = 0;
@@ -1439,6 +1493,14 @@ template <typename R, typename Op, typename OpD> struct Group {
       SHK_HIP(hipMemcpyAsync(qmax, B.qmax, S * sizeof(double), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipMemcpyAsync(&brk, B.broke, sizeof(int), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
+      if (timing) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_btimer.e0, g_btimer.e1) == hipSuccess) {
+          g_btimer.calls += 1;
+          g_btimer.ms += ms;
+          g_btimer.flops += 4.0 * 8.0 * (double)n * (k + 1) * S * S;
+        }
+      }
       ++outer_steps;
       kend = k + 1;
       if (ps.relax > 0.0) {
@@ -1457,14 +1519,22 @@ template <typename R, typename Op, typename OpD> struct Group {
     SHK_HIP(hipGetLastError());
     return SHK_OK;
   }
+  BlkLsqArgs lsq_args(int k, c128 tau) const {
+    return BlkLsqArgs{S, m, k, nf, (m + 1) * S, B.Hb, B.sigma, tau, B.Rf, B.Vr, B.Tr, B.Qb, B.Rdinv, B.Tile, B.Gq,
+                      B.brho};
+  }
+  // Step k of every shift's block least squares: earlier blocks' reflectors
+  // on the new block column, the new block's QR, its reflectors' product.
+  void blk_lsq_step(const BlkLsqArgs& la) { blk_lsq_launch(la, S, nf, st); }
   // X[:, j, r] (+)= extra_{j,r} Z y_{j,r} over kc block columns (FP64, matrix cores).
   void assemble_block(int kc, const c128* extra, c128* X, bool accumulate) {
     const int mS = m * S;
     const size_t lds = (size_t)S * (S + 1) * sizeof(c128);
     const dim3 g((unsigned)((n + 63) / 64), (unsigned)nf);
-    if (S == 64) k_blk_assemble<4, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, accumulate ? 1 : 0);
-    else if (S == 32) k_blk_assemble<2, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, accumulate ? 1 : 0);
-    else k_blk_assemble<1, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, accumulate ? 1 : 0);
+    const int acc = accumulate ? 1 : 0;
+    if (S == 64) k_blk_assemble<4, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, acc);
+    else if (S == 32) k_blk_assemble<2, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, acc);
+    else k_blk_assemble<1, 1><<<g, 256, lds, st>>>(B.Z, (size_t)N, kc, mS, B.Yp, extra, n, nf, s_real, X, acc);
   }
 };
 
@@ -1855,8 +1925,10 @@ int step_block_lsq(int K, int S, const c128* H, const c128* taus, int nf, const 
   Buffers<double> b0{};
   auto lay = [&](Carver& c, Buffers<double>& b) {
     b.Hb = c.take<c128>((size_t)ldh * mS); b.sigma = c.take<c128>(nf); b.beta_blk = c.take<c128>((size_t)S * S);
-    b.Rf = c.take<c128>((size_t)nf * rpk(0, mS)); b.Vr = c.take<c128>((size_t)nf * m * S * (S + 1));
-    b.Tr = c.take<double>((size_t)nf * m * S); b.Gq = c.take<c128>((size_t)nf * ldh * S);
+    b.Rf = c.take<c128>((size_t)nf * rpk(0, mS)); b.Vr = c.take<c128>((size_t)nf * S * (S + 1));
+    b.Tr = c.take<double>((size_t)nf * S); b.Gq = c.take<c128>((size_t)nf * ldh * S);
+    b.Qb = c.take<c128>((size_t)nf * m * 4 * S * S); b.Rdinv = c.take<c128>((size_t)nf * m * S * S);
+    b.Tile = c.take<c128>((size_t)nf * 2 * S * S); b.Gw = c.take<c128>((size_t)L * mS);
     b.Yp = c.take<c128>((size_t)L * mS); b.brho = c.take<double>(L); b.want = c.take<int>(L);
     b.pn = c.take<double>((size_t)mS); b.beta0 = c.take<double>(S); b.ls = c.take<LaneState>(L);
     b.broke = c.take<int>(4); b.g = c.take<c128>(L);
@@ -1883,19 +1955,18 @@ int step_block_lsq(int K, int S, const c128* H, const c128* taus, int nf, const 
   SHK_HIP(hipMemcpy(b.beta0, bn.data(), sizeof(double) * S, hipMemcpyHostToDevice));
   k_lanes_init<<<(L + BS - 1) / BS, BS>>>(L, S, S, b.beta0, b.ls, b.g);
   k_blk_g_init<<<grid_items((long)nf * ldh * S, 4096), BS>>>(S, ldh, nf, b.beta_blk, b.Gq);
-  const size_t lsq_lds = (size_t)S * (S + 1) * sizeof(c128) + S * sizeof(double) + 2 * (S + 1) * sizeof(c128) +
-                         2 * sizeof(double);
   std::vector<double> hr(L);
   for (int k = 0; k < K; ++k) {
-    BlkLsqArgs la{S, m, k, nf, ldh, b.Hb, b.sigma, taus[k], b.Rf, b.Vr, b.Tr, b.Gq, b.brho, b.ls};
-    k_blk_lsq<<<nf, BLK_LSQ_THREADS, lsq_lds>>>(la);
+    BlkLsqArgs la{S, m, k, nf, ldh, b.Hb, b.sigma, taus[k], b.Rf, b.Vr, b.Tr, b.Qb, b.Rdinv, b.Tile, b.Gq, b.brho};
+    blk_lsq_launch(la, S, nf, nullptr);
     SHK_HIP(hipGetLastError());
     SHK_HIP(hipMemcpy(hr.data(), b.brho, sizeof(double) * L, hipMemcpyDeviceToHost));
     for (int p = 0; p < L; ++p) rho[p + (size_t)L * k] = hr[p];
   }
   k_blk_mark<<<(L + BS - 1) / BS, BS>>>(L, S, b.brho, b.beta0, 0.0, 1, b.broke, K, b.ls, b.want);
-  BlkSolveArgs sa{S, m, K, nf, ldh, K, 1, b.Rf, b.Gq, b.want, b.Yp, b.pn, b.brho, b.beta0, 0.0, -1.0, b.broke, b.ls};
-  k_blk_backsolve<<<nf, BS>>>(sa);
+  BlkSolveArgs sa{S, m, K, nf, ldh, K, 1, b.Rf, b.Rdinv, b.Gq, b.want, b.Yp, b.Gw, b.pn, b.brho, b.beta0, 0.0, -1.0,
+                  b.broke, b.ls};
+  blk_backsolve_launch(sa, S, nf, nullptr);
   SHK_HIP(hipGetLastError());
   SHK_HIP(hipMemcpy(y, b.Yp, sizeof(c128) * (size_t)L * mS, hipMemcpyDeviceToHost));
   return SHK_OK;

@@ -228,6 +228,107 @@ def time_batched(P, torch, w, make, precision, single_rhs_sample=0, label=None, 
     return out
 
 
+def server_bench(P, torch, n_req=48, slots=4, budget_gb=200.0):
+    """Serving workload: the first n_req requests of the seeded Poisson trace
+    (20 requests/s; each a 2-D grid of 128^2, 256^2 or 512^2 with its own field,
+    5-200 shifts, 1-16 point sources), replayed in real time.  The server (one
+    device arena of min(budget_gb, 70% of free HBM), slots on their own
+    streams, each request's right-hand sides in lockstep on complex64 vectors,
+    multigrid inner solves, target 1e-6 after refinement) returns the solution
+    at the source cells (SHK_OUT_ROWS).  Baseline: the same arrivals served
+    one request at a time in arrival order by the plain FP64 solver, one
+    right-hand side at a time.  Latency = completion - arrival."""
+    import synth
+    trace = synth.server_trace(max_requests=n_req)
+    works = [synth.request_workload(r) for r in trace]
+    rows = [np.array([int(np.argmax(np.abs(w.b[:, r]))) for r in range(w.b.shape[1])], dtype=np.int64)
+            for w in works]
+    solves = sum(len(w.sigma) * w.b.shape[1] for w in works)
+    span = trace[-1].arrival - trace[0].arrival
+    free, _total = torch.cuda.mem_get_info()
+    budget = int(min(budget_gb * 1e9, 0.7 * free)) & ~255
+    arena = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    keep = []
+    srv = P.Server(budget, max_slots=slots, arena=arena)
+    t0 = time.perf_counter()
+    tickets = []
+    for req, w, rw in zip(trace, works, rows):
+        delay = req.arrival - trace[0].arrival - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        prm, k = P.make_params(w.tau_seq, m_restart=50, max_refine=4, tol=1e-6, eps_inner=1e-6,
+                               precision=P.SHK_MIXED, inner_precond=P.SHK_PRECOND_MULTIGRID,
+                               output=P.SHK_OUT_ROWS, out_rows=rw)
+        keep.append(k)
+        tickets.append(srv.submit(w.cell_K, w.sigma, w.b, prm, keep_solution=True))
+    srv.drain()
+    lat, ok, worst, t_first, t_last, errors = [], True, 0.0, None, 0.0, 0
+    for t, w in zip(tickets, works):
+        res, x, st = srv.poll(t, want_solution=True)
+        lat.append((res["t_done"] - res["t_arrival"]) * 1e3)
+        errors += res["error"] != 0
+        ok &= res["error"] == 0 and res["n_converged"] == len(w.sigma) * w.b.shape[1]
+        worst = max(worst, res["max_true_relres"])
+        t_first = res["t_arrival"] if t_first is None else min(t_first, res["t_arrival"])
+        t_last = max(t_last, res["t_done"])
+    # the same requests submitted at once: the rate the server sustains when
+    # arrivals never leave it idle
+    t_b0 = srv.clock()
+    bt = []
+    for w, rw in zip(works, rows):
+        prm, k = P.make_params(w.tau_seq, m_restart=50, max_refine=4, tol=1e-6, eps_inner=1e-6,
+                               precision=P.SHK_MIXED, inner_precond=P.SHK_PRECOND_MULTIGRID,
+                               output=P.SHK_OUT_ROWS, out_rows=rw)
+        keep.append(k)
+        bt.append(srv.submit(w.cell_K, w.sigma, w.b, prm, keep_solution=False))
+    srv.drain()
+    b_done = max(srv.poll(t)[0]["t_done"] for t in bt)
+    burst = {"solves_per_s": round(solves / (b_done - t_b0), 1), "makespan_s": round(b_done - t_b0, 3),
+             "requests_per_s": round(len(works) / (b_done - t_b0), 1)}
+    srv.close()
+    del arena
+    torch.cuda.empty_cache()
+    makespan = t_last - t_first
+    server = {"solves_per_s": round(solves / makespan, 1), "makespan_s": round(makespan, 3),
+              "p50_ms": round(percentile(lat, 0.5), 1), "p99_ms": round(percentile(lat, 0.99), 1),
+              "converged": bool(ok), "request_errors": errors, "max_true_relres": worst, "slots": slots,
+              "arena_gb": round(budget / 1e9, 1)}
+    # sequential plain FP64, one rhs at a time, arrivals replayed
+    gps = [P.Problem.fv2d(w.cell_K, w.Ss, w.h) for w in works]
+    lat2, worst2, ok2 = [], 0.0, True
+    t0 = time.perf_counter()
+    busy_until = 0.0
+    for req, w, gp in zip(trace, works, gps):
+        arr = req.arrival - trace[0].arrival
+        now = time.perf_counter() - t0
+        if arr > now:
+            time.sleep(arr - now)
+        prm, k = P.make_params(w.tau_seq, m_restart=50, max_refine=4, tol=1e-6, eps_inner=1e-6,
+                               precision=P.SHK_FP64, inner_precond=P.SHK_PRECOND_MULTIGRID)
+        for r in range(w.b.shape[1]):
+            b = torch.from_numpy(np.ascontiguousarray(w.b[:, r])).cuda()[None, :].contiguous()
+            _, st = P.fgmres_sh_solve(gp, prm, w.sigma, b)
+            worst2 = max(worst2, float(st["true_relres"].max()))
+            ok2 &= bool((st["status"] == P.SHK_CONVERGED).all())
+        torch.cuda.synchronize()
+        done = time.perf_counter() - t0
+        busy_until = done
+        lat2.append((done - arr) * 1e3)
+    for gp in gps:
+        gp.close()
+    seq = {"solves_per_s": round(solves / busy_until, 1), "makespan_s": round(busy_until, 3),
+           "p50_ms": round(percentile(lat2, 0.5), 1), "p99_ms": round(percentile(lat2, 0.99), 1),
+           "converged": bool(ok2), "max_true_relres": worst2}
+    return {"workload": f"first {n_req} requests of the seeded Poisson trace (20 req/s over {span:.2f} s): 2-D grids "
+                        f"128^2/256^2/512^2, 5-200 shifts, 1-16 rhs; {solves} shifted solves",
+            "server_mixed_batched": server, "sequential_fp64_single_rhs": seq,
+            "server_all_at_once": dict(burst, note="the same requests submitted together: sustainable rate"),
+            "speedup_solves_per_s": round(server["solves_per_s"] / seq["solves_per_s"], 2),
+            "saturated": bool(makespan > 1.2 * span),
+            "note": "saturated means the makespan exceeds the trace span by 20%: arrivals outpace the GPU and "
+                    "latency includes queueing; solves_per_s is then the sustainable rate"}
+
+
 def cpu_baseline(w, seconds, gpu_outer_steps):
     """The CPU oracle (FGMRES-Sh, complex128, multigrid-COCG inner) on the same
     workload, bounded to a few outer steps; scaled to a full solve with the
@@ -277,6 +378,9 @@ def main():
     ap.add_argument("--batched-only", choices=["2d", "3d", "2d-block", "3d-block"], default=None,
                     help="run only the mixed batched 256x256 x 64 rhs (2d) or 128^3 x 8 rhs (3d) workload, with "
                          "independent bases or the shared block basis (-block), and exit (profiler passes)")
+    ap.add_argument("--server-only", action="store_true",
+                    help="run only the serving workload (trace replay) and exit")
+    ap.add_argument("--no-server", action="store_true", help="skip the serving workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device-to-device with a plain copy kernel and exit "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -307,6 +411,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return
+    if a.server_only:
+        print(json.dumps(server_bench(P, torch)), flush=True)
         return
     if a.sensitivity_only:
         print(json.dumps(sensitivity_bench(P, torch, synth.config3(), lambda w: P.Problem.fv2d(w.cell_K, w.Ss, w.h))),
@@ -409,6 +516,8 @@ def main():
                                         label="multigrid-COCG inner iteration, 16 lanes (8 padded), complex64"),
             "fp64_batched": time_batched(P, torch, w4, mk3, P.SHK_FP64,
                                          label="multigrid-COCG inner iteration, 8 lanes, complex128")}
+    if not a.no_server:
+        out["serving"] = server_bench(P, torch)
     if not a.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds, mixed["outer"])

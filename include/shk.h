@@ -75,6 +75,9 @@ typedef struct shk_server shk_server;
                                built in lockstep (the paper's choice, section 5)  */
 #define SHK_RHS_BLOCK 1     /* one block basis shared by a group's right-hand
                                sides (block FGMRES-Sh)                           */
+#define SHK_OUT_FULL 0      /* x: every x_{j,r} in full                                 */
+#define SHK_OUT_ROWS 1      /* x: x_{j,r} at the cells out_rows only                    */
+#define SHK_OUT_FACTORED 2  /* x: Z and y with x_{j,r} = Z_r y_{j,r} (see shk_params)  */
 #define SHK_PRECOND_JACOBI 0     /* inner COCG with D = diag(K + tau M)              */
 #define SHK_PRECOND_MULTIGRID 1  /* inner COCG preconditioned by a geometric
                                     aggregation multigrid V-cycle (structured
@@ -148,6 +151,27 @@ typedef struct shk_server shk_server;
  *                 least-squares iterate and go to refinement.  Requires
  *                 variant SHK_GMRES and ortho SHK_CGS2 (else UNSUPPORTED) and
  *                 m_restart <= 100; workspace grows as n_shifts (m S)^2.
+ *  output         what fgmres_sh_solve writes to x (section 2: the family of
+ *                 solutions x_j, eq. multipleshifted, and its Krylov form x_j =
+ *                 Z y_j of Algorithm 4).  The FP64 true residuals and the
+ *                 refinement need every x_j, so the library forms them in its
+ *                 workspace whatever is returned; the modes shrink the output
+ *                 and its copy to the host, not the device working set.
+ *    SHK_OUT_FULL      x: n x n_shifts x n_rhs, x[c + n (j + n_shifts r)].
+ *    SHK_OUT_ROWS      x: n_out_rows x n_shifts x n_rhs, x[q + n_out_rows (j +
+ *                      n_shifts r)] = x_{j,r} at cell out_rows[q] (host array of
+ *                      n_out_rows cell indices in [0, n), repeats allowed).
+ *    SHK_OUT_FACTORED  x holds Z (n x k_cap x n_rhs, Z[c + n (i + k_cap r)])
+ *                      followed by Y (k_cap x n_shifts x n_rhs, Y[i + k_cap (j +
+ *                      n_shifts r)]) with x_{j,r} = sum_i Z[:, i, r] Y[i, j, r]:
+ *                      the flexible basis vectors z_i of every cycle and
+ *                      refinement pass in the order they were built, and their
+ *                      coefficients (zero for the cycles a pair did not use).
+ *                      k_cap = m_restart (max_restarts + 1) (max_refine + 1);
+ *                      columns past shk_status.basis_cols are zero.  Lockstep
+ *                      bases only (UNSUPPORTED with SHK_RHS_BLOCK).
+ *                 shk_output_elems gives the size of x for each mode.
+ *  n_out_rows, out_rows  cells of SHK_OUT_ROWS (ignored otherwise).
  */
 typedef struct {
   int m_restart;
@@ -169,6 +193,9 @@ typedef struct {
   double inner_eps_max;
   int ortho;
   int rhs_mode;
+  int output;
+  int n_out_rows;
+  const long long* out_rows;
 } shk_params;
 
 /* Per-(shift, rhs) result, host memory, n_shifts x n_rhs column-major. */
@@ -177,6 +204,9 @@ typedef struct {
   int outer_its;       /* outer steps taken when the shift was frozen          */
   int restarts;        /* restarts before it was frozen                        */
   int refine_sweeps;   /* refinement sweeps applied                            */
+  int basis_cols;      /* basis vectors built for this rhs (all cycles and
+                          refinement passes; the used columns of SHK_OUT_FACTORED) */
+  int reserved;
   long long inner_its; /* inner iterations of the whole solve (shared)         */
   double quasi_relres; /* ||beta e_1 - Hbar(sigma;T) y|| / ||b|| at freeze      */
   double bound_relres; /* eq. trueresidual bound / ||b|| at freeze             */
@@ -211,6 +241,13 @@ void shk_problem_destroy(shk_problem* p);
 /* Number of unknowns n of the problem. */
 long long shk_problem_size(const shk_problem* p);
 
+/* Number of complex128 elements fgmres_sh_solve writes to x for prm->output
+ * (FULL: n n_shifts n_rhs; ROWS: n_out_rows n_shifts n_rhs; FACTORED: k_cap
+ * (n + n_shifts) n_rhs) and, for FACTORED, k_cap (0 otherwise; k_cap may be
+ * NULL).  Errors: INVALID_ARG. */
+int shk_output_elems(const shk_problem* p, const shk_params* prm, int n_shifts, int n_rhs, size_t* elems,
+                     int* k_cap);
+
 /* Bytes of device workspace fgmres_sh_solve needs for these sizes. */
 int shk_workspace_bytes(const shk_problem* p, const shk_params* prm, int n_shifts, int n_rhs,
                         size_t* bytes);
@@ -221,8 +258,9 @@ int shk_workspace_bytes(const shk_problem* p, const shk_params* prm, int n_shift
  * the operator is read once for all of them).
  *  sigma      host, n_shifts complex shifts.
  *  b          n x n_rhs column-major complex128 (host or device per ptr_kind).
- *  x          n x n_shifts x n_rhs column-major complex128: x[c + n*(j + n_shifts*r)]
- *             (host or device per ptr_kind); overwritten.
+ *  x          complex128 output per prm->output (host or device per ptr_kind);
+ *             SHK_OUT_FULL: n x n_shifts x n_rhs column-major, x[c + n*(j +
+ *             n_shifts*r)]; the other modes as described with shk_params.
  *  st         host, n_shifts x n_rhs statuses, st[j + n_shifts*r].
  *  workspace  device buffer of >= shk_workspace_bytes(); NULL lets the library
  *             allocate and free it inside the call.
@@ -383,10 +421,15 @@ const char* shk_status_string(int code);
 const char* shk_last_error(void);
 
 /* ---------------------------------------------------------------------------
- * Solve server: requests (field, shifts, right-hand sides) arrive at any time;
- * a scheduler thread admits them while their Krylov-basis memory fits the
- * budget and a slot is free, runs admitted requests concurrently on separate
- * HIP streams, and records arrival, start and completion times.
+ * Solve server: requests (field, shifts, right-hand sides) arrive at any time.
+ * Every device byte a request needs (operator and multigrid hierarchy, Krylov
+ * workspace, right-hand sides, its output) is one contiguous region of the
+ * server's device arena.  Worker threads, one per slot and each with its own
+ * HIP stream, take the oldest pending request for which a region is free
+ * (first fit), so requests are admitted as slots and memory free up and run
+ * concurrently with the ones already on the device; arrival, start and
+ * completion times are recorded.  The server calls no device allocator per
+ * request.  Only 2-D finite-volume requests are served.
  * ------------------------------------------------------------------------ */
 typedef struct {
   int nx, ny;              /* 2-D finite-volume grid                             */
@@ -396,8 +439,10 @@ typedef struct {
   const shk_c128* sigma;   /* host, copied                                       */
   int n_rhs;
   const shk_c128* b;       /* host, n x n_rhs, copied                            */
-  shk_params params;       /* tau_seq copied                                     */
-  int keep_solution;       /* 1: keep x for shk_server_poll; 0: statuses only    */
+  shk_params params;       /* tau_seq and out_rows copied; params.output selects
+                              what the request returns (shk_params)              */
+  int keep_solution;       /* 1: keep the output for shk_server_poll; 0: statuses
+                              only                                               */
 } shk_request;
 
 typedef struct {
@@ -408,14 +453,18 @@ typedef struct {
   double max_true_relres;
 } shk_result;
 
-/* mem_budget_bytes bounds the sum of admitted workspaces; max_slots bounds the
- * number of concurrent requests (streams). */
-int shk_server_create(size_t mem_budget_bytes, int max_slots, shk_server** out);
-/* Copies the request, returns a ticket.  REJECTED if it can never fit. */
+/* device_arena: a device buffer of mem_budget_bytes (256-byte aligned) that
+ * the caller owns and keeps alive until shk_server_destroy returns, from which
+ * every request's memory is taken; NULL makes the server allocate the arena
+ * once here and free it at destroy.  max_slots (1..16) bounds the number of
+ * concurrent requests (streams).  Errors: INVALID_ARG, OOM, HIP. */
+int shk_server_create(size_t mem_budget_bytes, int max_slots, void* device_arena, shk_server** out);
+/* Copies the request, returns a ticket.  REJECTED if its region can never fit
+ * the arena; INVALID_ARG for bad sizes or out_rows. */
 int shk_server_submit(shk_server* s, const shk_request* req, long long* ticket);
 /* Non-blocking: NOT_READY until done; then fills *res.  With x != NULL (host,
- * n x n_shifts x n_rhs) and st != NULL (host, n_shifts x n_rhs) copies the
- * solution and statuses out. */
+ * shk_output_elems complex128 values for the request's output mode) and st !=
+ * NULL (host, n_shifts x n_rhs) copies the output and statuses out. */
 int shk_server_poll(shk_server* s, long long ticket, shk_result* res, shk_c128* x, shk_status* st);
 /* Blocks until every submitted request is done. */
 int shk_server_drain(shk_server* s);

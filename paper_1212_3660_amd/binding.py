@@ -25,6 +25,7 @@ SHK_FP64, SHK_MIXED = 0, 1
 SHK_PTR_HOST, SHK_PTR_DEVICE = 0, 1
 SHK_PRECOND_JACOBI, SHK_PRECOND_MULTIGRID = 0, 1
 SHK_RHS_LOCKSTEP, SHK_RHS_BLOCK = 0, 1
+SHK_OUT_FULL, SHK_OUT_ROWS, SHK_OUT_FACTORED = 0, 1, 2
 
 
 class shk_c128(C.Structure):
@@ -38,17 +39,20 @@ class shk_params(C.Structure):
                 ("precision", C.c_int), ("refine_tol", C.c_double), ("refine_eps_inner", C.c_double),
                 ("inner_precond", C.c_int), ("mg_sweeps", C.c_int), ("mg_omega", C.c_double),
                 ("inner_relax", C.c_double), ("inner_eps_max", C.c_double), ("ortho", C.c_int),
-                ("rhs_mode", C.c_int)]
+                ("rhs_mode", C.c_int), ("output", C.c_int), ("n_out_rows", C.c_int),
+                ("out_rows", C.POINTER(C.c_longlong))]
 
 
 class shk_status(C.Structure):
     _fields_ = [("status", C.c_int), ("outer_its", C.c_int), ("restarts", C.c_int),
-                ("refine_sweeps", C.c_int), ("inner_its", C.c_longlong), ("quasi_relres", C.c_double),
+                ("refine_sweeps", C.c_int), ("basis_cols", C.c_int), ("reserved", C.c_int),
+                ("inner_its", C.c_longlong), ("quasi_relres", C.c_double),
                 ("bound_relres", C.c_double), ("true_relres", C.c_double)]
 
 
 STATUS_DTYPE = np.dtype([("status", np.int32), ("outer_its", np.int32), ("restarts", np.int32),
-                         ("refine_sweeps", np.int32), ("inner_its", np.int64), ("quasi_relres", np.float64),
+                         ("refine_sweeps", np.int32), ("basis_cols", np.int32), ("reserved", np.int32),
+                         ("inner_its", np.int64), ("quasi_relres", np.float64),
                          ("bound_relres", np.float64), ("true_relres", np.float64)])
 assert STATUS_DTYPE.itemsize == C.sizeof(shk_status)
 
@@ -74,6 +78,8 @@ _SIGS = {
                                          C.POINTER(C.c_void_p)]),
     "shk_problem_destroy": (None, [C.c_void_p]),
     "shk_problem_size": (C.c_longlong, [C.c_void_p]),
+    "shk_output_elems": (C.c_int, [C.c_void_p, C.POINTER(shk_params), C.c_int, C.c_int, C.POINTER(C.c_size_t),
+                                   C.POINTER(C.c_int)]),
     "shk_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(shk_params), C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
     "fgmres_sh_solve": (C.c_int, [C.c_void_p, C.POINTER(shk_params), C.c_int, C.c_void_p, C.c_int, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_int]),
@@ -101,7 +107,7 @@ _SIGS = {
     "shk_profile_read_block": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "shk_status_string": (C.c_char_p, [C.c_int]),
     "shk_last_error": (C.c_char_p, []),
-    "shk_server_create": (C.c_int, [C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "shk_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     "shk_server_submit": (C.c_int, [C.c_void_p, C.POINTER(shk_request), C.POINTER(C.c_longlong)]),
     "shk_server_poll": (C.c_int, [C.c_void_p, C.c_longlong, C.POINTER(shk_result), C.c_void_p, C.c_void_p]),
     "shk_server_drain": (C.c_int, [C.c_void_p]),
@@ -150,8 +156,8 @@ def _c128_array(values) -> "C.Array":
 def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_maxit=0, tol=1e-8,
                 eps_inner=1e-10, precision=SHK_FP64, variant=SHK_GMRES, refine_tol=0.05,
                 refine_eps_inner=5e-3, inner_precond=None, mg_omega=0.8, inner_relax=0.0, inner_eps_max=1e-2,
-                ortho=SHK_CGS2, rhs_mode=SHK_RHS_LOCKSTEP):
-    """Returns (shk_params, keepalive) with tau_seq marshalled to C."""
+                ortho=SHK_CGS2, rhs_mode=SHK_RHS_LOCKSTEP, output=SHK_OUT_FULL, out_rows=None):
+    """Returns (shk_params, keepalive) with tau_seq (and out_rows) marshalled to C."""
     taus = _c128_array(tau_seq)
     p = shk_params()
     lib().shk_params_default(C.byref(p))
@@ -167,7 +173,13 @@ def make_params(tau_seq, *, m_restart=50, max_restarts=20, max_refine=2, inner_m
     p.inner_relax, p.inner_eps_max = inner_relax, inner_eps_max
     p.ortho = ortho
     p.rhs_mode = rhs_mode
-    return p, taus
+    p.output = output
+    rows = None
+    if out_rows is not None:
+        rows = np.ascontiguousarray(out_rows, dtype=np.int64)
+        p.n_out_rows = len(rows)
+        p.out_rows = rows.ctypes.data_as(C.POINTER(C.c_longlong))
+    return p, (taus, rows)
 
 
 def _stream_ptr(stream):
@@ -239,14 +251,40 @@ def shk_workspace_bytes(problem: Problem, params: shk_params, n_shifts: int, n_r
     return int(out.value)
 
 
+def shk_output_elems(problem: Problem, params: shk_params, n_shifts: int, n_rhs: int):
+    """(complex elements of x, k_cap) for params.output."""
+    e, k = C.c_size_t(), C.c_int()
+    _check(lib().shk_output_elems(problem.handle, C.byref(params), n_shifts, n_rhs, C.byref(e), C.byref(k)),
+           "shk_output_elems")
+    return int(e.value), int(k.value)
+
+
+def _split_output(flat, params, n, nf, nr, kcap, host):
+    """Views of a flat output buffer per mode: FULL (n, nf, nr) / ROWS
+    (n_rows, nf, nr) Fortran-ordered on the host, (nr, nf, n) / (nr, nf,
+    n_rows) on the device; FACTORED a pair (Z, Y)."""
+    if params.output == SHK_OUT_FACTORED:
+        nz = n * kcap * nr
+        if host:
+            return (flat[:nz].reshape((n, kcap, nr), order="F"), flat[nz:].reshape((kcap, nf, nr), order="F"))
+        return flat[:nz].view(nr, kcap, n), flat[nz:].view(nr, nf, kcap)
+    rows = params.n_out_rows if params.output == SHK_OUT_ROWS else n
+    if host:
+        return flat.reshape((rows, nf, nr), order="F")
+    return flat.view(nr, nf, rows)
+
+
 def fgmres_sh_solve(problem: Problem, params: shk_params, sigma, b, x=None, workspace=None, stream=None):
     """Solve all shifts for all right-hand sides.
 
     ``b``: NumPy (n,) / (n, n_rhs) complex128 -> host path, x returned as NumPy
     (n, n_shifts, n_rhs) in Fortran order; or a torch CUDA complex128 tensor of
     shape (n_rhs, n) (each row one rhs, i.e. n x n_rhs column-major) -> device
-    path, x a torch tensor (n_rhs, n_shifts, n).  Returns (x, statuses) with
-    statuses a structured array of shape (n_rhs, n_shifts)."""
+    path, x a torch tensor (n_rhs, n_shifts, n).  With params.output ROWS the
+    cell axis has n_out_rows entries; FACTORED returns x as a pair (Z, Y) with
+    x_{j,r} = Z[:, :, r] @ Y[:, j, r] (host) / Z[r].T @ Y[r, j] (device).
+    Returns (x, statuses) with statuses a structured array of shape
+    (n_rhs, n_shifts)."""
     sig = _c128_array(sigma)
     nf = len(sig)
     st = np.zeros(nf * 1, dtype=STATUS_DTYPE)
@@ -256,20 +294,23 @@ def fgmres_sh_solve(problem: Problem, params: shk_params, sigma, b, x=None, work
             bb = bb[:, None]
         n, nr = bb.shape
         bf = np.asfortranarray(bb)
-        xo = np.zeros((n, nf, nr), dtype=np.complex128, order="F")
+        elems, kcap = shk_output_elems(problem, params, nf, nr)
+        xflat = np.zeros(elems, dtype=np.complex128)
         st = np.zeros((nr, nf), dtype=STATUS_DTYPE)
         ws_ptr = workspace.data_ptr() if workspace is not None else None
         ws_len = workspace.numel() * workspace.element_size() if workspace is not None else 0
-        rc = lib().fgmres_sh_solve(problem.handle, C.byref(params), nf, sig, nr, bf.ctypes.data, xo.ctypes.data,
+        rc = lib().fgmres_sh_solve(problem.handle, C.byref(params), nf, sig, nr, bf.ctypes.data, xflat.ctypes.data,
                                    st.ctypes.data, ws_ptr, ws_len, None if stream is None else C.c_void_p(stream),
                                    SHK_PTR_HOST)
         _check(rc, "fgmres_sh_solve")
-        return xo, st
+        return _split_output(xflat, params, n, nf, nr, kcap, True), st
     import torch
     assert b.is_cuda and b.dtype == torch.complex128 and b.is_contiguous()
     nr, n = b.shape
+    elems, kcap = shk_output_elems(problem, params, nf, nr)
     if x is None:
-        x = torch.empty((nr, nf, n), dtype=torch.complex128, device=b.device)
+        x = torch.empty(elems, dtype=torch.complex128, device=b.device)
+    assert x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous() and x.numel() == elems
     st = np.zeros((nr, nf), dtype=STATUS_DTYPE)
     if workspace is None:
         need = shk_workspace_bytes(problem, params, nf, nr)
@@ -278,7 +319,7 @@ def fgmres_sh_solve(problem: Problem, params: shk_params, sigma, b, x=None, work
                                C.c_void_p(x.data_ptr()), st.ctypes.data, C.c_void_p(workspace.data_ptr()),
                                workspace.numel(), _stream_ptr(stream), SHK_PTR_DEVICE)
     _check(rc, "fgmres_sh_solve")
-    return x, st
+    return _split_output(x.view(-1), params, n, nf, nr, kcap, False), st
 
 
 def _prec(t):
@@ -419,9 +460,16 @@ def shk_profile_read_block():
 class Server:
     """Continuous-admission solve server (shk_server_*)."""
 
-    def __init__(self, mem_budget_bytes: int, max_slots: int = 4):
+    def __init__(self, mem_budget_bytes: int, max_slots: int = 4, arena=None):
+        """arena: a CUDA tensor of at least mem_budget_bytes (kept alive by this
+        object), or None to let the server allocate its arena once."""
         self._h = C.c_void_p()
-        _check(lib().shk_server_create(mem_budget_bytes, max_slots, C.byref(self._h)), "shk_server_create")
+        self._arena = arena
+        ptr = None
+        if arena is not None:
+            assert arena.is_cuda and arena.numel() * arena.element_size() >= mem_budget_bytes
+            ptr = C.c_void_p(arena.data_ptr())
+        _check(lib().shk_server_create(mem_budget_bytes, max_slots, ptr, C.byref(self._h)), "shk_server_create")
         self._keep = {}
 
     def submit(self, cell_K, sigma, b, params: shk_params, Ss=1e-5, h=1.0, keep_solution=False) -> int:
@@ -444,22 +492,34 @@ class Server:
         req.keep_solution = 1 if keep_solution else 0
         t = C.c_longlong()
         _check(lib().shk_server_submit(self._h, C.byref(req), C.byref(t)), "shk_server_submit")
-        self._keep[t.value] = (K.shape, len(sg), bf.shape[1])
+        out = shk_params()
+        C.pointer(out)[0] = params
+        kcap = params.m_restart * (params.max_restarts + 1) * (params.max_refine + 1)
+        self._keep[t.value] = (K.shape, len(sg), bf.shape[1], out, kcap)
         return t.value
 
     def poll(self, ticket: int, want_solution=False):
-        """None while running; else (result dict, x or None, statuses)."""
-        shape, nf, nr = self._keep[ticket]
+        """None while running; else (result dict, output or None, statuses);
+        the output is shaped per the request's output mode as in
+        fgmres_sh_solve's host path."""
+        shape, nf, nr, prm, kcap = self._keep[ticket]
         n = int(np.prod(shape))
         res = shk_result()
-        x = np.zeros((n, nf, nr), dtype=np.complex128, order="F") if want_solution else None
+        if prm.output == SHK_OUT_ROWS:
+            elems = prm.n_out_rows * nf * nr
+        elif prm.output == SHK_OUT_FACTORED:
+            elems = kcap * (n + nf) * nr
+        else:
+            elems = n * nf * nr
+        flat = np.zeros(elems, dtype=np.complex128) if want_solution else None
         st = np.zeros((nr, nf), dtype=STATUS_DTYPE)
-        rc = lib().shk_server_poll(self._h, ticket, C.byref(res), x.ctypes.data if x is not None else None,
+        rc = lib().shk_server_poll(self._h, ticket, C.byref(res), flat.ctypes.data if flat is not None else None,
                                    st.ctypes.data)
         if rc == SHK_ERR_NOT_READY:
             return None
         _check(rc, "shk_server_poll")
         d = {f: getattr(res, f) for f, _ in shk_result._fields_}
+        x = _split_output(flat, prm, n, nf, nr, kcap, True) if flat is not None else None
         return d, x, st
 
     def drain(self):

@@ -30,6 +30,9 @@ void shk_params_default(shk_params* p) {
   p->inner_eps_max = 1e-2;
   p->ortho = SHK_CGS2;
   p->rhs_mode = SHK_RHS_LOCKSTEP;
+  p->output = SHK_OUT_FULL;
+  p->n_out_rows = 0;
+  p->out_rows = nullptr;
 }
 
 static int create_fv(int nx, int ny, int nz, shk::Kind kind, const double* cell_K, double Ss, double h,
@@ -94,6 +97,13 @@ int shk_workspace_bytes(const shk_problem* p, const shk_params* prm, int n_shift
   if (!p || !prm || !bytes || n_shifts < 1 || n_rhs < 1 || prm->m_restart < 1)
     return shk::fail(SHK_ERR_INVALID_ARG, "workspace arguments");
   *bytes = shk::workspace_bytes(p, prm, n_shifts, n_rhs, false);
+  return SHK_OK;
+}
+
+int shk_output_elems(const shk_problem* p, const shk_params* prm, int n_shifts, int n_rhs, size_t* elems,
+                     int* k_cap) {
+  if (!p || !prm || !elems || n_shifts < 1 || n_rhs < 1) return shk::fail(SHK_ERR_INVALID_ARG, "output_elems arguments");
+  *elems = shk::output_elems(prm, p->n, n_shifts, n_rhs, k_cap);
   return SHK_OK;
 }
 

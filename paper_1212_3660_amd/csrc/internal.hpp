@@ -26,6 +26,19 @@ int fail(int code, const std::string& msg);
 
 enum class Kind { FV2D, FV3D, CSR };
 
+// Bump allocation from a caller-owned device region (the solve server's
+// per-request region): 256-byte aligned, nothing freed individually.
+struct Bump {
+  char* base = nullptr;
+  size_t off = 0, cap = 0;
+  void* take(size_t bytes) {
+    const size_t o = (off + 255) & ~size_t(255);
+    if (o + bytes > cap) return nullptr;
+    off = o + bytes;
+    return base + o;
+  }
+};
+
 // One coarse level of the multigrid hierarchy (level 0 is the problem's own
 // grid): cells, faces (FP64 and FP32) and per-cell mass on the device.
 struct MgLevel {
@@ -59,6 +72,7 @@ struct shk_problem {
   double* mdiag = nullptr;          // per-row mass (CSR only)
   long long nnz = 0;
   std::vector<shk::MgLevel> mg;     // coarse levels (finite-volume problems)
+  shk::Bump* bump = nullptr;        // device arrays from this region instead of the HIP allocator
   int max_dim() const { return nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz); }
 };
 
@@ -96,7 +110,9 @@ int problem_setup_csr(shk_problem* p, const int* rowptr, const int* col, const d
                       const double* mdiag, hipStream_t st);
 void problem_free(shk_problem* p, hipStream_t st);
 size_t problem_bytes(const shk_problem* p);
+void problem_plan_levels(shk_problem* p);
 size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x);
+size_t output_elems(const shk_params* prm, long n, int nf, int n_rhs, int* kcap);
 const char* last_error_text();
 int profile_enable(int on);
 int profile_read(long long* launches, double* ms, double* bytes);

@@ -1319,6 +1319,44 @@ __global__ void __launch_bounds__(BS) k_asm_scale(int L, int cycle, const LaneSt
   out[lane] = use ? (extra ? extra[lane] : c128{1.0, 0.0}) : c128{0.0, 0.0};
 }
 
+// ---------------------------------------------------------- output modes ---
+// Factored output of one assembly (x = Z y, Algorithm 4): the kc basis vectors
+// of the cycle (FP64 basis Z, lane-interleaved) appended as columns koff..
+// of fz (n x kcap per rhs) and the coefficients, scaled per (shift, rhs) as
+// the assembly scales them, into rows koff.. of fy (kcap x nf per rhs).
+__global__ void __launch_bounds__(BS) k_factored_out(long n, int S, int s_real, int nf, int kc, int m,
+                                                     const c128* __restrict__ Z, size_t cstride,
+                                                     const c128* __restrict__ Yb, const c128* __restrict__ ascale,
+                                                     c128* __restrict__ fz, c128* __restrict__ fy, int kcap,
+                                                     int koff) {
+  const long tz = n * kc * s_real, ty = (long)kc * nf * s_real;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < tz + ty; t += (long)gridDim.x * BS) {
+    if (t < tz) {
+      const long c = t % n, rest = t / n;
+      const int i = (int)(rest % kc), r = (int)(rest / kc);
+      fz[c + n * ((long)koff + i + (long)kcap * r)] = Z[(size_t)i * cstride + c * S + r];
+    } else {
+      const long u = t - tz;
+      const int i = (int)(u % kc);
+      const long rest = u / kc;
+      const int j = (int)(rest % nf), r = (int)(rest / nf);
+      fy[(koff + i) + (long)kcap * (j + (long)nf * r)] =
+          ascale[(size_t)j * S + r] * Yb[((size_t)j * S + r) * m + i];
+    }
+  }
+}
+
+// Solution rows at selected cells: out[q + nr (j + nf r)] = X[rows[q] + n (j + nf r)].
+__global__ void __launch_bounds__(BS) k_gather_rows(const c128* __restrict__ X, long n, long cols,
+                                                    const long long* __restrict__ rows, int nr,
+                                                    c128* __restrict__ out) {
+  const long total = (long)nr * cols;
+  for (long t = blockIdx.x * (long)BS + threadIdx.x; t < total; t += (long)gridDim.x * BS) {
+    const long q = t % nr, col = t / nr;
+    out[t] = X[rows[q] + n * col];
+  }
+}
+
 // ------------------------------------------------------------ assembly -----
 // X[:, j, r] (+)= scale_j * Z_r y_{j,r} (Algorithm 4, x = Z y), FP64
 // accumulation.  Thread per item (cell, lane), JT shifts per block row.

@@ -1,12 +1,16 @@
 // Solve server: continuous admission of shifted-system requests.
 //
 // A request is a 2-D field, a set of shifts and a block of right-hand sides.
-// Worker threads (one per slot, each with its own non-blocking HIP stream)
-// take the oldest pending request whose device footprint (operator faces,
-// Krylov workspace and solution) fits the unused part of the memory budget,
-// set the problem up, solve it, and release the memory; requests that arrive
-// while others run are admitted as soon as a slot and memory free up, and
-// their kernels overlap on the device with those of the running requests.
+// All device memory of a request (operator faces and multigrid hierarchy,
+// Krylov workspace, right-hand sides, output) comes from one contiguous
+// region of the server's device arena: the caller's buffer, or one
+// allocation the server makes when it is created.  Worker threads (one per
+// slot, each with its own non-blocking HIP stream) take the oldest pending
+// request for which a region of its footprint is free (first fit), set the
+// problem up, solve it, copy its output to the host and release the region;
+// requests that arrive while others run are admitted as soon as a slot and a
+// region free up, and their kernels overlap on the device with those of the
+// running requests.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -34,8 +38,10 @@ struct Job {
   std::vector<shk_c128> b;
   shk_params prm;
   std::vector<shk_c128> taus;
+  std::vector<long long> rows;
   size_t need = 0;
-  // results
+  size_t region = 0;   // arena offset while running
+  // results (written by the worker under the server mutex)
   shk_result res{};
   std::vector<shk_c128> x;
   std::vector<shk_status> st;
@@ -47,7 +53,9 @@ struct Job {
 struct shk_server {
   size_t budget;
   int slots;
-  size_t used = 0;
+  char* arena = nullptr;
+  bool own_arena = false;
+  std::map<size_t, size_t> free_;   // free regions of the arena: offset -> length
   int running = 0;
   bool stop = false;
   long long next_ticket = 1;
@@ -62,8 +70,41 @@ struct shk_server {
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  // First free region of at least len bytes (256-byte granules); false if none.
+  bool reserve(size_t len, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < len) continue;
+      *off = it->first;
+      const size_t rest = it->second - len;
+      const size_t at = it->first + len;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  // Returns a region, merging it with free neighbours.
+  void release(size_t off, size_t len) {
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + len == next->first) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
 };
 
+static size_t granule(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Device bytes of a request: problem arrays, workspace, right-hand sides and
+// the device copy of its output, each rounded to the region's alignment.
 static size_t footprint(const Job& j) {
   shk_problem tmp{};
   tmp.kind = shk::Kind::FV2D;
@@ -71,49 +112,50 @@ static size_t footprint(const Job& j) {
   tmp.ny = j.ny;
   tmp.nz = 1;
   tmp.n = (long long)j.nx * j.ny;
-  const size_t ws = shk::workspace_bytes(&tmp, &j.prm, (int)j.sigma.size(), j.n_rhs, false);
-  const size_t xb = sizeof(c128) * (size_t)tmp.n * j.sigma.size() * j.n_rhs;
-  return ws + xb + shk::problem_bytes(&tmp) + (64u << 20);
+  shk::problem_plan_levels(&tmp);   // the workspace holds multigrid buffers per level
+  const int nf = (int)j.sigma.size();
+  const size_t ws = shk::workspace_bytes(&tmp, &j.prm, nf, j.n_rhs, false);
+  const size_t xb = sizeof(c128) * shk::output_elems(&j.prm, tmp.n, nf, j.n_rhs, nullptr);
+  const size_t bb = sizeof(c128) * (size_t)tmp.n * j.n_rhs;
+  return granule(granule(shk::problem_bytes(&tmp)) + granule(ws) + granule(xb) + granule(bb) + (1u << 20));
 }
 
-// Runs one request on stream st.  Only this thread touches the request's
-// inputs while it runs; the outputs go to x_out / st_out / res_out, which the
-// caller publishes under the server mutex.
+// Runs one request on stream st inside its arena region.  Only this thread
+// touches the request's inputs while it runs; the outputs go to res_out /
+// x_out / st_out, which the caller publishes under the server mutex.
 static void run_job(shk_server* s, Job* j, hipStream_t st, shk_result& res_out, std::vector<shk_c128>& x_out,
                     std::vector<shk_status>& st_out) {
   res_out.t_start = s->now();
+  shk::Bump bump{s->arena + j->region, 0, j->need};
   shk_problem* p = new shk_problem();
   p->kind = shk::Kind::FV2D;
   p->nx = j->nx;
   p->ny = j->ny;
   p->nz = 1;
+  p->bump = &bump;
   int rc = shk::problem_setup_fv(p, j->K.data(), j->Ss, j->h, st);
   const long long n = (long long)j->nx * j->ny;
   const int nf = (int)j->sigma.size();
-  void* ws = nullptr;
-  void* xd = nullptr;
-  void* bd = nullptr;
   st_out.assign((size_t)nf * j->n_rhs, shk_status{});
   if (rc == SHK_OK) {
     const size_t wsb = shk::workspace_bytes(p, &j->prm, nf, j->n_rhs, false);
-    const size_t xb = sizeof(c128) * (size_t)n * nf * j->n_rhs;
-    if (hipMallocAsync(&ws, wsb, st) != hipSuccess || hipMallocAsync(&xd, xb, st) != hipSuccess ||
-        hipMallocAsync(&bd, sizeof(c128) * (size_t)n * j->n_rhs, st) != hipSuccess) {
-      rc = shk::fail(SHK_ERR_OOM, "server request allocation");
+    const size_t xe = shk::output_elems(&j->prm, n, nf, j->n_rhs, nullptr);
+    void* ws = bump.take(wsb);
+    void* xd = bump.take(sizeof(c128) * xe);
+    void* bd = bump.take(sizeof(c128) * (size_t)n * j->n_rhs);
+    if (!ws || !xd || !bd) {
+      rc = shk::fail(SHK_ERR_OOM, "server request region too small");
     } else {
       (void)hipMemcpyAsync(bd, j->b.data(), sizeof(c128) * (size_t)n * j->n_rhs, hipMemcpyHostToDevice, st);
       rc = shk::solve_all(p, &j->prm, nf, reinterpret_cast<const c128*>(j->sigma.data()), j->n_rhs,
                           reinterpret_cast<const c128*>(bd), reinterpret_cast<c128*>(xd), st_out.data(), ws, wsb,
                           st, SHK_PTR_DEVICE);
       if (rc == SHK_OK && j->keep_x) {
-        x_out.resize((size_t)n * nf * j->n_rhs);
-        (void)hipMemcpyAsync(x_out.data(), xd, xb, hipMemcpyDeviceToHost, st);
+        x_out.resize(xe);
+        (void)hipMemcpyAsync(x_out.data(), xd, sizeof(c128) * xe, hipMemcpyDeviceToHost, st);
       }
     }
   }
-  if (ws) (void)hipFreeAsync(ws, st);
-  if (xd) (void)hipFreeAsync(xd, st);
-  if (bd) (void)hipFreeAsync(bd, st);
   shk::problem_free(p, st);
   delete p;
   (void)hipStreamSynchronize(st);
@@ -138,20 +180,22 @@ static void worker(shk_server* s) {
     Job* pick = nullptr;
     s->cv_work.wait(lk, [&] {
       if (s->stop) return true;
-      for (Job* j : s->pending)
-        if (s->used + j->need <= s->budget) return true;
+      // the oldest pending request that a free region can hold
+      for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+        size_t off = 0;
+        if (s->reserve((*it)->need, &off)) {
+          pick = *it;
+          pick->region = off;
+          s->pending.erase(it);
+          return true;
+        }
+      }
       return false;
     });
-    if (s->stop && s->pending.empty()) break;
-    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
-      if (s->used + (*it)->need <= s->budget) {
-        pick = *it;
-        s->pending.erase(it);
-        break;
-      }
+    if (!pick) {
+      if (s->stop) break;
+      continue;
     }
-    if (!pick) continue;
-    s->used += pick->need;
     s->running += 1;
     shk_result res = pick->res;   // t_arrival, set at submit under the mutex
     lk.unlock();
@@ -166,7 +210,7 @@ static void worker(shk_server* s) {
     pick->st.swap(stv);
     std::vector<double>().swap(pick->K);      // the request's inputs are no longer needed
     std::vector<shk_c128>().swap(pick->b);
-    s->used -= pick->need;
+    s->release(pick->region, pick->need);
     s->running -= 1;
     s->cv_work.notify_all();
     s->cv_done.notify_all();
@@ -177,17 +221,33 @@ static void worker(shk_server* s) {
 
 extern "C" {
 
-int shk_server_create(size_t mem_budget_bytes, int max_slots, shk_server** out) {
-  if (!out || max_slots < 1 || max_slots > 16 || mem_budget_bytes == 0)
-    return shk::fail(SHK_ERR_INVALID_ARG, "server arguments (1 <= max_slots <= 16)");
+int shk_server_create(size_t mem_budget_bytes, int max_slots, void* device_arena, shk_server** out) {
+  if (!out || max_slots < 1 || max_slots > 16 || mem_budget_bytes < (1u << 20))
+    return shk::fail(SHK_ERR_INVALID_ARG, "server arguments (1 <= max_slots <= 16, budget >= 1 MiB)");
   shk_server* s = new shk_server();
-  s->budget = mem_budget_bytes;
+  s->budget = mem_budget_bytes & ~size_t(255);
   s->slots = max_slots;
   s->t0 = std::chrono::steady_clock::now();
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return shk::fail(SHK_ERR_HIP, "no HIP device");
   }
+  if (device_arena) {
+    if (reinterpret_cast<uintptr_t>(device_arena) & 255) {
+      delete s;
+      return shk::fail(SHK_ERR_INVALID_ARG, "the device arena must be 256-byte aligned");
+    }
+    s->arena = static_cast<char*>(device_arena);
+  } else {
+    void* a = nullptr;
+    if (hipMalloc(&a, s->budget) != hipSuccess) {
+      delete s;
+      return shk::fail(SHK_ERR_OOM, "server arena allocation");
+    }
+    s->arena = static_cast<char*>(a);
+    s->own_arena = true;
+  }
+  s->free_[0] = s->budget;
   for (int i = 0; i < max_slots; ++i) s->workers.emplace_back(worker, s);
   *out = s;
   return SHK_OK;
@@ -197,8 +257,14 @@ int shk_server_submit(shk_server* s, const shk_request* req, long long* ticket) 
   if (!s || !req || !ticket || !req->cell_K || !req->sigma || !req->b || req->nx < 1 || req->ny < 1 ||
       req->n_shifts < 1 || req->n_rhs < 1 || req->params.n_tau < 1 || !req->params.tau_seq)
     return shk::fail(SHK_ERR_INVALID_ARG, "request arguments");
-  auto j = std::make_unique<Job>();
+  const shk_params& pr = req->params;
   const long long n = (long long)req->nx * req->ny;
+  if (pr.output == SHK_OUT_ROWS) {
+    if (pr.n_out_rows < 1 || !pr.out_rows) return shk::fail(SHK_ERR_INVALID_ARG, "SHK_OUT_ROWS needs out_rows");
+    for (int q = 0; q < pr.n_out_rows; ++q)
+      if (pr.out_rows[q] < 0 || pr.out_rows[q] >= n) return shk::fail(SHK_ERR_INVALID_ARG, "out_rows outside [0, n)");
+  }
+  auto j = std::make_unique<Job>();
   j->nx = req->nx;
   j->ny = req->ny;
   j->K.assign(req->cell_K, req->cell_K + n);
@@ -207,9 +273,15 @@ int shk_server_submit(shk_server* s, const shk_request* req, long long* ticket) 
   j->sigma.assign(req->sigma, req->sigma + req->n_shifts);
   j->n_rhs = req->n_rhs;
   j->b.assign(req->b, req->b + n * req->n_rhs);
-  j->prm = req->params;
-  j->taus.assign(req->params.tau_seq, req->params.tau_seq + req->params.n_tau);
+  j->prm = pr;
+  j->taus.assign(pr.tau_seq, pr.tau_seq + pr.n_tau);
   j->prm.tau_seq = j->taus.data();
+  if (pr.output == SHK_OUT_ROWS) {
+    j->rows.assign(pr.out_rows, pr.out_rows + pr.n_out_rows);
+    j->prm.out_rows = j->rows.data();
+  } else {
+    j->prm.out_rows = nullptr;
+  }
   j->keep_x = req->keep_solution != 0;
   j->need = footprint(*j);
   std::lock_guard<std::mutex> g(s->mu);
@@ -219,7 +291,7 @@ int shk_server_submit(shk_server* s, const shk_request* req, long long* ticket) 
   *ticket = j->ticket;
   s->pending.push_back(j.get());
   s->jobs[j->ticket] = std::move(j);
-  s->cv_work.notify_one();
+  s->cv_work.notify_all();
   return SHK_OK;
 }
 
@@ -255,6 +327,7 @@ int shk_server_destroy(shk_server* s) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->workers) t.join();
+  if (s->own_arena) (void)hipFree(s->arena);
   delete s;
   return SHK_OK;
 }

@@ -120,7 +120,21 @@ int profile_read(long long* launches, double* ms, double* bytes) {
 }
 
 // --------------------------------------------------------------- problem ---
+// Device arrays of a problem: from its bump region when it has one, else from
+// the stream-ordered HIP allocator.
+static hipError_t dev_alloc(shk_problem* p, void** ptr, size_t bytes, hipStream_t st) {
+  if (p->bump) {
+    *ptr = p->bump->take(bytes);
+    return *ptr ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMallocAsync(ptr, bytes, st);
+}
+
 void problem_free(shk_problem* p, hipStream_t st) {
+  if (p->bump) {   // the region's owner releases it as a whole
+    p->mg.clear();
+    return;
+  }
   void* ptrs[] = {p->tx, p->ty, p->tz, p->tx32, p->ty32, p->tz32, p->rowptr, p->col, p->val, p->val32, p->diag, p->mdiag,
                   p->dK, p->dK32, p->cellK};
   for (void* q : ptrs)
@@ -154,13 +168,13 @@ static int mg_setup(shk_problem* p, hipStream_t st) {
     MgLevel& L = p->mg.back();
     for (int a = 0; a < d; ++a) {
       const long cnt = (long)(c.nx + (a == 0)) * (c.ny + (a == 1)) * (c.nz + (a == 2));
-      if (hipMallocAsync((void**)&L.t[a], cnt * sizeof(double), st) != hipSuccess ||
-          hipMallocAsync((void**)&L.t32[a], cnt * sizeof(float), st) != hipSuccess)
+      if (dev_alloc(p, (void**)&L.t[a], cnt * sizeof(double), st) != hipSuccess ||
+          dev_alloc(p, (void**)&L.t32[a], cnt * sizeof(float), st) != hipSuccess)
         return fail(SHK_ERR_OOM, "multigrid faces");
       k_mg_faces<<<grid_items(cnt, 4096), BS, 0, st>>>(f, c, a, ft[a], L.t[a], L.t32[a]);
       SHK_HIP(hipGetLastError());
     }
-    if (hipMallocAsync((void**)&L.mass, (size_t)c.n() * sizeof(double), st) != hipSuccess)
+    if (dev_alloc(p, (void**)&L.mass, (size_t)c.n() * sizeof(double), st) != hipSuccess)
       return fail(SHK_ERR_OOM, "multigrid mass");
     k_mg_mass<<<grid_items(c.n(), 4096), BS, 0, st>>>(f, c, fm, p->m0, L.mass);
     SHK_HIP(hipGetLastError());
@@ -171,15 +185,38 @@ static int mg_setup(shk_problem* p, hipStream_t st) {
   return SHK_OK;
 }
 
+// The multigrid levels' dimensions without device arrays (for sizing a
+// workspace before the problem is set up).
+void problem_plan_levels(shk_problem* p) {
+  p->mg.clear();
+  LevelDims f{p->nx, p->ny, p->nz};
+  while (f.n() > 1) {
+    const LevelDims c = f.coarse();
+    MgLevel l;
+    l.nx = c.nx; l.ny = c.ny; l.nz = c.nz; l.n = c.n();
+    p->mg.push_back(l);
+    f = c;
+  }
+}
+
+// Device bytes of a problem's arrays (an upper bound: every array rounded up
+// to the 256-byte alignment of a bump region).
 size_t problem_bytes(const shk_problem* p) {
-  if (p->kind == Kind::CSR) return (size_t)p->nnz * 16 + (size_t)p->n * 24;
+  if (p->kind == Kind::CSR) return (size_t)p->nnz * 16 + (size_t)p->n * 24 + 16 * 256;
   const size_t faces = (size_t)(p->nx + 1) * p->ny * p->nz + (size_t)p->nx * (p->ny + 1) * p->nz +
                        (p->kind == Kind::FV3D ? (size_t)p->nx * p->ny * (p->nz + 1) : 0);
-  size_t coarse = 0;
-  for (const MgLevel& l : p->mg)
-    coarse += (size_t)l.n * 8 + ((size_t)(l.nx + 1) * l.ny * l.nz + (size_t)l.nx * (l.ny + 1) * l.nz +
-                                 (p->kind == Kind::FV3D ? (size_t)l.nx * l.ny * (l.nz + 1) : 0)) * 12;
-  return faces * 12 + (size_t)p->n * 12 + coarse;
+  // the multigrid hierarchy from the grid dimensions (set up or not yet)
+  size_t coarse = 0, levels = 0;
+  LevelDims f{p->nx, p->ny, p->nz};
+  while (f.n() > 1) {
+    const LevelDims l = f.coarse();
+    coarse += (size_t)l.n() * 8 + ((size_t)(l.nx + 1) * l.ny * l.nz + (size_t)l.nx * (l.ny + 1) * l.nz +
+                                   (p->kind == Kind::FV3D ? (size_t)l.nx * l.ny * (l.nz + 1) : 0)) * 12;
+    ++levels;
+    f = l;
+  }
+  const size_t arrays = 16 + 8 * levels;
+  return faces * 12 + (size_t)p->n * 20 + coarse + arrays * 256;
 }
 
 int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipStream_t st) {
@@ -194,23 +231,23 @@ int problem_setup_fv(shk_problem* p, const double* K, double Ss, double h, hipSt
   const double scale = std::pow(h, d - 2);
   p->m0 = Ss * std::pow(h, d);
   double* Kd = nullptr;
-  if (hipMallocAsync((void**)&Kd, n * sizeof(double), st) != hipSuccess) return fail(SHK_ERR_OOM, "cell field");
+  if (dev_alloc(p, (void**)&Kd, n * sizeof(double), st) != hipSuccess) return fail(SHK_ERR_OOM, "cell field");
   SHK_HIP(hipMemcpyAsync(Kd, K, n * sizeof(double), hipMemcpyHostToDevice, st));
   const int axes = d;
   double** T[3] = {&p->tx, &p->ty, &p->tz};
   float** T32[3] = {&p->tx32, &p->ty32, &p->tz32};
   for (int a = 0; a < axes; ++a) {
     const long cnt = (long)(p->nx + (a == 0)) * (p->ny + (a == 1)) * (p->nz + (a == 2));
-    if (hipMallocAsync((void**)T[a], cnt * sizeof(double), st) != hipSuccess ||
-        hipMallocAsync((void**)T32[a], cnt * sizeof(float), st) != hipSuccess) {
-      (void)hipFreeAsync(Kd, st);
+    if (dev_alloc(p, (void**)T[a], cnt * sizeof(double), st) != hipSuccess ||
+        dev_alloc(p, (void**)T32[a], cnt * sizeof(float), st) != hipSuccess) {
+      if (!p->bump) (void)hipFreeAsync(Kd, st);
       return fail(SHK_ERR_OOM, "face arrays");
     }
     k_faces<<<grid_items(cnt, 8192), BS, 0, st>>>(Kd, p->nx, p->ny, p->nz, a, scale, *T[a], *T32[a]);
     SHK_HIP(hipGetLastError());
   }
-  if (hipMallocAsync((void**)&p->dK, n * sizeof(double), st) != hipSuccess ||
-      hipMallocAsync((void**)&p->dK32, n * sizeof(float), st) != hipSuccess)
+  if (dev_alloc(p, (void**)&p->dK, n * sizeof(double), st) != hipSuccess ||
+      dev_alloc(p, (void**)&p->dK32, n * sizeof(float), st) != hipSuccess)
     return fail(SHK_ERR_OOM, "diagonal arrays");
   if (p->kind == Kind::FV3D) {
     Op3D<double> od{p->nx, p->ny, p->nz, p->tx, p->ty, p->tz, nullptr, p->m0};
@@ -391,6 +428,8 @@ template <typename R> struct Buffers {
   double* rc;
   c128 *rs, *g, *Rp, *Yb, *Yt, *ascale, *extra;
   c128 *bint, *rsv, *X;
+  c128* ostage = nullptr;     // device staging of host ROWS / FACTORED output
+  long long* rows = nullptr;  // cells of ROWS output
   c128* rpart;      // residual partials [s][nf][Gr]
   c128* rrow;       // residual rows [s*nf]
   // multigrid inner preconditioner: u = B r, and per coarse level l >= 1 the
@@ -540,9 +579,36 @@ static void gram_schmidt(long N, int S, int kc, cx<R>* V, cx<R>* w, c128* H, c12
   }
 }
 
+// Where a group's solution goes.  X itself is formed in the caller's buffer
+// for device FULL output, otherwise in the workspace; host ROWS / FACTORED
+// output is staged on the device first.
+struct OutPlan {
+  int mode = SHK_OUT_FULL;
+  bool internal_x = false;
+  size_t stage = 0;    // complex elements of device staging (host ROWS / FACTORED output)
+  int n_rows = 0;
+  int kcap = 0;
+};
+static int factored_kcap(const shk_params* prm) {
+  return prm->m_restart * (prm->max_restarts + 1) * (prm->max_refine + 1);
+}
+static OutPlan out_plan(const shk_params* prm, long n, int nf, int s_real, bool host_x) {
+  OutPlan o;
+  o.mode = prm->output;
+  o.internal_x = host_x || o.mode != SHK_OUT_FULL;
+  if (o.mode == SHK_OUT_ROWS) {
+    o.n_rows = prm->n_out_rows;
+    if (host_x) o.stage = (size_t)o.n_rows * nf * s_real;
+  } else if (o.mode == SHK_OUT_FACTORED) {
+    o.kcap = factored_kcap(prm);
+    if (host_x) o.stage = (size_t)o.kcap * ((size_t)n + nf) * s_real;
+  }
+  return o;
+}
+
 template <typename R>
-static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, int s_real, bool host_x, bool mg,
-                        bool block = false) {
+static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, int s_real, const OutPlan& op,
+                        bool mg, bool block = false) {
   Carver cv{base};
   const long n = p->n;
   Buffers<R> b{};
@@ -594,7 +660,9 @@ static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, 
   b.extra = cv.take<c128>(L);
   b.bint = cv.take<c128>(N);
   b.rsv = cv.take<c128>(N);
-  b.X = host_x ? cv.take<c128>((size_t)n * nf * s_real) : nullptr;
+  b.X = op.internal_x ? cv.take<c128>((size_t)n * nf * s_real) : nullptr;
+  b.ostage = op.stage ? cv.take<c128>(op.stage) : nullptr;
+  b.rows = op.n_rows ? cv.take<long long>((size_t)op.n_rows) : nullptr;
   const int Gr = resid_grid(n);
   b.rpart = cv.take<c128>((size_t)s_real * nf * Gr);
   b.rrow = cv.take<c128>((size_t)s_real * nf);
@@ -611,10 +679,10 @@ static int lanes_of(int n_rhs, bool block = false) {
   return block ? std::max(16, s) : s;
 }
 
-static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real, int precision, bool host_x,
+static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real, int precision, const OutPlan& op,
                           bool mg, bool block) {
-  if (precision == SHK_MIXED) return carve<float>(nullptr, p, m, nf, S, s_real, host_x, mg, block).bytes;
-  return carve<double>(nullptr, p, m, nf, S, s_real, host_x, mg, block).bytes;
+  if (precision == SHK_MIXED) return carve<float>(nullptr, p, m, nf, S, s_real, op, mg, block).bytes;
+  return carve<double>(nullptr, p, m, nf, S, s_real, op, mg, block).bytes;
 }
 
 // ------------------------------------------------------- lane totals -------
@@ -1331,11 +1399,22 @@ template <typename R, typename Op, typename OpD> struct Group {
     return a;
   }
 
+  // factored output (SHK_OUT_FACTORED): every assembly also appends its basis
+  // vectors and scaled coefficients at column fz_off
+  c128 *fz = nullptr, *fy = nullptr;
+  int fz_cap = 0, fz_off = 0;
+
   int assemble(int kc, int cycle, const c128* extra, c128* X, bool accumulate) {
     const int Lb = (L + BS - 1) / BS;
     k_asm_scale<<<Lb, BS, 0, st>>>(L, cycle, B.ls, extra, B.ascale);
     launch_assemble<double>(n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, X, accumulate ? 1 : 0, st,
                             B.Yt);
+    if (fz) {
+      if (fz_off + kc > fz_cap) return fail(SHK_ERR_WORKSPACE, "factored output capacity exceeded");
+      k_factored_out<<<grid_items((long)(n + nf) * kc * s_real, 4096), BS, 0, st>>>(
+          n, S, s_real, nf, kc, m, B.Z, (size_t)N, B.Yb, B.ascale, fz, fy, fz_cap, fz_off);
+      fz_off += kc;
+    }
     SHK_HIP(hipGetLastError());
     return SHK_OK;
   }
@@ -1555,17 +1634,38 @@ static int residual_rows(const OpD& opd, long n, int S, int s_real, int nf, cons
   return SHK_OK;
 }
 
+// Output destinations of one group: x (FULL, ROWS) or the Z and Y parts of
+// the factored output, host or device per ptr_kind.
+struct GroupOut {
+  c128* x = nullptr;
+  c128* fz = nullptr;
+  c128* fy = nullptr;
+};
+
 template <typename R>
 static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128* sigma_h, int s_real,
-                       const c128* b_src, int ptr_kind, c128* x_dst, shk_status* st_out, char* ws, hipStream_t st) {
+                       const c128* b_src, int ptr_kind, const GroupOut& dst, shk_status* st_out, char* ws,
+                       hipStream_t st) {
   const bool blk = prm->rhs_mode == SHK_RHS_BLOCK;
   const int S = lanes_of(s_real, blk);
   const int m = prm->m_restart;
   const long n = p->n;
   const bool host_x = ptr_kind == SHK_PTR_HOST;
   const bool use_mg = prm->inner_precond == SHK_PRECOND_MULTIGRID;
-  Buffers<R> B = carve<R>(ws, p, m, nf, S, s_real, host_x, use_mg, blk);
-  c128* X = host_x ? B.X : x_dst;
+  const OutPlan op = out_plan(prm, n, nf, s_real, host_x);
+  Buffers<R> B = carve<R>(ws, p, m, nf, S, s_real, op, use_mg, blk);
+  c128* X = op.internal_x ? B.X : dst.x;
+  // factored output: device destinations (the caller's, or staging for host)
+  c128* fz = nullptr;
+  c128* fy = nullptr;
+  if (op.mode == SHK_OUT_FACTORED) {
+    fz = host_x ? B.ostage : dst.fz;
+    fy = host_x ? B.ostage + (size_t)op.kcap * n * s_real : dst.fy;
+    SHK_HIP(hipMemsetAsync(fz, 0, sizeof(c128) * (size_t)op.kcap * n * s_real, st));
+    SHK_HIP(hipMemsetAsync(fy, 0, sizeof(c128) * (size_t)op.kcap * nf * s_real, st));
+  }
+  if (op.mode == SHK_OUT_ROWS)
+    SHK_HIP(hipMemcpyAsync(B.rows, prm->out_rows, sizeof(long long) * op.n_rows, hipMemcpyHostToDevice, st));
   const long N = n * S;
   // rhs into interleaved c128
   const c128* bdev = b_src;
@@ -1591,6 +1691,9 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     g.mg = use_mg;
     g.mg_omega = prm->mg_omega;
     g.mgs = prm->ortho == SHK_MGS;
+    g.fz = fz;
+    g.fy = fy;
+    g.fz_cap = factored_kcap(prm);
     PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0, prm->inner_relax, prm->inner_eps_max,
                 prm->variant == SHK_FOM};
     SHK_TRY(blk ? g.pass_block(B.bint, ps, X, false, nullptr) : g.pass(B.bint, ps, X, false, nullptr));
@@ -1653,6 +1756,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
       SHK_TRY(measure());
     }
     inner_total = g.inner_its;
+    const int basis_cols = blk ? g.outer_steps * S : (fz ? g.fz_off : g.outer_steps);
     for (int r = 0; r < s_real; ++r)
       for (int j = 0; j < nf; ++j) {
         const LaneState& ls = lanes[j * S + r];
@@ -1660,6 +1764,8 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
         o.outer_its = ls.outer_its;
         o.restarts = ls.restarts;
         o.refine_sweeps = sweeps;
+        o.basis_cols = basis_cols;
+        o.reserved = 0;
         o.inner_its = inner_total;
         o.quasi_relres = bnorm[r] > 0 ? ls.rho / bnorm[r] : 0.0;
         o.bound_relres = bnorm[r] > 0 ? ls.bound / bnorm[r] : 0.0;
@@ -1673,8 +1779,18 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     return SHK_OK;
   });
   SHK_TRY(rc);
-  if (host_x) {
-    SHK_HIP(hipMemcpyAsync(x_dst, X, sizeof(c128) * n * nf * s_real, hipMemcpyDeviceToHost, st));
+  if (op.mode == SHK_OUT_FULL) {
+    if (host_x) SHK_HIP(hipMemcpyAsync(dst.x, X, sizeof(c128) * n * nf * s_real, hipMemcpyDeviceToHost, st));
+  } else if (op.mode == SHK_OUT_ROWS) {
+    const long cols = (long)nf * s_real;
+    c128* out = host_x ? B.ostage : dst.x;
+    k_gather_rows<<<grid_items((long)op.n_rows * cols, 4096), BS, 0, st>>>(X, n, cols, B.rows, op.n_rows, out);
+    SHK_HIP(hipGetLastError());
+    if (host_x)
+      SHK_HIP(hipMemcpyAsync(dst.x, out, sizeof(c128) * (size_t)op.n_rows * cols, hipMemcpyDeviceToHost, st));
+  } else if (host_x) {
+    SHK_HIP(hipMemcpyAsync(dst.fz, fz, sizeof(c128) * (size_t)op.kcap * n * s_real, hipMemcpyDeviceToHost, st));
+    SHK_HIP(hipMemcpyAsync(dst.fy, fy, sizeof(c128) * (size_t)op.kcap * nf * s_real, hipMemcpyDeviceToHost, st));
   }
   SHK_HIP(hipStreamSynchronize(st));
   return SHK_OK;
@@ -1699,6 +1815,15 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
     if (!(prm->mg_omega > 0.0 && prm->mg_omega <= 1.0)) return fail(SHK_ERR_INVALID_ARG, "mg_omega must be in (0, 1]");
   }
   if (prm->rhs_mode != SHK_RHS_LOCKSTEP && prm->rhs_mode != SHK_RHS_BLOCK) return fail(SHK_ERR_INVALID_ARG, "rhs_mode");
+  if (prm->output != SHK_OUT_FULL && prm->output != SHK_OUT_ROWS && prm->output != SHK_OUT_FACTORED)
+    return fail(SHK_ERR_INVALID_ARG, "output");
+  if (prm->output == SHK_OUT_ROWS) {
+    if (prm->n_out_rows < 1 || !prm->out_rows) return fail(SHK_ERR_INVALID_ARG, "SHK_OUT_ROWS needs out_rows");
+    for (int q = 0; q < prm->n_out_rows; ++q)
+      if (prm->out_rows[q] < 0 || prm->out_rows[q] >= p->n) return fail(SHK_ERR_INVALID_ARG, "out_rows outside [0, n)");
+  }
+  if (prm->output == SHK_OUT_FACTORED && prm->rhs_mode == SHK_RHS_BLOCK)
+    return fail(SHK_ERR_UNSUPPORTED, "factored output is provided for lockstep bases only");
   if (prm->rhs_mode == SHK_RHS_BLOCK) {
     if (prm->variant != SHK_GMRES) return fail(SHK_ERR_UNSUPPORTED, "the shared block basis solves least squares (GMRES) only");
     if (prm->ortho != SHK_CGS2) return fail(SHK_ERR_UNSUPPORTED, "the shared block basis uses block CGS2");
@@ -1717,8 +1842,15 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
 size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x) {
   const int s_real = std::min(n_rhs, 64);
   const bool blk = prm->rhs_mode == SHK_RHS_BLOCK;
-  return group_bytes(p, prm->m_restart, nf, lanes_of(s_real, blk), s_real, prm->precision, host_x,
-                     prm->inner_precond == SHK_PRECOND_MULTIGRID, blk);
+  return group_bytes(p, prm->m_restart, nf, lanes_of(s_real, blk), s_real, prm->precision,
+                     out_plan(prm, p->n, nf, s_real, host_x), prm->inner_precond == SHK_PRECOND_MULTIGRID, blk);
+}
+
+size_t output_elems(const shk_params* prm, long n, int nf, int n_rhs, int* kcap) {
+  if (kcap) *kcap = prm->output == SHK_OUT_FACTORED ? factored_kcap(prm) : 0;
+  if (prm->output == SHK_OUT_ROWS) return (size_t)prm->n_out_rows * nf * n_rhs;
+  if (prm->output == SHK_OUT_FACTORED) return (size_t)factored_kcap(prm) * ((size_t)n + nf) * n_rhs;
+  return (size_t)n * nf * n_rhs;
 }
 
 int solve_all(shk_problem* p, const shk_params* prm, int nf, const c128* sigma, int n_rhs, const c128* b, c128* x,
@@ -1738,15 +1870,24 @@ int solve_all(shk_problem* p, const shk_params* prm, int nf, const c128* sigma, 
   }
   int rc = SHK_OK;
   const long n = p->n;
+  const int kcap = prm->output == SHK_OUT_FACTORED ? factored_kcap(prm) : 0;
   for (int r0 = 0; r0 < n_rhs && rc == SHK_OK; r0 += 64) {
     const int s_real = std::min(64, n_rhs - r0);
     const c128* bg = b + (size_t)n * r0;
-    c128* xg = x + (size_t)n * nf * r0;
+    GroupOut go;
+    if (prm->output == SHK_OUT_FULL) {
+      go.x = x + (size_t)n * nf * r0;
+    } else if (prm->output == SHK_OUT_ROWS) {
+      go.x = x + (size_t)prm->n_out_rows * nf * r0;
+    } else {
+      go.fz = x + (size_t)n * kcap * r0;
+      go.fy = x + (size_t)n * kcap * n_rhs + (size_t)kcap * nf * r0;
+    }
     shk_status* sg = stat + (size_t)nf * r0;
     if (prm->precision == SHK_MIXED)
-      rc = solve_group<float>(p, prm, nf, sigma, s_real, bg, ptr_kind, xg, sg, (char*)ws, st);
+      rc = solve_group<float>(p, prm, nf, sigma, s_real, bg, ptr_kind, go, sg, (char*)ws, st);
     else
-      rc = solve_group<double>(p, prm, nf, sigma, s_real, bg, ptr_kind, xg, sg, (char*)ws, st);
+      rc = solve_group<double>(p, prm, nf, sigma, s_real, bg, ptr_kind, go, sg, (char*)ws, st);
   }
   if (own) {
     (void)hipStreamSynchronize(st);

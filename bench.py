@@ -360,6 +360,55 @@ def cpu_baseline(w, seconds, gpu_outer_steps):
             "host_cores_available": len(os.sched_getaffinity(0))}
 
 
+def graph_ab(P, torch, gp, w, steps, warmup):
+    """The 512x512 mixed solve with the inner iterations replayed from
+    captured HIP graphs and launched one by one (the class's other settings
+    unchanged), alternated twice; the class's setting is restored after."""
+    prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, precision=P.SHK_MIXED,
+                              inner_precond=P.SHK_PRECOND_MULTIGRID)
+    key = P.shk_tune_class(gp, prm, 1)
+    was = P.shk_tune_get(key, "graph")
+    ms = {0: [], 1: []}
+    try:
+        for g in (0, 1, 0, 1):
+            P.shk_tune_set(key, "graph", g)
+            r = time_path(P, torch, gp, w, P.SHK_MIXED, steps, warmup)
+            ms[g].append(r["total_ms"] / steps)
+    finally:
+        P.shk_tune_set(key, "graph", was)
+    off, on = float(np.mean(ms[0])), float(np.mean(ms[1]))
+    return {"ms_per_solve_launched": round(off, 3), "ms_per_solve_graph": round(on, 3),
+            "saving_frac": round((off - on) / off, 4), "runs": ms}
+
+
+def autotune_bench(P, torch, path, reps=2):
+    """Runs the autotuner on the benchmark workloads (both precisions) and
+    writes the tuning cache to path."""
+    import synth
+    from paper_1212_3660_amd import autotune as T
+    mk2 = lambda w: P.Problem.fv2d(w.cell_K, w.Ss, w.h)
+    mk3 = lambda w: P.Problem.fv3d(w.cell_K, w.Ss, w.h)
+    jobs = [("2-D FV 512x512, 1 rhs", synth.config2(n_grid=512), mk2, True),
+            ("2-D FV 256x256, 64 rhs", synth.config3(), mk2, False),
+            ("3-D FV 128^3, 8 rhs", synth.config4(), mk3, False)]
+    entries = []
+    for name, w, mk, one in jobs:
+        gp = mk(w)
+        bcols = w.b[:, :1] if one else w.b
+        b = torch.from_numpy(np.ascontiguousarray(bcols.T)).cuda()
+        for prec, pname in ((P.SHK_MIXED, "mixed"), (P.SHK_FP64, "fp64")):
+            kw = dict(taus=w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
+                      eps_inner=w.eps_inner, precision=prec, inner_precond=P.SHK_PRECOND_MULTIGRID)
+            print(f"[tune] {name}, {pname}", flush=True)
+            e = T.tune(gp, w.sigma, b, kw, reps=reps, log=lambda m: print(m, flush=True),
+                       workload=f"{name}, {pname}")
+            print(json.dumps(e), flush=True)
+            entries.append(e)
+        gp.close()
+    T.save(entries, path, device=torch.cuda.get_device_name(0))
+    return entries
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -381,6 +430,10 @@ def main():
     ap.add_argument("--server-only", action="store_true",
                     help="run only the serving workload (trace replay) and exit")
     ap.add_argument("--no-server", action="store_true", help="skip the serving workload")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner on the benchmark workloads, write the tuning cache and exit")
+    ap.add_argument("--tune-cache", default=None,
+                    help="cache file --autotune writes (default: the packaged paper_1212_3660_amd/tune_cache.json)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy MIB mebibytes device-to-device with a plain copy kernel and exit "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -390,9 +443,20 @@ def main():
               f"request or right-hand-side block, so N GPUs would run N independent copies", file=sys.stderr)
         sys.exit(2)
     import torch
+    torch.cuda.set_device(0)
+    # every solve on a stream of its own (graph capture needs a stream other
+    # than the legacy default one); torch's events record on it too
+    with torch.cuda.stream(torch.cuda.Stream()):
+        run(a)
+
+
+def run(a):
+    import torch
     import paper_1212_3660_amd as P
     import synth
-    torch.cuda.set_device(0)
+    if a.autotune:
+        autotune_bench(P, torch, a.tune_cache or P.autotune.CACHE)
+        return
     if a.batched_only:
         if a.batched_only.startswith("2d"):
             wb, mk, name = synth.config3(), (lambda w: P.Problem.fv2d(w.cell_K, w.Ss, w.h)), "2-D FV 256x256, 64 rhs"
@@ -485,6 +549,9 @@ def main():
                              "max_true_relres": relaxed["worst"], "inner_iterations": relaxed["inner"],
                              "outer_steps": relaxed["outer"], "refine_sweeps": relaxed["sweeps"]},
            "roofline": roof, "roofline_jacobi_step": roof_jac, "cpu_baseline": None}
+    out["captured_iterations"] = graph_ab(P, torch, gp, w, a.steps, a.warmup)
+    tuned = [e["workload"] for e in P.autotune.load(apply=False)]
+    out["tuning"] = {"cache": "paper_1212_3660_amd/tune_cache.json", "classes": tuned}
     if not a.no_extra:
         # the batched workloads: 256x256 with 32 well sources + 32 adjoint
         # receiver vectors, and 128^3 with 8 sources; mixed and FP64 paths in

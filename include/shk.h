@@ -66,8 +66,14 @@ typedef struct shk_server shk_server;
 #define SHK_CGS2 0
 #define SHK_MGS 1
 #define SHK_FP64 0   /* every vector complex128                                       */
-#define SHK_MIXED 1  /* operator, inner solve and Gram-Schmidt in complex64 with FP32
-                        accumulation; Hessenberg least squares, basis norms, true
+#define SHK_MIXED 1  /* Arnoldi basis V and the inner solve's vectors stored in
+                        complex64, the operator's products in FP32 arithmetic; the
+                        inner iterate, the flexible basis Z and x in complex128;
+                        every inner product and Gram-Schmidt projection formed from
+                        exact FP64 products of the complex64 values and summed in
+                        FP64 (SHK_RHS_BLOCK: the block projections V^H W and
+                        W - V C on the matrix cores in FP32, the CholQR Gram in
+                        FP64); Hessenberg least squares, basis norms, true
                         residual and refinement in FP64                             */
 #define SHK_PTR_HOST 0
 #define SHK_PTR_DEVICE 1
@@ -415,6 +421,46 @@ int shk_profile_read(long long* launches, double* total_ms, double* total_bytes)
  * calls, their summed time and their flops (4 x 8 n (k+1) s^2 real flops per
  * call, s the block width).  Reset by shk_profile_enable. */
 int shk_profile_read_block(long long* calls, double* total_ms, double* total_flops);
+
+/* ---------------------------------------------------------------------------
+ * Tuning table.  Launch and round settings (block sizes, lanes per thread,
+ * round tolerances, captured iterations, ...) are kept per workload class:
+ * (kind, n, lanes, precision, inner_precond), kind 0 = 2D finite volume, 1 =
+ * 3D finite volume, 2 = CSR; lanes = the power-of-two lane count of a group of
+ * right-hand sides (at least 16 with SHK_RHS_BLOCK).  A solve reads its class's
+ * entry once at its start; a class without an entry takes the shared settings,
+ * which kind < 0 addresses (the other key fields are then ignored).  Settings
+ * change the launch shapes and the inner solve's rounds only, never what the
+ * method computes: a solve converges to the same tolerance under any of them.
+ * The autotuner in the Python package fills the table from a measured search.
+ * Knobs (value ranges are checked; an unknown name or a bad value returns
+ * INVALID_ARG):
+ *   cg_block 256|512        block size of the inner iteration kernels
+ *   nt_store, nt_store32, nt_store64  0|1  streaming stores of the Jacobi step
+ *   sep_limit >= 0          partial-sum count above which a kernel folds them
+ *   ws_skew >= 0            bytes between the large workspace arrays
+ *   round_tol, round_tol_mg (0,1)  reduction per complex64 inner round
+ *                           (Jacobi / multigrid inner preconditioner)
+ *   stall_min, stall_mult >= 0  a round ends after max(min, mult x its
+ *                           productive length) iterations without halving
+ *   tail_lds                LDS bytes of the V-cycle's one-workgroup tail
+ *   mg_fuse 0|1             step fused with the finest restriction
+ *   post_lt, down_lt, up_lt 2|4|8  lanes per thread (complex64, several lanes)
+ *   lt64 0|2|4              lanes per thread on complex128
+ *   graph 0|1               inner iterations replayed from a HIP graph captured
+ *                           on the solve stream (needs a non-null stream)
+ * The table is process-wide and guarded by a lock; a solve in flight keeps the
+ * settings it started with.
+ */
+int shk_tune_set(int kind, long long n, int lanes, int precision, int inner_precond, const char* knob,
+                 double value);
+int shk_tune_get(int kind, long long n, int lanes, int precision, int inner_precond, const char* knob,
+                 double* value);
+/* Removes every entry and restores the shared settings' defaults. */
+int shk_tune_reset(void);
+/* The class key of a solve of p with prm and n_rhs right-hand sides (the first
+ * group of 64 when n_rhs > 64).  Errors: INVALID_ARG. */
+int shk_tune_class(const shk_problem* p, const shk_params* prm, int n_rhs, int* kind, long long* n, int* lanes);
 
 /* Text for a status or error code; last error message of the calling thread. */
 const char* shk_status_string(int code);

@@ -105,6 +105,12 @@ _SIGS = {
     "shk_profile_enable": (C.c_int, [C.c_int]),
     "shk_profile_read": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "shk_profile_read_block": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "shk_tune_set": (C.c_int, [C.c_int, C.c_longlong, C.c_int, C.c_int, C.c_int, C.c_char_p, C.c_double]),
+    "shk_tune_get": (C.c_int, [C.c_int, C.c_longlong, C.c_int, C.c_int, C.c_int, C.c_char_p,
+                               C.POINTER(C.c_double)]),
+    "shk_tune_reset": (C.c_int, []),
+    "shk_tune_class": (C.c_int, [C.c_void_p, C.POINTER(shk_params), C.c_int, C.POINTER(C.c_int),
+                                 C.POINTER(C.c_longlong), C.POINTER(C.c_int)]),
     "shk_status_string": (C.c_char_p, [C.c_int]),
     "shk_last_error": (C.c_char_p, []),
     "shk_server_create": (C.c_int, [C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -124,12 +130,18 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1212_3660_amd.build`")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded instead of bringing up a second one in the process
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
         _lib = L
+        # the packaged autotuner picks, when there are any
+        from . import autotune
+        autotune.load()
     return _lib
 
 
@@ -455,6 +467,38 @@ def shk_profile_read_block():
     n, ms, fl = C.c_longlong(), C.c_double(), C.c_double()
     _check(lib().shk_profile_read_block(C.byref(n), C.byref(ms), C.byref(fl)), "shk_profile_read_block")
     return int(n.value), float(ms.value), float(fl.value)
+
+
+# Workload class key of the tuning table: (kind, n, lanes, precision, precond);
+# kind -1 addresses the settings shared by every class without an entry.
+TUNE_ALL = (-1, 0, 0, 0, 0)
+
+
+def shk_tune_set(key, knob: str, value: float):
+    """Sets one knob of a class (shk_tune_set)."""
+    k, n, lanes, prec, pc = key
+    _check(lib().shk_tune_set(int(k), int(n), int(lanes), int(prec), int(pc), knob.encode(), float(value)),
+           "shk_tune_set")
+
+
+def shk_tune_get(key, knob: str) -> float:
+    k, n, lanes, prec, pc = key
+    v = C.c_double()
+    _check(lib().shk_tune_get(int(k), int(n), int(lanes), int(prec), int(pc), knob.encode(), C.byref(v)),
+           "shk_tune_get")
+    return float(v.value)
+
+
+def shk_tune_reset():
+    _check(lib().shk_tune_reset(), "shk_tune_reset")
+
+
+def shk_tune_class(problem: Problem, params: shk_params, n_rhs: int):
+    """The class key (kind, n, lanes, precision, precond) of a solve."""
+    k, n, lanes = C.c_int(), C.c_longlong(), C.c_int()
+    _check(lib().shk_tune_class(problem.handle, C.byref(params), int(n_rhs), C.byref(k), C.byref(n),
+                                C.byref(lanes)), "shk_tune_class")
+    return (int(k.value), int(n.value), int(lanes.value), int(params.precision), int(params.inner_precond))
 
 
 class Server:

@@ -180,6 +180,19 @@ int shk_true_residual_noalloc(shk_problem* p, int n_shifts, const shk_c128* sigm
                                          (hipStream_t)hip_stream);
 }
 
+int shk_tune_set(int kind, long long n, int lanes, int precision, int inner_precond, const char* knob,
+                 double value) {
+  return shk::tune_set(kind, n, lanes, precision, inner_precond, knob, value);
+}
+int shk_tune_get(int kind, long long n, int lanes, int precision, int inner_precond, const char* knob,
+                 double* value) {
+  return shk::tune_get(kind, n, lanes, precision, inner_precond, knob, value);
+}
+int shk_tune_reset(void) { return shk::tune_reset(); }
+int shk_tune_class(const shk_problem* p, const shk_params* prm, int n_rhs, int* kind, long long* n, int* lanes) {
+  return shk::tune_class(p, prm, n_rhs, kind, n, lanes);
+}
+
 const char* shk_status_string(int code) {
   switch (code) {
     case SHK_CONVERGED: return "converged";

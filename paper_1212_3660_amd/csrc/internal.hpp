@@ -117,5 +117,9 @@ const char* last_error_text();
 int profile_enable(int on);
 int profile_read(long long* launches, double* ms, double* bytes);
 int profile_read_block(long long* calls, double* ms, double* flops);
+int tune_set(int kind, long long n, int lanes, int precision, int precond, const char* knob, double value);
+int tune_get(int kind, long long n, int lanes, int precision, int precond, const char* knob, double* value);
+int tune_reset();
+int tune_class(const shk_problem* p, const shk_params* prm, int n_rhs, int* kind, long long* n, int* lanes);
 
 }  // namespace shk

@@ -305,6 +305,12 @@ struct CgCfg {
                      // new round's forms (multigrid path), 0: it forms them (RW)
 };
 
+// The settings of the running inner solve live in device memory, so that a
+// captured sequence of iterations serves every inner solve with the same tau.
+__global__ void k_set_cfg(CgCfg* __restrict__ d, CgCfg c) {
+  if (threadIdx.x == 0) *d = c;
+}
+
 // Per-lane state of the inner solve (kept small: a single-lane launch holds it
 // in scalar registers).
 struct CgScal {
@@ -584,11 +590,13 @@ __device__ __forceinline__ void cg_compute(const CgCell<Op, R>& L, int t, cx<R> 
 // tiles in XCD-aware order.
 template <typename Op, typename OpD, typename R, int CGB, bool NT, bool ONE, bool MULTI>
 __global__ void __launch_bounds__(CGB) k_cg_step(Op op, OpD opd, const cx<R>* __restrict__ dinv, c128 tau, int n,
-                                                 int lS_, CgCfg cfg, const cx<R>* __restrict__ v,
+                                                 int lS_, const CgCfg* __restrict__ cfgp,
+                                                 const cx<R>* __restrict__ v,
                                                  const c128* __restrict__ partIn, int Gin,
                                                  const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
                                                  CgVecs<R> vec, int par, c128* __restrict__ partOut,
                                                  int* __restrict__ all_done) {
+  const CgCfg cfg = *cfgp;
   const int lS = ONE ? 0 : lS_;
   const int S = 1 << lS;
   const int rl = ONE ? 0 : (int)threadIdx.x & (S - 1);

@@ -401,7 +401,11 @@ __global__ void __launch_bounds__(BS) k_mg_up_lanes(Op op, LevelDims f, LevelDim
 // on global memory.
 constexpr int MG_MAXL = 14;
 constexpr int MG_TAIL_THREADS = 1024;
-constexpr int MG_TAIL_LDS = 63 * 1024;   // dynamic LDS; the level table takes static LDS beside it
+// Dynamic LDS of the tail: the default budget, and the largest one (gfx950
+// gives a workgroup 160 KB; the level table takes static LDS beside it).
+// Each size has its own instantiation, whose staging registers scale with it.
+constexpr int MG_TAIL_LDS = 63 * 1024;
+constexpr int MG_TAIL_LDS_MAX = 159 * 1024;
 constexpr int MG_MAXSEG = 5 * MG_MAXL;
 struct MgTailLevel {
   int nx, ny, nz;
@@ -442,14 +446,14 @@ __global__ void __launch_bounds__(BS) k_mg_pack(MgPack p, unsigned* __restrict__
   }
 }
 
-template <typename Op, typename R>
+template <typename Op, typename R, int CAP>
 __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau, double omega, int lS,
                                                              const unsigned* __restrict__ pack,
                                                              const cx<R>* __restrict__ btop, cx<R>* __restrict__ xtop,
                                                              const int* __restrict__ all_done) {
   using F = typename std::remove_const<typename std::remove_pointer<decltype(Op::tx)>::type>::type;
-  constexpr int NW = MG_TAIL_LDS / 4 / MG_TAIL_THREADS + 1;                       // packed words per thread
-  constexpr int NB0 = MG_TAIL_LDS / (2 * (int)sizeof(cx<R>)) / MG_TAIL_THREADS + 1; // top rhs elements per thread
+  constexpr int NW = CAP / 4 / MG_TAIL_THREADS + 1;                        // packed words per thread
+  constexpr int NB0 = CAP / (2 * (int)sizeof(cx<R>)) / MG_TAIL_THREADS + 1; // top rhs elements per thread
   constexpr int NP = (int)(sizeof(MgTailLevel) * MG_MAXL / 4);                    // level table words
   static_assert(NP <= MG_TAIL_THREADS, "level table");
   extern __shared__ __align__(16) char lds_raw[];
@@ -623,11 +627,13 @@ __device__ __forceinline__ bool cg_prologue(int lS, const CgCfg& cfg, const c128
 //   KX:   x += u, one preconditioned Richardson step on the iterate (u = B r of
 //         the residual just formed), before a new residual.
 template <typename Op, typename OpD, typename R, int CGB, bool ONE, bool MULTI>
-__global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int lS_, CgCfg cfg,
+__global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int lS_,
+                                                   const CgCfg* __restrict__ cfgp,
                                                    const cx<R>* __restrict__ v, const cx<R>* __restrict__ u,
                                                    const c128* __restrict__ partIn, int Gin,
                                                    const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
                                                    CgVecs<R> vec, int par, int* __restrict__ all_done) {
+  const CgCfg cfg = *cfgp;
   const int lS = ONE ? 0 : lS_;
   const int rl = ONE ? 0 : (int)threadIdx.x & ((1 << lS) - 1);
   const int N = n << lS;
@@ -682,12 +688,14 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
 // second read of r'.
 template <typename Op, typename OpD, typename R>
 __global__ void __launch_bounds__(BS) k_cgmg_step_down(Op op, OpD opd, LevelDims f, LevelDims c, c128 tau,
-                                                       double omega, CgCfg cfg, const cx<R>* __restrict__ v,
+                                                       double omega, const CgCfg* __restrict__ cfgp,
+                                                       const cx<R>* __restrict__ v,
                                                        const cx<R>* __restrict__ u,
                                                        const c128* __restrict__ partIn, int Gin,
                                                        const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
                                                        CgVecs<R> vec, int par, const cx<R>* __restrict__ dinv,
                                                        cx<R>* __restrict__ out, int* __restrict__ all_done) {
+  const CgCfg cfg = *cfgp;
   constexpr int D = Op::NB / 2;
   constexpr int Q = 1 << D;
   int bx, J, L;

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <type_traits>
 #include <string>
@@ -332,59 +333,177 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
   return with_ops<F>(p, [&](auto op, auto) { return fn(op); });
 }
 
-// Launch shape of the iteration kernel: block size (256 or 512), streaming
-// (non-temporal) stores, the partial count above which a separate kernel folds
-// the partials, and a skew added between the large workspace arrays.
-// Defaults are the fastest measured on MI355X at 512x512 (256-thread blocks,
-// streaming stores on the complex64 path); SHK_CG_BLOCK, SHK_NT_STORE,
-// SHK_SEP_LIMIT and SHK_WS_SKEW override them for tuning sweeps.  The
-// complex64 inner rounds' reduction target and stall rule ("min,mult") are
-// SHK_ROUND_TOL and SHK_STALL.  SHK_MG_TAIL_LDS lowers the LDS budget of the
-// V-cycle's one-workgroup tail (so that it starts on a coarser level);
-// SHK_MG_FUSE=0 keeps the multigrid step and the finest restriction apart;
-// SHK_MG_POST_LT (0, 2, 4, 8) sets the lanes a thread of the multigrid
-// product handles when several right-hand sides run on complex64 vectors;
-// SHK_MG_DOWN_LT and SHK_MG_UP_LT (2, 4, 8) cap the lane chunk of the grid legs;
-// SHK_MG_LT64 (0, 2, 4) does so for the complex128 path.
+// Launch and round settings of the solver, per workload class.  Defaults are
+// the fastest measured on MI355X at the benchmarked workloads; the table
+// below holds what shk_tune_set (the autotuner) picked for a class.
+//  cgb         block size of the iteration kernels (256 or 512)
+//  nt64, nt32  streaming (non-temporal) stores of the Jacobi step, per precision
+//  sep_limit   partial count above which a separate kernel folds the partials
+//  skew        bytes added between the large workspace arrays
+//  round_tol   complex64 inner rounds: reduction per round (Jacobi / multigrid)
+//  stall_*     stall rule of a round (no halving for max(min, mult x length))
+//  tail_lds    LDS budget of the V-cycle's one-workgroup tail
+//  mg_fuse     step fused with the finest restriction where it applies
+//  post_lt, down_lt, up_lt   lanes per thread of the product and grid legs
+//              (complex64, several lanes); lt64 the same on complex128
+//  graph       inner iterations replayed from a captured HIP graph
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
   int nt32 = 1;
-  long sep_limit = 3072;   // fold partials in a separate kernel above this many
+  long sep_limit = 3072;
   size_t skew = 0;
-  double round_tol = 1e-2;    // complex64 inner rounds: reduction per round (Jacobi inner solve)
-  double round_tol_mg = 1e-3; // the same with the multigrid inner solve (few, fast iterations)
+  double round_tol = 1e-2;
+  double round_tol_mg = 1e-3;
   int stall_min = 150, stall_mult = 3;
   int tail_lds = MG_TAIL_LDS;
-  int mg_fuse = 1;   // step fused with the finest restriction where it applies
-  int post_lt = 2;   // lanes per thread of the multigrid product on the complex64 path (0: one)
-  int down_lt = 4, up_lt = 4;   // largest lane chunk of the grid legs on the complex64 path
-  int lt64 = 2;   // the same on the complex128 path (0: a lane per thread; product at most 2)
-  Tune() {
-    if (const char* e = getenv("SHK_MG_LT64")) lt64 = atoi(e) >= 4 ? 4 : atoi(e) >= 2 ? 2 : 0;
-    auto chunk = [](const char* e) { const int v = atoi(e); return v >= 8 ? 8 : v >= 4 ? 4 : 2; };
-    if (const char* e = getenv("SHK_MG_DOWN_LT")) down_lt = chunk(e);
-    if (const char* e = getenv("SHK_MG_UP_LT")) up_lt = chunk(e);
-    if (const char* e = getenv("SHK_MG_POST_LT")) {
-      const int v = atoi(e);
-      post_lt = v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 0;
-    }
-    if (const char* e = getenv("SHK_MG_FUSE")) mg_fuse = atoi(e) != 0;
-    if (const char* e = getenv("SHK_MG_TAIL_LDS")) tail_lds = std::max(0, std::min(atoi(e), MG_TAIL_LDS));
-    if (const char* e = getenv("SHK_CG_BLOCK")) {
-      const int v = atoi(e);
-      if (v == 256 || v == 512) cgb = v;
-    }
-    if (const char* e = getenv("SHK_WS_SKEW")) skew = (size_t)strtoull(e, nullptr, 10) & ~size_t(255);
-    if (const char* e = getenv("SHK_NT_STORE")) nt64 = nt32 = atoi(e) != 0;
-    if (const char* e = getenv("SHK_SEP_LIMIT")) sep_limit = atol(e);
-    if (const char* e = getenv("SHK_ROUND_TOL")) round_tol = round_tol_mg = atof(e);
-    if (const char* e = getenv("SHK_STALL")) {
-      if (sscanf(e, "%d,%d", &stall_min, &stall_mult) != 2) stall_min = stall_mult = 0;
-    }
+  int mg_fuse = 1;
+  int post_lt = 2;
+  int down_lt = 4, up_lt = 4;
+  int lt64 = 2;
+  int graph = 0;
+
+  // Sets a knob by name; false for an unknown name or a value out of range.
+  bool set(const std::string& k, double v) {
+    const int iv = (int)v;
+    auto chunk = [](int x) { return x >= 8 ? 8 : x >= 4 ? 4 : 2; };
+    if (k == "cg_block") { if (iv != 256 && iv != 512) return false; cgb = iv; }
+    else if (k == "nt_store") { nt64 = nt32 = iv != 0; }
+    else if (k == "nt_store64") { nt64 = iv != 0; }
+    else if (k == "nt_store32") { nt32 = iv != 0; }
+    else if (k == "sep_limit") { if (v < 0) return false; sep_limit = (long)v; }
+    else if (k == "ws_skew") { if (v < 0) return false; skew = (size_t)v & ~size_t(255); }
+    else if (k == "round_tol") { if (!(v > 0 && v < 1)) return false; round_tol = v; }
+    else if (k == "round_tol_mg") { if (!(v > 0 && v < 1)) return false; round_tol_mg = v; }
+    else if (k == "stall_min") { if (iv < 0) return false; stall_min = iv; }
+    else if (k == "stall_mult") { if (iv < 0) return false; stall_mult = iv; }
+    else if (k == "tail_lds") { if (iv < 0 || iv > MG_TAIL_LDS_MAX) return false; tail_lds = iv; }
+    else if (k == "mg_fuse") { mg_fuse = iv != 0; }
+    else if (k == "post_lt") { post_lt = iv >= 8 ? 8 : iv >= 4 ? 4 : iv >= 2 ? 2 : 0; }
+    else if (k == "down_lt") { down_lt = chunk(iv); }
+    else if (k == "up_lt") { up_lt = chunk(iv); }
+    else if (k == "lt64") { lt64 = iv >= 4 ? 4 : iv >= 2 ? 2 : 0; }
+    else if (k == "graph") { graph = iv != 0; }
+    else return false;
+    return true;
+  }
+  bool get(const std::string& k, double* v) const {
+    if (k == "cg_block") *v = cgb;
+    else if (k == "nt_store64") *v = nt64;
+    else if (k == "nt_store32" || k == "nt_store") *v = nt32;
+    else if (k == "sep_limit") *v = (double)sep_limit;
+    else if (k == "ws_skew") *v = (double)skew;
+    else if (k == "round_tol") *v = round_tol;
+    else if (k == "round_tol_mg") *v = round_tol_mg;
+    else if (k == "stall_min") *v = stall_min;
+    else if (k == "stall_mult") *v = stall_mult;
+    else if (k == "tail_lds") *v = tail_lds;
+    else if (k == "mg_fuse") *v = mg_fuse;
+    else if (k == "post_lt") *v = post_lt;
+    else if (k == "down_lt") *v = down_lt;
+    else if (k == "up_lt") *v = up_lt;
+    else if (k == "lt64") *v = lt64;
+    else if (k == "graph") *v = graph;
+    else return false;
+    return true;
   }
 };
-static Tune g_tune;
+static const Tune g_tune_default;
+
+// A workload class: operator kind, unknowns, lanes, precision, inner
+// preconditioner.
+struct TuneKey {
+  int kind;
+  long long n;
+  int lanes, precision, precond;
+  bool operator<(const TuneKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (n != o.n) return n < o.n;
+    if (lanes != o.lanes) return lanes < o.lanes;
+    if (precision != o.precision) return precision < o.precision;
+    return precond < o.precond;
+  }
+};
+static std::mutex g_tune_mu;
+static Tune g_tune_base;                  // every class without an entry of its own
+static std::map<TuneKey, Tune> g_tune_table;
+static thread_local const Tune* t_tune = &g_tune_default;
+
+// The settings in force on this thread (those of the running solve's class).
+static const Tune& tn() { return *t_tune; }
+
+static int tune_kind(const shk_problem* p) { return p->kind == Kind::FV2D ? 0 : p->kind == Kind::FV3D ? 1 : 2; }
+
+// Selects the settings of a class for the scope of a solve on this thread.
+struct TuneScope {
+  const Tune* prev;
+  Tune local;
+  TuneScope(int kind, long long n, int lanes, int precision, int precond) : prev(t_tune) {
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune_table.find(TuneKey{kind, n, lanes, precision, precond});
+      local = it != g_tune_table.end() ? it->second : g_tune_base;
+    }
+    t_tune = &local;
+  }
+  ~TuneScope() { t_tune = prev; }
+};
+
+// kind < 0 addresses the settings of every class without an entry of its own.
+int tune_set(int kind, long long n, int lanes, int precision, int precond, const char* knob, double value) {
+  if (!knob) return fail(SHK_ERR_INVALID_ARG, "null knob name");
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  if (kind < 0) {
+    Tune t = g_tune_base;
+    if (!t.set(knob, value)) return fail(SHK_ERR_INVALID_ARG, std::string("unknown knob or value: ") + knob);
+    g_tune_base = t;
+    return SHK_OK;
+  }
+  const TuneKey key{kind, n, lanes, precision, precond};
+  auto it = g_tune_table.find(key);
+  Tune t = it != g_tune_table.end() ? it->second : g_tune_base;
+  if (!t.set(knob, value)) return fail(SHK_ERR_INVALID_ARG, std::string("unknown knob or value: ") + knob);
+  g_tune_table[key] = t;
+  return SHK_OK;
+}
+int tune_get(int kind, long long n, int lanes, int precision, int precond, const char* knob, double* value) {
+  if (!knob || !value) return fail(SHK_ERR_INVALID_ARG, "null knob name or value");
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = kind < 0 ? g_tune_table.end() : g_tune_table.find(TuneKey{kind, n, lanes, precision, precond});
+  const Tune& t = it != g_tune_table.end() ? it->second : g_tune_base;
+  if (!t.get(knob, value)) return fail(SHK_ERR_INVALID_ARG, std::string("unknown knob: ") + knob);
+  return SHK_OK;
+}
+int tune_reset() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_table.clear();
+  g_tune_base = g_tune_default;
+  return SHK_OK;
+}
+
+// ------------------------------------------------ captured inner iterations --
+// HIP graphs of two inner iterations (an even and an odd one: the parities
+// alternate the vector buffers and partial-sum slots), one per tau, captured
+// on the solve stream by the first inner solve with that tau and replayed for
+// every pair of iterations after that.  Every argument of the captured
+// launches is fixed for the life of a solve's workspace layout except tau: the
+// settings are read from device memory and the right-hand side and iterate
+// sit in fixed buffers.  Owned by one solve, destroyed after its stream has
+// drained.
+struct GraphSet {
+  hipStream_t st = nullptr;
+  std::vector<std::pair<c128, hipGraphExec_t>> execs;
+  hipGraphExec_t find(c128 tau) const {
+    for (const auto& e : execs)
+      if (e.first.re == tau.re && e.first.im == tau.im) return e.second;
+    return nullptr;
+  }
+  ~GraphSet() {
+    if (execs.empty()) return;
+    (void)hipStreamSynchronize(st);
+    for (auto& e : execs) (void)hipGraphExecDestroy(e.second);
+  }
+};
 
 // ----------------------------------------------------------- workspace -----
 struct Carver {
@@ -393,7 +512,7 @@ struct Carver {
   template <typename T> T* take(size_t count) {
     T* r = base ? reinterpret_cast<T*>(base + off) : nullptr;
     off = align_up(off + count * sizeof(T));
-    if (count * sizeof(T) >= (1u << 20)) off += g_tune.skew;   // large arrays only
+    if (count * sizeof(T) >= (1u << 20)) off += tn().skew;   // large arrays only
     return r;
   }
 };
@@ -406,10 +525,10 @@ struct Grid {
   bool separate;  // fold partials with k_lane_totals before consumers read them
 };
 static Grid item_plan(long N, int S) {
-  const int CGB = g_tune.cgb;
+  const int CGB = tn().cgb;
   long G = (N + CGB - 1) / CGB;
   G = std::max<long>(1, std::min<long>(G, 2048));
-  Grid g{(int)G, G * 3 * S > g_tune.sep_limit};
+  Grid g{(int)G, G * 3 * S > tn().sep_limit};
   return g;
 }
 
@@ -420,6 +539,11 @@ template <typename R> struct Buffers {
   cx<R>* dinv;            // inverse Jacobi diagonal of the current inner solve
   CgScal* sc;             // two buffers of S lanes
   int* all_done;
+  CgCfg* cfgd;            // settings of the running inner solve
+  // captured inner iterations: fixed right-hand side and iterate buffers
+  // (the basis column in use is copied in and the iterate out)
+  cx<R>* gv = nullptr;
+  c128* gx = nullptr;
   double *beta0, *hn, *mz, *pn, *nzs;
   c128 *H, *h2, *taus, *sigma, *zs;
   int *seed, *nact;
@@ -491,7 +615,7 @@ template <typename R> static void carve_mg(Carver& cv, Buffers<R>& b, const shk_
     b.mx.push_back(cv.take<cx<R>>((size_t)l.n * S));
     b.mdinv.push_back(cv.take<cx<R>>((size_t)l.n));
   }
-  b.mpack = cv.take<unsigned>(MG_TAIL_LDS / 4);
+  b.mpack = cv.take<unsigned>(MG_TAIL_LDS_MAX / 4);
 }
 
 // Norms from block partials: one block for few lanes, one block per lane
@@ -635,6 +759,11 @@ static Buffers<R> carve(char* base, const shk_problem* p, int m, int nf, int S, 
   b.part = cv.take<c128>(std::max<size_t>({(size_t)1024 * 2 * S, (size_t)Gd * (m + 1) * S, (size_t)Gu * S}));
   b.sc = cv.take<CgScal>(2 * S);
   b.all_done = cv.take<int>(4);
+  b.cfgd = cv.take<CgCfg>(1);
+  if (tn().graph) {
+    b.gv = cv.take<cx<R>>(N);
+    b.gx = cv.take<c128>(N);
+  }
   b.beta0 = cv.take<double>(S);
   b.hn = cv.take<double>(S);
   b.mz = cv.take<double>(S);
@@ -846,7 +975,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   template <int CGB, bool NT, bool ONE, bool MULTI>
   void step_k(int G, c128 tau, int ni, int lS, const CgCfg& e, const c128* in, int Gin, const CgScal* scIn,
               CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
-    k_cg_step<Op, OpD, R, CGB, NT, ONE, MULTI><<<G, CGB, 0, st>>>(op, opd, B.dinv, tau, ni, lS, e, cur_v, in, Gin,
+    k_cg_step<Op, OpD, R, CGB, NT, ONE, MULTI><<<G, CGB, 0, st>>>(op, opd, B.dinv, tau, ni, lS, B.cfgd, cur_v, in, Gin,
                                                                   scIn, scOut, vec, par, out, B.all_done);
   }
   template <int CGB, bool NT>
@@ -864,14 +993,14 @@ template <typename R, typename Op, typename OpD> struct Group {
   template <int CGB>
   void step_cgb(int G, c128 tau, int ni, int lS, const CgCfg& e, const c128* in, int Gin, const CgScal* scIn,
                 CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
-    if (std::is_same<R, float>::value ? g_tune.nt32 : g_tune.nt64)
+    if (std::is_same<R, float>::value ? tn().nt32 : tn().nt64)
       step_nt<CGB, true>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
     else
       step_nt<CGB, false>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
   }
   void launch_step(int G, c128 tau, int ni, int lS, const CgCfg& e, const c128* in, int Gin, const CgScal* scIn,
                    CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
-    if (g_tune.cgb == 512) step_cgb<512>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
+    if (tn().cgb == 512) step_cgb<512>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
     else step_cgb<256>(G, tau, ni, lS, e, in, Gin, scIn, scOut, vec, par, out);
   }
 
@@ -971,7 +1100,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     const int Lv = mg_levels();
     int t = Lv;
     for (int l = Lv - 1; l >= 0; --l) {
-      if (mg_tail_bytes(l, lS) > (size_t)g_tune.tail_lds || Lv - l > MG_MAXL) break;
+      if (mg_tail_bytes(l, lS) > (size_t)tn().tail_lds || Lv - l > MG_MAXL) break;
       t = l;
     }
     return t;   // Lv: not even the one-cell level fits (many lanes)
@@ -1027,7 +1156,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   // complex64 path and of 2 on the complex128 path (each measured faster
   // than the other sizes and than a lane per thread).
   static constexpr bool c64 = std::is_same<R, float>::value;
-  bool lane_chunks() const { return c64 || g_tune.lt64 >= 2; }
+  bool lane_chunks() const { return c64 || tn().lt64 >= 2; }
   template <int LT>
   void mg_down_lt(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
                   cx<R>* out) {
@@ -1038,7 +1167,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   void mg_down_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                      const cx<R>* dl, cx<R>* out) {
-    const int lt = std::min(c64 ? g_tune.down_lt : g_tune.lt64, 1 << lS);
+    const int lt = std::min(c64 ? tn().down_lt : tn().lt64, 1 << lS);
     if (lt == 2) mg_down_lt<2>(l, f, c, tau, lS, bl, dl, out);
     else if (lt == 4) mg_down_lt<4>(l, f, c, tau, lS, bl, dl, out);
     else mg_down_lt<8>(l, f, c, tau, lS, bl, dl, out);
@@ -1053,7 +1182,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
   void mg_up_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                    const cx<R>* dl, const cx<R>* xcoarse, cx<R>* out) {
-    const int lt = std::min(c64 ? g_tune.up_lt : g_tune.lt64, 1 << lS);
+    const int lt = std::min(c64 ? tn().up_lt : tn().lt64, 1 << lS);
     if (lt == 2) mg_up_lt<2>(l, f, c, tau, lS, bl, dl, xcoarse, out);
     else if (lt == 4) mg_up_lt<4>(l, f, c, tau, lS, bl, dl, xcoarse, out);
     else mg_up_lt<8>(l, f, c, tau, lS, bl, dl, xcoarse, out);
@@ -1079,7 +1208,11 @@ template <typename R, typename Op, typename OpD> struct Group {
       }
       if (t < Lv) {
         cx<R>* xt = t == 0 ? uout : B.mx[t - 1];   // mg_ta, mg_lds: laid out by mg_prepare
-        k_mg_tail<Op, R><<<1, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lS, B.mpack, bl, xt,
+        if (mg_lds > MG_TAIL_LDS)
+          k_mg_tail<Op, R, MG_TAIL_LDS_MAX><<<1, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lS,
+                                                                                        B.mpack, bl, xt, B.all_done);
+        else
+          k_mg_tail<Op, R, MG_TAIL_LDS><<<1, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lS, B.mpack, bl, xt,
                                                                      B.all_done);
       } else {
         // the coarsest level alone exceeds the tail: solve it on the grid
@@ -1107,7 +1240,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   template <int CGB>
   bool mg_post_lanes(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
     if constexpr (Op::NB > 0) {
-      const int lt = std::min(c64 ? g_tune.post_lt : std::min(g_tune.lt64, 2), 1 << lS);
+      const int lt = std::min(c64 ? tn().post_lt : std::min(tn().lt64, 2), 1 << lS);
       if (lS == 0 || lt < 2) return false;
       if (lt == 2) {
         k_cgmg_post_lanes<Op, R, CGB, 2><<<G, CGB, 0, st>>>(op, tau, ni, lS, sc, r, B.u, w, out, B.all_done);
@@ -1134,14 +1267,14 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
   }
   void mg_post(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
-    if (g_tune.cgb == 512) mg_post_cgb<512>(G, tau, ni, lS, sc, r, w, out);
+    if (tn().cgb == 512) mg_post_cgb<512>(G, tau, ni, lS, sc, r, w, out);
     else mg_post_cgb<256>(G, tau, ni, lS, sc, r, w, out);
   }
   // The step fused with the finest restriction: one lane, the default block
   // size, the finest down leg on the grid, and few enough blocks that each
   // summing every partial stays cheap.
   bool mg_fused(int lS) const {
-    if (Op::NB == 0 || lS != 0 || g_tune.cgb != BS || !g_tune.mg_fuse) return false;
+    if (Op::NB == 0 || lS != 0 || tn().cgb != BS || !tn().mg_fuse) return false;
     if (mg_levels() < 2 || mg_tail_level(lS) < 1) return false;
     const LevelDims c = mg_dims(1);
     const long blocks = ((long)c.nx * (1 << (Op::NB / 2)) + BS - 1) / BS * c.ny * c.nz;
@@ -1154,11 +1287,11 @@ template <typename R, typename Op, typename OpD> struct Group {
       if (mg_fused(lS)) {
         const LevelDims f = mg_dims(0), c = mg_dims(1);
         const dim3 g((unsigned)(((long)c.nx * (1 << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
-        k_cgmg_step_down<Op, OpD, R><<<g, BS, 0, st>>>(op, opd, f, c, tau, mg_omega, cfg, cur_v, B.u, in, Gin, scIn,
+        k_cgmg_step_down<Op, OpD, R><<<g, BS, 0, st>>>(op, opd, f, c, tau, mg_omega, B.cfgd, cur_v, B.u, in, Gin, scIn,
                                                        scOut, vec, par, B.dinv, B.mb[0], B.all_done);
         mg_vcycle(vec.r[par ^ 1], tau, lS, B.u, 1);
       } else {
-        k_cgmg_step<Op, OpD, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(opd, tau, ni, lS, cfg, cur_v, B.u, in, Gin, scIn,
+        k_cgmg_step<Op, OpD, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(opd, tau, ni, lS, B.cfgd, cur_v, B.u, in, Gin, scIn,
                                                                     scOut, vec, par, B.all_done);
         mg_vcycle(vec.r[par ^ 1], tau, lS, B.u);
       }
@@ -1182,12 +1315,13 @@ template <typename R, typename Op, typename OpD> struct Group {
   // one multigrid-COCG iteration: vector updates, V-cycle, operator product
   void mg_iteration(int G, c128 tau, int ni, int lS, const CgCfg& cfg, const c128* in, int Gin,
                     const CgScal* scIn, CgScal* scOut, const CgVecs<R>& vec, int par, c128* out) {
-    if (g_tune.cgb == 512) mg_iter_cgb<512>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
+    if (tn().cgb == 512) mg_iter_cgb<512>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
     else mg_iter_cgb<256>(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, par, out);
   }
 
   // ---- inner solve of (K + tau M) z = v (section 4) into z, w = M z ----
   const cx<R>* cur_v = nullptr;   // right-hand side of the running inner solve
+  GraphSet graphs;                // captured iterations, per tau
   int inner(c128 tau, const cx<R>* v, c128* z, double eps, int maxit, int fixed, double* pn_out) {
     const int G = gp.G;
     const bool rounds = std::is_same<R, float>::value && fixed <= 0;
@@ -1195,8 +1329,17 @@ template <typename R, typename Op, typename OpD> struct Group {
     const int cap = fixed > 0 ? fixed : maxit;
     const int lS = ilog2(S);
     const int ni = (int)n;
+    // captured iterations: not while the per-iteration timer runs, and not
+    // on the legacy default stream (it cannot be captured)
+    const bool timing = g_timer.on;
+    const bool use_graph = tn().graph && B.gx && !timing && st != nullptr;
     cur_v = v;
     CgVecs<R> vec{{B.cr[0], B.cr[1]}, {B.cw[0], B.cw[1]}, {B.cs[0], B.cs[1]}, B.cp, z};
+    if (use_graph) {
+      SHK_HIP(hipMemcpyAsync(B.gv, v, (size_t)N * sizeof(cx<R>), hipMemcpyDeviceToDevice, st));
+      cur_v = B.gv;
+      vec.x = B.gx;
+    }
     k_dinv<OpD, R><<<grid_items(n, 2048), BS, 0, st>>>(opd, p->dK, tau, ni, B.dinv);
     // partials of launch L live in cpart[L & 1] (totals in ctot[L & 1])
     auto totals = [&](int slot) -> const c128* {
@@ -1209,12 +1352,13 @@ template <typename R, typename Op, typename OpD> struct Group {
     cfg.eps = fixed > 0 ? -1.0 : eps;
     cfg.maxit = cap;
     cfg.trust = rounds ? 0 : 1;
-    const double rtol = mg ? g_tune.round_tol_mg : g_tune.round_tol;
+    const double rtol = mg ? tn().round_tol_mg : tn().round_tol;
     cfg.round_tol = rounds ? rtol : 0.0;
-    cfg.stall_min = g_tune.stall_min;
-    cfg.stall_mult = g_tune.stall_mult;
+    cfg.stall_min = tn().stall_min;
+    cfg.stall_mult = tn().stall_mult;
     cfg.fused_start = mg ? 1 : 0;
-    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, v, vec, B.cpart[0], B.sc, B.all_done);
+    k_set_cfg<<<1, 64, 0, st>>>(B.cfgd, cfg);
+    k_cg_init<Op, R><<<G, BS, 0, st>>>(op, B.dinv, tau, ni, lS, cur_v, vec, B.cpart[0], B.sc, B.all_done);
     if (mg) {
       if constexpr (Op::NB > 0) {
         // the first round's u = B v, w = A u and forms
@@ -1244,37 +1388,57 @@ template <typename R, typename Op, typename OpD> struct Group {
     // Jacobi (one short kernel per iteration, where an event each would
     // slow the loop): events around the chunk, counted when every launch of
     // it worked.  Either way kernel time plus the back-to-back gaps.
-    const bool timing = g_timer.on;
     int live_before = 0;
     // per lane: iteration count and residual norm seen at the previous poll
     std::vector<int> prev_its(S, 0);
     std::vector<double> prev_rn(S, 0.0);
-    int its_before = 0, rounds_before = S;
     const double lrt = std::log(std::max(rtol, 1e-12));
     while (true) {
       if (timing) {
         g_timer.ensure((size_t)chunk / 2 + 1);
         if (!mg) (void)hipEventRecord(g_timer.ev[0], st);
       }
-      for (int c = 0; c < chunk; ++c, ++it) {
-        const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
-        CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
-        const int out = (int)((it + 1) & 1);
-        if (mg) mg_iteration(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
-        else launch_step(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
-        in = totals(out);
-        if (timing && mg) (void)hipEventRecord(g_timer.ev[c + 1], st);
+      if (use_graph) {
+        // pairs of iterations from the captured graph (it stays even)
+        chunk += chunk & 1;
+        hipGraphExec_t ex = graphs.find(tau);
+        if (!ex) {
+          hipGraph_t gr = nullptr;
+          SHK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          const c128* in2 = in;
+          for (int par = 0; par < 2; ++par) {
+            const CgScal* scIn = B.sc + (size_t)par * S;
+            CgScal* scOut = B.sc + (size_t)(par ^ 1) * S;
+            if (mg) mg_iteration(G, tau, ni, lS, cfg, in2, Gin, scIn, scOut, vec, par, B.cpart[par ^ 1]);
+            else launch_step(G, tau, ni, lS, cfg, in2, Gin, scIn, scOut, vec, par, B.cpart[par ^ 1]);
+            in2 = totals(par ^ 1);
+          }
+          const hipError_t ce = hipStreamEndCapture(st, &gr);
+          if (ce != hipSuccess) return fail(SHK_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+          const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          if (ie != hipSuccess) return fail(SHK_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+          graphs.st = st;
+          graphs.execs.emplace_back(tau, ex);
+        }
+        for (int c = 0; c < chunk; c += 2) SHK_HIP(hipGraphLaunch(ex, st));
+        it += chunk;
+      } else {
+        for (int c = 0; c < chunk; ++c, ++it) {
+          const CgScal* scIn = B.sc + (size_t)(it & 1) * S;
+          CgScal* scOut = B.sc + (size_t)((it + 1) & 1) * S;
+          const int out = (int)((it + 1) & 1);
+          if (mg) mg_iteration(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
+          else launch_step(G, tau, ni, lS, cfg, in, Gin, scIn, scOut, vec, (int)(it & 1), B.cpart[out]);
+          in = totals(out);
+          if (timing && mg) (void)hipEventRecord(g_timer.ev[c + 1], st);
+        }
       }
       if (timing && !mg) (void)hipEventRecord(g_timer.ev[1], st);
       SHK_HIP(hipGetLastError());
       SHK_HIP(hipMemcpyAsync(&snap->all_done, B.all_done, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipMemcpyAsync(snap->sc, B.sc + (size_t)(it & 1) * S, S * sizeof(CgScal), hipMemcpyDeviceToHost, st));
       SHK_HIP(hipStreamSynchronize(st));
-      int its_now = 0, rounds_now = 0;
-      for (int r = 0; r < S; ++r) {
-        its_now = std::max(its_now, snap->sc[r].its);
-        rounds_now += snap->sc[r].rounds;
-      }
       if (timing) {
         const int live = snap->live - live_before;
         float ms = 0.f;
@@ -1289,8 +1453,6 @@ template <typename R, typename Op, typename OpD> struct Group {
         }
       }
       live_before = snap->live;
-      its_before = its_now;
-      rounds_before = rounds_now;
       if (snap->all_done) break;
       // hang guard only: every lane stops itself after cap iterations and a
       // bounded number of round changes; the rest are the tails of chunks
@@ -1332,6 +1494,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     for (int r = 0; r < S; ++r) its_max = std::max<long long>(its_max, snap->sc[r].its);
     inner_its += its_max;
     if (mg && fixed <= 0) mg_hist_put(tau, snap->live);
+    if (use_graph) SHK_HIP(hipMemcpyAsync(z, B.gx, (size_t)N * sizeof(c128), hipMemcpyDeviceToDevice, st));
     const int Gf = grid_items(N, 1024);
     k_cocg_finish<OpD, R><<<Gf, BS, 0, st>>>(opd, tau, n, S, v, z, B.W, B.part);
     launch_final_sqrt<2>(B.part, Gf, S, pn_out, B.mz, nullptr, st);
@@ -1652,6 +1815,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
   const long n = p->n;
   const bool host_x = ptr_kind == SHK_PTR_HOST;
   const bool use_mg = prm->inner_precond == SHK_PRECOND_MULTIGRID;
+  const TuneScope ts(tune_kind(p), p->n, S, prm->precision, prm->inner_precond);
   const OutPlan op = out_plan(prm, n, nf, s_real, host_x);
   Buffers<R> B = carve<R>(ws, p, m, nf, S, s_real, op, use_mg, blk);
   c128* X = op.internal_x ? B.X : dst.x;
@@ -1839,9 +2003,18 @@ static int check_params(const shk_problem* p, const shk_params* prm, int nf, int
   return SHK_OK;
 }
 
+int tune_class(const shk_problem* p, const shk_params* prm, int n_rhs, int* kind, long long* n, int* lanes) {
+  if (!p || !prm || !kind || !n || !lanes || n_rhs < 1) return fail(SHK_ERR_INVALID_ARG, "tune class arguments");
+  *kind = tune_kind(p);
+  *n = p->n;
+  *lanes = lanes_of(std::min(n_rhs, 64), prm->rhs_mode == SHK_RHS_BLOCK);
+  return SHK_OK;
+}
+
 size_t workspace_bytes(const shk_problem* p, const shk_params* prm, int nf, int n_rhs, bool host_x) {
   const int s_real = std::min(n_rhs, 64);
   const bool blk = prm->rhs_mode == SHK_RHS_BLOCK;
+  const TuneScope ts(tune_kind(p), p->n, lanes_of(s_real, blk), prm->precision, prm->inner_precond);
   return group_bytes(p, prm->m_restart, nf, lanes_of(s_real, blk), s_real, prm->precision,
                      out_plan(prm, p->n, nf, s_real, host_x), prm->inner_precond == SHK_PRECOND_MULTIGRID, blk);
 }
@@ -1929,6 +2102,7 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
     return fail(SHK_ERR_UNSUPPORTED, "multigrid: ny and nz must be at most 65535");
   const bool use_mg = precond == SHK_PRECOND_MULTIGRID;
   if (maxit <= 0) maxit = 20 * p->max_dim();
+  const TuneScope ts(tune_kind(p), p->n, S, precision, precond);
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
     const long N = p->n * S;
@@ -1943,6 +2117,11 @@ int step_inner(shk_problem* p, c128 tau, int S, const void* v, void* z, void* w,
       b.dinv = c.take<cx<R>>(p->n);
       b.part = c.take<c128>((size_t)grid_items(N, 1024) * 2 * S);
       b.sc = c.take<CgScal>(2 * S); b.all_done = c.take<int>(4);
+      b.cfgd = c.take<CgCfg>(1);
+      if (tn().graph) {
+        b.gv = c.take<cx<R>>(N);
+        b.gx = c.take<c128>(N);
+      }
       b.mz = c.take<double>(S); b.pn = c.take<double>(S);
       if (use_mg) carve_mg(c, b, p, N, S);
     };

@@ -1,0 +1,56 @@
+"""The packaged tuning cache (written by the autotuner on MI355X): every entry
+names a valid class and only knobs that apply to it, with values the library
+accepts (shk_tune_set checks names and ranges on the host; no GPU needed)."""
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_packaged_cache_is_valid():
+    import paper_1212_3660_amd as P
+    from paper_1212_3660_amd import autotune as T
+    if not os.path.exists(T.CACHE):
+        pytest.skip("no packaged tuning cache")
+    doc = json.load(open(T.CACHE))
+    assert doc["version"] == 1 and doc["entries"]
+    keys = set()
+    for e in doc["entries"]:
+        key = T._key_of(e["class"])
+        assert key not in keys
+        keys.add(key)
+        assert key[0] in T.KINDS and key[1] > 0 and key[2] in (1, 2, 4, 8, 16, 32, 64)
+        assert set(e["knobs"]) <= set(T.knobs_for(key))
+        assert e["ms"] <= e["ms_start"] and e["workload"]
+    P.shk_tune_reset()
+    try:
+        T.load()
+        for e in doc["entries"]:
+            for k, v in e["knobs"].items():
+                assert P.shk_tune_get(T._key_of(e["class"]), k) == pytest.approx(float(v))
+    finally:
+        P.shk_tune_reset()
+        T.load()
+
+
+def test_tune_table_rejects_bad_settings():
+    import paper_1212_3660_amd as P
+    key = (0, 1000, 1, P.SHK_MIXED, P.SHK_PRECOND_MULTIGRID)
+    for k, v in (("cg_block", 128), ("tail_lds", 200 * 1024), ("round_tol", 1.5), ("no_such_knob", 1)):
+        with pytest.raises(P.ShkError):
+            P.shk_tune_set(key, k, v)
+    from paper_1212_3660_amd import autotune as T
+    P.shk_tune_reset()
+    try:
+        P.shk_tune_set(key, "post_lt", 4)
+        assert P.shk_tune_get(key, "post_lt") == 4
+        assert P.shk_tune_get(P.TUNE_ALL, "post_lt") == 2
+        P.shk_tune_set(P.TUNE_ALL, "down_lt", 8)          # shared: classes without an entry
+        assert P.shk_tune_get((1, 5, 1, 0, 0), "down_lt") == 8
+        P.shk_tune_reset()
+        assert P.shk_tune_get(key, "post_lt") == 2 and P.shk_tune_get(P.TUNE_ALL, "down_lt") == 4
+    finally:
+        P.shk_tune_reset()
+        T.load()

@@ -221,7 +221,11 @@ def time_batched(P, torch, w, make, precision, single_rhs_sample=0, label=None, 
         prof = P.shk_profile_read()
         bprof = P.shk_profile_read_block()
         P.shk_profile_enable(False)
-        out["roofline_iteration"] = roofline(prof, "none", label, "iteration")
+        tfile = "none"
+        if precision == P.SHK_MIXED and not block and not single_rhs_sample:
+            tfile = {65536: "traffic_mg_iteration_256x256_64rhs.json",
+                     2097152: "traffic_mg_iteration_128cubed_8rhs.json"}.get(gp.n, "none")
+        out["roofline_iteration"] = roofline(prof, tfile, label, "iteration")
         if block:
             out["roofline_block_gs"] = block_gs_roofline(bprof, "fp32" if precision == P.SHK_MIXED else "fp64")
     gp.close()
@@ -354,10 +358,33 @@ def cpu_baseline(w, seconds, gpu_outer_steps):
     est = per_step * max(gpu_outer_steps, 1)
     threads = max(1, int(round(cpu / el)))
     return {"value": len(w.sigma) / est, "unit": "shifted solves/s", "cores": threads, "kind": "oracle",
+            "extrapolated": True,
             "sample": (f"{steps} outer steps (all {len(w.sigma)} shifts, multigrid-COCG inner to {w.eps_inner}) "
-                       f"of the 512x512 workload in {el:.1f} s; scaled to the {gpu_outer_steps} outer steps "
+                       f"of the 512x512 workload in {el:.1f} s, extrapolated to the {gpu_outer_steps} outer steps "
                        f"of the GPU solve (refinement sweeps not counted)"),
-            "host_cores_available": len(os.sched_getaffinity(0))}
+            "host_cores_available": len(os.sched_getaffinity(0)),
+            "direct": cpu_direct(w, max(2.0, 0.5 * seconds))}
+
+
+def cpu_direct(w, seconds):
+    """The sparse direct alternative: one SuperLU factorization and solve per
+    shift (complex128, the oracle's exact solver), on the first shifts of the
+    512x512 workload until about `seconds` have passed; every shift costs the
+    same, so the rate is per shift measured, not extrapolated from a partial
+    solve."""
+    from oracle import Problem as OProblem, superlu_solve
+    op = OProblem.fv(w.cell_K, w.Ss, w.h)
+    b = w.b[:, 0]
+    c0, t0 = time.process_time(), time.perf_counter()
+    done = 0
+    for sg in w.sigma:
+        superlu_solve(op.shifted(sg), b)
+        done += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "shifted solves/s", "cores": max(1, int(round((time.process_time() - c0) / el))),
+            "kind": "superlu (scipy splu, complex128)", "sample": f"{done} of {len(w.sigma)} shifts in {el:.1f} s"}
 
 
 def graph_ab(P, torch, gp, w, steps, warmup):

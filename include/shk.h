@@ -449,6 +449,10 @@ int shk_profile_read_block(long long* calls, double* total_ms, double* total_flo
  *   lt64 0|2|4              lanes per thread on complex128
  *   graph 0|1               inner iterations replayed from a HIP graph captured
  *                           on the solve stream (needs a non-null stream)
+ *   tile3 >= 0              3-D levels with at least this many cells run the
+ *                           plane-marching V-cycle legs (0: none)
+ *   tile3_zb 2..64, even    planes per block of those legs
+ *   tile3_lt 2|4|8          complex64 lanes per thread of those legs
  * The table is process-wide and guarded by a lock; a solve in flight keeps the
  * settings it started with.
  */

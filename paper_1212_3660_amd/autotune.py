@@ -43,6 +43,9 @@ SPACE = {
     "nt_store32": [0, 1],
     "nt_store64": [0, 1],
     "graph": [0, 1],
+    "tile3": [0, 32768, 262144],
+    "tile3_zb": [4, 8, 16],
+    "tile3_lt": [4, 8],
 }
 
 
@@ -54,6 +57,8 @@ def knobs_for(key, n_lanes_real=None):
     ks = ["cg_block", "graph"]
     if pc == B.SHK_PRECOND_MULTIGRID and kind in (0, 1):
         ks += ["tail_lds"]
+        if kind == 1:
+            ks += ["tile3", "tile3_zb"] + (["tile3_lt"] if mixed else [])
         if lanes == 1:
             ks += ["mg_fuse"]
         elif mixed:

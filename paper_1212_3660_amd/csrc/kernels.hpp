@@ -31,6 +31,53 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
   return (b & 7) * (G >> 3) + (b >> 3);
 }
 
+// Grid-stride walk over the items (cell, lane chunk) of a stencil kernel,
+// chunks fastest (lC = log2 of the chunks per cell).  On a grid operator with
+// the launch grid and ny
+// multiples of 8, XCD x takes the cells of the rows [x ny/8, (x+1) ny/8) of
+// every plane, in order (x, then y in the slab, then z), and its blocks stride
+// through them together, so the rows and planes next to the ones in work are
+// its own, in its L2.  Otherwise the items go in order, dealt to the XCDs in
+// bands per stride (xcd_tile).
+struct SlabWalk {
+  long start, step, end;
+  int slab, nx, ny, ry, lC;
+  template <typename Op>
+  __device__ SlabWalk(const Op& op, long items, int lC_, int cgb) : lC(lC_) {
+    const int G = gridDim.x;
+    nx = ny = 1;
+    int nz = 1;
+    if constexpr (Op::NB > 0) {
+      nx = op.nx;
+      ny = op.ny;
+    }
+    if constexpr (Op::NB == 6) nz = op.nz;
+    if (Op::NB > 0 && (G & 7) == 0 && (ny & 7) == 0) {
+      slab = (int)(blockIdx.x & 7);
+      ry = ny >> 3;
+      start = (long)(blockIdx.x >> 3) * cgb + threadIdx.x;
+      step = (long)(G >> 3) * cgb;
+      end = ((long)nx * ry * nz) << lC;
+    } else {
+      slab = -1;
+      ry = 0;
+      start = (long)xcd_tile(blockIdx.x, G) * cgb + threadIdx.x;
+      step = (long)G * cgb;
+      end = items;
+    }
+  }
+  __device__ long first() const { return start; }
+  __device__ int cell(long t) const {
+    const long c = t >> lC;
+    if (slab < 0) return (int)c;
+    const long r = c / nx;
+    const int i = (int)(c - r * nx);
+    const long z = r / ry;
+    const int y = slab * ry + (int)(r - z * ry);
+    return i + nx * (y + ny * (int)z);
+  }
+};
+
 // ------------------------------------------------------------ reductions ---
 // Workgroup barrier that orders LDS only: outstanding global loads stay in
 // flight across it (a full __syncthreads would wait for them).
@@ -616,7 +663,8 @@ __global__ void __launch_bounds__(CGB) k_cg_step(Op op, OpD opd, const cx<R>* __
   // the thread's cells: one, or a grid-stride loop when the grid is capped
   auto for_cells = [&](auto&& f) {
     if constexpr (MULTI) {
-      for (int t = t0; t < N; t += gridDim.x * CGB) f(t);
+      const SlabWalk sw(op, N, lS, CGB);
+      for (long q = sw.first(); q < sw.end; q += sw.step) f((sw.cell(q) << lS) + rl);
     } else {
       if (t0 < N) f(t0);
     }
@@ -1532,7 +1580,8 @@ __global__ void __launch_bounds__(BS) k_assemble_lds(long n, int S, int s_real, 
 // ------------------------------------------------------ true residuals -----
 // Partial ||b_r - (K + sigma_j M) x_{j,r}||^2 (mode 0) or conj(rs_r)^T
 // (b_r - (K + sigma_j M) x_{j,r}) (mode 1) per block; blockIdx.y = shift,
-// blockIdx.z = rhs; cells over blockIdx.x.
+// blockIdx.z = rhs; cells over blockIdx.x in y-slabs per XCD (SlabWalk), so
+// the neighbours' x comes from the XCD's own L2.
 template <typename Op>
 __global__ void __launch_bounds__(BS) k_resid(Op op, long n, int S, int nf, const c128* __restrict__ sigma,
                                               const c128* __restrict__ bint, const c128* __restrict__ X,
@@ -1542,7 +1591,9 @@ __global__ void __launch_bounds__(BS) k_resid(Op op, long n, int S, int nf, cons
   const c128 sg = sigma[j];
   auto g = [&](long cc) { return xj[cc]; };
   c128 a{0.0, 0.0};
-  for (long c = blockIdx.x * (long)BS + threadIdx.x; c < n; c += (long)gridDim.x * BS) {
+  const SlabWalk sw(op, n, 0, BS);
+  for (long q = sw.first(); q < sw.end; q += sw.step) {
+    const long c = sw.cell(q);
     const c128 res = bint[c * S + r] - op.template apply<double>(c, sg, g);
     if (mode == 0) a.re += abs2(res);
     else a = a + cdot(rs[c * S + r], res);
@@ -1563,7 +1614,9 @@ __global__ void __launch_bounds__(BS) k_resid_jr(Op op, long n, int S, int nf, c
   c128 a[JR];
 #pragma unroll
   for (int q = 0; q < JR; ++q) a[q] = c128{0.0, 0.0};
-  for (long c = blockIdx.x * (long)BS + threadIdx.x; c < n; c += (long)gridDim.x * BS) {
+  const SlabWalk sw(op, n, 0, BS);
+  for (long q = sw.first(); q < sw.end; q += sw.step) {
+    const long c = sw.cell(q);
     const c128 bc = bint[c * S + r];
     const c128 rc = mode == 0 ? c128{0.0, 0.0} : rs[c * S + r];
 #pragma unroll

@@ -207,9 +207,23 @@ __device__ __forceinline__ cx<R> mg_up_cell(const Op& op, const LevelDims& f, co
 // Block coordinates of a (gx, gy, gz) launch, the linear block index taken
 // through xcd_tile: each XCD walks a contiguous band of rows (and planes), so
 // the stencil's neighbour rows are mostly in its own L2.
+// In 3-D with gy a multiple of 8, XCD x (workgroups are dealt out to the XCDs
+// round-robin, linear id mod 8) takes instead the y-slab of rows
+// [x gy/8, (x+1) gy/8) of every plane, walked plane after plane: the blocks an
+// XCD runs at once then span a few planes of its slab, whose planes before and
+// after are still in its L2 (a band of whole planes is too large for it).
 __device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
   const int gx = gridDim.x, gy = gridDim.y;
-  const int T = xcd_tile(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gridDim.z);
+  const int w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if (gridDim.z > 1 && (gy & 7) == 0) {
+    const int ry = gy >> 3, u = w >> 3;
+    bx = u % gx;
+    const int r = u / gx;
+    by = (w & 7) * ry + r % ry;
+    bz = r / ry;
+    return;
+  }
+  const int T = xcd_tile(w, gx * gy * gridDim.z);
   const int r = T / gx;
   bx = T - r * gx;
   by = r % gy;
@@ -389,6 +403,198 @@ __global__ void __launch_bounds__(BS) k_mg_up_lanes(Op op, LevelDims f, LevelDim
     cx<R>* o = xout + ((long)cell << lS) + lc * LT;
 #pragma unroll
     for (int l = 0; l < LT; ++l) o[l] = v[l];
+  }
+}
+
+// ------------------------------------------- 3-D legs, marching the planes --
+// The grid legs of a 3-D level with the x-y neighbours taken from LDS: a block
+// owns a T3X x T3Y tile of cells (a thread per cell) and one chunk of LT lanes
+// (blockIdx.x = tile column * C + chunk), and marches through ZB planes.  On
+// each plane the block forms the smoothed value (x1 = omega D^-1 b, plus the
+// prolongated coarse solution on the way up) of its cells and of the tile's
+// ring of 2 T3X + 2 T3Y neighbours once, in LDS; the x-y neighbours of the
+// stencil come from there, the z neighbours from the thread's registers (its
+// cell's values on the planes below and above).  Each input is read about once
+// (plus the ring and the two planes past the block's ends) where the one-cell
+// kernels read it once per stencil point, which made them bound by the
+// requests their vector caches serve rather than by HBM.  Same arithmetic per
+// lane as k_mg_down_lanes / k_mg_up_lanes: slots of neighbours outside the
+// grid hold zeros and their face coefficients are zero.
+constexpr int T3X = 64, T3Y = 8, T3T = T3X * T3Y, T3H = 2 * (T3X + T3Y);
+
+// This thread's ring cell (tile coordinates, -1 .. T3X / T3Y), or hx = -2.
+__device__ __forceinline__ void tile3_ring(int t, int& hx, int& hy) {
+  hx = hy = -2;
+  if (t >= T3H) return;
+  if (t < T3X) { hx = t; hy = -1; }
+  else if (t < 2 * T3X) { hx = t - T3X; hy = T3Y; }
+  else if (t < 2 * T3X + T3Y) { hx = -1; hy = t - 2 * T3X; }
+  else { hx = T3X; hy = t - 2 * T3X - T3Y; }
+}
+
+// One cell's inputs of the smoothed value: b, D^-1 and (on the way up) x_c of
+// its parent.
+template <typename R, int LT, bool UP> struct Tile3Raw {
+  cx<R> b[LT];
+  cx<R> x[UP ? LT : 1];
+  cx<R> d;
+};
+
+template <typename Op, typename R, int LT, bool UP>
+__global__ void __launch_bounds__(T3T) k_mg_leg_tile3(Op op, LevelDims f, LevelDims cd, c128 tau, double omega,
+                                                      int lS, int C, int ZB, const cx<R>* __restrict__ b,
+                                                      const cx<R>* __restrict__ dinv,
+                                                      const cx<R>* __restrict__ xc, cx<R>* __restrict__ out,
+                                                      const int* __restrict__ all_done) {
+  __shared__ cx<R> sh[T3Y + 2][T3X + 2][LT];
+  __shared__ cx<R> stg[UP ? 1 : T3Y][UP ? 1 : T3X][LT];   // restriction: the children's sums
+  const int flag = *all_done;
+  int bxc, by, bz;
+  xcd_block3(bxc, by, bz);
+  const int ch = bxc % C, bx = bxc / C;
+  const int tx = (int)threadIdx.x % T3X, ty = (int)threadIdx.x / T3X;
+  const int i = bx * T3X + tx, j = by * T3Y + ty;
+  const bool own = i < f.nx && j < f.ny;
+  const int z0 = bz * ZB, z1 = min(z0 + ZB, f.nz);
+  int hx, hy;
+  tile3_ring((int)threadIdx.x, hx, hy);
+  const int hi = bx * T3X + hx, hj = by * T3Y + hy;
+  const bool ring = hx > -2 && hi >= 0 && hi < f.nx && hj >= 0 && hj < f.ny;
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  const int l0 = ch * LT;
+  using Raw = Tile3Raw<R, LT, UP>;
+  auto load = [&](int ci, int cj, int k, Raw& r) {
+    const int c = ci + f.nx * (cj + f.ny * k);
+    r.d = dinv[c];
+    const long bb = ((long)c << lS) + l0;
+#pragma unroll
+    for (int l = 0; l < LT; ++l) r.b[l] = b[bb + l];
+    if constexpr (UP) {
+      const int pc = (ci >> 1) + cd.nx * ((cj >> 1) + cd.ny * (k >> 1));
+      const long pb = ((long)pc << lS) + l0;
+#pragma unroll
+      for (int l = 0; l < LT; ++l) r.x[l] = xc[pb + l];
+    }
+  };
+  // smoothed value: x1 = om D^-1 b, plus x_c of the parent on the way up
+  auto smooth = [&](const Raw& r, cx<R> (&o)[LT]) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+      if constexpr (UP) o[l] = om * (r.d * r.b[l]) + r.x[l];
+      else o[l] = om * (r.d * r.b[l]);
+    }
+  };
+  auto zero = [](cx<R> (&o)[LT]) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) o[l] = cx<R>{0, 0};
+  };
+  cx<R> xp[LT], xcur[LT], xn[LT], bcur[LT], hv[LT], acc[LT];
+  cx<R> dcur{0, 0};
+  Raw rn, hr;
+  zero(xp);
+  zero(xcur);
+  zero(bcur);
+  zero(acc);
+  if (ring) load(hi, hj, z0, hr);
+  if (own) {
+    if (z0 > 0) {
+      load(i, j, z0 - 1, rn);
+      smooth(rn, xp);
+    }
+    load(i, j, z0, rn);
+    smooth(rn, xcur);
+#pragma unroll
+    for (int l = 0; l < LT; ++l) bcur[l] = rn.b[l];
+    dcur = rn.d;
+  }
+  for (int k = z0; k < z1; ++k) {
+    // the ring's values on this plane (inputs loaded on the previous step),
+    // then every load this step and the next need, issued together: the
+    // ring's inputs on the next plane, this cell's on the next plane and
+    // this cell's faces and mass
+    zero(hv);
+    if (ring) smooth(hr, hv);
+    if (ring && k + 1 < z1) load(hi, hj, k + 1, hr);
+    const bool up_in = own && k + 1 < f.nz;
+    if (up_in) load(i, j, k + 1, rn);
+    const int c = i + f.nx * (j + f.ny * k);
+    int idx[Op::NB];
+    R fo[Op::NB];
+    R fsum = 0;
+    R m = 0;
+    if (own) {
+      op.template stencil_at<R>(i, j, k, c, idx, fo, fsum);
+      m = (R)op.mass(c);
+    }
+    __syncthreads();   // the previous plane's reads of sh are done
+#pragma unroll
+    for (int l = 0; l < LT; ++l) sh[ty + 1][tx + 1][l] = xcur[l];
+    if (hx > -2) {
+#pragma unroll
+      for (int l = 0; l < LT; ++l) sh[hy + 1][hx + 1][l] = hv[l];
+    }
+    __syncthreads();
+    zero(xn);
+    if (up_in) smooth(rn, xn);
+    cx<R> v[LT];
+    zero(v);
+    if (own) {
+#pragma unroll
+      for (int l = 0; l < LT; ++l) {
+        const cx<R> xi = xcur[l];
+        cx<R> ax = fsum * xi + m * (tr * xi);
+        ax = ax - fo[0] * sh[ty + 1][tx][l];
+        ax = ax - fo[1] * sh[ty + 1][tx + 2][l];
+        ax = ax - fo[2] * sh[ty][tx + 1][l];
+        ax = ax - fo[3] * sh[ty + 2][tx + 1][l];
+        ax = ax - fo[4] * xp[l];
+        ax = ax - fo[5] * xn[l];
+        if constexpr (UP) v[l] = xi + om * (dcur * (bcur[l] - ax));
+        else v[l] = bcur[l] - ax;
+      }
+    }
+    if constexpr (UP) {
+      int fl = flag;
+      hold(v[0], fl);
+      if (own && !fl) {
+        cx<R>* o = out + ((long)c << lS) + l0;
+#pragma unroll
+        for (int l = 0; l < LT; ++l) o[l] = v[l];
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < LT; ++l) acc[l] = acc[l] + v[l];
+      if ((k & 1) || k + 1 == z1) {
+        // both child planes of coarse plane k / 2 are in: sum the 2 x 2
+        // children in the plane and store the coarse cell
+#pragma unroll
+        for (int l = 0; l < LT; ++l) stg[ty][tx][l] = acc[l];
+        __syncthreads();
+        const int I = i >> 1, J = j >> 1;
+        if (!(tx & 1) && !(ty & 1) && I < cd.nx && J < cd.ny) {
+          cx<R> s2[LT];
+#pragma unroll
+          for (int l = 0; l < LT; ++l)
+            s2[l] = (stg[ty][tx][l] + stg[ty][tx + 1][l]) + (stg[ty + 1][tx][l] + stg[ty + 1][tx + 1][l]);
+          int fl = flag;
+          hold(s2[0], fl);
+          if (!fl) {
+            cx<R>* o = out + ((long)(I + cd.nx * (J + cd.ny * (k >> 1))) << lS) + l0;
+#pragma unroll
+            for (int l = 0; l < LT; ++l) o[l] = s2[l];
+          }
+        }
+        zero(acc);
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+      xp[l] = xcur[l];
+      xcur[l] = xn[l];
+      if (up_in) bcur[l] = rn.b[l];
+    }
+    if (up_in) dcur = rn.d;
   }
 }
 
@@ -773,8 +979,7 @@ __global__ void __launch_bounds__(CGB) k_cgmg_post(Op op, c128 tau, int n, int l
   // The operands are loaded whatever the flags say (done lanes' sums are
   // masked out) and the done flag is read after their loads are issued, so
   // its round trip overlaps theirs.
-  auto cell = [&](int t) {
-    const int c = t >> lS;
+  auto cell = [&](int c, int t) {
     constexpr int NB = Op::NB;
     int idx[NB];
     R fo[NB];
@@ -797,9 +1002,13 @@ __global__ void __launch_bounds__(CGB) k_cgmg_post(Op op, c128 tau, int n, int l
     }
   };
   if constexpr (MULTI) {
-    for (int t = t0; t < N; t += gridDim.x * CGB) cell(t);
+    const SlabWalk sw(op, N, lS, CGB);
+    for (long q = sw.first(); q < sw.end; q += sw.step) {
+      const int c = sw.cell(q);
+      cell(c, (c << lS) + rl);
+    }
   } else {
-    if (t0 < N) cell(t0);
+    if (t0 < N) cell(t0 >> lS, t0);
   }
   if (*opaque(all_done)) return;
   c128 acc[3] = {ag, ad, {arr, 0.0}};
@@ -830,8 +1039,9 @@ __global__ void __launch_bounds__(CGB) k_cgmg_post_lanes(Op op, c128 tau, int n,
   c128 acc[3][LT];
 #pragma unroll
   for (int j = 0; j < LT; ++j) acc[0][j] = acc[1][j] = acc[2][j] = c128{0.0, 0.0};
-  for (long t = (long)xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x; t < items; t += (long)gridDim.x * CGB) {
-    const int c = (int)(t >> lC);
+  const SlabWalk sw(op, items, lC, CGB);
+  for (long t = sw.first(); t < sw.end; t += sw.step) {
+    const int c = sw.cell(t);
     int idx[NB];
     R fo[NB];
     R fsum;

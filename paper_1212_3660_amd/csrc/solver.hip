@@ -347,6 +347,9 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 //  post_lt, down_lt, up_lt   lanes per thread of the product and grid legs
 //              (complex64, several lanes); lt64 the same on complex128
 //  graph       inner iterations replayed from a captured HIP graph
+//  tile3, tile3_zb, tile3_lt   3-D levels of at least tile3 cells: plane-
+//              marching grid legs, tile3_zb planes per block, tile3_lt complex64
+//              lanes per thread
 struct Tune {
   int cgb = 256;
   int nt64 = 0;
@@ -362,6 +365,9 @@ struct Tune {
   int down_lt = 4, up_lt = 4;
   int lt64 = 2;
   int graph = 0;
+  long tile3 = 262144;  // 3-D levels with at least this many cells use the plane-marching legs (0: none)
+  int tile3_zb = 4;     // planes per block of those legs (even)
+  int tile3_lt = 4;   // complex64 lanes per thread of those legs (4 or 8)
 
   // Sets a knob by name; false for an unknown name or a value out of range.
   bool set(const std::string& k, double v) {
@@ -384,6 +390,9 @@ struct Tune {
     else if (k == "up_lt") { up_lt = chunk(iv); }
     else if (k == "lt64") { lt64 = iv >= 4 ? 4 : iv >= 2 ? 2 : 0; }
     else if (k == "graph") { graph = iv != 0; }
+    else if (k == "tile3") { if (v < 0) return false; tile3 = (long)v; }
+    else if (k == "tile3_zb") { if (iv < 2 || iv > 64 || (iv & 1)) return false; tile3_zb = iv; }
+    else if (k == "tile3_lt") { if (iv != 2 && iv != 4 && iv != 8) return false; tile3_lt = iv; }
     else return false;
     return true;
   }
@@ -404,6 +413,9 @@ struct Tune {
     else if (k == "up_lt") *v = up_lt;
     else if (k == "lt64") *v = lt64;
     else if (k == "graph") *v = graph;
+    else if (k == "tile3") *v = (double)tile3;
+    else if (k == "tile3_zb") *v = tile3_zb;
+    else if (k == "tile3_lt") *v = tile3_lt;
     else return false;
     return true;
   }
@@ -815,16 +827,25 @@ static size_t group_bytes(const shk_problem* p, int m, int nf, int S, int s_real
 }
 
 // ------------------------------------------------------- lane totals -------
-// One block per (sum q, lane r), grid NV*S: totals of NV partial sums over G
-// blocks -> tot[q*S+r] (the layout of a single block's partials, so consumers
-// read it with G=1).  Each thread issues its first LTK loads together, then
-// sums them in order (a strided loop takes blocks beyond LTK*BS), then a
-// fixed-order block sum.
+// One block per entry e = q*S + r (sum q, lane r): totals of NV partial sums
+// over G blocks -> tot[e] (the layout of a single block's partials, so
+// consumers read it with G=1).  The partials of a block are a row of NV*S
+// entries; the 8 entries of each 128-byte line of a row go to blocks on one
+// XCD (workgroups are dealt out to the XCDs round-robin, id mod 8), so each
+// line comes from HBM into one XCD's L2 only: block i works entry
+// ((i >> 6) * 8 + (i & 7)) * 8 + ((i >> 3) & 7), the grid rounded up to whole
+// groups of 64 blocks (the blocks past the last entry return at once).  Each
+// thread issues its first LTK loads together, then sums them in order (a
+// strided loop takes blocks beyond LTK*BS), then a fixed-order block sum.
 constexpr int LTK = 8;
+static int lane_totals_grid(int entries) { return 64 * (((entries + 7) / 8 + 7) / 8); }
 template <int NV>
 __global__ void __launch_bounds__(BS) k_lane_totals(const c128* __restrict__ part, int G, int S,
                                                     c128* __restrict__ tot) {
-  const int q = (int)blockIdx.x / S, r = (int)blockIdx.x - q * S;
+  const int i = (int)blockIdx.x;
+  const int e = (((i >> 6) * 8 + (i & 7)) * 8) + ((i >> 3) & 7);
+  if (e >= NV * S) return;
+  const int q = e / S, r = e - q * S;
   const c128* col = part + (size_t)q * S + r;
   const size_t stride = (size_t)NV * S;
   c128 v[LTK];
@@ -1187,6 +1208,32 @@ template <typename R, typename Op, typename OpD> struct Group {
     else if (lt == 4) mg_up_lt<4>(l, f, c, tau, lS, bl, dl, xcoarse, out);
     else mg_up_lt<8>(l, f, c, tau, lS, bl, dl, xcoarse, out);
   }
+  // plane-marching 3-D legs: a chunk of tile3_lt (complex64) or 2 (complex128)
+  // lanes per block
+  bool tile3_for(const LevelDims& f) const {
+    return Op::NB == 6 && tn().tile3 > 0 && (long)f.n() >= tn().tile3;
+  }
+  template <bool UP, int LT>
+  void leg_tile3_lt(const LevelDims& f, const LevelDims& c, const Op& o, c128 tau, int lS, const cx<R>* bl,
+                    const cx<R>* dl, const cx<R>* xcoarse, cx<R>* out) {
+    if constexpr (Op::NB == 6) {
+      const int C = (1 << lS) / LT, ZB = tn().tile3_zb;
+      const dim3 g((unsigned)(((f.nx + T3X - 1) / T3X) * C), (unsigned)((f.ny + T3Y - 1) / T3Y),
+                   (unsigned)((f.nz + ZB - 1) / ZB));
+      k_mg_leg_tile3<Op, R, LT, UP><<<g, T3T, 0, st>>>(o, f, c, tau, mg_omega, lS, C, ZB, bl, dl, xcoarse, out,
+                                                        B.all_done);
+    }
+  }
+  template <bool UP>
+  void leg_tile3(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
+                 const cx<R>* xcoarse, cx<R>* out) {
+    const Op o = mg_op<Op, R>(op, l);
+    const int lt = std::min(1 << lS, c64 ? tn().tile3_lt : 2);
+    if (lt == 1) leg_tile3_lt<UP, 1>(f, c, o, tau, lS, bl, dl, xcoarse, out);
+    else if (lt == 2) leg_tile3_lt<UP, 2>(f, c, o, tau, lS, bl, dl, xcoarse, out);
+    else if (lt == 4) leg_tile3_lt<UP, 4>(f, c, o, tau, lS, bl, dl, xcoarse, out);
+    else if constexpr (c64) leg_tile3_lt<UP, 8>(f, c, o, tau, lS, bl, dl, xcoarse, out);
+  }
   void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout, int from = 0) {
     if constexpr (Op::NB > 0) {
       const int Lv = mg_levels();
@@ -1197,7 +1244,9 @@ template <typename R, typename Op, typename OpD> struct Group {
       for (int l = from; l < gdown; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
-        if (lS > 0 && lane_chunks()) {
+        if (tile3_for(f)) {
+          leg_tile3<false>(l, f, c, tau, lS, bl, dl, nullptr, B.mb[l]);
+        } else if (lS > 0 && lane_chunks()) {
           mg_down_lanes(l, f, c, tau, lS, bl, dl, B.mb[l]);
         } else {
           const dim3 g((unsigned)((((long)c.nx * S_ << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
@@ -1225,7 +1274,9 @@ template <typename R, typename Op, typename OpD> struct Group {
         const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
         cx<R>* out = l == 0 ? uout : B.mx[l - 1];
-        if (lS > 0 && lane_chunks()) {
+        if (tile3_for(f)) {
+          leg_tile3<true>(l, f, c, tau, lS, bl2, dl, B.mx[l], out);
+        } else if (lS > 0 && lane_chunks()) {
           mg_up_lanes(l, f, c, tau, lS, bl2, dl, B.mx[l], out);
         } else {
           const dim3 g((unsigned)(((long)f.nx * S_ + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
@@ -1344,7 +1395,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     // partials of launch L live in cpart[L & 1] (totals in ctot[L & 1])
     auto totals = [&](int slot) -> const c128* {
       if (!gp.separate) return B.cpart[slot];
-      k_lane_totals<3><<<3 * S, BS, 0, st>>>(B.cpart[slot], G, S, B.ctot[slot]);
+      k_lane_totals<3><<<lane_totals_grid(3 * S), BS, 0, st>>>(B.cpart[slot], G, S, B.ctot[slot]);
       return B.ctot[slot];
     };
     const int Gin = gp.separate ? 1 : G;

@@ -32,6 +32,8 @@ SETTINGS = [
     "graph=1",
     "tail_lds=162816",
     "tail_lds=16384,mg_fuse=0,cg_block=512",
+    "tile3=1,tail_lds=16384",
+    "tile3=1,tile3_zb=2,tile3_lt=8,tail_lds=4096",
 ]
 
 def _cached_picks():

@@ -387,6 +387,34 @@ def cpu_direct(w, seconds):
             "kind": "superlu (scipy splu, complex128)", "sample": f"{done} of {len(w.sigma)} shifts in {el:.1f} s"}
 
 
+def phase_breakdown(P, torch, gp, w, precision, steps):
+    """Where one solve's time goes, from the library's phase timer (HIP events
+    at the phase boundaries on the solve stream, no per-iteration events), over
+    `steps` solves after a warm-up; ms per solve."""
+    prm, keep = P.make_params(w.tau_seq, m_restart=w.m_restart, max_restarts=20, max_refine=4, tol=w.tol,
+                              eps_inner=w.eps_inner, precision=precision, inner_precond=P.SHK_PRECOND_MULTIGRID)
+    nf = len(w.sigma)
+    b = torch.from_numpy(w.b[:, 0]).cuda()[None, :].contiguous()
+    x = torch.empty((1, nf, gp.n), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(P.shk_workspace_bytes(gp, prm, nf, 1), dtype=torch.uint8, device="cuda")
+    P.fgmres_sh_solve(gp, prm, w.sigma, b, x=x, workspace=ws)
+    torch.cuda.synchronize()
+    P.shk_profile_enable(False, phases=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        P.fgmres_sh_solve(gp, prm, w.sigma, b, x=x, workspace=ws)
+    e1.record()
+    e1.synchronize()
+    ph = P.shk_profile_read_phases()
+    P.shk_profile_enable(False)
+    total = e0.elapsed_time(e1) / steps
+    out = {k: round(v / steps, 3) for k, v in ph.items() if v > 0}
+    out["outside the solves' marks"] = round(total - sum(ph.values()) / steps, 3)
+    out["ms_per_solve"] = round(total, 3)
+    return out
+
+
 def graph_ab(P, torch, gp, w, steps, warmup):
     """The 512x512 mixed solve with the inner iterations replayed from
     captured HIP graphs and launched one by one (the class's other settings
@@ -449,6 +477,8 @@ def main():
                     help="run one solve of the workload and exit (for profiler counter passes)")
     ap.add_argument("--precond", choices=["multigrid", "jacobi"], default="multigrid",
                     help="inner preconditioner of --single-solve")
+    ap.add_argument("--solves", type=int, default=1,
+                    help="solves --single-solve runs back to back (the first one cold)")
     ap.add_argument("--sensitivity-only", action="store_true",
                     help="run only the sensitivity measurement of the 256x256 workload and exit (profiler passes)")
     ap.add_argument("--batched-only", choices=["2d", "3d", "2d-block", "3d-block"], default=None,
@@ -515,8 +545,9 @@ def run(a):
     if a.single_solve:
         prec = P.SHK_MIXED if a.single_solve == "mixed" else P.SHK_FP64
         pc = P.SHK_PRECOND_MULTIGRID if a.precond == "multigrid" else P.SHK_PRECOND_JACOBI
-        r = time_path(P, torch, gp, w, prec, 1, 0, profile=False, precond=pc)
-        print(json.dumps({"single_solve": a.single_solve, "precond": a.precond, "ms": r["total_ms"], "inner_iterations": r["inner"],
+        r = time_path(P, torch, gp, w, prec, max(1, a.solves), 0, profile=False, precond=pc)
+        print(json.dumps({"single_solve": a.single_solve, "precond": a.precond, "ms": r["total_ms"],
+                          "ms_each": [round(v, 3) for v in r["per_ms"]], "inner_iterations": r["inner"],
                           "converged": r["ok"]}), flush=True)
         return
     # the inner-iteration kernel is timed inside the timed region itself
@@ -576,6 +607,8 @@ def run(a):
                              "max_true_relres": relaxed["worst"], "inner_iterations": relaxed["inner"],
                              "outer_steps": relaxed["outer"], "refine_sweeps": relaxed["sweeps"]},
            "roofline": roof, "roofline_jacobi_step": roof_jac, "cpu_baseline": None}
+    out["phases"] = {"mixed": phase_breakdown(P, torch, gp, w, P.SHK_MIXED, a.steps),
+                     "fp64": phase_breakdown(P, torch, gp, w, P.SHK_FP64, a.steps)}
     out["captured_iterations"] = graph_ab(P, torch, gp, w, a.steps, a.warmup)
     tuned = [e["workload"] for e in P.autotune.load(apply=False)]
     out["tuning"] = {"cache": "paper_1212_3660_amd/tune_cache.json", "classes": tuned}

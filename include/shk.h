@@ -412,7 +412,9 @@ int shk_sensitivity(shk_problem* p, int n_shifts, int n_src, const shk_c128* phi
  *    V-cycle leg's operands and output, the tail's coefficients, the product).
  * launches: the count (kernel launches or iterations); total_ms: summed time;
  * total_bytes: summed algorithmic bytes.  Process-wide; enable/disable/read are
- * not meant to race with solves on other threads. */
+ * not meant to race with solves on other threads.
+ * on: bit 0 this iteration instrumentation, bit 1 the phase timer
+ * (shk_profile_read_phases); each call resets the totals. */
 int shk_profile_enable(int on);
 int shk_profile_read(long long* launches, double* total_ms, double* total_bytes);
 /* With the instrumentation on, each block Gram-Schmidt of the shared block
@@ -421,6 +423,20 @@ int shk_profile_read(long long* launches, double* total_ms, double* total_bytes)
  * calls, their summed time and their flops (4 x 8 n (k+1) s^2 real flops per
  * call, s the block width).  Reset by shk_profile_enable. */
 int shk_profile_read_block(long long* calls, double* total_ms, double* total_flops);
+/* Phase timer (shk_profile_enable bit 1): HIP events on the solve stream at the
+ * boundaries of a solve's phases; the GPU time between two marks is charged to
+ * the phase the later mark closes, so time the GPU spends waiting for the host
+ * falls into the phase whose launches follow the wait.  ms[0..n-1] receives the
+ * totals since the last enable, in this order: 0 start of a pass (norms, lane
+ * set-up); 1 inner solves (set-up, iterations, the host's polls, finish); 2
+ * Gram-Schmidt; 3 shifted least squares and the outer step's test (up to the
+ * copy of the active counts); 4 turnaround (the host's wait on that copy and its
+ * launch of the next phase: between outer steps, before the assembly and
+ * around the true-residual checks); 5 assembly and restarts; 6 true residuals
+ * and the refinement's residual; 7 whole block-basis passes (SHK_RHS_BLOCK is
+ * timed as one phase).  For one solve at a time (lockstep or block path).
+ * Returns the number of phases (8), or INVALID_ARG for a null ms. */
+int shk_profile_read_phases(double* ms, int n);
 
 /* ---------------------------------------------------------------------------
  * Tuning table.  Launch and round settings (block sizes, lanes per thread,

@@ -10,6 +10,6 @@ from .binding import (Problem, Server, fgmres_sh_solve, make_params, shk_apply_s
                       SHK_GMRES, SHK_FOM, SHK_CGS2, SHK_MGS, SHK_CONVERGED, SHK_NOT_CONVERGED, SHK_INNER_LIMITED,
                       SHK_BREAKDOWN_EXACT, SHK_NAN, SHK_PRECOND_JACOBI, SHK_PRECOND_MULTIGRID, SHK_RHS_LOCKSTEP, SHK_RHS_BLOCK,
                       SHK_OUT_FULL, SHK_OUT_ROWS, SHK_OUT_FACTORED, shk_output_elems, TUNE_ALL, shk_tune_set,
-                      shk_tune_get, shk_tune_reset, shk_tune_class,
+                      shk_tune_get, shk_tune_reset, shk_tune_class, shk_profile_read_phases, PHASES,
                       ShkError)
 from . import autotune  # noqa: F401,E402

@@ -105,6 +105,7 @@ _SIGS = {
     "shk_profile_enable": (C.c_int, [C.c_int]),
     "shk_profile_read": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "shk_profile_read_block": (C.c_int, [C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "shk_profile_read_phases": (C.c_int, [C.POINTER(C.c_double), C.c_int]),
     "shk_tune_set": (C.c_int, [C.c_int, C.c_longlong, C.c_int, C.c_int, C.c_int, C.c_char_p, C.c_double]),
     "shk_tune_get": (C.c_int, [C.c_int, C.c_longlong, C.c_int, C.c_int, C.c_int, C.c_char_p,
                                C.POINTER(C.c_double)]),
@@ -451,8 +452,9 @@ def shk_sensitivity(problem: Problem, phi, psi, J, n_shifts: int, n_src: int, n_
            "shk_sensitivity")
 
 
-def shk_profile_enable(on: bool = True):
-    _check(lib().shk_profile_enable(1 if on else 0), "shk_profile_enable")
+def shk_profile_enable(on: bool = True, phases: bool = False):
+    """on: the inner-iteration instrumentation; phases: the phase timer."""
+    _check(lib().shk_profile_enable((1 if on else 0) | (2 if phases else 0)), "shk_profile_enable")
 
 
 def shk_profile_read():
@@ -499,6 +501,20 @@ def shk_tune_class(problem: Problem, params: shk_params, n_rhs: int):
     _check(lib().shk_tune_class(problem.handle, C.byref(params), int(n_rhs), C.byref(k), C.byref(n),
                                 C.byref(lanes)), "shk_tune_class")
     return (int(k.value), int(n.value), int(lanes.value), int(params.precision), int(params.inner_precond))
+
+
+PHASES = ("pass start", "inner solves", "Gram-Schmidt", "least squares and step test", "host turnaround",
+          "assembly and restarts", "true residuals", "block passes")
+
+
+def shk_profile_read_phases():
+    """Phase totals (ms) since shk_profile_enable with bit 1 set, keyed by
+    PHASES."""
+    ms = (C.c_double * len(PHASES))()
+    n = lib().shk_profile_read_phases(ms, len(PHASES))
+    if n < 0:
+        _check(n, "shk_profile_read_phases")
+    return {PHASES[i]: float(ms[i]) for i in range(min(n, len(PHASES)))}
 
 
 class Server:

@@ -180,6 +180,8 @@ int shk_true_residual_noalloc(shk_problem* p, int n_shifts, const shk_c128* sigm
                                          (hipStream_t)hip_stream);
 }
 
+int shk_profile_read_phases(double* ms, int n) { return shk::profile_read_phases(ms, n); }
+
 int shk_tune_set(int kind, long long n, int lanes, int precision, int inner_precond, const char* knob,
                  double value) {
   return shk::tune_set(kind, n, lanes, precision, inner_precond, knob, value);

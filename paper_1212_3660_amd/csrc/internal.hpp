@@ -117,6 +117,7 @@ const char* last_error_text();
 int profile_enable(int on);
 int profile_read(long long* launches, double* ms, double* bytes);
 int profile_read_block(long long* calls, double* ms, double* flops);
+int profile_read_phases(double* ms, int n);
 int tune_set(int kind, long long n, int lanes, int precision, int precond, const char* knob, double value);
 int tune_get(int kind, long long n, int lanes, int precision, int precond, const char* knob, double* value);
 int tune_reset();

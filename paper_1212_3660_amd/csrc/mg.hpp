@@ -292,8 +292,8 @@ __global__ void __launch_bounds__(BS) k_mg_up(Op op, LevelDims f, LevelDims c, c
 // mass and D^-1 once for them instead of once per lane; per lane the
 // expressions of mg_down_fine and mg_up_cell.  Lane chunk lc holds lanes
 // lc LT .. lc LT + LT - 1; lNC = log2(S / LT).
-// Down: grid (ceil(c.nx 2^(lNC + d) / BS), c.ny, c.nz), the 2^d children of a
-// coarse cell (per chunk) in adjacent threads.
+// Down: grid (ceil(c.nx 2^(lNC + d) / BS), c.ny, c.nz); the 2^d children of a
+// coarse cell and its chunks share a run of 2^(d + lNC) threads.
 template <typename Op, typename R, int LT>
 __global__ void __launch_bounds__(BS) k_mg_down_lanes(Op op, LevelDims f, LevelDims c, c128 tau, double omega,
                                                       int lS, int lNC, const cx<R>* __restrict__ b,
@@ -307,7 +307,14 @@ __global__ void __launch_bounds__(BS) k_mg_down_lanes(Op op, LevelDims f, LevelD
   xcd_block3(bx, J, L);
   const int t = bx * BS + threadIdx.x;
   if (t >= (c.nx << (lNC + D))) return;   // whole groups of 2^d lanes leave together
-  const int q = t & (Q - 1), lc = (t >> D) & ((1 << lNC) - 1), I = t >> (D + lNC);
+  // Chunks fastest when a coarse cell's children and chunks fit in a wave
+  // (2^(d + lNC) <= 64): consecutive threads read consecutive pieces of one
+  // cell's lanes (coalesced) and the 2^d children of a coarse cell sit 2^lNC
+  // lanes apart; otherwise children fastest (summed by quad permutes)
+  const bool cf = D + lNC <= 6;
+  const int q = cf ? (t >> lNC) & (Q - 1) : t & (Q - 1);
+  const int lc = cf ? t & ((1 << lNC) - 1) : (t >> D) & ((1 << lNC) - 1);
+  const int I = t >> (D + lNC);
   const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * L + (q >> 2);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
@@ -337,8 +344,22 @@ __global__ void __launch_bounds__(BS) k_mg_down_lanes(Op op, LevelDims f, LevelD
       v[l] = bi - ax;
     }
   }
+  if (cf) {
+    // the children, 2^lNC lanes apart: a butterfly in the same order in
+    // every lane of the group
 #pragma unroll
-  for (int l = 0; l < LT; ++l) v[l] = group_sum<Q>(v[l]);
+    for (int e = 0; e < D; ++e) {
+      const int dl = 1 << (lNC + e);
+#pragma unroll
+      for (int l = 0; l < LT; ++l) {
+        v[l].re += __shfl_xor(v[l].re, dl);
+        v[l].im += __shfl_xor(v[l].im, dl);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) v[l] = group_sum<Q>(v[l]);
+  }
   hold(v[0], flag);
   if (!flag && q == 0) {
     cx<R>* o = out + ((long)(I + c.nx * (J + c.ny * L)) << lS) + lc * LT;

@@ -97,7 +97,50 @@ struct BlockTimer {
 };
 static BlockTimer g_btimer;
 
+// Phase timing (shk_profile_read_phases): HIP events recorded on the solve
+// stream at the boundaries of the solve's phases.  The GPU time between two
+// marks is charged to the phase the later mark closes, so time in which the
+// GPU waits for the host falls into the phase whose launches follow the wait
+// (the turnaround between outer steps is a phase of its own).  For one solve
+// at a time; the events are read when the solve's stream has drained.
+enum { PH_START, PH_INNER, PH_GS, PH_LSQ, PH_TURN, PH_ASM, PH_RESID, PH_BLOCK, PH_N };
+struct PhaseTimer {
+  bool on = false;
+  double ms[PH_N] = {};
+  std::vector<hipEvent_t> pool;
+  std::vector<int> ph;      // phase closed by each recorded mark
+  void mark(hipStream_t st, int phase) {
+    if (!on) return;
+    if (ph.size() == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      pool.push_back(e);
+    }
+    if (hipEventRecord(pool[ph.size()], st) == hipSuccess) ph.push_back(phase);
+  }
+  // after the stream has drained: charge the intervals and start over
+  void flush() {
+    if (!on) return;
+    for (size_t i = 1; i < ph.size(); ++i) {
+      float t = 0.f;
+      if (ph[i] >= 0 && hipEventElapsedTime(&t, pool[i - 1], pool[i]) == hipSuccess) ms[ph[i]] += t;
+    }
+    ph.clear();
+  }
+};
+static PhaseTimer g_phase;
+
+int profile_read_phases(double* ms, int n) {
+  if (!ms || n < 0) return fail(SHK_ERR_INVALID_ARG, "phase output");
+  for (int i = 0; i < n && i < PH_N; ++i) ms[i] = g_phase.ms[i];
+  return PH_N;
+}
+
 int profile_enable(int on) {
+  g_phase.on = (on & 2) != 0;
+  g_phase.ph.clear();
+  for (double& v : g_phase.ms) v = 0.0;
+  on &= 1;
   g_timer.on = on != 0;
   g_timer.launches = 0;
   g_timer.total_ms = 0.0;
@@ -1644,6 +1687,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     k_scale_conv<R><<<grid_items(N, 4096), BS, 0, st>>>(rhs, N, S, B.beta0, B.V);
     k_lanes_init<<<Lb, BS, 0, st>>>(L, S, s_real, B.beta0, B.ls, B.g);
     SHK_HIP(hipGetLastError());
+    g_phase.mark(st, PH_START);
     const std::vector<c128>& taus = *ps.taus;
     long long kglob = ps.kglob0;
     std::vector<c128> tcyc(m);
@@ -1659,9 +1703,12 @@ template <typename R, typename Op, typename OpD> struct Group {
       int kend = 0;
       bool any_active = true;
       for (int k = 0; k < m; ++k) {
+        g_phase.mark(st, PH_TURN);
         SHK_TRY(inner(tcyc[k], B.V + (size_t)k * N, B.Z + (size_t)k * N, eps_k, ps.inner_maxit, 0,
                       B.pn + (size_t)k * S));
+        g_phase.mark(st, PH_INNER);
         SHK_TRY(orthogonalize(k, B.W));
+        g_phase.mark(st, PH_GS);
         GivensArgs a = gargs(k, cycle, (int)(kglob - ps.kglob0), ps.tol);
         a.fom = ps.fom ? 1 : 0;
         launch_givens(a, st);
@@ -1669,6 +1716,7 @@ template <typename R, typename Op, typename OpD> struct Group {
         SHK_HIP(hipGetLastError());
         SHK_HIP(hipMemcpyAsync(nact, B.nact, S * sizeof(int), hipMemcpyDeviceToHost, st));
         if (ps.relax > 0.0) SHK_HIP(hipMemcpyAsync(qmax, B.qmax, S * sizeof(double), hipMemcpyDeviceToHost, st));
+        g_phase.mark(st, PH_LSQ);
         SHK_HIP(hipStreamSynchronize(st));
         if (ps.relax > 0.0) {
           // relaxed inner tolerance for the next step: the outer residual has
@@ -1689,9 +1737,11 @@ template <typename R, typename Op, typename OpD> struct Group {
       }
       if (!any_active || cycle == ps.max_restarts) {
         // final cycle: lanes still active keep their last least-squares y
+        g_phase.mark(st, PH_TURN);
         SHK_TRY(assemble(kend, cycle, extra, X, !first_write));
         if (any_active) k_finalize_active<<<Lb, BS, 0, st>>>(L, B.ls);
         SHK_HIP(hipGetLastError());
+        g_phase.mark(st, PH_ASM);
         break;
       }
       GivensArgs a = gargs(m - 1, cycle, 0, ps.tol);
@@ -1714,6 +1764,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       k_basis_combine<R><<<grid_items(N, 4096), BS, 0, st>>>(N, S, m + 1, B.V, (size_t)N, B.zs, B.W);
       k_copy<R><<<grid_items(N, 4096), BS, 0, st>>>(B.W, N, B.V);
       SHK_HIP(hipGetLastError());
+      g_phase.mark(st, PH_ASM);
     }
     return SHK_OK;
   }
@@ -1911,7 +1962,9 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     g.fz_cap = factored_kcap(prm);
     PassSpec ps{m, prm->max_restarts, maxit, prm->tol, prm->eps_inner, &taus, 0, prm->inner_relax, prm->inner_eps_max,
                 prm->variant == SHK_FOM};
+    g_phase.mark(st, -1);
     SHK_TRY(blk ? g.pass_block(B.bint, ps, X, false, nullptr) : g.pass(B.bint, ps, X, false, nullptr));
+    if (blk) g_phase.mark(st, PH_BLOCK);
     SHK_HIP(hipMemcpyAsync(lanes.data(), B.ls, sizeof(LaneState) * nf * S, hipMemcpyDeviceToHost, st));
     SHK_HIP(hipMemcpyAsync(bnorm.data(), B.beta0, sizeof(double) * S, hipMemcpyDeviceToHost, st));
     SHK_HIP(hipStreamSynchronize(st));
@@ -1922,8 +1975,10 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     std::vector<int> seeds(S);
     int sweeps = 0;
     auto measure = [&]() -> int {
+      g_phase.mark(st, PH_TURN);
       SHK_TRY(residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, nullptr, 0, B.rpart, B.rrow, st));
       SHK_HIP(hipMemcpyAsync(rows.data(), B.rrow, sizeof(c128) * rows.size(), hipMemcpyDeviceToHost, st));
+      g_phase.mark(st, PH_RESID);
       SHK_HIP(hipStreamSynchronize(st));
       for (int r = 0; r < s_real; ++r)
         for (int j = 0; j < nf; ++j) {
@@ -1949,11 +2004,13 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
         if (!bad_r) seeds[r] = -1;
       }
       if (!any_bad) break;
+      g_phase.mark(st, PH_TURN);
       SHK_HIP(hipMemcpyAsync(B.seed, seeds.data(), sizeof(int) * S, hipMemcpyHostToDevice, st));
       k_resid_vec<OpD><<<grid_items(N, 4096), BS, 0, st>>>(opd, n, S, s_real, nf, B.sigma, B.seed, B.bint, X, B.rsv);
       SHK_HIP(hipGetLastError());
       SHK_TRY(residual_rows(opd, n, S, s_real, nf, B.sigma, B.bint, X, B.rsv, 1, B.rpart, B.rrow, st));
       SHK_HIP(hipMemcpyAsync(rows.data(), B.rrow, sizeof(c128) * rows.size(), hipMemcpyDeviceToHost, st));
+      g_phase.mark(st, PH_RESID);
       SHK_HIP(hipStreamSynchronize(st));
       for (int r = 0; r < S; ++r)
         for (int j = 0; j < nf; ++j) {
@@ -1965,9 +2022,11 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
           extra[j * S + r] = gmm;
         }
       SHK_HIP(hipMemcpyAsync(B.extra, extra.data(), sizeof(c128) * nf * S, hipMemcpyHostToDevice, st));
+      g_phase.mark(st, PH_TURN);
       PassSpec pr{m, prm->max_restarts, maxit, prm->refine_tol, prm->refine_eps_inner, &taus, 0, prm->inner_relax,
                   prm->inner_eps_max, prm->variant == SHK_FOM};
       SHK_TRY(blk ? g.pass_block(B.rsv, pr, X, true, B.extra) : g.pass(B.rsv, pr, X, true, B.extra));
+      if (blk) g_phase.mark(st, PH_BLOCK);
       SHK_TRY(measure());
     }
     inner_total = g.inner_its;
@@ -2008,6 +2067,7 @@ static int solve_group(shk_problem* p, const shk_params* prm, int nf, const c128
     SHK_HIP(hipMemcpyAsync(dst.fy, fy, sizeof(c128) * (size_t)op.kcap * nf * s_real, hipMemcpyDeviceToHost, st));
   }
   SHK_HIP(hipStreamSynchronize(st));
+  g_phase.flush();
   return SHK_OK;
 }
 

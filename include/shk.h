@@ -465,6 +465,9 @@ int shk_profile_read_phases(double* ms, int n);
  *   lt64 0|2|4              lanes per thread on complex128
  *   graph 0|1               inner iterations replayed from a HIP graph captured
  *                           on the solve stream (needs a non-null stream)
+ *   mg_chain 0|1            2-D, one lane: up to 3 middle legs of each direction
+ *                           of the V-cycle in one launch
+ *   asm_mfma 0|1            solution assembly X = Z Y on the FP64 matrix cores
  *   tile3 >= 0              3-D levels with at least this many cells run the
  *                           plane-marching V-cycle legs (0: none)
  *   tile3_zb 2..64, even    planes per block of those legs

@@ -46,6 +46,7 @@ SPACE = {
     "tile3": [0, 32768, 262144],
     "tile3_zb": [4, 8, 16],
     "tile3_lt": [4, 8],
+    "mg_chain": [0, 1],
 }
 
 
@@ -60,7 +61,7 @@ def knobs_for(key, n_lanes_real=None):
         if kind == 1:
             ks += ["tile3", "tile3_zb"] + (["tile3_lt"] if mixed else [])
         if lanes == 1:
-            ks += ["mg_fuse"]
+            ks += ["mg_fuse"] + (["mg_chain"] if kind == 0 else [])
         elif mixed:
             ks += ["post_lt", "down_lt", "up_lt"]
         else:

@@ -39,6 +39,66 @@ template <typename T> __device__ __forceinline__ int mfma_row(int g, int v) {
   return std::is_same<T, double>::value ? g + 4 * v : 4 * g + v;
 }
 
+// ---------------------------------------------- lockstep-basis assembly ----
+// X[:, j, r] (+)= scale_{j,r} Z_r y_{j,r} for independent bases (one basis
+// per right-hand-side lane r; Algorithm 4, x = Z y) on the FP64 matrix cores:
+// per lane a product of the n x kc block Z_r of its basis columns and the
+// kc x nf block of its coefficients.  A wave computes 16 cells x 16 TN shifts
+// of one lane (TN output tiles, complex as four real products per step of 4
+// basis columns); the waves of a block take consecutive (cell tile, lane)
+// pairs, lanes fastest, so a block reads adjacent lanes' pieces of the same
+// cells.  Z is read once per 16 TN shifts and X written once.  FP64
+// accumulation (the order over the basis columns is the matrix core's).
+template <typename R, int TN>
+__global__ void __launch_bounds__(256) k_assemble_mfma(long n, int S, int s_real, int nf, int kc, int m,
+                                                       const cx<R>* __restrict__ Z, size_t cstride,
+                                                       const c128* __restrict__ Yb,
+                                                       const c128* __restrict__ ascale, c128* __restrict__ X,
+                                                       int acc) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, mm = lane & 15;
+  const long q = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int r = (int)(q % S);
+  const long cell0 = (q / S) * 16;
+  if (cell0 >= n || r >= s_real) return;   // whole waves
+  const int j0 = (int)blockIdx.y * 16 * TN;
+  d4m re[TN], im[TN];
+#pragma unroll
+  for (int t = 0; t < TN; ++t) {
+    re[t] = d4m{0, 0, 0, 0};
+    im[t] = d4m{0, 0, 0, 0};
+  }
+  const bool zin = cell0 + mm < n;
+  const size_t zc = (size_t)(cell0 + mm) * S + r;
+  for (int i0 = 0; i0 < kc; i0 += 4) {
+    const int i = i0 + g;
+    const bool iin = i < kc;
+    const c128 a = zin && iin ? cvt<double>(Z[(size_t)i * cstride + zc]) : c128{0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      const int j = j0 + 16 * t + mm;
+      const c128 y = iin && j < nf ? Yb[((size_t)j * S + r) * m + i] : c128{0.0, 0.0};
+      re[t] = mfma16(a.re, y.re, re[t]);
+      re[t] = mfma16(a.im, -y.im, re[t]);
+      im[t] = mfma16(a.re, y.im, im[t]);
+      im[t] = mfma16(a.im, y.re, im[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TN; ++t) {
+    const int j = j0 + 16 * t + mm;
+    if (j >= nf) continue;
+    const c128 sc = ascale[(size_t)j * S + r];
+    c128* col = X + n * ((long)j + (long)nf * r);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long cell = cell0 + mfma_row<double>(g, v);
+      if (cell >= n) continue;
+      const c128 val = sc * c128{re[t][v], im[t][v]};
+      col[cell] = acc ? col[cell] + val : val;
+    }
+  }
+}
+
 // ------------------------------------------------- block projections ------
 // Partial products C_i = A_i^H B over one chunk of cells, for block i of A
 // (blocks astride elements apart) and one group of TN n-tiles: one wave per

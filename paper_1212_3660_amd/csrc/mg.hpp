@@ -427,6 +427,292 @@ __global__ void __launch_bounds__(BS) k_mg_up_lanes(Op op, LevelDims f, LevelDim
   }
 }
 
+// ------------------------------------------------ 2-D chains of legs ------
+// Several consecutive grid legs of a single-lane 2-D V-cycle in one launch,
+// for the middle levels whose one-leg launches are latency-bound: each block
+// owns a tile of the chain's last level and recomputes the cells of the
+// earlier levels that its tile depends on (a ring of one cell per level and
+// the children of that).  Every input of every level (right-hand side, D^-1,
+// faces, masses) is loaded into LDS at the start, all loads in flight at
+// once; the legs then run from LDS with a barrier between levels, so the
+// chain costs one memory round trip instead of one or two per leg.  Only the
+// chain's outputs go to memory.  Same per-cell expressions and children order
+// as k_mg_down / k_mg_up.
+constexpr int MGC_F = 3;   // legs per chain at most
+template <typename Op, typename R> struct MgChain {
+  int nl;                        // legs in the chain (1..MGC_F)
+  LevelDims d[MGC_F + 1];        // level dims, d[0] the chain's finest level
+  Op op[MGC_F];                  // operators of levels 0..nl-1
+  const cx<R>* dinv[MGC_F + 1];  // inverse diagonals of levels 0..nl
+  const cx<R>* b[MGC_F];         // down: b[0] the input; up: right-hand sides of levels 0..nl-1
+  cx<R>* out[MGC_F + 1];         // down: out[k] the right-hand side of level k (1..nl); up: out[0]
+  const cx<R>* xc;               // up: solution of level nl
+};
+
+// One cell's stencil data staged in LDS: its four face coefficients (west,
+// east, south, north; boundary faces included) and its mass.
+template <typename R> struct MgcCell {
+  R f[4];
+  R m;
+};
+template <typename Op, typename R>
+__device__ __forceinline__ MgcCell<R> mgc_load_cell(const Op& o, int i, int j) {
+  const int fx = i + (o.nx + 1) * j, fy = i + o.nx * j;
+  MgcCell<R> a;
+  a.f[0] = (R)o.tx[fx];
+  a.f[1] = (R)o.tx[fx + 1];
+  a.f[2] = (R)o.ty[fy];
+  a.f[3] = (R)o.ty[fy + o.nx];
+  a.m = (R)o.mass(i + o.nx * j);
+  return a;
+}
+// A x at cell (i, j) of an nx x ny level from its staged stencil data, x at
+// the cell and at its four neighbours (the face coefficient of a neighbour
+// outside the grid is zero, as in the stencil's own form).
+template <typename R>
+__device__ __forceinline__ cx<R> mgc_apply(const MgcCell<R>& a, int i, int j, int nx, int ny, cx<R> tr, cx<R> xi,
+                                           cx<R> xw, cx<R> xe, cx<R> xs, cx<R> xn) {
+  const R fsum = a.f[0] + a.f[1] + a.f[2] + a.f[3];
+  const R fo0 = i > 0 ? a.f[0] : (R)0, fo1 = i < nx - 1 ? a.f[1] : (R)0;
+  const R fo2 = j > 0 ? a.f[2] : (R)0, fo3 = j < ny - 1 ? a.f[3] : (R)0;
+  cx<R> ax = fsum * xi + a.m * (tr * xi);
+  ax = ax - fo0 * xw;
+  ax = ax - fo1 * xe;
+  ax = ax - fo2 * xs;
+  ax = ax - fo3 * xn;
+  return ax;
+}
+
+// Restriction chain: right-hand sides of levels 1..nl from that of level 0.
+// Block tile T x T of level nl; level k's region is the children of level
+// k+1's region and one ring more (the stencil).
+template <int T> __host__ __device__ constexpr int mgc_down_side(int up) {   // up = nl - k
+  return up == 0 ? T : 2 * mgc_down_side<T>(up - 1) + 2;
+}
+template <int T> constexpr int mgc_down_cells() {
+  return mgc_down_side<T>(1) * mgc_down_side<T>(1) + mgc_down_side<T>(2) * mgc_down_side<T>(2) +
+         mgc_down_side<T>(3) * mgc_down_side<T>(3);
+}
+template <typename Op, typename R, int T>
+__global__ void __launch_bounds__(BS) k_mg_down_chain2d(MgChain<Op, R> ch, c128 tau, double omega,
+                                                        const int* __restrict__ all_done) {
+  constexpr int NC = mgc_down_cells<T>();
+  __shared__ cx<R> sb[NC], sx[NC], sd[NC];   // b, x1 and D^-1 of levels 0..nl-1 (level 0 first)
+  __shared__ MgcCell<R> sc[NC];              // stencil data of the same cells
+  const int flag = *all_done;
+  const int nl = ch.nl;
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  int lox[MGC_F + 1], loy[MGC_F + 1], side[MGC_F + 1], off[MGC_F + 1];
+  // level k's region, k = nl .. 0 (entries past nl unused)
+#pragma unroll
+  for (int k = MGC_F; k >= 0; --k) {
+    if (k >= nl) {
+      lox[k] = (int)blockIdx.x * T;
+      loy[k] = (int)blockIdx.y * T;
+      side[k] = T;
+    } else {
+      lox[k] = 2 * lox[k + 1] - 1;
+      loy[k] = 2 * loy[k + 1] - 1;
+      side[k] = 2 * side[k + 1] + 2;
+    }
+  }
+  off[0] = 0;
+#pragma unroll
+  for (int k = 1; k <= MGC_F; ++k) off[k] = off[k - 1] + (k <= nl ? side[k - 1] * side[k - 1] : 0);
+  // every level's inputs over its region, all loads issued together; x1 of
+  // level 0 (the later levels' x1 follow their right-hand sides)
+#pragma unroll
+  for (int k = 0; k < MGC_F; ++k) {
+    if (k >= nl) break;
+    const int W = side[k];
+    const LevelDims d = ch.d[k];
+    for (int le = threadIdx.x; le < W * W; le += BS) {
+      const int e = off[k] + le;
+      const int gi = lox[k] + le % W, gj = loy[k] + le / W;
+      cx<R> bv{0, 0}, dv{0, 0};
+      MgcCell<R> cl{};
+      if (gi >= 0 && gi < d.nx && gj >= 0 && gj < d.ny) {
+        const int c = gi + d.nx * gj;
+        dv = ch.dinv[k][c];
+        if (k == 0) bv = ch.b[0][c];
+        cl = mgc_load_cell<Op, R>(ch.op[k], gi, gj);
+      }
+      sd[e] = dv;
+      sc[e] = cl;
+      if (k == 0) {
+        sb[e] = bv;
+        sx[e] = om * (dv * bv);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < MGC_F; ++k) {
+    if (k >= nl) break;
+    const LevelDims f = ch.d[k], c = ch.d[k + 1];
+    const int Wf = side[k], W = side[k + 1];
+    const cx<R>* bf = sb + off[k];
+    const cx<R>* xf = sx + off[k];
+    const MgcCell<R>* cf = sc + off[k];
+    // this block's own cells of level k + 1 (the rest of its region is ring)
+    const int sh = nl - (k + 1);
+    const int ox0 = (int)blockIdx.x * T << sh, oy0 = (int)blockIdx.y * T << sh;
+    const int ow = T << sh;
+    for (int e = threadIdx.x; e < W * W; e += BS) {
+      const int pi = e % W, pj = e / W;
+      const int PI = lox[k + 1] + pi, PJ = loy[k + 1] + pj;
+      cx<R> v{0, 0};
+      const bool in = PI >= 0 && PI < c.nx && PJ >= 0 && PJ < c.ny;
+      if (in) {
+        cx<R> r[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 2 * PI + (q & 1), j = 2 * PJ + (q >> 1);
+          r[q] = cx<R>{0, 0};
+          if (i < f.nx && j < f.ny) {
+            const int lc = (i - lox[k]) + Wf * (j - loy[k]);
+            const cx<R> ax = mgc_apply(cf[lc], i, j, f.nx, f.ny, tr, xf[lc], xf[lc - 1], xf[lc + 1], xf[lc - Wf],
+                                       xf[lc + Wf]);
+            r[q] = bf[lc] - ax;
+          }
+        }
+        v = (r[0] + r[1]) + (r[2] + r[3]);
+      }
+      if (k + 1 < nl) {
+        sb[off[k + 1] + e] = v;
+        sx[off[k + 1] + e] = om * (sd[off[k + 1] + e] * v);
+      }
+      int fl = flag;
+      hold(v, fl);
+      if (in && !fl && PI >= ox0 && PI < ox0 + ow && PJ >= oy0 && PJ < oy0 + ow) ch.out[k + 1][PI + c.nx * PJ] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Prolongation chain: x of level 0 from x of level nl.  Block tile T0 x T0 of
+// level 0; level k needs x2 = om D^-1 b + P x_{k+1} on its region and a ring,
+// and x_{k+1} on the parents of those cells.
+template <int T0> __host__ __device__ constexpr int mgc_up_reg(int k) {   // side of level k's region, at most
+  return k == 0 ? T0 : (mgc_up_reg<T0>(k - 1) + 2) / 2 + 1;
+}
+template <int T0> constexpr int mgc_up_ext_cells() {
+  int n = 0;
+  for (int k = 0; k < MGC_F; ++k) n += (mgc_up_reg<T0>(k) + 2) * (mgc_up_reg<T0>(k) + 2);
+  return n;
+}
+template <int T0> constexpr int mgc_up_reg_cells() {
+  int n = 0;
+  for (int k = 0; k <= MGC_F; ++k) n += mgc_up_reg<T0>(k) * mgc_up_reg<T0>(k);
+  return n;
+}
+template <typename Op, typename R, int T0>
+__global__ void __launch_bounds__(BS) k_mg_up_chain2d(MgChain<Op, R> ch, c128 tau, double omega,
+                                                      const int* __restrict__ all_done) {
+  constexpr int NE = mgc_up_ext_cells<T0>(), NR = mgc_up_reg_cells<T0>();
+  __shared__ cx<R> sbe[NE], sde[NE], sx2[NE];   // b, D^-1, x2 over each level's region and ring
+  __shared__ cx<R> sxr[NR];                     // x over each level's region (levels 1..nl)
+  __shared__ MgcCell<R> scr[NR];                // stencil data over each level's region (levels 0..nl-1)
+  const int flag = *all_done;
+  const int nl = ch.nl;
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  // regions: reg[k] = [lo, lo + side); ext[k] = reg[k] and one ring
+  int lox[MGC_F + 1], loy[MGC_F + 1], sw[MGC_F + 1], shh[MGC_F + 1], oe[MGC_F + 1], orr[MGC_F + 2];
+  lox[0] = (int)blockIdx.x * T0;
+  loy[0] = (int)blockIdx.y * T0;
+  sw[0] = shh[0] = T0;
+#pragma unroll
+  for (int k = 0; k < MGC_F; ++k) {
+    lox[k + 1] = (lox[k] - 1) >> 1;
+    loy[k + 1] = (loy[k] - 1) >> 1;
+    sw[k + 1] = ((lox[k] + sw[k]) >> 1) - lox[k + 1] + 1;
+    shh[k + 1] = ((loy[k] + shh[k]) >> 1) - loy[k + 1] + 1;
+  }
+  oe[0] = 0;
+#pragma unroll
+  for (int k = 0; k < MGC_F; ++k) oe[k + 1] = oe[k] + (k < nl ? (sw[k] + 2) * (shh[k] + 2) : 0);
+  orr[0] = 0;
+#pragma unroll
+  for (int k = 0; k <= MGC_F; ++k) orr[k + 1] = orr[k] + (k <= nl ? sw[k] * shh[k] : 0);
+  // every input, all loads issued together: b and D^-1 over each level's
+  // region and ring, the stencil data over each region, x of level nl
+#pragma unroll
+  for (int k = 0; k <= MGC_F; ++k) {
+    if (k > nl) break;
+    const LevelDims d = ch.d[k];
+    if (k < nl) {
+      const int W2 = sw[k] + 2, H2 = shh[k] + 2;
+      for (int le = threadIdx.x; le < W2 * H2; le += BS) {
+        const int gi = lox[k] - 1 + le % W2, gj = loy[k] - 1 + le / W2;
+        cx<R> bv{0, 0}, dv{0, 0};
+        if (gi >= 0 && gi < d.nx && gj >= 0 && gj < d.ny) {
+          const int c = gi + d.nx * gj;
+          bv = ch.b[k][c];
+          dv = ch.dinv[k][c];
+        }
+        sbe[oe[k] + le] = bv;
+        sde[oe[k] + le] = dv;
+      }
+    }
+    const int W = sw[k], H = shh[k];
+    for (int le = threadIdx.x; le < W * H; le += BS) {
+      const int gi = lox[k] + le % W, gj = loy[k] + le / W;
+      const bool in = gi >= 0 && gi < d.nx && gj >= 0 && gj < d.ny;
+      if (k == nl) {
+        sxr[orr[k] + le] = in ? ch.xc[gi + d.nx * gj] : cx<R>{0, 0};
+      } else {
+        MgcCell<R> cl{};
+        if (in) cl = mgc_load_cell<Op, R>(ch.op[k], gi, gj);
+        scr[orr[k] + le] = cl;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = MGC_F - 1; k >= 0; --k) {
+    if (k >= nl) continue;
+    const LevelDims f = ch.d[k];
+    const int W2 = sw[k] + 2, H2 = shh[k] + 2;
+    const int Wc = sw[k + 1];
+    // x2 over the region and its ring
+    for (int e = threadIdx.x; e < W2 * H2; e += BS) {
+      const int gi = lox[k] - 1 + e % W2, gj = loy[k] - 1 + e / W2;
+      cx<R> v{0, 0};
+      if (gi >= 0 && gi < f.nx && gj >= 0 && gj < f.ny) {
+        const int pl = ((gi >> 1) - lox[k + 1]) + Wc * ((gj >> 1) - loy[k + 1]);
+        v = om * (sde[oe[k] + e] * sbe[oe[k] + e]) + sxr[orr[k + 1] + pl];
+      }
+      sx2[oe[k] + e] = v;
+    }
+    __syncthreads();
+    // x = x2 + om D^-1 (b - A x2) over the region
+    const int W = sw[k], H = shh[k];
+    for (int e = threadIdx.x; e < W * H; e += BS) {
+      const int li = e % W, lj = e / W;
+      const int gi = lox[k] + li, gj = loy[k] + lj;
+      cx<R> v{0, 0};
+      const bool in = gi >= 0 && gi < f.nx && gj >= 0 && gj < f.ny;
+      if (in) {
+        const int lc = oe[k] + (li + 1) + W2 * (lj + 1);
+        const cx<R> xi = sx2[lc];
+        const cx<R> ax = mgc_apply(scr[orr[k] + e], gi, gj, f.nx, f.ny, tr, xi, sx2[lc - 1], sx2[lc + 1],
+                                   sx2[lc - W2], sx2[lc + W2]);
+        v = xi + om * (sde[lc] * (sbe[lc] - ax));
+      }
+      if (k > 0) {
+        sxr[orr[k] + e] = v;
+      } else {
+        int fl = flag;
+        hold(v, fl);
+        if (in && !fl) ch.out[0][gi + f.nx * gj] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------- 3-D legs, marching the planes --
 // The grid legs of a 3-D level with the x-y neighbours taken from LDS: a block
 // owns a T3X x T3Y tile of cells (a thread per cell) and one chunk of LT lanes

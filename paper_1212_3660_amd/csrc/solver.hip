@@ -390,6 +390,9 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 //  post_lt, down_lt, up_lt   lanes per thread of the product and grid legs
 //              (complex64, several lanes); lt64 the same on complex128
 //  graph       inner iterations replayed from a captured HIP graph
+//  mg_chain    2-D, one lane: up to 3 middle legs of each V-cycle direction in
+//              one launch
+//  asm_mfma    solution assembly X = Z Y on the FP64 matrix cores
 //  tile3, tile3_zb, tile3_lt   3-D levels of at least tile3 cells: plane-
 //              marching grid legs, tile3_zb planes per block, tile3_lt complex64
 //              lanes per thread
@@ -411,6 +414,8 @@ struct Tune {
   long tile3 = 262144;  // 3-D levels with at least this many cells use the plane-marching legs (0: none)
   int tile3_zb = 4;     // planes per block of those legs (even)
   int tile3_lt = 4;   // complex64 lanes per thread of those legs (4 or 8)
+  int mg_chain = 0;   // 2-D one-lane V-cycle: chain up to 3 middle legs per launch
+  int asm_mfma = 1;   // solution assembly on the FP64 matrix cores
 
   // Sets a knob by name; false for an unknown name or a value out of range.
   bool set(const std::string& k, double v) {
@@ -436,6 +441,8 @@ struct Tune {
     else if (k == "tile3") { if (v < 0) return false; tile3 = (long)v; }
     else if (k == "tile3_zb") { if (iv < 2 || iv > 64 || (iv & 1)) return false; tile3_zb = iv; }
     else if (k == "tile3_lt") { if (iv != 2 && iv != 4 && iv != 8) return false; tile3_lt = iv; }
+    else if (k == "mg_chain") { if (iv < 0 || iv > 1) return false; mg_chain = iv; }
+    else if (k == "asm_mfma") { asm_mfma = iv != 0; }
     else return false;
     return true;
   }
@@ -459,6 +466,8 @@ struct Tune {
     else if (k == "tile3") *v = (double)tile3;
     else if (k == "tile3_zb") *v = tile3_zb;
     else if (k == "tile3_lt") *v = tile3_lt;
+    else if (k == "mg_chain") *v = mg_chain;
+    else if (k == "asm_mfma") *v = asm_mfma;
     else return false;
     return true;
   }
@@ -691,6 +700,13 @@ static void launch_assemble(long n, int S, int s_real, int nf, int kc, int m, co
                             const c128* Yb, const c128* ascale, c128* X, int acc, hipStream_t st,
                             c128* Yt = nullptr) {
   const long N = n * S;
+  if (tn().asm_mfma) {
+    // matrix cores: a wave per (16 cells, lane, 64 shifts)
+    const long pairs = (n + 15) / 16 * S;
+    const dim3 grid((unsigned)((pairs + 3) / 4), (unsigned)((nf + 63) / 64));
+    k_assemble_mfma<R, 4><<<grid, 256, 0, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);
+    return;
+  }
   const size_t lds = (size_t)kc * JT * S * sizeof(c128);
   if (lds <= 65536) {
     dim3 grid(grid_items((N + 1) / 2, 4096), (nf + JT - 1) / JT);
@@ -1277,6 +1293,42 @@ template <typename R, typename Op, typename OpD> struct Group {
     else if (lt == 4) leg_tile3_lt<UP, 4>(f, c, o, tau, lS, bl, dl, xcoarse, out);
     else if constexpr (c64) leg_tile3_lt<UP, 8>(f, c, o, tau, lS, bl, dl, xcoarse, out);
   }
+  // chains of middle legs (2-D, one lane)
+  bool chain_ok(int lS) const { return Op::NB == 4 && lS == 0 && tn().mg_chain > 0; }
+  const cx<R>* lvl_dinv(int l) const { return l == 0 ? B.dinv : B.mdinv[l - 1]; }
+  MgChain<Op, R> chain_args(int a, int nl) const {
+    MgChain<Op, R> c{};
+    c.nl = nl;
+    for (int k = 0; k <= nl; ++k) {
+      c.d[k] = mg_dims(a + k);
+      c.dinv[k] = lvl_dinv(a + k);
+    }
+    for (int k = 0; k < nl; ++k) c.op[k] = mg_op<Op, R>(op, a + k);
+    return c;
+  }
+  // restrictions a -> a + nl: right-hand side of level a in, of levels a+1..a+nl out
+  void down_chain(int a, int nl, c128 tau, const cx<R>* bin) {
+    if constexpr (Op::NB == 4) {
+      MgChain<Op, R> c = chain_args(a, nl);
+      c.b[0] = bin;
+      for (int k = 1; k <= nl; ++k) c.out[k] = B.mb[a + k - 1];
+      const LevelDims d = c.d[nl];
+      const dim3 g((unsigned)((d.nx + 1) / 2), (unsigned)((d.ny + 1) / 2));
+      k_mg_down_chain2d<Op, R, 2><<<g, BS, 0, st>>>(c, tau, mg_omega, B.all_done);
+    }
+  }
+  // prolongations a + nl -> a: x of level a + nl in, x of level a out
+  void up_chain(int a, int nl, c128 tau, const cx<R>* b0, const cx<R>* xcoarse, cx<R>* xout) {
+    if constexpr (Op::NB == 4) {
+      MgChain<Op, R> c = chain_args(a, nl);
+      for (int k = 0; k < nl; ++k) c.b[k] = a + k == 0 ? b0 : B.mb[a + k - 1];
+      c.xc = xcoarse;
+      c.out[0] = xout;
+      const LevelDims d = c.d[0];
+      const dim3 g((unsigned)((d.nx + 15) / 16), (unsigned)((d.ny + 15) / 16));
+      k_mg_up_chain2d<Op, R, 16><<<g, BS, 0, st>>>(c, tau, mg_omega, B.all_done);
+    }
+  }
   void mg_vcycle(const cx<R>* b0, c128 tau, int lS, cx<R>* uout, int from = 0) {
     if constexpr (Op::NB > 0) {
       const int Lv = mg_levels();
@@ -1284,7 +1336,9 @@ template <typename R, typename Op, typename OpD> struct Group {
       const int t = mg_tail_level(lS);
       const int gdown = std::min(t, Lv - 1);   // levels whose down leg runs on the grid
       const cx<R>* bl = from > 0 ? B.mb[from - 1] : b0;
-      for (int l = from; l < gdown; ++l) {
+      // the last legs above the tail as one chain
+      const int dchain = chain_ok(lS) && gdown - from >= 2 ? std::min(MGC_F, gdown - from) : 0;
+      for (int l = from; l < gdown - dchain; ++l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];
         if (tile3_for(f)) {
@@ -1297,6 +1351,10 @@ template <typename R, typename Op, typename OpD> struct Group {
                                               B.all_done);
         }
         bl = B.mb[l];
+      }
+      if (dchain > 0) {
+        down_chain(gdown - dchain, dchain, tau, bl);
+        bl = B.mb[gdown - 1];
       }
       if (t < Lv) {
         cx<R>* xt = t == 0 ? uout : B.mx[t - 1];   // mg_ta, mg_lds: laid out by mg_prepare
@@ -1312,7 +1370,15 @@ template <typename R, typename Op, typename OpD> struct Group {
         k_mg_scale_grid<R><<<grid_items((long)S_, 8192), BS, 0, st>>>((long)mg_dims(l).n() << lS, lS,
                                                                        B.mdinv[l - 1], bl, B.mx[l - 1], B.all_done);
       }
-      for (int l = std::min(t, Lv - 1) - 1; l >= 0; --l) {
+      int ltop = std::min(t, Lv - 1) - 1;
+      // the first legs below the tail (not the finest) as one chain
+      if (chain_ok(lS) && ltop >= 2) {
+        const int nl = std::min(MGC_F, ltop);
+        const int a = ltop - nl + 1;
+        up_chain(a, nl, tau, b0, B.mx[a + nl - 1], a == 0 ? uout : B.mx[a - 1]);
+        ltop = a - 1;
+      }
+      for (int l = ltop; l >= 0; --l) {
         const LevelDims f = mg_dims(l), c = mg_dims(l + 1);
         const cx<R>* bl2 = l == 0 ? b0 : B.mb[l - 1];
         const cx<R>* dl = l == 0 ? B.dinv : B.mdinv[l - 1];

@@ -34,6 +34,9 @@ SETTINGS = [
     "tail_lds=16384,mg_fuse=0,cg_block=512",
     "tile3=1,tail_lds=16384",
     "tile3=1,tile3_zb=2,tile3_lt=8,tail_lds=4096",
+    "mg_chain=1",
+    "mg_chain=1,tail_lds=4096",
+    "asm_mfma=0",
 ]
 
 def _cached_picks():

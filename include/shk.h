@@ -468,6 +468,8 @@ int shk_profile_read_phases(double* ms, int n);
  *   mg_chain 0|1            2-D, one lane: up to 3 middle legs of each direction
  *                           of the V-cycle in one launch
  *   asm_mfma 0|1            solution assembly X = Z Y on the FP64 matrix cores
+ *   tile3_post 0|1          the product w = A u on the plane-marching tiles too
+ *   post3_lt 2|4            complex64 lanes per thread of that product
  *   tile3 >= 0              3-D levels with at least this many cells run the
  *                           plane-marching V-cycle legs (0: none)
  *   tile3_zb 2..64, even    planes per block of those legs

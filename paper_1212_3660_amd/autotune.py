@@ -47,6 +47,8 @@ SPACE = {
     "tile3_zb": [4, 8, 16],
     "tile3_lt": [4, 8],
     "mg_chain": [0, 1],
+    "tile3_post": [0, 1],
+    "asm_mfma": [0, 1],
 }
 
 
@@ -55,11 +57,11 @@ def knobs_for(key, n_lanes_real=None):
     precond)."""
     kind, n, lanes, prec, pc = key
     mixed = prec == B.SHK_MIXED
-    ks = ["cg_block", "graph"]
+    ks = ["cg_block", "graph", "asm_mfma"]
     if pc == B.SHK_PRECOND_MULTIGRID and kind in (0, 1):
         ks += ["tail_lds"]
         if kind == 1:
-            ks += ["tile3", "tile3_zb"] + (["tile3_lt"] if mixed else [])
+            ks += ["tile3", "tile3_zb"] + (["tile3_lt"] if mixed else []) + (["tile3_post"] if lanes > 1 else [])
         if lanes == 1:
             ks += ["mg_fuse"] + (["mg_chain"] if kind == 0 else [])
         elif mixed:

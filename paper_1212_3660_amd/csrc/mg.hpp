@@ -905,6 +905,138 @@ __global__ void __launch_bounds__(T3T) k_mg_leg_tile3(Op op, LevelDims f, LevelD
   }
 }
 
+// The product w = A u and the next iteration's forms (k_cgmg_post_lanes) on the
+// same plane-marching tiles: u of the tile and its ring in LDS per plane, u of
+// the planes below and above in registers.  Block partials of the forms go to
+// row (tile index) of partOut, lanes l0 .. l0 + LT - 1 of it written by the
+// block of that chunk, so the rows number the tiles (fewer than the one-cell
+// kernel's blocks; the fold of the partials is told how many).
+template <typename Op, typename R, int LT>
+__global__ void __launch_bounds__(T3T) k_cgmg_post_tile3(Op op, LevelDims f, c128 tau, int lS, int C, int ZB,
+                                                         const CgScal* __restrict__ sc,
+                                                         const cx<R>* __restrict__ r, const cx<R>* __restrict__ u,
+                                                         cx<R>* __restrict__ w, c128* __restrict__ partOut,
+                                                         const int* __restrict__ all_done) {
+  __shared__ cx<R> sh[T3Y + 2][T3X + 2][LT];
+  __shared__ c128 red[T3T / WAVE][3 * LT];
+  const int flag = *all_done;
+  int bxc, by, bz;
+  xcd_block3(bxc, by, bz);
+  const int ch = bxc % C, bx = bxc / C;
+  const int tx = (int)threadIdx.x % T3X, ty = (int)threadIdx.x / T3X;
+  const int i = bx * T3X + tx, j = by * T3Y + ty;
+  const bool own = i < f.nx && j < f.ny;
+  const int z0 = bz * ZB, z1 = min(z0 + ZB, f.nz);
+  int hx, hy;
+  tile3_ring((int)threadIdx.x, hx, hy);
+  const int hi = bx * T3X + hx, hj = by * T3Y + hy;
+  const bool ring = hx > -2 && hi >= 0 && hi < f.nx && hj >= 0 && hj < f.ny;
+  const cx<R> tr = cvt<R>(tau);
+  const int l0 = ch * LT;
+  const int plane = f.nx * f.ny;
+  bool live[LT];
+#pragma unroll
+  for (int l = 0; l < LT; ++l) live[l] = !sc[l0 + l].done;
+  auto load = [&](int c, cx<R> (&o)[LT]) {
+    const long bb = ((long)c << lS) + l0;
+#pragma unroll
+    for (int l = 0; l < LT; ++l) o[l] = u[bb + l];
+  };
+  auto zero = [](cx<R> (&o)[LT]) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) o[l] = cx<R>{0, 0};
+  };
+  c128 acc[3][LT];
+#pragma unroll
+  for (int l = 0; l < LT; ++l) acc[0][l] = acc[1][l] = acc[2][l] = c128{0.0, 0.0};
+  cx<R> up_[LT], uc[LT], un[LT], hu[LT], hv[LT];
+  zero(up_);
+  zero(uc);
+  zero(hu);
+  const int c0 = i + f.nx * j;
+  if (ring) load(hi + f.nx * (hj + f.ny * z0), hu);
+  if (own) {
+    if (z0 > 0) load(c0 + plane * (z0 - 1), up_);
+    load(c0 + plane * z0, uc);
+  }
+  for (int k = z0; k < z1; ++k) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) hv[l] = hu[l];
+    if (ring && k + 1 < z1) load(hi + f.nx * (hj + f.ny * (k + 1)), hu);
+    const bool up_in = own && k + 1 < f.nz;
+    zero(un);
+    if (up_in) load(c0 + plane * (k + 1), un);
+    const int c = c0 + plane * k;
+    int idx[Op::NB];
+    R fo[Op::NB];
+    R fsum = 0, m = 0;
+    cx<R> rr[LT];
+    zero(rr);
+    if (own) {
+      op.template stencil_at<R>(i, j, k, c, idx, fo, fsum);
+      m = (R)op.mass(c);
+      const long bb = ((long)c << lS) + l0;
+#pragma unroll
+      for (int l = 0; l < LT; ++l) rr[l] = r[bb + l];
+    }
+    __syncthreads();   // the previous plane's reads of sh are done
+#pragma unroll
+    for (int l = 0; l < LT; ++l) sh[ty + 1][tx + 1][l] = uc[l];
+    if (hx > -2) {
+#pragma unroll
+      for (int l = 0; l < LT; ++l) sh[hy + 1][hx + 1][l] = hv[l];
+    }
+    __syncthreads();
+    if (own && !flag) {
+      cx<R> ww[LT];
+#pragma unroll
+      for (int l = 0; l < LT; ++l) {
+        ww[l] = fsum * uc[l] + m * (tr * uc[l]);
+        ww[l] = ww[l] - fo[0] * sh[ty + 1][tx][l];
+        ww[l] = ww[l] - fo[1] * sh[ty + 1][tx + 2][l];
+        ww[l] = ww[l] - fo[2] * sh[ty][tx + 1][l];
+        ww[l] = ww[l] - fo[3] * sh[ty + 2][tx + 1][l];
+        ww[l] = ww[l] - fo[4] * up_[l];
+        ww[l] = ww[l] - fo[5] * un[l];
+      }
+      const long bb = ((long)c << lS) + l0;
+#pragma unroll
+      for (int l = 0; l < LT; ++l) {
+        if (!live[l]) continue;
+        w[bb + l] = ww[l];
+        const c128 rd = cvt<double>(rr[l]), ud = cvt<double>(uc[l]);
+        acc[0][l] = acc[0][l] + rd * ud;
+        acc[1][l] = acc[1][l] + cvt<double>(ww[l]) * ud;
+        acc[2][l].re += abs2(rd);
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+      up_[l] = uc[l];
+      uc[l] = un[l];
+    }
+  }
+  if (flag) return;
+  // block partials: a wave sum per (form, lane), then the waves in order
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+      const c128 v = wave_sum_strided(acc[q][l], 1);
+      if (lane == 0) red[wv][q * LT + l] = v;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < 3 * LT) {
+    const int e = threadIdx.x, q = e / LT, l = e - q * LT;
+    c128 a = red[0][e];
+    for (int v = 1; v < T3T / WAVE; ++v) a = a + red[v][e];
+    const int gxt = (int)gridDim.x / C;
+    const long tile = bx + (long)gxt * (by + (long)gridDim.y * bz);
+    partOut[(tile * 3 + q) * (1 << lS) + l0 + l] = a;
+  }
+}
+
 // The coarse end of the V-cycle in one workgroup: levels t..L-1 (right-hand
 // side of level t from global memory, solution of level t back to it), every
 // level's b and x in LDS, a barrier between legs.  Saves two launches per

@@ -393,6 +393,8 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 //  mg_chain    2-D, one lane: up to 3 middle legs of each V-cycle direction in
 //              one launch
 //  asm_mfma    solution assembly X = Z Y on the FP64 matrix cores
+//  tile3_post, post3_lt   3-D, several lanes, finest level plane-marching: the
+//              product w = A u on the same tiles, post3_lt complex64 lanes per thread
 //  tile3, tile3_zb, tile3_lt   3-D levels of at least tile3 cells: plane-
 //              marching grid legs, tile3_zb planes per block, tile3_lt complex64
 //              lanes per thread
@@ -416,6 +418,8 @@ struct Tune {
   int tile3_lt = 4;   // complex64 lanes per thread of those legs (4 or 8)
   int mg_chain = 0;   // 2-D one-lane V-cycle: chain up to 3 middle legs per launch
   int asm_mfma = 1;   // solution assembly on the FP64 matrix cores
+  int tile3_post = 0; // the product w = A u on the plane-marching tiles too (3-D, several lanes)
+  int post3_lt = 2;   // complex64 lanes per thread of that product (2 or 4)
 
   // Sets a knob by name; false for an unknown name or a value out of range.
   bool set(const std::string& k, double v) {
@@ -443,6 +447,8 @@ struct Tune {
     else if (k == "tile3_lt") { if (iv != 2 && iv != 4 && iv != 8) return false; tile3_lt = iv; }
     else if (k == "mg_chain") { if (iv < 0 || iv > 1) return false; mg_chain = iv; }
     else if (k == "asm_mfma") { asm_mfma = iv != 0; }
+    else if (k == "tile3_post") { tile3_post = iv != 0; }
+    else if (k == "post3_lt") { if (iv != 2 && iv != 4) return false; post3_lt = iv; }
     else return false;
     return true;
   }
@@ -468,6 +474,8 @@ struct Tune {
     else if (k == "tile3_lt") *v = tile3_lt;
     else if (k == "mg_chain") *v = mg_chain;
     else if (k == "asm_mfma") *v = asm_mfma;
+    else if (k == "tile3_post") *v = tile3_post;
+    else if (k == "post3_lt") *v = post3_lt;
     else return false;
     return true;
   }
@@ -1395,6 +1403,27 @@ template <typename R, typename Op, typename OpD> struct Group {
       }
     }
   }
+  // The product on the plane-marching tiles (3-D, several lanes, separate fold
+  // of the partials); Gpost = the partial rows it writes.
+  int Gpost = 0;
+  bool post_tile3(c128 tau, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
+    if constexpr (Op::NB == 6) {
+      const LevelDims f = mg_dims(0);
+      if (!tn().tile3_post || !tile3_for(f) || !gp.separate || lS == 0) return false;
+      const int lt = std::min(1 << lS, c64 ? tn().post3_lt : 2);
+      const int C = (1 << lS) / lt, ZB = tn().tile3_zb;
+      const int gx = (f.nx + T3X - 1) / T3X, gy = (f.ny + T3Y - 1) / T3Y, gz = (f.nz + ZB - 1) / ZB;
+      if ((long)gx * gy * gz > gp.G) return false;   // the partial rows must fit
+      Gpost = gx * gy * gz;
+      const dim3 g((unsigned)(gx * C), (unsigned)gy, (unsigned)gz);
+      if (lt == 2)
+        k_cgmg_post_tile3<Op, R, 2><<<g, T3T, 0, st>>>(op, f, tau, lS, C, ZB, sc, r, B.u, w, out, B.all_done);
+      else if (lt == 4)
+        k_cgmg_post_tile3<Op, R, 4><<<g, T3T, 0, st>>>(op, f, tau, lS, C, ZB, sc, r, B.u, w, out, B.all_done);
+      return true;
+    }
+    return false;
+  }
   // w = A u and the forms with r, on the iteration kernels' grid
   // Several lanes: a thread per cell and chunk of lanes.
   template <int CGB>
@@ -1427,6 +1456,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
   }
   void mg_post(int G, c128 tau, int ni, int lS, const CgScal* sc, const cx<R>* r, cx<R>* w, c128* out) {
+    if (post_tile3(tau, lS, sc, r, w, out)) return;
     if (tn().cgb == 512) mg_post_cgb<512>(G, tau, ni, lS, sc, r, w, out);
     else mg_post_cgb<256>(G, tau, ni, lS, sc, r, w, out);
   }
@@ -1455,7 +1485,8 @@ template <typename R, typename Op, typename OpD> struct Group {
                                                                     scOut, vec, par, B.all_done);
         mg_vcycle(vec.r[par ^ 1], tau, lS, B.u);
       }
-      if (!mg_post_lanes<CGB>(G, tau, ni, lS, scOut, vec.r[par ^ 1], vec.w[par ^ 1], out))
+      if (!post_tile3(tau, lS, scOut, vec.r[par ^ 1], vec.w[par ^ 1], out) &&
+          !mg_post_lanes<CGB>(G, tau, ni, lS, scOut, vec.r[par ^ 1], vec.w[par ^ 1], out))
         k_cgmg_post<Op, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(op, tau, ni, lS, scOut, vec.r[par ^ 1], B.u,
                                                                vec.w[par ^ 1], out, B.all_done);
     }
@@ -1504,7 +1535,8 @@ template <typename R, typename Op, typename OpD> struct Group {
     // partials of launch L live in cpart[L & 1] (totals in ctot[L & 1])
     auto totals = [&](int slot) -> const c128* {
       if (!gp.separate) return B.cpart[slot];
-      k_lane_totals<3><<<lane_totals_grid(3 * S), BS, 0, st>>>(B.cpart[slot], G, S, B.ctot[slot]);
+      k_lane_totals<3><<<lane_totals_grid(3 * S), BS, 0, st>>>(B.cpart[slot], Gpost > 0 ? Gpost : G, S,
+                                                              B.ctot[slot]);
       return B.ctot[slot];
     };
     const int Gin = gp.separate ? 1 : G;

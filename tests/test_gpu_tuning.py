@@ -33,7 +33,8 @@ SETTINGS = [
     "tail_lds=162816",
     "tail_lds=16384,mg_fuse=0,cg_block=512",
     "tile3=1,tail_lds=16384",
-    "tile3=1,tile3_zb=2,tile3_lt=8,tail_lds=4096",
+    "tile3=1,tile3_zb=2,tile3_lt=8,tile3_post=1,post3_lt=4,tail_lds=4096",
+    "tile3=1,tile3_post=1",
     "mg_chain=1",
     "mg_chain=1,tail_lds=4096",
     "asm_mfma=0",

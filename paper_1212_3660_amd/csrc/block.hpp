@@ -45,10 +45,12 @@ template <typename T> __device__ __forceinline__ int mfma_row(int g, int v) {
 // per lane a product of the n x kc block Z_r of its basis columns and the
 // kc x nf block of its coefficients.  A wave computes 16 cells x 16 TN shifts
 // of one lane (TN output tiles, complex as four real products per step of 4
-// basis columns); the waves of a block take consecutive (cell tile, lane)
-// pairs, lanes fastest, so a block reads adjacent lanes' pieces of the same
-// cells.  Z is read once per 16 TN shifts and X written once.  FP64
-// accumulation (the order over the basis columns is the matrix core's).
+// basis columns); a block's 4 waves take 4 adjacent lanes of one tile of 16
+// cells, and the blocks of the other lanes of that tile sit 8 block indices
+// apart, on the same XCD (workgroups go to the XCDs round-robin), so the
+// basis rows of a tile come into one L2 only.  Z is read once per 16 TN
+// shifts and X written once.  FP64 accumulation (the order over the basis
+// columns is the matrix core's).
 template <typename R, int TN>
 __global__ void __launch_bounds__(256) k_assemble_mfma(long n, int S, int s_real, int nf, int kc, int m,
                                                        const cx<R>* __restrict__ Z, size_t cstride,
@@ -56,9 +58,24 @@ __global__ void __launch_bounds__(256) k_assemble_mfma(long n, int S, int s_real
                                                        const c128* __restrict__ ascale, c128* __restrict__ X,
                                                        int acc) {
   const int lane = threadIdx.x & 63, g = lane >> 4, mm = lane & 15;
-  const long q = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int r = (int)(q % S);
-  const long cell0 = (q / S) * 16;
+  // block -> (tile of 16 cells, group of 4 lanes): groups of 8 tiles x LG lane
+  // groups, the tile's XCD slot fastest (fewer than 4 lanes: 4 / S tiles per
+  // block)
+  long tile;
+  int r;
+  if (S >= 4) {
+    const int LG = S >> 2;
+    const long b = blockIdx.x, per = 8L * LG;
+    const long grp = b / per;
+    const int rem = (int)(b - grp * per);
+    tile = grp * 8 + (rem & 7);
+    r = (rem >> 3) * 4 + (int)(threadIdx.x >> 6);
+  } else {
+    const long qq = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    tile = qq / S;
+    r = (int)(qq % S);
+  }
+  const long cell0 = tile * 16;
   if (cell0 >= n || r >= s_real) return;   // whole waves
   const int j0 = (int)blockIdx.y * 16 * TN;
   d4m re[TN], im[TN];

@@ -709,9 +709,11 @@ static void launch_assemble(long n, int S, int s_real, int nf, int kc, int m, co
                             c128* Yt = nullptr) {
   const long N = n * S;
   if (tn().asm_mfma) {
-    // matrix cores: a wave per (16 cells, lane, 64 shifts)
-    const long pairs = (n + 15) / 16 * S;
-    const dim3 grid((unsigned)((pairs + 3) / 4), (unsigned)((nf + 63) / 64));
+    // matrix cores: a wave per (16 cells, lane, 64 shifts); with 4 lanes or
+    // more the tiles go in groups of 8 (one per XCD slot) x S/4 lane groups
+    const long tiles = (n + 15) / 16;
+    const long blocks = S >= 4 ? (tiles + 7) / 8 * 8 * (S / 4) : (tiles * S + 3) / 4;
+    const dim3 grid((unsigned)blocks, (unsigned)((nf + 63) / 64));
     k_assemble_mfma<R, 4><<<grid, 256, 0, st>>>(n, S, s_real, nf, kc, m, Z, cstride, Yb, ascale, X, acc);
     return;
   }

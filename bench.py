@@ -575,7 +575,9 @@ def run(a):
     # inside the timed region; no single launch of it dominates.
     roof = roofline(mixed["prof"], "traffic_mg_iteration_512x512.json",
                     "multigrid-COCG inner iteration, mixed path: k_cgmg_step_down (step fused with the finest "
-                    "restriction), k_mg_down x3, k_mg_tail, k_mg_up x4, k_cgmg_post (10 launches)", "iteration")
+                    "restriction), the middle restrictions (k_mg_down_chain2d), k_mg_tail, the middle "
+                    "prolongations (k_mg_up_chain2d), the finest k_mg_up, k_cgmg_post (6 launches; 10 without "
+                    "the chains)", "iteration")
     roof_jac = roofline(jac["mixed"]["prof"], "traffic_cg_step_512x512.json",
                         "k_cg_step<Op2D<float>, float, ...> (Jacobi-COCG iteration, mixed path)", "launch")
     out = {"metric": METRIC, "value": round(value, 2), "unit": "shifted solves/s", "n_gpus": 1,

@@ -133,7 +133,7 @@ def test_mg_tail_two_levels_down(shape, S):
         assert true <= 1e-6 * np.linalg.norm(V32[:, r]) * 1.01
 
 
-@pytest.mark.parametrize("shape,S", [((40, 36), 8), ((24, 20), 16), ((12, 10, 9), 4)])
+@pytest.mark.parametrize("shape,S", [((40, 36), 8), ((24, 20), 16), ((12, 10, 9), 4), ((24, 20, 18), 8)])
 def test_mg_complex64_lanes_iterates(shape, S):
     """Complex64 path with several lanes (grid legs and product working chunks
     of lanes per thread): fixed iteration counts against the oracle's FP64

@@ -70,4 +70,4 @@ def test_tuning_settings(tune):
            "--timeout-method", "thread", "--shk-tune", tune] + TESTS
     r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-2000:]
-    assert "13 passed" in r.stdout, r.stdout[-2000:]
+    assert "14 passed" in r.stdout, r.stdout[-2000:]

@@ -459,7 +459,11 @@ int shk_profile_read_phases(double* ms, int n);
  *                           (Jacobi / multigrid inner preconditioner)
  *   stall_min, stall_mult >= 0  a round ends after max(min, mult x its
  *                           productive length) iterations without halving
- *   tail_lds                LDS bytes of the V-cycle's one-workgroup tail
+ *   tail_lds                LDS bytes of a workgroup of the V-cycle's tail
+ *   tail_lanes 0|1|2|..|64  lanes per tail workgroup (default 1; 0: all in
+ *                           one): the lanes are split over workgroups and the
+ *                           tail starts at the finest level where the coarser
+ *                           levels of that many lanes fit
  *   mg_fuse 0|1             step fused with the finest restriction
  *   post_lt, down_lt, up_lt 2|4|8  lanes per thread (complex64, several lanes)
  *   lt64 0|2|4              lanes per thread on complex128

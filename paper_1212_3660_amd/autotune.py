@@ -4,8 +4,8 @@ A workload class is the key of the library's tuning table (shk_tune_class):
 operator kind, unknowns, lane count, precision and inner preconditioner.  For
 one representative solve of a class the tuner runs a coordinate search over
 the knobs that apply to it (lanes per thread of the multigrid legs, the LDS
-budget of the V-cycle's one-workgroup tail, the fused first restriction, the
-iteration block size, the complex64 round tolerance, graph-captured
+budget of the V-cycle's coarse tail and its lanes per workgroup, the fused
+first restriction, the iteration block size, the complex64 round tolerance, graph-captured
 iterations) and, when asked, over the restart length: each candidate is timed
 as whole solves on the device (median of several, after an untimed one), and
 a candidate counts only when every (shift, rhs) pair converges to the
@@ -32,6 +32,7 @@ KINDS = {0: "2-D finite volume", 1: "3-D finite volume", 2: "CSR"}
 # knob -> candidate values, searched in this order
 SPACE = {
     "tail_lds": [16384, 32768, 64512, 98304, 162816],
+    "tail_lanes": [0, 1, 2, 4, 8],
     "mg_fuse": [0, 1],
     "post_lt": [0, 2, 4, 8],
     "down_lt": [2, 4, 8],
@@ -59,7 +60,7 @@ def knobs_for(key, n_lanes_real=None):
     mixed = prec == B.SHK_MIXED
     ks = ["cg_block", "graph", "asm_mfma"]
     if pc == B.SHK_PRECOND_MULTIGRID and kind in (0, 1):
-        ks += ["tail_lds"]
+        ks += ["tail_lds"] + (["tail_lanes"] if lanes > 1 else [])
         if kind == 1:
             ks += ["tile3", "tile3_zb"] + (["tile3_lt"] if mixed else []) + (["tile3_post"] if lanes > 1 else [])
         if lanes == 1:

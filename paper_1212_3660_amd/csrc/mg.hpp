@@ -1091,8 +1091,11 @@ __global__ void __launch_bounds__(BS) k_mg_pack(MgPack p, unsigned* __restrict__
   }
 }
 
+// Lanes are independent systems: the launch may split them over 2^(lSg - lS)
+// workgroups, workgroup g taking lanes g 2^lS .. (g + 1) 2^lS - 1 of the 2^lSg
+// that btop and xtop interleave (lS: lanes per workgroup, the layout in LDS).
 template <typename Op, typename R, int CAP>
-__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau, double omega, int lS,
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau, double omega, int lS, int lSg,
                                                              const unsigned* __restrict__ pack,
                                                              const cx<R>* __restrict__ btop, cx<R>* __restrict__ xtop,
                                                              const int* __restrict__ all_done) {
@@ -1108,6 +1111,9 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
   const int tid = threadIdx.x;
   const int T = a.T;
   const int n0 = (a.lv[0].nx * a.lv[0].ny * a.lv[0].nz) << lS;
+  // element j of the workgroup's top level in the interleaved global arrays
+  const int g0 = (int)blockIdx.x << lS, lmask = (1 << lS) - 1;
+  auto gidx = [&](int j) { return ((j >> lS) << lSg) + g0 + (j & lmask); };
   {
     // every global load of the kernel is issued here, at once: the level
     // table, the packed coefficients and the top right-hand side
@@ -1122,7 +1128,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
 #pragma unroll
     for (int k = 0; k < NB0; ++k) {
       const int j = tid + k * MG_TAIL_THREADS;
-      bv[k] = j < n0 ? btop[j] : cx<R>{0, 0};
+      bv[k] = j < n0 ? btop[gidx(j)] : cx<R>{0, 0};
     }
     if (tid < NP) reinterpret_cast<int*>(lv)[tid] = pw0;
     unsigned* pw = reinterpret_cast<unsigned*>(lds_raw + a.pack_lds);
@@ -1217,7 +1223,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
     }
     __syncthreads();
   }
-  for (int j = tid; j < n0; j += nth) xtop[j] = sh[n0 + j];
+  for (int j = tid; j < n0; j += nth) xtop[gidx(j)] = sh[n0 + j];
 }
 
 // The coarsest level solved on the grid (only when even its lanes exceed the

@@ -386,6 +386,9 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 //  round_tol   complex64 inner rounds: reduction per round (Jacobi / multigrid)
 //  stall_*     stall rule of a round (no halving for max(min, mult x length))
 //  tail_lds    LDS budget of the V-cycle's one-workgroup tail
+//  tail_lanes  lanes per workgroup of that tail (0: all; else the lanes are
+//              split over several workgroups, and the tail starts where the
+//              levels of that many lanes fit)
 //  mg_fuse     step fused with the finest restriction where it applies
 //  post_lt, down_lt, up_lt   lanes per thread of the product and grid legs
 //              (complex64, several lanes); lt64 the same on complex128
@@ -408,6 +411,7 @@ struct Tune {
   double round_tol_mg = 1e-3;
   int stall_min = 150, stall_mult = 3;
   int tail_lds = MG_TAIL_LDS;
+  int tail_lanes = 1;  // lanes per tail workgroup (0: all lanes in one)
   int mg_fuse = 1;
   int post_lt = 2;
   int down_lt = 4, up_lt = 4;
@@ -436,6 +440,7 @@ struct Tune {
     else if (k == "stall_min") { if (iv < 0) return false; stall_min = iv; }
     else if (k == "stall_mult") { if (iv < 0) return false; stall_mult = iv; }
     else if (k == "tail_lds") { if (iv < 0 || iv > MG_TAIL_LDS_MAX) return false; tail_lds = iv; }
+    else if (k == "tail_lanes") { if (iv < 0 || iv > 64 || (iv & (iv - 1))) return false; tail_lanes = iv; }
     else if (k == "mg_fuse") { mg_fuse = iv != 0; }
     else if (k == "post_lt") { post_lt = iv >= 8 ? 8 : iv >= 4 ? 4 : iv >= 2 ? 2 : 0; }
     else if (k == "down_lt") { down_lt = chunk(iv); }
@@ -463,6 +468,7 @@ struct Tune {
     else if (k == "stall_min") *v = stall_min;
     else if (k == "stall_mult") *v = stall_mult;
     else if (k == "tail_lds") *v = tail_lds;
+    else if (k == "tail_lanes") *v = tail_lanes;
     else if (k == "mg_fuse") *v = mg_fuse;
     else if (k == "post_lt") *v = post_lt;
     else if (k == "down_lt") *v = down_lt;
@@ -1157,7 +1163,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       const int t = mg_tail_level(ilog2(S));
       if (t < mg_levels()) {
         MgPack pk;
-        mg_tail_layout(t, ilog2(S), mg_ta, pk, mg_lds);
+        mg_tail_layout(t, tail_lg(ilog2(S)), mg_ta, pk, mg_lds);
         k_mg_pack<<<pk.nseg, BS, 0, st>>>(pk, B.mpack);
       }
     }
@@ -1184,13 +1190,18 @@ template <typename R, typename Op, typename OpD> struct Group {
     return align16(vec) + pack;
   }
   static size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
-  // First level of the one-workgroup tail: the finest level from which all
-  // coarser levels fit in the tail's LDS.
+  // log2 of the lanes one tail workgroup takes, for 2^lS lanes in all.
+  static int tail_lg(int lS) {
+    const int tl = tn().tail_lanes;
+    return tl > 0 ? std::min(lS, ilog2(tl)) : lS;
+  }
+  // First level of the tail: the finest level from which all coarser levels
+  // of one tail workgroup's lanes fit in its LDS.
   int mg_tail_level(int lS) const {
-    const int Lv = mg_levels();
+    const int Lv = mg_levels(), lg = tail_lg(lS);
     int t = Lv;
     for (int l = Lv - 1; l >= 0; --l) {
-      if (mg_tail_bytes(l, lS) > (size_t)tn().tail_lds || Lv - l > MG_MAXL) break;
+      if (mg_tail_bytes(l, lg) > (size_t)tn().tail_lds || Lv - l > MG_MAXL) break;
       t = l;
     }
     return t;   // Lv: not even the one-cell level fits (many lanes)
@@ -1368,12 +1379,14 @@ template <typename R, typename Op, typename OpD> struct Group {
       }
       if (t < Lv) {
         cx<R>* xt = t == 0 ? uout : B.mx[t - 1];   // mg_ta, mg_lds: laid out by mg_prepare
+        const int lg = tail_lg(lS);
+        const unsigned gt = 1u << (lS - lg);
         if (mg_lds > MG_TAIL_LDS)
-          k_mg_tail<Op, R, MG_TAIL_LDS_MAX><<<1, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lS,
-                                                                                        B.mpack, bl, xt, B.all_done);
+          k_mg_tail<Op, R, MG_TAIL_LDS_MAX><<<gt, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(
+              mg_ta, tau, mg_omega, lg, lS, B.mpack, bl, xt, B.all_done);
         else
-          k_mg_tail<Op, R, MG_TAIL_LDS><<<1, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lS, B.mpack, bl, xt,
-                                                                     B.all_done);
+          k_mg_tail<Op, R, MG_TAIL_LDS><<<gt, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lg, lS,
+                                                                                   B.mpack, bl, xt, B.all_done);
       } else {
         // the coarsest level alone exceeds the tail: solve it on the grid
         const int l = Lv - 1;

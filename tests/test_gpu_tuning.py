@@ -38,6 +38,9 @@ SETTINGS = [
     "mg_chain=1",
     "mg_chain=1,tail_lds=4096",
     "asm_mfma=0",
+    "tail_lanes=0",
+    "tail_lanes=2,tail_lds=162816",
+    "tail_lanes=4,tail_lds=16384",
 ]
 
 def _cached_picks():

@@ -359,9 +359,11 @@ __global__ void k_set_cfg(CgCfg* __restrict__ d, CgCfg c) {
 }
 
 // Per-lane state of the inner solve (kept small: a single-lane launch holds it
-// in scalar registers).
+// in scalar registers; the flags fill one whole dword, as the scalar loads
+// that fetch the state need).
 struct CgScal {
   c128 gamma, alpha, beta;
+  c128 apend;        // multigrid path: coefficient of a deferred x += apend p
   double vnorm, rnorm, rstop;
   double rn0;        // residual norm at the start of the current round
   double rbest;      // best residual of the round, halving by halving
@@ -369,6 +371,7 @@ struct CgScal {
   int its0;          // iteration count at the start of the current round
   int its_best;      // iteration at which rbest was reached
   int rounds;        // rounds started
+  int pend;          // 1: x lacks apend p (p as stored now)
   signed char done, conv;
   signed char mode;  // CgMode of the launch that produced this state
   signed char kick;  // 1: a Jacobi step was taken for the current round

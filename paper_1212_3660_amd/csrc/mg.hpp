@@ -427,6 +427,178 @@ __global__ void __launch_bounds__(BS) k_mg_up_lanes(Op op, LevelDims f, LevelDim
   }
 }
 
+// One cell's inputs of the smoothed value: b, D^-1 and (on the way up) x_c of
+// its parent.
+template <typename R, int LT, bool UP> struct Tile3Raw {
+  cx<R> b[LT];
+  cx<R> x[UP ? LT : 1];
+  cx<R> d;
+};
+
+// ------------------------------------------ 2-D legs, marching the rows ----
+// The two legs of a 2-D level for several lanes with every input read once:
+// a block owns a segment of SW = BS / 2^lNC cells of a row (a thread per cell
+// and chunk of LT lanes, chunks fastest, so a row segment's lanes are one
+// contiguous run) and marches through YB rows.  On each row the block forms
+// the smoothed value x1 (omega D^-1 b, plus the prolongated coarse solution
+// on the way up) of its cells and of the segment's two end neighbours once,
+// in LDS; the x neighbours of the stencil come from there, the y neighbours
+// from the thread's registers (its cell's x1 on the rows below and above).
+// The one-cell kernels read every lane chunk once per stencil point.  Same
+// arithmetic per lane as k_mg_down_lanes / k_mg_up_lanes, and the same
+// children order on the way down (the x pair of each row, then the rows).
+// Needs 2^lNC <= 32 and even YB; launched on G = ceil(nx / SW) ceil(ny / YB)
+// blocks, block b taking tile xcd_tile(b, G) (segment fastest).
+template <typename Op, typename R, int LT, bool UP>
+__global__ void __launch_bounds__(BS) k_mg_leg_rows(Op op, LevelDims f, LevelDims cd, c128 tau, double omega,
+                                                    int lS, int lNC, int YB, const cx<R>* __restrict__ b,
+                                                    const cx<R>* __restrict__ dinv, const cx<R>* __restrict__ xc,
+                                                    cx<R>* __restrict__ out, const int* __restrict__ all_done) {
+  static_assert(Op::NB == 4, "2-D operator");
+  __shared__ cx<R> xs[2][BS * LT + 2 * 64];   // x1 of a row: (SW + 2) cells x S lanes, double-buffered
+  const int flag = *all_done;
+  const int NC = 1 << lNC, S = 1 << lS, SW = BS >> lNC;
+  const int nseg = (f.nx + SW - 1) / SW;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int seg = tile % nseg, rb = tile / nseg;
+  const int lc = (int)threadIdx.x & (NC - 1), ci = (int)threadIdx.x >> lNC;
+  const int i = seg * SW + ci;
+  const bool own = i < f.nx;
+  // the segment's end neighbours: threads 0 .. 2 NC - 1, left then right
+  const int hs = (int)threadIdx.x >> lNC;
+  const bool hal = (int)threadIdx.x < 2 * NC;
+  const int hi = hs == 0 ? seg * SW - 1 : seg * SW + SW;
+  const bool hin = hal && hi >= 0 && hi < f.nx;
+  const int j0 = rb * YB, j1 = min(j0 + YB, f.ny);
+  const cx<R> tr = cvt<R>(tau);
+  const R om = (R)omega;
+  const int l0 = lc * LT;
+  using Raw = Tile3Raw<R, LT, UP>;
+  auto load = [&](int ci_, int cj, Raw& r) {
+    const int c = ci_ + f.nx * cj;
+    r.d = dinv[c];
+    const long bb = ((long)c << lS) + l0;
+#pragma unroll
+    for (int l = 0; l < LT; ++l) r.b[l] = b[bb + l];
+    if constexpr (UP) {
+      const long pb = ((long)((ci_ >> 1) + cd.nx * (cj >> 1)) << lS) + l0;
+#pragma unroll
+      for (int l = 0; l < LT; ++l) r.x[l] = xc[pb + l];
+    }
+  };
+  auto smooth = [&](const Raw& r, cx<R> (&o)[LT]) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+      if constexpr (UP) o[l] = om * (r.d * r.b[l]) + r.x[l];
+      else o[l] = om * (r.d * r.b[l]);
+    }
+  };
+  auto zero = [](cx<R> (&o)[LT]) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) o[l] = cx<R>{0, 0};
+  };
+  cx<R> xp[LT], xcur[LT], xn[LT], bcur[LT], hv[LT], acc[LT];
+  cx<R> dcur{0, 0};
+  Raw rn, hr;
+  zero(xp);
+  zero(xcur);
+  zero(bcur);
+  zero(acc);
+  if (hin && j0 < j1) load(hi, j0, hr);
+  if (own && j0 < j1) {
+    if (j0 > 0) {
+      load(i, j0 - 1, rn);
+      smooth(rn, xp);
+    }
+    load(i, j0, rn);
+    smooth(rn, xcur);
+#pragma unroll
+    for (int l = 0; l < LT; ++l) bcur[l] = rn.b[l];
+    dcur = rn.d;
+  }
+  const int own_slot = (ci + 1) * S + l0;
+  const int hal_slot = (hs == 0 ? 0 : (SW + 1) * S) + l0;
+  int buf = 0;
+  for (int j = j0; j < j1; ++j) {
+    // this row's end neighbours (inputs loaded on the previous step), then
+    // the loads this step and the next need, issued together
+    zero(hv);
+    if (hin) smooth(hr, hv);
+    if (hin && j + 1 < j1) load(hi, j + 1, hr);
+    const bool up_in = own && j + 1 < f.ny;
+    if (up_in) load(i, j + 1, rn);
+    const int c = i + f.nx * j;
+    int idx[4];
+    R fo[4];
+    R fsum = 0;
+    R m = 0;
+    if (own) {
+      op.template stencil_at<R>(i, j, 0, c, idx, fo, fsum);
+      m = (R)op.mass(c);
+    }
+    cx<R>* row = xs[buf];
+#pragma unroll
+    for (int l = 0; l < LT; ++l) row[own_slot + l] = xcur[l];   // zeros past the grid's end
+    if (hal) {
+#pragma unroll
+      for (int l = 0; l < LT; ++l) row[hal_slot + l] = hv[l];
+    }
+    __syncthreads();   // one barrier a row: the buffers alternate
+    zero(xn);
+    if (up_in) smooth(rn, xn);
+    cx<R> v[LT];
+    zero(v);
+    if (own) {
+#pragma unroll
+      for (int l = 0; l < LT; ++l) {
+        const cx<R> xi = xcur[l];
+        cx<R> ax = fsum * xi + m * (tr * xi);
+        ax = ax - fo[0] * row[own_slot - S + l];
+        ax = ax - fo[1] * row[own_slot + S + l];
+        ax = ax - fo[2] * xp[l];
+        ax = ax - fo[3] * xn[l];
+        if constexpr (UP) v[l] = xi + om * (dcur * (bcur[l] - ax));
+        else v[l] = bcur[l] - ax;
+      }
+    }
+    if constexpr (UP) {
+      int fl = flag;
+      hold(v[0], fl);
+      if (own && !fl) {
+        cx<R>* o = out + ((long)c << lS) + l0;
+#pragma unroll
+        for (int l = 0; l < LT; ++l) o[l] = v[l];
+      }
+    } else {
+      // the x pair of children on this row (2^lNC lanes apart), then the rows
+#pragma unroll
+      for (int l = 0; l < LT; ++l) {
+        v[l].re += __shfl_xor(v[l].re, NC);
+        v[l].im += __shfl_xor(v[l].im, NC);
+        acc[l] = (j & 1) ? acc[l] + v[l] : v[l];
+      }
+      if ((j & 1) || j + 1 == f.ny) {
+        const int I = i >> 1, J = j >> 1;
+        int fl = flag;
+        hold(acc[0], fl);
+        if (!(ci & 1) && I < cd.nx && !fl) {
+          cx<R>* o = out + ((long)(I + cd.nx * J) << lS) + l0;
+#pragma unroll
+          for (int l = 0; l < LT; ++l) o[l] = acc[l];
+        }
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < LT; ++l) {
+      xp[l] = xcur[l];
+      xcur[l] = xn[l];
+      if (up_in) bcur[l] = rn.b[l];
+    }
+    if (up_in) dcur = rn.d;
+    buf ^= 1;
+  }
+}
+
 // ------------------------------------------------ 2-D chains of legs ------
 // Several consecutive grid legs of a single-lane 2-D V-cycle in one launch,
 // for the middle levels whose one-leg launches are latency-bound: each block
@@ -738,14 +910,6 @@ __device__ __forceinline__ void tile3_ring(int t, int& hx, int& hy) {
   else if (t < 2 * T3X + T3Y) { hx = -1; hy = t - 2 * T3X; }
   else { hx = T3X; hy = t - 2 * T3X - T3Y; }
 }
-
-// One cell's inputs of the smoothed value: b, D^-1 and (on the way up) x_c of
-// its parent.
-template <typename R, int LT, bool UP> struct Tile3Raw {
-  cx<R> b[LT];
-  cx<R> x[UP ? LT : 1];
-  cx<R> d;
-};
 
 template <typename Op, typename R, int LT, bool UP>
 __global__ void __launch_bounds__(T3T) k_mg_leg_tile3(Op op, LevelDims f, LevelDims cd, c128 tau, double omega,
@@ -1237,13 +1401,49 @@ __global__ void __launch_bounds__(BS) k_mg_scale_grid(long N, int lS, const cx<R
 }
 
 // ------------------------------------------------------- COCG with the V-cycle
-// Lane prologue shared with the Jacobi kernel: the flag, the previous
-// partials and the state in one round trip, the sums, then the advance.
-// Returns false when the launch has nothing to do.
+// What a launch of the multigrid step does with a lane's FP64 iterate.  The
+// update x += alpha p of an iteration may wait for the next launch: p is
+// updated in place, so that launch still reads the same p, and it adds both
+// terms in the order the immediate updates would, (x + a0 p) + alpha p' (the
+// same values up to FP64 rounding).  x is then read and written every other
+// iteration.  A lane
+// defers at even launch parity only, so the lanes of a cache line of x skip
+// together.  A residual replacement reads x + a0 p at the neighbours (the
+// term stays deferred), a Jacobi step adds it, and the launch in which the
+// lane stops adds it alone.
+struct XPlan {
+  c128 a0;      // coefficient of the deferred term
+  bool fold;    // a deferred term a0 p is pending from the previous launch
+  bool write;   // ITER: x is read and written in this launch
+  bool stop;    // the lane stopped in this launch with a term to add
+};
+__device__ __forceinline__ XPlan x_plan(CgScal& s, bool was_done, int par) {
+  XPlan xp;
+  xp.fold = s.pend != 0;
+  xp.a0 = s.apend;
+  xp.write = true;
+  xp.stop = false;
+  if (s.done) {
+    xp.stop = !was_done && xp.fold;
+    s.pend = 0;
+  } else if (s.mode == CG_ITER) {
+    xp.write = xp.fold || par != 0;
+    s.pend = xp.write ? 0 : 1;
+    s.apend = xp.write ? c128{0.0, 0.0} : s.alpha;
+  } else if (s.mode == CG_KX) {
+    s.pend = 0;
+  }
+  return xp;
+}
+
+// Lane prologue of the step kernels: the flag, the previous partials and the
+// state in one round trip, the sums, then the advance and the iterate's plan.
+// Returns false when the launch has nothing to do (when every lane has
+// stopped, true only while a stopping lane still has a term to add to x).
 template <int CGB, bool ONE>
 __device__ __forceinline__ bool cg_prologue(int lS, const CgCfg& cfg, const c128* __restrict__ partIn, int Gin,
                                             const CgScal* __restrict__ scIn, CgScal* __restrict__ scOut,
-                                            int* __restrict__ all_done, CgScal& s, bool lead) {
+                                            int* __restrict__ all_done, CgScal& s, XPlan& xp, int par, bool lead) {
   const int S = 1 << lS;
   const int rl = ONE ? 0 : (int)threadIdx.x & (S - 1);
   const int flag = *all_done;
@@ -1253,16 +1453,22 @@ __device__ __forceinline__ bool cg_prologue(int lS, const CgCfg& cfg, const c128
   s = scIn[rl];
   c128 tot[3];
   part_sum<3, KMAX, CGB>(partIn, Gin, S, PL, tot);
-  if (flag) {
+  // The flag is set by the lead block of the launch in which the last lanes
+  // stop, while other blocks of that launch may still be starting: a block
+  // that sees it while a lane was still running before this launch carries
+  // on as the lead block does (its stopping lanes' deferred terms go into x).
+  if (flag && __all(s.done != 0)) {
     if (lead && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
     return false;
   }
+  const bool was_done = s.done != 0;
   cg_advance(s, cfg, tot[0], tot[1], tot[2].re);
+  xp = x_plan(s, was_done, par);
   const bool any_open = __any(!s.done);
   if (lead && (int)threadIdx.x < S) scOut[threadIdx.x] = s;
   if (!any_open) {
     if (lead && threadIdx.x == 0) *all_done = 1;
-    return false;
+    return __any(xp.stop);
   }
   count_live(all_done, lead);
   return true;
@@ -1271,7 +1477,7 @@ __device__ __forceinline__ bool cg_prologue(int lS, const CgCfg& cfg, const c128
 // Vector part of one multigrid-COCG iteration (the V-cycle and the operator
 // product follow in their own launches):
 //   ITER: s' = w + beta s, r' = r - alpha s', p' = u + beta p, x += alpha p'
-//         (u = B r from the previous V-cycle);
+//         (u = B r from the previous V-cycle; the x update as XPlan says);
 //   RR:   r' = v - (K + tau M) x in FP64, stored rounded (a round change of the
 //         complex64 path; the V-cycle and the product then give the new round's
 //         forms directly);
@@ -1295,8 +1501,8 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
   cx<R>* __restrict__ s1 = vec.s[par ^ 1];
   const int t0 = xcd_tile(blockIdx.x, gridDim.x) * CGB + threadIdx.x;
   CgScal s;
-  if (!cg_prologue<CGB, ONE>(lS, cfg, partIn, Gin, scIn, scOut, all_done, s, blockIdx.x == 0)) return;
-  if (s.done) return;
+  XPlan xp;
+  if (!cg_prologue<CGB, ONE>(lS, cfg, partIn, Gin, scIn, scOut, all_done, s, xp, par, blockIdx.x == 0)) return;
   auto for_cells = [&](auto&& f) {
     if constexpr (MULTI) {
       for (int t = t0; t < N; t += gridDim.x * CGB) f(t);
@@ -1304,27 +1510,39 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
       if (t0 < N) f(t0);
     }
   };
+  // x with the deferred term (the value the immediate updates give)
+  auto xeff = [&](int t) {
+    const c128 xv = vec.x[t];
+    return xp.fold ? xv + xp.a0 * cvt<double>(vec.p[t]) : xv;
+  };
+  if (s.done) {
+    if (xp.stop) for_cells([&](int t) { vec.x[t] = xeff(t); });
+    return;
+  }
   if (s.mode == CG_ITER) {
     const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta);
     const c128 al64 = s.alpha;
     for_cells([&](int t) {
+      const cx<R> po = vec.p[t];
       const cx<R> sn = w0[t] + be * s0[t];
-      const cx<R> pn = u[t] + be * vec.p[t];
+      const cx<R> pn = u[t] + be * po;
       r1[t] = r0[t] - al * sn;
       s1[t] = sn;
       vec.p[t] = pn;
-      vec.x[t] = vec.x[t] + al64 * cvt<double>(pn);
+      if (xp.write) {
+        const c128 xv = vec.x[t];
+        vec.x[t] = (xp.fold ? xv + xp.a0 * cvt<double>(po) : xv) + al64 * cvt<double>(pn);
+      }
     });
   } else if (s.mode == CG_RR) {
-    const c128* __restrict__ x = vec.x;
-    auto gx = [&](int cc) { return x[(cc << lS) + rl]; };
+    auto gx = [&](int cc) { return xeff((cc << lS) + rl); };
     for_cells([&](int t) {
       const int c = t >> lS;
       r1[t] = cvt<R>(cvt<double>(v[t]) - opd.template apply<double>(c, tau, gx));
       s1[t] = cx<R>{0, 0};
     });
   } else if (s.mode == CG_KX) {
-    for_cells([&](int t) { vec.x[t] = vec.x[t] + cvt<double>(u[t]); });
+    for_cells([&](int t) { vec.x[t] = xeff(t) + cvt<double>(u[t]); });
   }
 }
 
@@ -1353,13 +1571,23 @@ __global__ void __launch_bounds__(BS) k_cgmg_step_down(Op op, OpD opd, LevelDims
   xcd_block3(bx, J, L);
   const bool lead = (blockIdx.x | blockIdx.y | blockIdx.z) == 0;
   CgScal s;
-  if (!cg_prologue<BS, true>(0, cfg, partIn, Gin, scIn, scOut, all_done, s, lead)) return;
+  XPlan xp;
+  if (!cg_prologue<BS, true>(0, cfg, partIn, Gin, scIn, scOut, all_done, s, xp, par, lead)) return;
   const int t = bx * BS + threadIdx.x;
   if (t >= (c.nx << D)) return;   // after the prologue's barriers; whole groups of 2^d lanes
   const int q = t & (Q - 1), I = t >> D;
   const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * L + (q >> 2);
   const bool in = i < f.nx && j < f.ny && k < f.nz;
   const int cell = i + f.nx * (j + f.ny * k);
+  // x with the deferred term (the value the immediate updates give)
+  auto xeff = [&](int e) {
+    const c128 xv = vec.x[e];
+    return xp.fold ? xv + xp.a0 * cvt<double>(vec.p[e]) : xv;
+  };
+  if (s.done) {   // only a lane that stops here with a deferred term
+    if (in) vec.x[cell] = xeff(cell);
+    return;
+  }
   const cx<R>* __restrict__ r0 = vec.r[par];
   const cx<R>* __restrict__ w0 = vec.w[par];
   const cx<R>* __restrict__ s0 = vec.s[par];
@@ -1375,16 +1603,19 @@ __global__ void __launch_bounds__(BS) k_cgmg_step_down(Op op, OpD opd, LevelDims
     auto gb = [&](int n) { return r0[n] - al * (w0[n] + be * s0[n]); };
     if (in) {
       res = mg_down_fine<Op, R>(op, i, j, k, cell, tr, om, gb, gd);
+      const cx<R> po = vec.p[cell];
       const cx<R> sn = w0[cell] + be * s0[cell];
-      const cx<R> pn = u[cell] + be * vec.p[cell];
+      const cx<R> pn = u[cell] + be * po;
       r1[cell] = gb(cell);
       s1[cell] = sn;
       vec.p[cell] = pn;
-      vec.x[cell] = vec.x[cell] + al64 * cvt<double>(pn);
+      if (xp.write) {
+        const c128 xv = vec.x[cell];
+        vec.x[cell] = (xp.fold ? xv + xp.a0 * cvt<double>(po) : xv) + al64 * cvt<double>(pn);
+      }
     }
   } else if (s.mode == CG_RR) {
-    const c128* __restrict__ x = vec.x;
-    auto gx = [&](int cc) { return x[cc]; };
+    auto gx = [&](int cc) { return xeff(cc); };
     auto gb = [&](int n) { return cvt<R>(cvt<double>(v[n]) - opd.template apply<double>(n, tau, gx)); };
     if (in) {
       res = mg_down_fine<Op, R>(op, i, j, k, cell, tr, om, gb, gd);
@@ -1395,7 +1626,7 @@ __global__ void __launch_bounds__(BS) k_cgmg_step_down(Op op, OpD opd, LevelDims
     auto gb = [&](int n) { return r1[n]; };
     if (in) {
       res = mg_down_fine<Op, R>(op, i, j, k, cell, tr, om, gb, gd);
-      if (s.mode == CG_KX) vec.x[cell] = vec.x[cell] + cvt<double>(u[cell]);
+      if (s.mode == CG_KX) vec.x[cell] = xeff(cell) + cvt<double>(u[cell]);
     }
   }
   res = group_sum<Q>(res);

@@ -398,6 +398,8 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 //  asm_mfma    solution assembly X = Z Y on the FP64 matrix cores
 //  tile3_post, post3_lt   3-D, several lanes, finest level plane-marching: the
 //              product w = A u on the same tiles, post3_lt complex64 lanes per thread
+//  rows, rows_yb   2-D levels of at least `rows` cells, several lanes: legs
+//              marching rows_yb rows per block
 //  tile3, tile3_zb, tile3_lt   3-D levels of at least tile3 cells: plane-
 //              marching grid legs, tile3_zb planes per block, tile3_lt complex64
 //              lanes per thread
@@ -424,6 +426,8 @@ struct Tune {
   int asm_mfma = 1;   // solution assembly on the FP64 matrix cores
   int tile3_post = 0; // the product w = A u on the plane-marching tiles too (3-D, several lanes)
   int post3_lt = 2;   // complex64 lanes per thread of that product (2 or 4)
+  long rows = 0;      // 2-D levels of at least this many cells, several lanes: row-marching legs (0: none)
+  int rows_yb = 8;    // rows per block of those legs (even)
 
   // Sets a knob by name; false for an unknown name or a value out of range.
   bool set(const std::string& k, double v) {
@@ -454,6 +458,8 @@ struct Tune {
     else if (k == "asm_mfma") { asm_mfma = iv != 0; }
     else if (k == "tile3_post") { tile3_post = iv != 0; }
     else if (k == "post3_lt") { if (iv != 2 && iv != 4) return false; post3_lt = iv; }
+    else if (k == "rows") { if (v < 0) return false; rows = (long)v; }
+    else if (k == "rows_yb") { if (iv < 2 || iv > 256 || (iv & 1)) return false; rows_yb = iv; }
     else return false;
     return true;
   }
@@ -482,6 +488,8 @@ struct Tune {
     else if (k == "asm_mfma") *v = asm_mfma;
     else if (k == "tile3_post") *v = tile3_post;
     else if (k == "post3_lt") *v = post3_lt;
+    else if (k == "rows") *v = (double)rows;
+    else if (k == "rows_yb") *v = rows_yb;
     else return false;
     return true;
   }
@@ -1258,10 +1266,28 @@ template <typename R, typename Op, typename OpD> struct Group {
   // than the other sizes and than a lane per thread).
   static constexpr bool c64 = std::is_same<R, float>::value;
   bool lane_chunks() const { return c64 || tn().lt64 >= 2; }
+  // row-marching 2-D legs (several lanes, levels of at least `rows` cells)
+  bool rows_for(const LevelDims& f, int lNC) const {
+    return Op::NB == 4 && tn().rows > 0 && (long)f.n() >= tn().rows && lNC <= 5;
+  }
+  template <bool UP, int LT>
+  void leg_rows(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, int lNC, const cx<R>* bl,
+                const cx<R>* dl, const cx<R>* xcoarse, cx<R>* out) {
+    if constexpr (Op::NB == 4 && LT * sizeof(cx<R>) <= 32) {
+      const int SW = BS >> lNC, YB = tn().rows_yb;
+      const long G = (long)((f.nx + SW - 1) / SW) * ((f.ny + YB - 1) / YB);
+      k_mg_leg_rows<Op, R, LT, UP><<<(unsigned)G, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, YB,
+                                                               bl, dl, xcoarse, out, B.all_done);
+    }
+  }
   template <int LT>
   void mg_down_lt(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
                   cx<R>* out) {
     const int lNC = lS - ilog2(LT);
+    if (LT * sizeof(cx<R>) <= 32 && rows_for(f, lNC)) {
+      leg_rows<false, LT>(l, f, c, tau, lS, lNC, bl, dl, nullptr, out);
+      return;
+    }
     const dim3 g((unsigned)((((long)c.nx << (lNC + Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
     k_mg_down_lanes<Op, R, LT><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, bl, dl, out,
                                                  B.all_done);
@@ -1277,6 +1303,10 @@ template <typename R, typename Op, typename OpD> struct Group {
   void mg_up_lt(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl, const cx<R>* dl,
                 const cx<R>* xcoarse, cx<R>* out) {
     const int lNC = lS - ilog2(LT);
+    if (LT * sizeof(cx<R>) <= 32 && rows_for(f, lNC)) {
+      leg_rows<true, LT>(l, f, c, tau, lS, lNC, bl, dl, xcoarse, out);
+      return;
+    }
     const dim3 g((unsigned)((((long)f.nx << lNC) + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
     k_mg_up_lanes<Op, R, LT><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, bl, dl, xcoarse,
                                                out, B.all_done);
@@ -1735,7 +1765,8 @@ template <typename R, typename Op, typename OpD> struct Group {
   }
 
   // Algorithmic bytes of one multigrid-COCG iteration (all its launches):
-  // k_cgmg_step reads r, w, s, u, p and x and writes r, s, p and x; on every
+  // k_cgmg_step reads r, w, s, u, p and writes r, s, p, and reads and writes
+  // the FP64 x every other iteration (the deferred update); on every
   // level above the tail the down leg reads b, D^-1, the faces (and the mass
   // on coarse levels) and writes the coarse b, and the up leg reads b, D^-1,
   // the faces, the mass and the coarse x and writes x; the tail reads its top
@@ -1746,7 +1777,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     const double fpc = (p->kind == Kind::FV3D ? 3.0 : 2.0) * sizeof(R);
     const int lS = ilog2(S);
     const int Lv = mg_levels(), t = mg_tail_level(lS);
-    double bytes = (double)N * (8.0 * w + 32.0);                       // vector updates
+    double bytes = (double)N * (8.0 * w + 16.0);                       // vector updates (FP64 x every other)
     if (mg_fused(lS)) bytes -= (double)N * w;                           // fused: r' not read back
     for (int l = 0; l < std::min(t, Lv - 1); ++l) {
       const double nl = mg_dims(l).n(), nc = mg_dims(l + 1).n();

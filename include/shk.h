@@ -467,6 +467,10 @@ int shk_profile_read_phases(double* ms, int n);
  *   mg_fuse 0|1             step fused with the finest restriction
  *   post_lt, down_lt, up_lt 2|4|8  lanes per thread (complex64, several lanes)
  *   lt64 0|2|4              lanes per thread on complex128
+ *   rows, rows64 >= 0       2-D levels of at least this many cells, several
+ *                           lanes, complex64 / complex128: grid legs marching
+ *                           the rows (0: none; defaults 0 and 16384)
+ *   rows_yb 2..256, even    rows per block of those legs (default 4)
  *   graph 0|1               inner iterations replayed from a HIP graph captured
  *                           on the solve stream (needs a non-null stream)
  *   mg_chain 0|1            2-D, one lane: up to 3 middle legs of each direction

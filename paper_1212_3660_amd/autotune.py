@@ -44,6 +44,9 @@ SPACE = {
     "nt_store32": [0, 1],
     "nt_store64": [0, 1],
     "graph": [0, 1],
+    "rows": [0, 65536, 16384],
+    "rows64": [0, 65536, 16384],
+    "rows_yb": [2, 4, 8],
     "tile3": [0, 32768, 262144],
     "tile3_zb": [4, 8, 16],
     "tile3_lt": [4, 8],
@@ -66,9 +69,9 @@ def knobs_for(key, n_lanes_real=None):
         if lanes == 1:
             ks += ["mg_fuse"] + (["mg_chain"] if kind == 0 else [])
         elif mixed:
-            ks += ["post_lt", "down_lt", "up_lt"]
+            ks += ["post_lt", "down_lt", "up_lt"] + (["rows", "rows_yb"] if kind == 0 else [])
         else:
-            ks += ["lt64"]
+            ks += ["lt64"] + (["rows64", "rows_yb"] if kind == 0 else [])
         if mixed:
             ks += ["round_tol_mg"]
     else:

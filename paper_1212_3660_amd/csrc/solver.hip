@@ -398,8 +398,9 @@ template <typename F, typename Fn> static int with_op(const shk_problem* p, Fn&&
 //  asm_mfma    solution assembly X = Z Y on the FP64 matrix cores
 //  tile3_post, post3_lt   3-D, several lanes, finest level plane-marching: the
 //              product w = A u on the same tiles, post3_lt complex64 lanes per thread
-//  rows, rows_yb   2-D levels of at least `rows` cells, several lanes: legs
-//              marching rows_yb rows per block
+//  rows, rows64, rows_yb   2-D levels of at least `rows` (complex64) or
+//              `rows64` (complex128) cells, several lanes: legs marching
+//              rows_yb rows per block
 //  tile3, tile3_zb, tile3_lt   3-D levels of at least tile3 cells: plane-
 //              marching grid legs, tile3_zb planes per block, tile3_lt complex64
 //              lanes per thread
@@ -426,8 +427,9 @@ struct Tune {
   int asm_mfma = 1;   // solution assembly on the FP64 matrix cores
   int tile3_post = 0; // the product w = A u on the plane-marching tiles too (3-D, several lanes)
   int post3_lt = 2;   // complex64 lanes per thread of that product (2 or 4)
-  long rows = 0;      // 2-D levels of at least this many cells, several lanes: row-marching legs (0: none)
-  int rows_yb = 8;    // rows per block of those legs (even)
+  long rows = 0;        // 2-D levels of at least this many cells, several complex64 lanes: row-marching legs
+  long rows64 = 16384;  // the same for complex128 lanes (0: none)
+  int rows_yb = 4;      // rows per block of those legs (even)
 
   // Sets a knob by name; false for an unknown name or a value out of range.
   bool set(const std::string& k, double v) {
@@ -459,6 +461,7 @@ struct Tune {
     else if (k == "tile3_post") { tile3_post = iv != 0; }
     else if (k == "post3_lt") { if (iv != 2 && iv != 4) return false; post3_lt = iv; }
     else if (k == "rows") { if (v < 0) return false; rows = (long)v; }
+    else if (k == "rows64") { if (v < 0) return false; rows64 = (long)v; }
     else if (k == "rows_yb") { if (iv < 2 || iv > 256 || (iv & 1)) return false; rows_yb = iv; }
     else return false;
     return true;
@@ -489,6 +492,7 @@ struct Tune {
     else if (k == "tile3_post") *v = tile3_post;
     else if (k == "post3_lt") *v = post3_lt;
     else if (k == "rows") *v = (double)rows;
+    else if (k == "rows64") *v = (double)rows64;
     else if (k == "rows_yb") *v = rows_yb;
     else return false;
     return true;
@@ -1268,7 +1272,8 @@ template <typename R, typename Op, typename OpD> struct Group {
   bool lane_chunks() const { return c64 || tn().lt64 >= 2; }
   // row-marching 2-D legs (several lanes, levels of at least `rows` cells)
   bool rows_for(const LevelDims& f, int lNC) const {
-    return Op::NB == 4 && tn().rows > 0 && (long)f.n() >= tn().rows && lNC <= 5;
+    const long th = c64 ? tn().rows : tn().rows64;
+    return Op::NB == 4 && th > 0 && (long)f.n() >= th && lNC <= 5;
   }
   template <bool UP, int LT>
   void leg_rows(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, int lNC, const cx<R>* bl,

@@ -41,6 +41,8 @@ SETTINGS = [
     "tail_lanes=0",
     "tail_lanes=2,tail_lds=162816",
     "tail_lanes=4,tail_lds=16384",
+    "rows=1,rows64=1,rows_yb=2,down_lt=2,up_lt=2",
+    "rows=1,rows64=0,rows_yb=8,down_lt=8,up_lt=8",
 ]
 
 def _cached_picks():

@@ -38,7 +38,9 @@ def test_packaged_cache_is_valid():
 def test_tune_table_rejects_bad_settings():
     import paper_1212_3660_amd as P
     key = (0, 1000, 1, P.SHK_MIXED, P.SHK_PRECOND_MULTIGRID)
-    for k, v in (("cg_block", 128), ("tail_lds", 200 * 1024), ("round_tol", 1.5), ("no_such_knob", 1)):
+    for k, v in (("cg_block", 128), ("tail_lds", 200 * 1024), ("round_tol", 1.5), ("no_such_knob", 1),
+                 ("tail_lanes", 3), ("tail_lanes", 128), ("rows", -1), ("rows64", -5), ("rows_yb", 3),
+                 ("rows_yb", 0), ("tile3_lt", 16), ("post3_lt", 8), ("mg_chain", 2)):
         with pytest.raises(P.ShkError):
             P.shk_tune_set(key, k, v)
     from paper_1212_3660_amd import autotune as T
@@ -51,6 +53,13 @@ def test_tune_table_rejects_bad_settings():
         assert P.shk_tune_get((1, 5, 1, 0, 0), "down_lt") == 8
         P.shk_tune_reset()
         assert P.shk_tune_get(key, "post_lt") == 2 and P.shk_tune_get(P.TUNE_ALL, "down_lt") == 4
+        # the defaults of the lane-split tail and the row-marching legs
+        assert P.shk_tune_get(P.TUNE_ALL, "tail_lanes") == 1
+        assert P.shk_tune_get(P.TUNE_ALL, "rows") == 0 and P.shk_tune_get(P.TUNE_ALL, "rows64") == 16384
+        assert P.shk_tune_get(P.TUNE_ALL, "rows_yb") == 4
+        for k, v in (("tail_lanes", 0), ("tail_lanes", 64), ("rows", 65536), ("rows_yb", 16)):
+            P.shk_tune_set(key, k, v)
+            assert P.shk_tune_get(key, k) == v
     finally:
         P.shk_tune_reset()
         T.load()

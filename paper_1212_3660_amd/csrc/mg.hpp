@@ -1492,7 +1492,6 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
                                                    CgVecs<R> vec, int par, int* __restrict__ all_done) {
   const CgCfg cfg = *cfgp;
   const int lS = ONE ? 0 : lS_;
-  const int rl = ONE ? 0 : (int)threadIdx.x & ((1 << lS) - 1);
   const int N = n << lS;
   const cx<R>* __restrict__ r0 = vec.r[par];
   const cx<R>* __restrict__ w0 = vec.w[par];
@@ -1517,9 +1516,7 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
   };
   if (s.done) {
     if (xp.stop) for_cells([&](int t) { vec.x[t] = xeff(t); });
-    return;
-  }
-  if (s.mode == CG_ITER) {
+  } else if (s.mode == CG_ITER) {
     const cx<R> al = cvt<R>(s.alpha), be = cvt<R>(s.beta);
     const c128 al64 = s.alpha;
     for_cells([&](int t) {
@@ -1535,14 +1532,66 @@ __global__ void __launch_bounds__(CGB) k_cgmg_step(OpD opd, c128 tau, int n, int
       }
     });
   } else if (s.mode == CG_RR) {
-    auto gx = [&](int cc) { return xeff((cc << lS) + rl); };
-    for_cells([&](int t) {
-      const int c = t >> lS;
-      r1[t] = cvt<R>(cvt<double>(v[t]) - opd.template apply<double>(c, tau, gx));
-      s1[t] = cx<R>{0, 0};
-    });
+    if constexpr (ONE) {
+      auto gx = [&](int cc) { return xeff(cc); };
+      for_cells([&](int t) {
+        r1[t] = cvt<R>(cvt<double>(v[t]) - opd.template apply<double>(t, tau, gx));
+        s1[t] = cx<R>{0, 0};
+      });
+    }
   } else if (s.mode == CG_KX) {
     for_cells([&](int t) { vec.x[t] = xeff(t) + cvt<double>(u[t]); });
+  }
+  if constexpr (!ONE) {
+    // Residual replacements of several lanes: the block's (cell, lane) items
+    // of the lanes in mode RR, compacted over all its threads (lanes fastest),
+    // instead of each thread forming its own lane's: a launch in which a few
+    // lanes replace theirs then pays their FP64 stencil once per block rather
+    // than once per wave and cell.  Every wave holds every lane, so the
+    // ballot gives the block's lane set.
+    const int S = 1 << lS;
+    const unsigned long long bal = __ballot(!s.done && s.mode == CG_RR);
+    const unsigned long long lanes = S == 64 ? bal : bal & ((1ull << S) - 1);
+    if (lanes == 0) return;   // uniform over the block
+    __shared__ c128 rr_a0[64];
+    __shared__ int rr_fold[64];
+    if ((int)threadIdx.x < S) {
+      rr_a0[threadIdx.x] = xp.a0;
+      rr_fold[threadIdx.x] = xp.fold ? 1 : 0;
+    }
+    __syncthreads();
+    const int nrr = __popcll(lanes);
+    const int cpb = CGB >> lS;                              // cells per block and step
+    const long base = (long)xcd_tile(blockIdx.x, gridDim.x) * CGB;
+    const long stride = MULTI ? (long)gridDim.x * CGB : (long)N;
+    const long steps = base < N ? (N - base + stride - 1) / stride : 0;
+    const long items = steps * cpb * nrr;
+    for (long it = threadIdx.x; it < items; it += CGB) {
+      const int q = (int)(it % nrr);
+      const long rest = it / nrr;
+      const int j = (int)(rest % cpb);
+      const long k = rest / cpb;
+      const long c = ((base + k * stride) >> lS) + j;
+      if (c >= n) continue;
+      int lane;
+      if (nrr == S) {
+        lane = q;
+      } else {
+        unsigned long long mm = lanes;
+        for (int z = 0; z < q; ++z) mm &= mm - 1;
+        lane = __builtin_ctzll(mm);
+      }
+      const bool fo = rr_fold[lane] != 0;
+      const c128 a0 = rr_a0[lane];
+      auto gx = [&](int cc) {
+        const long e = ((long)cc << lS) + lane;
+        const c128 xv = vec.x[e];
+        return fo ? xv + a0 * cvt<double>(vec.p[e]) : xv;
+      };
+      const long e = (c << lS) + lane;
+      r1[e] = cvt<R>(cvt<double>(v[e]) - opd.template apply<double>((int)c, tau, gx));
+      s1[e] = cx<R>{0, 0};
+    }
   }
 }
 

@@ -63,3 +63,25 @@ def test_tune_table_rejects_bad_settings():
     finally:
         P.shk_tune_reset()
         T.load()
+
+
+def test_tuner_knobs_follow_the_class():
+    """The autotuner searches a knob only where it changes something: the
+    tail's lanes per workgroup with several lanes, the row-marching legs on
+    2-D several-lane classes (rows for complex64, rows64 for complex128), the
+    plane-marching ones in 3-D, the chained legs with one 2-D lane."""
+    import paper_1212_3660_amd as P
+    from paper_1212_3660_amd import autotune as T
+    mg, jac = P.SHK_PRECOND_MULTIGRID, P.SHK_PRECOND_JACOBI
+    k2m = T.knobs_for((0, 65536, 64, P.SHK_MIXED, mg))
+    k2d = T.knobs_for((0, 65536, 64, P.SHK_FP64, mg))
+    k1 = T.knobs_for((0, 262144, 1, P.SHK_MIXED, mg))
+    k3 = T.knobs_for((1, 2097152, 8, P.SHK_MIXED, mg))
+    kj = T.knobs_for((0, 262144, 4, P.SHK_MIXED, jac))
+    assert {"tail_lanes", "rows", "rows_yb"} <= set(k2m) and "rows64" not in k2m
+    assert {"tail_lanes", "rows64", "rows_yb", "lt64"} <= set(k2d) and "rows" not in k2d
+    assert "tail_lanes" not in k1 and "rows" not in k1 and {"mg_chain", "mg_fuse"} <= set(k1)
+    assert "rows" not in k3 and {"tile3", "tile3_zb", "tile3_lt", "tail_lanes"} <= set(k3)
+    assert not {"tail_lds", "tail_lanes", "rows", "tile3"} & set(kj) and "round_tol" in kj
+    for k in k2m + k2d + k1 + k3 + kj:
+        assert k in T.SPACE

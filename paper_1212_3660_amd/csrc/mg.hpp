@@ -287,6 +287,16 @@ __global__ void __launch_bounds__(BS) k_mg_up(Op op, LevelDims f, LevelDims c, c
   if (!flag) xout[((long)cell << lS) + rl] = v;
 }
 
+// True when some lane of the chunk l0 .. l0 + LT - 1 still runs (its state as
+// the step of this iteration left it): the V-cycle and the product skip the
+// chunks whose lanes have all stopped, whose results nothing reads.
+template <int LT> __device__ __forceinline__ bool chunk_live(const CgScal* __restrict__ sc, int l0) {
+  bool live = false;
+#pragma unroll
+  for (int l = 0; l < LT; ++l) live = live || !sc[l0 + l].done;
+  return live;
+}
+
 // The two legs for several right-hand sides: a thread works LT lanes of one
 // cell (down: of one child of a coarse cell) and loads the cell's stencil,
 // mass and D^-1 once for them instead of once per lane; per lane the
@@ -298,7 +308,7 @@ template <typename Op, typename R, int LT>
 __global__ void __launch_bounds__(BS) k_mg_down_lanes(Op op, LevelDims f, LevelDims c, c128 tau, double omega,
                                                       int lS, int lNC, const cx<R>* __restrict__ b,
                                                       const cx<R>* __restrict__ dinv, cx<R>* __restrict__ out,
-                                                      const int* __restrict__ all_done) {
+                                                      const CgScal* __restrict__ sc, const int* __restrict__ all_done) {
   constexpr int D = Op::NB / 2;
   constexpr int Q = 1 << D;
   constexpr int NB = Op::NB;
@@ -318,10 +328,11 @@ __global__ void __launch_bounds__(BS) k_mg_down_lanes(Op op, LevelDims f, LevelD
   const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = 2 * L + (q >> 2);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
+  const bool live = chunk_live<LT>(sc, lc * LT);
   cx<R> v[LT];
 #pragma unroll
   for (int l = 0; l < LT; ++l) v[l] = cx<R>{0, 0};
-  if (i < f.nx && j < f.ny && k < f.nz) {
+  if (live && i < f.nx && j < f.ny && k < f.nz) {
     const int cell = i + f.nx * (j + f.ny * k);
     int idx[NB];
     R fo[NB];
@@ -361,7 +372,7 @@ __global__ void __launch_bounds__(BS) k_mg_down_lanes(Op op, LevelDims f, LevelD
     for (int l = 0; l < LT; ++l) v[l] = group_sum<Q>(v[l]);
   }
   hold(v[0], flag);
-  if (!flag && q == 0) {
+  if (!flag && q == 0 && live) {
     cx<R>* o = out + ((long)(I + c.nx * (J + c.ny * L)) << lS) + lc * LT;
 #pragma unroll
     for (int l = 0; l < LT; ++l) o[l] = v[l];
@@ -374,7 +385,8 @@ template <typename Op, typename R, int LT>
 __global__ void __launch_bounds__(BS) k_mg_up_lanes(Op op, LevelDims f, LevelDims cd, c128 tau, double omega, int lS,
                                                     int lNC, const cx<R>* __restrict__ b,
                                                     const cx<R>* __restrict__ dinv, const cx<R>* __restrict__ xc,
-                                                    cx<R>* __restrict__ xout, const int* __restrict__ all_done) {
+                                                    cx<R>* __restrict__ xout, const CgScal* __restrict__ sc,
+                                                    const int* __restrict__ all_done) {
   constexpr int NB = Op::NB;
   int flag = *all_done;
   int bx, j, k;
@@ -382,6 +394,7 @@ __global__ void __launch_bounds__(BS) k_mg_up_lanes(Op op, LevelDims f, LevelDim
   const int t = bx * BS + threadIdx.x;
   if (t >= (f.nx << lNC)) return;
   const int lc = t & ((1 << lNC) - 1), i = t >> lNC;
+  if (!chunk_live<LT>(sc, lc * LT)) return;
   const int cell = i + f.nx * (j + f.ny * k);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
@@ -453,7 +466,8 @@ template <typename Op, typename R, int LT, bool UP>
 __global__ void __launch_bounds__(BS) k_mg_leg_rows(Op op, LevelDims f, LevelDims cd, c128 tau, double omega,
                                                     int lS, int lNC, int YB, const cx<R>* __restrict__ b,
                                                     const cx<R>* __restrict__ dinv, const cx<R>* __restrict__ xc,
-                                                    cx<R>* __restrict__ out, const int* __restrict__ all_done) {
+                                                    cx<R>* __restrict__ out, const CgScal* __restrict__ sc,
+                                                    const int* __restrict__ all_done) {
   static_assert(Op::NB == 4, "2-D operator");
   __shared__ cx<R> xs[2][BS * LT + 2 * 64];   // x1 of a row: (SW + 2) cells x S lanes, double-buffered
   const int flag = *all_done;
@@ -463,12 +477,13 @@ __global__ void __launch_bounds__(BS) k_mg_leg_rows(Op op, LevelDims f, LevelDim
   const int seg = tile % nseg, rb = tile / nseg;
   const int lc = (int)threadIdx.x & (NC - 1), ci = (int)threadIdx.x >> lNC;
   const int i = seg * SW + ci;
-  const bool own = i < f.nx;
+  const bool live = chunk_live<LT>(sc, lc * LT);   // a stopped chunk loads and stores nothing
+  const bool own = i < f.nx && live;
   // the segment's end neighbours: threads 0 .. 2 NC - 1, left then right
   const int hs = (int)threadIdx.x >> lNC;
   const bool hal = (int)threadIdx.x < 2 * NC;
   const int hi = hs == 0 ? seg * SW - 1 : seg * SW + SW;
-  const bool hin = hal && hi >= 0 && hi < f.nx;
+  const bool hin = hal && hi >= 0 && hi < f.nx && live;
   const int j0 = rb * YB, j1 = min(j0 + YB, f.ny);
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
@@ -581,7 +596,7 @@ __global__ void __launch_bounds__(BS) k_mg_leg_rows(Op op, LevelDims f, LevelDim
         const int I = i >> 1, J = j >> 1;
         int fl = flag;
         hold(acc[0], fl);
-        if (!(ci & 1) && I < cd.nx && !fl) {
+        if (!(ci & 1) && I < cd.nx && live && !fl) {
           cx<R>* o = out + ((long)(I + cd.nx * J) << lS) + l0;
 #pragma unroll
           for (int l = 0; l < LT; ++l) o[l] = acc[l];
@@ -916,6 +931,7 @@ __global__ void __launch_bounds__(T3T) k_mg_leg_tile3(Op op, LevelDims f, LevelD
                                                       int lS, int C, int ZB, const cx<R>* __restrict__ b,
                                                       const cx<R>* __restrict__ dinv,
                                                       const cx<R>* __restrict__ xc, cx<R>* __restrict__ out,
+                                                      const CgScal* __restrict__ sc,
                                                       const int* __restrict__ all_done) {
   __shared__ cx<R> sh[T3Y + 2][T3X + 2][LT];
   __shared__ cx<R> stg[UP ? 1 : T3Y][UP ? 1 : T3X][LT];   // restriction: the children's sums
@@ -923,6 +939,7 @@ __global__ void __launch_bounds__(T3T) k_mg_leg_tile3(Op op, LevelDims f, LevelD
   int bxc, by, bz;
   xcd_block3(bxc, by, bz);
   const int ch = bxc % C, bx = bxc / C;
+  if (!chunk_live<LT>(sc, ch * LT)) return;   // the block's chunk has stopped (uniform)
   const int tx = (int)threadIdx.x % T3X, ty = (int)threadIdx.x / T3X;
   const int i = bx * T3X + tx, j = by * T3Y + ty;
   const bool own = i < f.nx && j < f.ny;
@@ -1262,6 +1279,7 @@ template <typename Op, typename R, int CAP>
 __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau, double omega, int lS, int lSg,
                                                              const unsigned* __restrict__ pack,
                                                              const cx<R>* __restrict__ btop, cx<R>* __restrict__ xtop,
+                                                             const CgScal* __restrict__ sc,
                                                              const int* __restrict__ all_done) {
   using F = typename std::remove_const<typename std::remove_pointer<decltype(Op::tx)>::type>::type;
   constexpr int NW = CAP / 4 / MG_TAIL_THREADS + 1;                        // packed words per thread
@@ -1273,6 +1291,8 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
   cx<R>* sh = reinterpret_cast<cx<R>*>(lds_raw);
   const int flag = *all_done;
   const int tid = threadIdx.x;
+  // the workgroup's lanes still running (loaded with everything else)
+  const int run = tid < (1 << lS) && !sc[((int)blockIdx.x << lS) + tid].done;
   const int T = a.T;
   const int n0 = (a.lv[0].nx * a.lv[0].ny * a.lv[0].nz) << lS;
   // element j of the workgroup's top level in the interleaved global arrays
@@ -1309,6 +1329,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
   }
   if (flag) return;   // uniform: the whole workgroup leaves
   __syncthreads();
+  if (!__syncthreads_or(run)) return;   // every lane of the workgroup has stopped
   const int S = 1 << lS;
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
@@ -1758,14 +1779,18 @@ __global__ void __launch_bounds__(CGB) k_cgmg_post_lanes(Op op, c128 tau, int n,
   const int ch = (int)threadIdx.x & (C - 1);
   const long items = (long)n << lC;
   bool live[LT];
+  bool any = false;
 #pragma unroll
-  for (int j = 0; j < LT; ++j) live[j] = !sc[ch * LT + j].done;
+  for (int j = 0; j < LT; ++j) {
+    live[j] = !sc[ch * LT + j].done;
+    any = any || live[j];
+  }
   const cx<R> tr = cvt<R>(tau);
   c128 acc[3][LT];
 #pragma unroll
   for (int j = 0; j < LT; ++j) acc[0][j] = acc[1][j] = acc[2][j] = c128{0.0, 0.0};
   const SlabWalk sw(op, items, lC, CGB);
-  for (long t = sw.first(); t < sw.end; t += sw.step) {
+  for (long t = any ? sw.first() : sw.end; t < sw.end; t += sw.step) {   // a stopped chunk loads nothing
     const int c = sw.cell(t);
     int idx[NB];
     R fo[NB];

@@ -1116,6 +1116,7 @@ template <typename R, typename Op, typename OpD> struct Group {
   bool mg = false;                // COCG preconditioned by the V-cycle
   double mg_omega = 0.8;
   MgTail mg_ta{};                 // tail arguments for the current inner solve
+  const CgScal* vsc = nullptr;    // lane states the V-cycle's launches read (the step's output)
   // working launches of the last inner solve per tau (a handful of taus)
   std::vector<std::pair<c128, int>> mg_hist;
   int mg_hist_get(c128 tau) const {
@@ -1282,7 +1283,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       const int SW = BS >> lNC, YB = tn().rows_yb;
       const long G = (long)((f.nx + SW - 1) / SW) * ((f.ny + YB - 1) / YB);
       k_mg_leg_rows<Op, R, LT, UP><<<(unsigned)G, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, YB,
-                                                               bl, dl, xcoarse, out, B.all_done);
+                                                               bl, dl, xcoarse, out, vsc, B.all_done);
     }
   }
   template <int LT>
@@ -1295,7 +1296,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
     const dim3 g((unsigned)((((long)c.nx << (lNC + Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
     k_mg_down_lanes<Op, R, LT><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, bl, dl, out,
-                                                 B.all_done);
+                                                 vsc, B.all_done);
   }
   void mg_down_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                      const cx<R>* dl, cx<R>* out) {
@@ -1314,7 +1315,7 @@ template <typename R, typename Op, typename OpD> struct Group {
     }
     const dim3 g((unsigned)((((long)f.nx << lNC) + BS - 1) / BS), (unsigned)f.ny, (unsigned)f.nz);
     k_mg_up_lanes<Op, R, LT><<<g, BS, 0, st>>>(mg_op<Op, R>(op, l), f, c, tau, mg_omega, lS, lNC, bl, dl, xcoarse,
-                                               out, B.all_done);
+                                               out, vsc, B.all_done);
   }
   void mg_up_lanes(int l, const LevelDims& f, const LevelDims& c, c128 tau, int lS, const cx<R>* bl,
                    const cx<R>* dl, const cx<R>* xcoarse, cx<R>* out) {
@@ -1336,7 +1337,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       const dim3 g((unsigned)(((f.nx + T3X - 1) / T3X) * C), (unsigned)((f.ny + T3Y - 1) / T3Y),
                    (unsigned)((f.nz + ZB - 1) / ZB));
       k_mg_leg_tile3<Op, R, LT, UP><<<g, T3T, 0, st>>>(o, f, c, tau, mg_omega, lS, C, ZB, bl, dl, xcoarse, out,
-                                                        B.all_done);
+                                                        vsc, B.all_done);
     }
   }
   template <bool UP>
@@ -1418,10 +1419,10 @@ template <typename R, typename Op, typename OpD> struct Group {
         const unsigned gt = 1u << (lS - lg);
         if (mg_lds > MG_TAIL_LDS)
           k_mg_tail<Op, R, MG_TAIL_LDS_MAX><<<gt, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(
-              mg_ta, tau, mg_omega, lg, lS, B.mpack, bl, xt, B.all_done);
+              mg_ta, tau, mg_omega, lg, lS, B.mpack, bl, xt, vsc, B.all_done);
         else
           k_mg_tail<Op, R, MG_TAIL_LDS><<<gt, MG_TAIL_THREADS, (size_t)mg_lds, st>>>(mg_ta, tau, mg_omega, lg, lS,
-                                                                                   B.mpack, bl, xt, B.all_done);
+                                                                                   B.mpack, bl, xt, vsc, B.all_done);
       } else {
         // the coarsest level alone exceeds the tail: solve it on the grid
         const int l = Lv - 1;
@@ -1529,10 +1530,12 @@ template <typename R, typename Op, typename OpD> struct Group {
         const dim3 g((unsigned)(((long)c.nx * (1 << (Op::NB / 2)) + BS - 1) / BS), (unsigned)c.ny, (unsigned)c.nz);
         k_cgmg_step_down<Op, OpD, R><<<g, BS, 0, st>>>(op, opd, f, c, tau, mg_omega, B.cfgd, cur_v, B.u, in, Gin, scIn,
                                                        scOut, vec, par, B.dinv, B.mb[0], B.all_done);
+        vsc = scOut;
         mg_vcycle(vec.r[par ^ 1], tau, lS, B.u, 1);
       } else {
         k_cgmg_step<Op, OpD, R, CGB, ONE, MULTI><<<G, CGB, 0, st>>>(opd, tau, ni, lS, B.cfgd, cur_v, B.u, in, Gin, scIn,
                                                                     scOut, vec, par, B.all_done);
+        vsc = scOut;
         mg_vcycle(vec.r[par ^ 1], tau, lS, B.u);
       }
       if (!post_tile3(tau, lS, scOut, vec.r[par ^ 1], vec.w[par ^ 1], out) &&
@@ -1605,6 +1608,7 @@ template <typename R, typename Op, typename OpD> struct Group {
       if constexpr (Op::NB > 0) {
         // the first round's u = B v, w = A u and forms
         mg_prepare(tau);
+        vsc = B.sc;   // the states k_cg_init wrote: every lane running
         mg_vcycle(vec.r[0], tau, lS, B.u);
         mg_post(G, tau, ni, lS, B.sc, vec.r[0], vec.w[0], B.cpart[0]);
       }

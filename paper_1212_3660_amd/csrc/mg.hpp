@@ -1291,8 +1291,9 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
   cx<R>* sh = reinterpret_cast<cx<R>*>(lds_raw);
   const int flag = *all_done;
   const int tid = threadIdx.x;
-  // the workgroup's lanes still running (loaded with everything else)
-  const int run = tid < (1 << lS) && !sc[((int)blockIdx.x << lS) + tid].done;
+  // several lanes: the workgroup's lanes still running (loaded with everything
+  // else; one lane stops with the all-done flag)
+  const int run = lSg > 0 && tid < (1 << lS) && !sc[((int)blockIdx.x << lS) + tid].done;
   const int T = a.T;
   const int n0 = (a.lv[0].nx * a.lv[0].ny * a.lv[0].nz) << lS;
   // element j of the workgroup's top level in the interleaved global arrays
@@ -1329,7 +1330,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(MgTail a, c128 tau,
   }
   if (flag) return;   // uniform: the whole workgroup leaves
   __syncthreads();
-  if (!__syncthreads_or(run)) return;   // every lane of the workgroup has stopped
+  if (lSg > 0 && !__syncthreads_or(run)) return;   // every lane of the workgroup has stopped
   const int S = 1 << lS;
   const cx<R> tr = cvt<R>(tau);
   const R om = (R)omega;
